@@ -1,0 +1,641 @@
+"""FP64 NumPy/SciPy oracle of the FluSI hot path (arXiv:1506.06513).
+
+TEST INFRASTRUCTURE ONLY -- used by tests/, the smoke check and the benchmark's
+CPU-baseline leg.  It is written from the paper, step by step, with no blocking,
+fusion or pruning, and it shares no code with the HIP library.
+
+What it computes (paper section / equation in brackets):
+
+* the volume-penalized Navier-Stokes equations in rotational form
+  [Sec. 2.1, eq. PNST_org_momentum] without the sponge term,
+* Fourier pseudo-spectral discretization: derivatives as multiplication by
+  i*k, products in physical space, the 2/3 rule always on [Sec. 2.4],
+* the pressure handled by the projection of Algorithm 1 step (d) [Alg. 1],
+* Adams-Bashforth 2 with integrating factor for the viscous term [Sec. 2.4,
+  Alg. 1 step (e)],
+* the smoothed mask from a signed distance [Sec. 2.2, eq.
+  smoothing_mask_as_function_of_delta],
+* the insect model: rotation matrices, body/stroke/wing frames, body and wing
+  velocity fields [Sec. 3.1-3.3, eqs. M_body_yawpitchroll,
+  body_velocity_field, wing_velocity_field], body shape [Sec. 3.2] and the
+  polar-radius wing shape [Sec. 3.4],
+* force and torque from the penalization integral with the unsteady
+  correction [Sec. 2.1, eqs. force_with_unst_corrections, moment_of_love],
+* the time loop of Algorithm 1 (mask -> dt -> sources -> projection -> AB2).
+
+Where the paper is silent or garbled the readings below are used (each is
+listed in the design notes of the repository):
+
+  FFT sign/normalization: forward unnormalized with exp(-i k.x), inverse
+      scaled by 1/(nx ny nz); arrays are [z][y][x] with x fastest and the
+      half spectrum along x.
+  Wavenumbers: j = i for i < n/2, j = i - n otherwise (Nyquist = -n/2); the
+      derivative of a Nyquist mode is zero.
+  2/3 rule: a mode is kept iff 3|j| < n on every axis; applied to the whole
+      right-hand side after the forward transform and to the initial field.
+  k = 0: the projection is the identity there; mean mode FIXED sets the k=0
+      right-hand side to zero (the mean velocity stays at its initial value),
+      FREE keeps it.
+  Nonlinear term on the right-hand side: u x w (= -w x u).
+  AB2-IF with variable step: AB2 on v = exp(nu|k|^2 t) u_hat with the
+      variable-step weights b1 = 1 + r/2, b2 = -r/2, r = dt_n/dt_{n-1};
+      the first step is integrating-factor Euler.
+  Time step: dt = min(CFL dx / max|u|, eta_cap*C_eta (only with a mask),
+      dt_max), clamped to land on t_end; or a fixed dt.
+  Mask: cosine layer with h = c_smth*dx, or 0.5*(1 - tanh(delta/(c_smth*dx)));
+      delta < 0 inside the solid.
+  Ellipsoid thorax: max(sqrt(y^2+z^2) - b sqrt(max(0, 1-(x/a)^2)), |x| - a).
+  Elliptic wing: polar-radius form with the ellipse centred at (0, B) in the
+      wing plane, span along +y_w, chord along x_w, thickness along z_w.
+  Frames: x_w = M_wing M_stroke (x_b - pivot); the wing angular velocity in
+      the wing frame is M_wing M_stroke Omega_w^(b), and the wing velocity in
+      the global frame is M_body^T M_stroke^T M_wing^T (Omega^(w) x x_w).
+  Parts combine by the maximum of chi; u_s and colour come from the argmax
+      part (ties -> lowest colour).  Colours: 0 fluid, 1 body, 2 left wing,
+      3 right wing.
+  Force on the solid: F = (1/C_eta) sum chi (u - u_s) dV + (I^n - I^{n-1})/dt_{n-1}
+      with I = sum chi u_s dV (no unsteady term at the first step); torques
+      about the body centre (body) or the wing pivot (wings).
+  Energy: E = 1/2 sum |u|^2 dV.
+"""
+from __future__ import annotations
+
+import math
+import os
+from dataclasses import dataclass
+
+import numpy as np
+import scipy.fft as sfft
+
+_WORKERS = max(1, os.cpu_count() or 1)
+
+MEAN_FIXED = 0
+MEAN_FREE = 1
+
+COLOUR_FLUID, COLOUR_BODY, COLOUR_WING_L, COLOUR_WING_R = 0, 1, 2, 3
+
+
+# ---------------------------------------------------------------------------
+# Grid, wavenumbers and the 2/3 rule  [Sec. 2.4]
+# ---------------------------------------------------------------------------
+
+def signed_index(n: int) -> np.ndarray:
+    """Integer wavenumber of FFT bin i on an axis of n points (Nyquist -> -n/2)."""
+    i = np.arange(n, dtype=np.int64)
+    return np.where(i < n // 2, i, i - n)
+
+
+def half_index(n: int) -> np.ndarray:
+    """Integer wavenumbers 0..n/2 of the half (real-to-complex) axis."""
+    return np.arange(n // 2 + 1, dtype=np.int64)
+
+
+def dealias_keep(j: np.ndarray, n: int) -> np.ndarray:
+    """2/3 rule on one axis: keep a mode iff 3|j| < n  [Sec. 2.4]."""
+    return 3 * np.abs(j) < n
+
+
+def dealias_kmax(n: int) -> int:
+    """Largest kept |j| under the 2/3 rule."""
+    j = np.arange(n)
+    return int(j[dealias_keep(j, n)].max())
+
+
+@dataclass
+class Grid:
+    """Cubic periodic box of side L with n points per axis, x_i = i*L/n."""
+    n: int
+    L: float
+
+    @property
+    def dx(self) -> float:
+        return self.L / self.n
+
+    @property
+    def dV(self) -> float:
+        return self.dx ** 3
+
+    def coords(self):
+        """Physical coordinates as three [z][y][x] arrays."""
+        x1 = np.arange(self.n, dtype=np.float64) * self.dx
+        z, y, x = np.meshgrid(x1, x1, x1, indexing="ij")
+        return x, y, z
+
+    def wavenumbers(self):
+        """(jx, jy, jz) integer tables broadcastable over [kz][ky][kx]."""
+        n = self.n
+        jx = half_index(n)[None, None, :]
+        jy = signed_index(n)[None, :, None]
+        jz = signed_index(n)[:, None, None]
+        return jx, jy, jz
+
+    def k_vectors(self, derivative: bool):
+        """Wavevector components (2 pi / L) j.  For derivatives the Nyquist
+        wavenumber is zeroed (a Nyquist mode has no defined derivative)."""
+        n = self.n
+        c = 2.0 * math.pi / self.L
+        jx, jy, jz = self.wavenumbers()
+        kx, ky, kz = (c * jx.astype(np.float64), c * jy.astype(np.float64),
+                      c * jz.astype(np.float64))
+        if derivative:
+            kx = np.where(jx == n // 2, 0.0, kx)
+            ky = np.where(np.abs(jy) == n // 2, 0.0, ky)
+            kz = np.where(np.abs(jz) == n // 2, 0.0, kz)
+        return kx, ky, kz
+
+    def k2(self):
+        kx, ky, kz = self.k_vectors(derivative=False)
+        return kx * kx + ky * ky + kz * kz
+
+    def dealias(self):
+        """Boolean mask over the half spectrum: True where the 2/3 rule keeps the mode."""
+        n = self.n
+        jx, jy, jz = self.wavenumbers()
+        return dealias_keep(jx, n) & dealias_keep(jy, n) & dealias_keep(jz, n)
+
+
+# ---------------------------------------------------------------------------
+# 3D real transforms  [Sec. 2.4]
+# ---------------------------------------------------------------------------
+
+def r2c(f: np.ndarray) -> np.ndarray:
+    """Forward real-to-complex 3D transform of [..., z, y, x] arrays, unnormalized."""
+    return sfft.rfftn(f, axes=(-3, -2, -1), workers=_WORKERS)
+
+
+def c2r(fh: np.ndarray, n: int) -> np.ndarray:
+    """Inverse complex-to-real 3D transform, scaled by 1/n^3."""
+    return sfft.irfftn(fh, s=(n, n, n), axes=(-3, -2, -1), workers=_WORKERS)
+
+
+# ---------------------------------------------------------------------------
+# Spectral operators  [Sec. 2.4, Alg. 1 step (d)]
+# ---------------------------------------------------------------------------
+
+def curl_hat(g: Grid, uh: np.ndarray) -> np.ndarray:
+    """Vorticity coefficients w_hat = i k x u_hat."""
+    kx, ky, kz = g.k_vectors(derivative=True)
+    ux, uy, uz = uh
+    return np.stack([1j * (ky * uz - kz * uy),
+                     1j * (kz * ux - kx * uz),
+                     1j * (kx * uy - ky * ux)])
+
+
+def divergence_hat(g: Grid, uh: np.ndarray) -> np.ndarray:
+    kx, ky, kz = g.k_vectors(derivative=True)
+    return 1j * (kx * uh[0] + ky * uh[1] + kz * uh[2])
+
+
+def project(g: Grid, fh: np.ndarray) -> np.ndarray:
+    """Leray projection F - k (k.F)/|k|^2 of Alg. 1 step (d); identity at k = 0.
+
+    Step (d) subtracts the gradient of the solution of a Poisson problem whose
+    right-hand side is the divergence of F; in Fourier space that is the
+    subtraction of the component of F_hat along k."""
+    kx, ky, kz = g.k_vectors(derivative=True)
+    k2 = kx * kx + ky * ky + kz * kz
+    kdotf = kx * fh[0] + ky * fh[1] + kz * fh[2]
+    with np.errstate(invalid="ignore", divide="ignore"):
+        s = np.where(k2 > 0.0, kdotf / np.where(k2 > 0.0, k2, 1.0), 0.0)
+    return np.stack([fh[0] - kx * s, fh[1] - ky * s, fh[2] - kz * s])
+
+
+def import_field(g: Grid, u0: np.ndarray) -> np.ndarray:
+    """Initial coefficients: 2/3 rule and projection of the sampled field [Eq. PNST_inicond]."""
+    uh = r2c(u0) * g.dealias()
+    return project(g, uh)
+
+
+# ---------------------------------------------------------------------------
+# Rotation matrices and insect kinematics  [Sec. 3]
+# ---------------------------------------------------------------------------
+
+def Rx(a: float) -> np.ndarray:
+    c, s = math.cos(a), math.sin(a)
+    return np.array([[1.0, 0.0, 0.0], [0.0, c, s], [0.0, -s, c]])
+
+
+def Ry(a: float) -> np.ndarray:
+    c, s = math.cos(a), math.sin(a)
+    return np.array([[c, 0.0, -s], [0.0, 1.0, 0.0], [s, 0.0, c]])
+
+
+def Rz(a: float) -> np.ndarray:
+    c, s = math.cos(a), math.sin(a)
+    return np.array([[c, s, 0.0], [-s, c, 0.0], [0.0, 0.0, 1.0]])
+
+
+@dataclass
+class Insect:
+    """Rigid tethered insect (or a single body) with sinusoidal wing angles.
+
+    Angles in radians.  Each wing angle is mean + amp*cos(2 pi freq t + phase).
+    body: 'none' | 'sphere' | 'ellipsoid'.  smooth: 'cos' | 'tanh'."""
+    body: str = "none"
+    x_cntr: tuple = (0.0, 0.0, 0.0)
+    u_cntr: tuple = (0.0, 0.0, 0.0)
+    psi: float = 0.0
+    beta: float = 0.0
+    gamma: float = 0.0
+    psi_dot: float = 0.0
+    beta_dot: float = 0.0
+    gamma_dot: float = 0.0
+    radius: float = 0.5
+    a: float = 0.5
+    b: float = 0.1
+    smooth: str = "cos"
+    c_smth: float = 1.0
+    wings: bool = False
+    eta_stroke: float = 0.0
+    pivot_l: tuple = (0.0, 0.15, 0.0)
+    pivot_r: tuple = (0.0, -0.15, 0.0)
+    wing_A: float = 0.175
+    wing_B: float = 0.5
+    wing_t: float = 0.0
+    freq: float = 1.0
+    phi: tuple = (0.0, 0.0, 0.0)
+    alpha: tuple = (0.0, 0.0, 0.0)
+    theta: tuple = (0.0, 0.0, 0.0)
+
+    @staticmethod
+    def from_dict(d: dict) -> "Insect":
+        return Insect(**d)
+
+
+def wing_angles(ins: Insect, t: float):
+    """(phi, alpha, theta) and their time derivatives at time t."""
+    w = 2.0 * math.pi * ins.freq
+    out = []
+    for mean, amp, ph in (ins.phi, ins.alpha, ins.theta):
+        out.append((mean + amp * math.cos(w * t + ph), -amp * w * math.sin(w * t + ph)))
+    (phi, dphi), (alpha, dalpha), (theta, dtheta) = out
+    return phi, alpha, theta, dphi, dalpha, dtheta
+
+
+def body_angles(ins: Insect, t: float):
+    """Body roll/pitch/yaw at t (constant rates from the initial angles)."""
+    return (ins.psi + ins.psi_dot * t, ins.beta + ins.beta_dot * t,
+            ins.gamma + ins.gamma_dot * t)
+
+
+def M_body(ins: Insect, t: float) -> np.ndarray:
+    """x_b = M_body (x_g - x_cntr), M_body = Rx(psi) Ry(beta) Rz(gamma)  [eq. M_body_yawpitchroll]."""
+    psi, beta, gamma = body_angles(ins, t)
+    return Rx(psi) @ Ry(beta) @ Rz(gamma)
+
+
+def omega_body_b(ins: Insect, t: float) -> np.ndarray:
+    """Body angular velocity in the body frame  [Sec. 3.1]."""
+    psi, beta, gamma = body_angles(ins, t)
+    og = Rz(gamma).T @ (np.array([0.0, 0.0, ins.gamma_dot])
+                        + Ry(beta).T @ (np.array([0.0, ins.beta_dot, 0.0])
+                                        + Rx(psi).T @ np.array([ins.psi_dot, 0.0, 0.0])))
+    return M_body(ins, t) @ og
+
+
+def M_stroke(ins: Insect, side: str) -> np.ndarray:
+    """Stroke-plane matrices: left Ry(eta), right Rx(pi) Ry(eta)  [Sec. 3.3]."""
+    if side == "l":
+        return Ry(ins.eta_stroke)
+    return Rx(math.pi) @ Ry(ins.eta_stroke)
+
+
+def M_wing(ins: Insect, t: float, side: str) -> np.ndarray:
+    """Wing matrices: left Ry(a) Rz(-th) Rx(phi); right Ry(-a) Rz(-th) Rx(-phi)  [Sec. 3.3]."""
+    phi, alpha, theta, *_ = wing_angles(ins, t)
+    if side == "l":
+        return Ry(alpha) @ Rz(-theta) @ Rx(phi)
+    return Ry(-alpha) @ Rz(-theta) @ Rx(-phi)
+
+
+def omega_wing_b(ins: Insect, t: float, side: str) -> np.ndarray:
+    """Wing angular velocity in the body frame  [Sec. 3.3].
+
+    Right wing: the same expression with (alpha, phi) and their rates negated,
+    matching its wing matrix."""
+    phi, alpha, theta, dphi, dalpha, dtheta = wing_angles(ins, t)
+    if side == "r":
+        phi, alpha, dphi, dalpha = -phi, -alpha, -dphi, -dalpha
+    # Omega^(s) = Rx^T(phi)[ (dphi,0,0) + Rz^T(-theta)[ (0,0,-dtheta) + Ry^T(alpha)(0,dalpha,0) ] ]
+    om_s = Rx(phi).T @ (np.array([dphi, 0.0, 0.0])
+                        + Rz(-theta).T @ (np.array([0.0, 0.0, -dtheta])
+                                          + Ry(alpha).T @ np.array([0.0, dalpha, 0.0])))
+    return M_stroke(ins, side).T @ om_s
+
+
+# ---------------------------------------------------------------------------
+# Mask from signed distances  [Sec. 2.2, 3.2, 3.4]
+# ---------------------------------------------------------------------------
+
+def chi_of_delta(delta: np.ndarray, ins: Insect, dx: float) -> np.ndarray:
+    h = ins.c_smth * dx
+    if ins.smooth == "tanh":
+        return 0.5 * (1.0 - np.tanh(delta / h))
+    # eq. smoothing_mask_as_function_of_delta
+    out = np.where(delta <= -h, 1.0, 0.0)
+    mid = (delta > -h) & (delta < h)
+    return np.where(mid, 0.5 * (1.0 + np.cos(math.pi * (delta + h) / (2.0 * h))), out)
+
+
+def delta_ellipsoid(xb, yb, zb, a, b):
+    """Thorax ellipsoid, continued for |x| > a so that it is defined everywhere."""
+    rad = np.sqrt(yb * yb + zb * zb)
+    prof = b * np.sqrt(np.maximum(0.0, 1.0 - (xb / a) ** 2))
+    return np.maximum(rad - prof, np.abs(xb) - a)
+
+
+def delta_elliptic_wing(xw, yw, zw, A, B, t):
+    """Polar-radius wing [Sec. 3.4] with the closed-form radius of an ellipse
+    with semi-axes A (chord, x_w) and B (span, y_w) centred at (0, B)."""
+    ex = xw
+    ey = yw - B
+    r = np.sqrt(ex * ex + ey * ey)
+    rho = np.sqrt((ex / A) ** 2 + (ey / B) ** 2)
+    with np.errstate(invalid="ignore", divide="ignore"):
+        inplane = np.where(r > 0.0, r - r / np.where(rho > 0.0, rho, 1.0), -A)
+    return np.maximum(np.abs(zw) - 0.5 * t, inplane)
+
+
+def _cross(a, b):
+    return np.stack([a[1] * b[2] - a[2] * b[1],
+                     a[2] * b[0] - a[0] * b[2],
+                     a[0] * b[1] - a[1] * b[0]])
+
+
+def _apply(M, v):
+    """M @ v for a 3x3 matrix and a [3][...] array of vectors."""
+    return np.einsum("ij,j...->i...", M, v)
+
+
+def body_velocity(ins: Insect, t: float, xb):
+    """u_b = u_cntr + M_body^T (Omega_b^(b) x x_b)  [eq. body_velocity_field]."""
+    Mb = M_body(ins, t)
+    om = omega_body_b(ins, t).reshape((3,) + (1,) * (np.ndim(xb) - 1))
+    ub = _apply(Mb.T, _cross(np.broadcast_to(om, np.shape(xb)), xb))
+    return ub + np.asarray(ins.u_cntr, dtype=np.float64).reshape((3,) + (1,) * (np.ndim(xb) - 1))
+
+
+def wing_frame(ins: Insect, t: float, side: str, xb):
+    """x_w = M_wing M_stroke (x_b - pivot)  [Sec. 3.3]."""
+    piv = np.asarray(ins.pivot_l if side == "l" else ins.pivot_r, dtype=np.float64)
+    xrel = xb - piv.reshape((3,) + (1,) * (np.ndim(xb) - 1))
+    return _apply(M_wing(ins, t, side) @ M_stroke(ins, side), xrel)
+
+
+def wing_velocity(ins: Insect, t: float, side: str, xb):
+    """Solid velocity inside a wing, u_w + u_b  [eq. wing_velocity_field]:
+    u_w^(w) = Omega_w^(w) x x_w with Omega_w^(w) = M_wing M_stroke Omega_w^(b),
+    u_w^(g) = M_body^T M_stroke^T M_wing^T u_w^(w)."""
+    Ms = M_stroke(ins, side)
+    Mw = M_wing(ins, t, side)
+    xw = wing_frame(ins, t, side, xb)
+    om_w = (Mw @ Ms @ omega_wing_b(ins, t, side)).reshape((3,) + (1,) * (np.ndim(xb) - 1))
+    uw_w = _cross(np.broadcast_to(om_w, np.shape(xw)), xw)
+    back = M_body(ins, t).T @ Ms.T @ Mw.T
+    return _apply(back, uw_w) + body_velocity(ins, t, xb)
+
+
+def to_body(ins: Insect, t: float, xg):
+    """x_b = M_body (x_g - x_cntr)  [eq. M_body_yawpitchroll]."""
+    xc = np.asarray(ins.x_cntr, dtype=np.float64).reshape((3,) + (1,) * (np.ndim(xg) - 1))
+    return _apply(M_body(ins, t), xg - xc)
+
+
+def insect_mask(g: Grid, ins: Insect, t: float):
+    """chi, u_s [3] and colour on every grid point at time t  [Alg. 1 step (a)]."""
+    n = g.n
+    x, y, z = g.coords()
+    xg = np.stack([x, y, z])
+    xb = to_body(ins, t, xg)
+    ub = body_velocity(ins, t, xb)
+
+    chis, uss = [], []
+    if ins.body == "sphere":
+        xc = np.asarray(ins.x_cntr, dtype=np.float64)
+        d = np.sqrt((x - xc[0]) ** 2 + (y - xc[1]) ** 2 + (z - xc[2]) ** 2) - ins.radius
+        chis.append(chi_of_delta(d, ins, g.dx))
+        uss.append(ub)
+    elif ins.body == "ellipsoid":
+        d = delta_ellipsoid(xb[0], xb[1], xb[2], ins.a, ins.b)
+        chis.append(chi_of_delta(d, ins, g.dx))
+        uss.append(ub)
+    else:
+        chis.append(np.zeros((n, n, n)))
+        uss.append(np.zeros((3, n, n, n)))
+
+    if ins.wings:
+        for side in ("l", "r"):
+            xw = wing_frame(ins, t, side, xb)
+            d = delta_elliptic_wing(xw[0], xw[1], xw[2], ins.wing_A, ins.wing_B, ins.wing_t)
+            chis.append(chi_of_delta(d, ins, g.dx))
+            uss.append(wing_velocity(ins, t, side, xb))
+    else:
+        chis += [np.zeros((n, n, n))] * 2
+        uss += [np.zeros((3, n, n, n))] * 2
+
+    stack = np.stack(chis)
+    part = np.argmax(stack, axis=0)             # first maximum -> lowest colour on ties
+    chi = np.max(stack, axis=0)
+    us = np.zeros((3, n, n, n))
+    for p in range(3):
+        sel = part == p
+        us[:, sel] = uss[p][:, sel]
+    colour = np.where(chi > 0.0, part + 1, 0).astype(np.int16)
+    us = us * (chi > 0.0)
+    return chi, us, colour
+
+
+def reference_points(ins: Insect, t: float) -> np.ndarray:
+    """Torque reference points (global frame) per colour 1..3: body centre, pivots."""
+    Mb = M_body(ins, t)
+    xc = np.asarray(ins.x_cntr, dtype=np.float64)
+    return np.stack([xc, xc + Mb.T @ np.asarray(ins.pivot_l, dtype=np.float64),
+                     xc + Mb.T @ np.asarray(ins.pivot_r, dtype=np.float64)])
+
+
+# ---------------------------------------------------------------------------
+# Right-hand side, time step and diagnostics  [Alg. 1 steps (b)-(e)]
+# ---------------------------------------------------------------------------
+
+@dataclass
+class Params:
+    n: int
+    L: float
+    nu: float
+    eta: float
+    mean_mode: int = MEAN_FIXED
+
+
+def physical_fields(g: Grid, uh: np.ndarray):
+    """u and w = curl u on the grid."""
+    return c2r(uh, g.n), c2r(curl_hat(g, uh), g.n)
+
+
+def source_physical(u, w, chi, us, eta):
+    """N = u x w - (chi/C_eta)(u - u_s)  [Alg. 1 step (c), sign per -w x u]."""
+    cross = np.stack([u[1] * w[2] - u[2] * w[1],
+                      u[2] * w[0] - u[0] * w[2],
+                      u[0] * w[1] - u[1] * w[0]])
+    return cross - (chi / eta) * (u - us)
+
+
+def rhs_hat(p: Params, g: Grid, uh, chi, us):
+    """Dealiased, projected right-hand side N_hat and the physical velocity."""
+    u, w = physical_fields(g, uh)
+    if chi is None:
+        nphys = source_physical(u, w, 0.0, 0.0, p.eta)
+    else:
+        nphys = source_physical(u, w, chi, us, p.eta)
+    nh = r2c(nphys) * g.dealias()
+    nh = project(g, nh)
+    if p.mean_mode == MEAN_FIXED:
+        nh[:, 0, 0, 0] = 0.0
+    return nh, u
+
+
+def umax_of(u) -> float:
+    m = np.sqrt(u[0] ** 2 + u[1] ** 2 + u[2] ** 2)
+    return float(np.max(m))
+
+
+@dataclass
+class StepControl:
+    dt_fixed: float = 0.0
+    cfl: float = 0.1
+    dt_max: float = math.inf
+    t_end: float = math.inf
+    eta_cap: float = 0.5
+
+
+def choose_dt(ctl: StepControl, umax: float, dx: float, eta: float, masked: bool, t: float) -> float:
+    if ctl.dt_fixed > 0.0:
+        dt = ctl.dt_fixed
+    else:
+        dt = ctl.cfl * dx / umax if umax > 0.0 else math.inf
+        if masked:
+            dt = min(dt, ctl.eta_cap * eta)
+        dt = min(dt, ctl.dt_max)
+    if t + dt > ctl.t_end:
+        dt = ctl.t_end - t
+    return dt
+
+
+def ab2_if(p: Params, g: Grid, uh, nh, nh_prev, dt, dt_prev):
+    """Integrating-factor AB2 (Euler on the first step)  [Alg. 1 step (e)]."""
+    k2 = g.k2()
+    e_now = np.exp(-p.nu * k2 * dt)
+    if nh_prev is None:
+        return e_now * (uh + dt * nh)
+    r = dt / dt_prev
+    b1, b2 = 1.0 + 0.5 * r, -0.5 * r
+    e_prev = np.exp(-p.nu * k2 * dt_prev)
+    return e_now * (uh + dt * (b1 * nh + b2 * e_prev * nh_prev))
+
+
+@dataclass
+class State:
+    uh: np.ndarray
+    nh_prev: np.ndarray | None = None
+    t: float = 0.0
+    dt_prev: float = 0.0
+    n: int = 0
+    I_prev: np.ndarray | None = None     # [3 colours][6]: sum chi u_s dV and its moment
+
+
+def init_state(p: Params, u0: np.ndarray, t0: float = 0.0) -> State:
+    g = Grid(p.n, p.L)
+    return State(uh=import_field(g, u0), t=t0)
+
+
+def force_sums(g: Grid, u, chi, us, colour, xref, eta):
+    """Per colour 1..3: penalization force/torque and I = sum chi u_s dV (+ moment)."""
+    x, y, z = g.coords()
+    pos = np.stack([x, y, z])
+    pen = chi * (u - us) / eta * g.dV
+    ius = chi * us * g.dV
+    F = np.zeros((3, 3)); M = np.zeros((3, 3)); I = np.zeros((3, 6))
+    for c in range(3):
+        sel = colour == (c + 1)
+        r = pos[:, sel] - xref[c][:, None]
+        pc = pen[:, sel]
+        ic = ius[:, sel]
+        F[c] = pc.sum(axis=1)
+        M[c] = np.cross(r.T, pc.T).sum(axis=0)
+        I[c, :3] = ic.sum(axis=1)
+        I[c, 3:] = np.cross(r.T, ic.T).sum(axis=0)
+    return F, M, I
+
+
+def step(p: Params, st: State, ctl: StepControl, ins: Insect | None, fixed_mask=None):
+    """One pass of Algorithm 1; returns the new state and the diagnostics at t^n.
+
+    fixed_mask = (chi, u_s, colour, xref) replaces the insect by a
+    time-independent mask (used by tests)."""
+    g = Grid(p.n, p.L)
+    masked = ins is not None or fixed_mask is not None
+    if fixed_mask is not None:
+        chi, us, colour, xref = fixed_mask
+    elif ins is not None:
+        chi, us, colour = insect_mask(g, ins, st.t)                    # (a)
+        xref = reference_points(ins, st.t)
+    else:
+        chi = us = colour = xref = None
+    u, w = physical_fields(g, st.uh)                                   # u^n, w^n
+    umax = umax_of(u)
+    if not np.isfinite(umax):
+        raise FloatingPointError("non-finite velocity")
+    dt = choose_dt(ctl, umax, g.dx, p.eta, masked, st.t)               # (b)
+    nphys = source_physical(u, w, 0.0 if chi is None else chi,
+                            0.0 if us is None else us, p.eta)          # (c)
+    nh = project(g, r2c(nphys) * g.dealias())                          # (d)
+    if p.mean_mode == MEAN_FIXED:
+        nh[:, 0, 0, 0] = 0.0
+    diag = {"t": st.t, "dt": dt, "umax": umax,
+            "E": 0.5 * float(np.sum(u * u)) * g.dV}
+    if masked:
+        F, M, I = force_sums(g, u, chi, us, colour, xref, p.eta)
+        if st.I_prev is not None and st.dt_prev > 0.0:
+            F = F + (I[:, :3] - st.I_prev[:, :3]) / st.dt_prev
+            M = M + (I[:, 3:] - st.I_prev[:, 3:]) / st.dt_prev
+        diag["F"] = F
+        diag["M"] = M
+        I_now = I
+    else:
+        I_now = None
+    uh_new = ab2_if(p, g, st.uh, nh, st.nh_prev, dt,
+                    st.dt_prev if st.nh_prev is not None else dt)      # (e)
+    new = State(uh=uh_new, nh_prev=nh, t=st.t + dt, dt_prev=dt, n=st.n + 1, I_prev=I_now)
+    return new, diag
+
+
+def run(p: Params, u0: np.ndarray, nsteps: int, ctl: StepControl,
+        ins: Insect | None = None, t0: float = 0.0, fixed_mask=None):
+    """Run nsteps of Algorithm 1 from the sampled initial field u0."""
+    st = init_state(p, u0, t0)
+    hist = []
+    for _ in range(nsteps):
+        st, d = step(p, st, ctl, ins, fixed_mask)
+        hist.append(d)
+    return st, hist
+
+
+def velocity(p: Params, st: State) -> np.ndarray:
+    return c2r(st.uh, p.n)
+
+
+def energy_spectral(g: Grid, uh: np.ndarray) -> float:
+    """E = 1/2 sum |u|^2 dV through Parseval on the half spectrum."""
+    n = g.n
+    w = np.full(uh.shape[-1], 2.0)
+    w[0] = 1.0
+    if n % 2 == 0:
+        w[-1] = 1.0
+    return 0.5 * g.L ** 3 / float(n) ** 6 * float(np.sum(w * np.abs(uh) ** 2))
+
+
+def penalization_K(nu: float, eta: float, dx: float) -> float:
+    """Points per penalization boundary layer, K = sqrt(nu C_eta)/dx  [Sec. 2.1]."""
+    return math.sqrt(nu * eta) / dx
+
+
+__all__ = [n for n in dir() if not n.startswith("_")]
