@@ -1,0 +1,205 @@
+/*
+ * flusi.h -- C ABI of the MI355X (gfx950) pseudo-spectral penalized
+ * Navier-Stokes hot path.
+ *
+ * Method: Engels, Kolomenskiy, Schneider, Sesterhenn, "FluSI: A novel parallel
+ * simulation tool for flapping insect flight using a Fourier method with
+ * volume penalization", arXiv:1506.06513.  Section and equation names below
+ * refer to that paper.
+ *
+ * Conventions shared by every call
+ * --------------------------------
+ *  - Every call returns an int status: FLUSI_OK (0) or a negative FLUSI_E*
+ *    code.  flusi_last_error() returns a thread-local message for the last
+ *    failure.  No C++ exception crosses the ABI.
+ *  - Box: cubic, side L, n points per axis (nx = ny = nz = n), grid points
+ *    x_i = i*L/n.  Supported n: 16, 24, 32, 48, 64, 96, 128, 192, 256, 384,
+ *    512 (even and of the form 2^a 3^b).
+ *  - Physical fields: [field][z][y][x] row-major, x fastest, real type of the
+ *    plan (float for FLUSI_F32, double for FLUSI_F64).
+ *  - Spectral fields, full layout: [field][kz][ky][kx] with kx = 0..n/2
+ *    (fastest), ky and kz in FFT order (bin i holds j = i for i < n/2 and
+ *    j = i - n otherwise); complex values are interleaved (re, im) pairs of
+ *    the plan's real type.  The forward transform is unnormalized with
+ *    exp(-i k.x); the inverse is scaled by 1/n^3.
+ *  - Every field/state pointer is a DEVICE pointer owned by the caller,
+ *    contiguous and 16-byte aligned.  The plan owns twiddle tables, integer
+ *    tables and scratch memory.
+ *  - Work is enqueued on the stream set with flusi_set_stream (default: the
+ *    null stream); calls return without synchronizing unless their
+ *    description says otherwise.
+ *  - Scalars (times, forces, coefficients) are always double.
+ */
+#ifndef FLUSI_H
+#define FLUSI_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define FLUSI_OK 0
+#define FLUSI_EINVAL (-1)        /* bad argument (null pointer, wrong size, ...) */
+#define FLUSI_EUNSUPPORTED (-2)  /* grid size or combination not supported */
+#define FLUSI_ENOMEM (-3)        /* device allocation failed */
+#define FLUSI_EDEVICE (-4)       /* a HIP runtime call failed */
+#define FLUSI_ENONFINITE (-5)    /* the velocity became NaN or infinite */
+
+#define FLUSI_F32 0
+#define FLUSI_F64 1
+
+#define FLUSI_BODY_NONE 0
+#define FLUSI_BODY_SPHERE 1
+#define FLUSI_BODY_ELLIPSOID 2
+
+#define FLUSI_SMOOTH_COS 0   /* cosine layer, Sec. 2.2 eq. smoothing_mask_as_function_of_delta */
+#define FLUSI_SMOOTH_TANH 1  /* 0.5*(1 - tanh(delta/h)) */
+
+#define FLUSI_MEAN_FIXED 0   /* k = 0 right-hand side set to zero: the mean velocity is held */
+#define FLUSI_MEAN_FREE 1    /* k = 0 right-hand side kept */
+
+/* Per-step diagnostics record (doubles), written by flusi_step and returned
+ * by flusi_forces:
+ *   [0] t^n   [1] dt_n   [2] max|u|   [3] E = 1/2 sum |u|^2 dV
+ *   [4 + 6*(c-1) + 0..2]  force  F on colour c (c = 1 body, 2 left wing, 3 right wing)
+ *   [4 + 6*(c-1) + 3..5]  torque m on colour c
+ * Force and torque follow eqs. force_with_unst_corrections / moment_of_love
+ * (Sec. 2.1): the penalization integral plus the time derivative of the solid
+ * momentum, as the force acting on the solid.  Torques are taken about the
+ * body centre (body) and the wing pivots (wings). */
+#define FLUSI_NDIAG 22
+
+typedef struct flusi_plan_s* flusi_plan;
+
+/* Rigid insect (Sec. 3), or a single body when wings == 0.  Angles in
+ * radians.  Body angles evolve as angle + rate*t.  Each wing angle is
+ * mean + amplitude*cos(2*pi*freq*t + phase).  x_cntr is the body centre at
+ * the current time (the body is not translated by the library) and u_cntr
+ * its velocity. */
+typedef struct {
+    int body;            /* FLUSI_BODY_* */
+    int wings;           /* 0: no wings; 1: left and right wing */
+    int smooth;          /* FLUSI_SMOOTH_* */
+    int reserved;
+    double c_smth;       /* smoothing half-width h = c_smth*dx */
+    double x_cntr[3];
+    double u_cntr[3];
+    double psi, beta, gamma;              /* roll, pitch, yaw: M_body = Rx(psi) Ry(beta) Rz(gamma) */
+    double psi_dot, beta_dot, gamma_dot;
+    double radius;       /* sphere radius */
+    double a, b;         /* ellipsoid thorax: semi-axis a along x_b, b across */
+    double eta_stroke;   /* anatomical stroke-plane angle */
+    double pivot_l[3];   /* wing pivots in the body frame */
+    double pivot_r[3];
+    double wing_A;       /* elliptic wing: half chord (x_w) */
+    double wing_B;       /* half span (y_w); the ellipse is centred at (0, B) */
+    double wing_t;       /* wing thickness (z_w) */
+    double freq;
+    double phi[3];       /* positional angle: mean, amplitude, phase */
+    double alpha[3];     /* feathering angle */
+    double theta[3];     /* deviation angle */
+} flusi_insect;
+
+/* Controls of flusi_step (Algorithm 1 steps (a)-(e)). */
+typedef struct {
+    int nsteps;          /* number of time steps to take */
+    int mean_mode;       /* FLUSI_MEAN_* */
+    double dt_fixed;     /* > 0: use this step; otherwise adaptive */
+    double cfl;          /* adaptive: dt = cfl*dx/max|u| ... */
+    double dt_max;       /* ... capped by dt_max (<= 0: no cap) ... */
+    double eta_cap;      /* ... and by eta_cap*C_eta when a mask is present ... */
+    double t_end;        /* ... and clamped to land on t_end (<= 0: none) */
+    double* history;     /* optional DEVICE pointer [nsteps][FLUSI_NDIAG]; may be NULL */
+} flusi_step_params;
+
+/* Message for the last failed call on this thread (never NULL). */
+const char* flusi_last_error(void);
+
+/* Create a plan for a cubic periodic box (Sec. 2.4: Fourier discretization
+ * with the 2/3 rule).  nu: kinematic viscosity; eta: penalization constant
+ * C_eta (Sec. 2.1); dtype: FLUSI_F32 or FLUSI_F64.  Builds the integer
+ * wavenumber and dealiasing tables (kept iff 3|j| < n on each axis), FP64
+ * twiddle tables (and FP32 copies rounded from them) and the scratch buffers
+ * of the stepping schedule.  Errors: EINVAL, EUNSUPPORTED (nx != ny != nz or
+ * n not supported), ENOMEM. */
+int flusi_plan_create(int nx, int ny, int nz, double L, double nu, double eta, int dtype,
+                      flusi_plan* out);
+int flusi_plan_destroy(flusi_plan plan);
+
+/* All further launches of this plan go to `stream` (a hipStream_t). */
+int flusi_set_stream(flusi_plan plan, void* stream);
+
+/* Device bytes held by the plan (tables + scratch) and bytes of one state
+ * buffer (header + velocity coefficients + previous right-hand side). */
+size_t flusi_plan_workspace_bytes(flusi_plan plan);
+size_t flusi_state_bytes(flusi_plan plan);
+
+/* Copies of the integer tables the plan uses: j for the n bins of the signed
+ * axis (FFT order), and the dealias flags (1 kept, 0 removed) of those bins.
+ * Host pointers of n ints each; synchronous. */
+int flusi_tables(flusi_plan plan, int* j_signed, int* keep_signed);
+
+/* Forward 3D real-to-complex transform of nf fields (Sec. 2.4).
+ * in: [nf][n][n][n] real; out: [nf][n][n][n/2+1] complex (full layout). */
+int flusi_fft_r2c(flusi_plan plan, const void* in, void* out, int nf);
+
+/* Inverse 3D complex-to-real transform with 1/n^3, input preserved.  The
+ * imaginary parts of the kx = 0 and kx = n/2 bins are ignored (Hermitian
+ * input assumed).  May allocate plan scratch on first use. */
+int flusi_fft_c2r(flusi_plan plan, const void* in, void* out, int nf);
+
+/* Algorithm 1 step (a): mask chi, solid velocity u_s and colour at time t
+ * (Sec. 2.2, Sec. 3.1-3.4).  chi: [n][n][n] real; us: [3][n][n][n] real;
+ * colour: [n][n][n] int16 (0 fluid, 1 body, 2 left wing, 3 right wing).  Parts
+ * combine by the maximum of chi; u_s and colour come from that part (ties go
+ * to the lower colour); u_s = 0 where chi = 0.  Any output pointer may be
+ * NULL. */
+int flusi_mask_insect(flusi_plan plan, const flusi_insect* ins, double t, void* chi, void* us,
+                      int16_t* colour);
+
+/* Unfused right-hand side of Algorithm 1 steps (c)-(d): from full-layout
+ * uhat [3] (assumed dealiased), chi and us (physical, may be NULL for no
+ * mask) computes rhs_hat = P D r2c(u x w - (chi/C_eta)(u - u_s)) with w the
+ * curl, D the 2/3 rule and P the projection (identity at k = 0; the k = 0
+ * value is zeroed for FLUSI_MEAN_FIXED).  umax_host (may be NULL) receives
+ * max|u| (this call then synchronizes). */
+int flusi_rhs(flusi_plan plan, const void* uhat, const void* chi, const void* us, void* rhs_hat,
+              int mean_mode, double* umax_host);
+
+/* Initialize a state buffer of flusi_state_bytes() bytes (caller-owned device
+ * memory) from the physical velocity u0 [3][n][n][n] sampled on the grid
+ * (eq. PNST_inicond): the coefficients are dealiased and projected; time t0,
+ * no step history. */
+int flusi_state_init(flusi_plan plan, void* state, const void* u0, double t0);
+
+/* Write the velocity of a state as a full-layout spectrum [3][n][n][n/2+1]
+ * (zeros outside the 2/3 band). */
+int flusi_state_export_uhat(flusi_plan plan, const void* state, void* uhat);
+
+/* Physical velocity u [3][n][n][n] of a state. */
+int flusi_state_velocity(flusi_plan plan, const void* state, void* u);
+
+/* Time and step count of a state (synchronous). */
+int flusi_state_time(flusi_plan plan, const void* state, double* t, long long* n);
+
+/* Advance a state by p->nsteps steps of Algorithm 1: mask and solid velocity
+ * at t^n (ins may be NULL: no mask), dt from the FP64 max|u| reduction, the
+ * source u x w - (chi/C_eta)(u - u_s) with the FP64 force, torque and energy
+ * integrals, the 2/3 rule and projection, and the integrating-factor AB2
+ * update (Euler on the first step of a state).  No host synchronization;
+ * graph-capturable once the plan exists.  A non-finite velocity stops the
+ * state (later steps do nothing) and is reported by flusi_forces. */
+int flusi_step(flusi_plan plan, void* state, const flusi_insect* ins, const flusi_step_params* p);
+
+/* Diagnostics record (FLUSI_NDIAG doubles, see above) of the last step taken
+ * on this state, copied to host memory (synchronous).  Returns
+ * FLUSI_ENONFINITE if the state was stopped by a non-finite velocity. */
+int flusi_forces(flusi_plan plan, const void* state, double* out);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* FLUSI_H */

@@ -1,0 +1,335 @@
+"""Python binding of libflusi (the MI355X pseudo-spectral penalized Navier-Stokes path).
+
+Argument marshalling only: every step of the computation runs in the HIP
+kernels of libflusi.so.  PyTorch supplies device memory and the stream.  The
+flusi_* functions mirror the C ABI of include/flusi.h one to one; `Plan` is a
+small convenience wrapper around them that allocates torch tensors.
+
+There is no fallback: if libflusi.so is missing or no GPU is present, the calls
+raise.
+"""
+from __future__ import annotations
+
+import ctypes
+import math
+import os
+import re
+
+import numpy as np
+import torch  # loads the HIP runtime that libflusi shares
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libflusi.so")
+HEADER_PATH = os.path.join(os.path.dirname(_HERE), "include", "flusi.h")
+
+FLUSI_OK = 0
+FLUSI_EINVAL = -1
+FLUSI_EUNSUPPORTED = -2
+FLUSI_ENOMEM = -3
+FLUSI_EDEVICE = -4
+FLUSI_ENONFINITE = -5
+FLUSI_F32, FLUSI_F64 = 0, 1
+FLUSI_BODY_NONE, FLUSI_BODY_SPHERE, FLUSI_BODY_ELLIPSOID = 0, 1, 2
+FLUSI_SMOOTH_COS, FLUSI_SMOOTH_TANH = 0, 1
+FLUSI_MEAN_FIXED, FLUSI_MEAN_FREE = 0, 1
+FLUSI_NDIAG = 22
+SUPPORTED_N = (16, 24, 32, 48, 64, 96, 128, 192, 256, 384, 512)
+
+
+class FlusiError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"flusi error {code}: {msg}")
+        self.code = code
+
+
+class flusi_insect(ctypes.Structure):
+    _fields_ = [
+        ("body", ctypes.c_int), ("wings", ctypes.c_int), ("smooth", ctypes.c_int), ("reserved", ctypes.c_int),
+        ("c_smth", ctypes.c_double),
+        ("x_cntr", ctypes.c_double * 3), ("u_cntr", ctypes.c_double * 3),
+        ("psi", ctypes.c_double), ("beta", ctypes.c_double), ("gamma", ctypes.c_double),
+        ("psi_dot", ctypes.c_double), ("beta_dot", ctypes.c_double), ("gamma_dot", ctypes.c_double),
+        ("radius", ctypes.c_double), ("a", ctypes.c_double), ("b", ctypes.c_double),
+        ("eta_stroke", ctypes.c_double),
+        ("pivot_l", ctypes.c_double * 3), ("pivot_r", ctypes.c_double * 3),
+        ("wing_A", ctypes.c_double), ("wing_B", ctypes.c_double), ("wing_t", ctypes.c_double),
+        ("freq", ctypes.c_double),
+        ("phi", ctypes.c_double * 3), ("alpha", ctypes.c_double * 3), ("theta", ctypes.c_double * 3),
+    ]
+
+
+class flusi_step_params(ctypes.Structure):
+    _fields_ = [
+        ("nsteps", ctypes.c_int), ("mean_mode", ctypes.c_int),
+        ("dt_fixed", ctypes.c_double), ("cfl", ctypes.c_double), ("dt_max", ctypes.c_double),
+        ("eta_cap", ctypes.c_double), ("t_end", ctypes.c_double),
+        ("history", ctypes.c_void_p),
+    ]
+
+
+_P = ctypes.c_void_p
+_SIGS = {
+    "flusi_last_error": (ctypes.c_char_p, []),
+    "flusi_plan_create": (ctypes.c_int, [ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_double,
+                                         ctypes.c_double, ctypes.c_double, ctypes.c_int, ctypes.POINTER(_P)]),
+    "flusi_plan_destroy": (ctypes.c_int, [_P]),
+    "flusi_set_stream": (ctypes.c_int, [_P, _P]),
+    "flusi_plan_workspace_bytes": (ctypes.c_size_t, [_P]),
+    "flusi_state_bytes": (ctypes.c_size_t, [_P]),
+    "flusi_tables": (ctypes.c_int, [_P, _P, _P]),
+    "flusi_fft_r2c": (ctypes.c_int, [_P, _P, _P, ctypes.c_int]),
+    "flusi_fft_c2r": (ctypes.c_int, [_P, _P, _P, ctypes.c_int]),
+    "flusi_mask_insect": (ctypes.c_int, [_P, ctypes.POINTER(flusi_insect), ctypes.c_double, _P, _P, _P]),
+    "flusi_rhs": (ctypes.c_int, [_P, _P, _P, _P, _P, ctypes.c_int, ctypes.POINTER(ctypes.c_double)]),
+    "flusi_state_init": (ctypes.c_int, [_P, _P, _P, ctypes.c_double]),
+    "flusi_state_export_uhat": (ctypes.c_int, [_P, _P, _P]),
+    "flusi_state_velocity": (ctypes.c_int, [_P, _P, _P]),
+    "flusi_state_time": (ctypes.c_int, [_P, _P, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_longlong)]),
+    "flusi_step": (ctypes.c_int, [_P, _P, ctypes.POINTER(flusi_insect), ctypes.POINTER(flusi_step_params)]),
+    "flusi_forces": (ctypes.c_int, [_P, _P, ctypes.POINTER(ctypes.c_double)]),
+}
+
+_lib = None
+
+
+def lib() -> ctypes.CDLL:
+    """Load libflusi.so (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"{LIB_PATH} is missing: build it with `python -m paper_1506_06513_amd.build`")
+        L = ctypes.CDLL(LIB_PATH)
+        for name, (res, args) in _SIGS.items():
+            fn = getattr(L, name)
+            fn.restype = res
+            fn.argtypes = args
+        _lib = L
+    return _lib
+
+
+def header_functions() -> list[str]:
+    """Names of the functions declared in include/flusi.h."""
+    txt = open(HEADER_PATH).read()
+    return sorted(set(re.findall(r"^\s*(?:const\s+)?[\w\*\s]+?\b(flusi_\w+)\s*\(", txt, re.M)))
+
+
+def _check(rc: int):
+    if rc != FLUSI_OK:
+        raise FlusiError(rc, lib().flusi_last_error().decode())
+
+
+def _ptr(t) -> int | None:
+    if t is None:
+        return None
+    if isinstance(t, torch.Tensor):
+        if not t.is_cuda:
+            raise ValueError("flusi needs device tensors")
+        if not t.is_contiguous():
+            raise ValueError("flusi needs contiguous tensors")
+        return t.data_ptr()
+    return int(t)
+
+
+# ----------------------------------------------------------------------------
+# C ABI, one to one
+# ----------------------------------------------------------------------------
+
+def flusi_plan_create(nx: int, ny: int, nz: int, L: float, nu: float, eta: float, dtype: int):
+    h = _P()
+    _check(lib().flusi_plan_create(nx, ny, nz, L, nu, eta, dtype, ctypes.byref(h)))
+    return h
+
+
+def flusi_plan_destroy(plan):
+    _check(lib().flusi_plan_destroy(plan))
+
+
+def flusi_set_stream(plan, stream):
+    _check(lib().flusi_set_stream(plan, _P(stream)))
+
+
+def flusi_plan_workspace_bytes(plan) -> int:
+    return int(lib().flusi_plan_workspace_bytes(plan))
+
+
+def flusi_state_bytes(plan) -> int:
+    return int(lib().flusi_state_bytes(plan))
+
+
+def flusi_tables(plan, n: int):
+    j = (ctypes.c_int * n)()
+    k = (ctypes.c_int * n)()
+    _check(lib().flusi_tables(plan, ctypes.cast(j, _P), ctypes.cast(k, _P)))
+    return np.array(j[:], dtype=np.int64), np.array(k[:], dtype=np.int64)
+
+
+def flusi_fft_r2c(plan, inp, out, nf: int):
+    _check(lib().flusi_fft_r2c(plan, _ptr(inp), _ptr(out), nf))
+
+
+def flusi_fft_c2r(plan, inp, out, nf: int):
+    _check(lib().flusi_fft_c2r(plan, _ptr(inp), _ptr(out), nf))
+
+
+def flusi_mask_insect(plan, ins: flusi_insect, t: float, chi, us, colour):
+    _check(lib().flusi_mask_insect(plan, ctypes.byref(ins), t, _ptr(chi), _ptr(us), _ptr(colour)))
+
+
+def flusi_rhs(plan, uhat, chi, us, rhs_hat, mean_mode: int, want_umax: bool = False):
+    um = ctypes.c_double(0.0)
+    _check(lib().flusi_rhs(plan, _ptr(uhat), _ptr(chi), _ptr(us), _ptr(rhs_hat), mean_mode,
+                           ctypes.byref(um) if want_umax else None))
+    return um.value if want_umax else None
+
+
+def flusi_state_init(plan, state, u0, t0: float):
+    _check(lib().flusi_state_init(plan, _ptr(state), _ptr(u0), t0))
+
+
+def flusi_state_export_uhat(plan, state, uhat):
+    _check(lib().flusi_state_export_uhat(plan, _ptr(state), _ptr(uhat)))
+
+
+def flusi_state_velocity(plan, state, u):
+    _check(lib().flusi_state_velocity(plan, _ptr(state), _ptr(u)))
+
+
+def flusi_state_time(plan, state):
+    t = ctypes.c_double()
+    n = ctypes.c_longlong()
+    _check(lib().flusi_state_time(plan, _ptr(state), ctypes.byref(t), ctypes.byref(n)))
+    return t.value, n.value
+
+
+def flusi_step(plan, state, ins: flusi_insect | None, params: flusi_step_params):
+    _check(lib().flusi_step(plan, _ptr(state), ctypes.byref(ins) if ins is not None else None,
+                            ctypes.byref(params)))
+
+
+def flusi_forces(plan, state):
+    out = (ctypes.c_double * FLUSI_NDIAG)()
+    rc = lib().flusi_forces(plan, _ptr(state), out)
+    return rc, np.array(out[:])
+
+
+# ----------------------------------------------------------------------------
+# Conveniences
+# ----------------------------------------------------------------------------
+
+_BODY = {"none": FLUSI_BODY_NONE, "sphere": FLUSI_BODY_SPHERE, "ellipsoid": FLUSI_BODY_ELLIPSOID}
+_SMOOTH = {"cos": FLUSI_SMOOTH_COS, "tanh": FLUSI_SMOOTH_TANH}
+
+
+def make_insect(d: dict | None) -> flusi_insect | None:
+    """flusi_insect from a plain parameter dict (the keys of the struct)."""
+    if d is None:
+        return None
+    s = flusi_insect()
+    s.body = _BODY[d.get("body", "none")]
+    s.wings = 1 if d.get("wings", False) else 0
+    s.smooth = _SMOOTH[d.get("smooth", "cos")]
+    s.c_smth = float(d.get("c_smth", 1.0))
+    for k in ("x_cntr", "u_cntr", "pivot_l", "pivot_r", "phi", "alpha", "theta"):
+        default = {"pivot_l": (0.0, 0.15, 0.0), "pivot_r": (0.0, -0.15, 0.0)}.get(k, (0.0, 0.0, 0.0))
+        getattr(s, k)[:] = [float(v) for v in d.get(k, default)]
+    for k, dv in (("psi", 0.0), ("beta", 0.0), ("gamma", 0.0), ("psi_dot", 0.0), ("beta_dot", 0.0),
+                  ("gamma_dot", 0.0), ("radius", 0.5), ("a", 0.5), ("b", 0.1), ("eta_stroke", 0.0),
+                  ("wing_A", 0.175), ("wing_B", 0.5), ("wing_t", 0.0), ("freq", 1.0)):
+        setattr(s, k, float(d.get(k, dv)))
+    return s
+
+
+class Plan:
+    """A plan plus torch-allocated buffers on the current device and stream."""
+
+    def __init__(self, n: int, L: float, nu: float, eta: float, dtype: str = "f64"):
+        if not torch.cuda.is_available():
+            raise RuntimeError("flusi needs a ROCm GPU")
+        self.n, self.L, self.nu, self.eta = n, L, nu, eta
+        self.dtype = dtype
+        self.rdt = torch.float64 if dtype == "f64" else torch.float32
+        self.cdt = torch.complex128 if dtype == "f64" else torch.complex64
+        self.handle = flusi_plan_create(n, n, n, L, nu, eta, FLUSI_F64 if dtype == "f64" else FLUSI_F32)
+        self.dev = torch.device("cuda", torch.cuda.current_device())
+        self.sync_stream()
+
+    def sync_stream(self):
+        flusi_set_stream(self.handle, torch.cuda.current_stream().cuda_stream)
+
+    def close(self):
+        if self.handle is not None:
+            flusi_plan_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # tensors
+    def real(self, nf: int):
+        return torch.empty((nf, self.n, self.n, self.n), dtype=self.rdt, device=self.dev)
+
+    def spec(self, nf: int):
+        return torch.empty((nf, self.n, self.n, self.n // 2 + 1), dtype=self.cdt, device=self.dev)
+
+    def r2c(self, f: torch.Tensor) -> torch.Tensor:
+        f = f.to(self.dev, self.rdt).contiguous()
+        nf = f.shape[0]
+        out = self.spec(nf)
+        flusi_fft_r2c(self.handle, f, out, nf)
+        return out
+
+    def c2r(self, fh: torch.Tensor) -> torch.Tensor:
+        fh = fh.to(self.dev, self.cdt).contiguous()
+        nf = fh.shape[0]
+        out = self.real(nf)
+        flusi_fft_c2r(self.handle, fh, out, nf)
+        return out
+
+    def mask(self, insect: dict, t: float):
+        chi = torch.empty((self.n,) * 3, dtype=self.rdt, device=self.dev)
+        us = self.real(3)
+        col = torch.empty((self.n,) * 3, dtype=torch.int16, device=self.dev)
+        flusi_mask_insect(self.handle, make_insect(insect), t, chi, us, col)
+        return chi, us, col
+
+    def rhs(self, uhat, chi=None, us=None, mean_mode: int = FLUSI_MEAN_FIXED, want_umax=False):
+        uhat = uhat.to(self.dev, self.cdt).contiguous()
+        out = self.spec(3)
+        chi = None if chi is None else chi.to(self.dev, self.rdt).contiguous()
+        us = None if us is None else us.to(self.dev, self.rdt).contiguous()
+        um = flusi_rhs(self.handle, uhat, chi, us, out, mean_mode, want_umax)
+        return (out, um) if want_umax else out
+
+    def new_state(self, u0, t0: float = 0.0) -> torch.Tensor:
+        st = torch.empty(flusi_state_bytes(self.handle), dtype=torch.uint8, device=self.dev)
+        u0 = torch.as_tensor(u0).to(self.dev, self.rdt).contiguous()
+        flusi_state_init(self.handle, st, u0, t0)
+        return st
+
+    def step(self, state, nsteps: int, insect: dict | None = None, dt_fixed: float = 0.0, cfl: float = 0.1,
+             dt_max: float = 0.0, eta_cap: float = 0.5, t_end: float = 0.0, mean_mode: int = FLUSI_MEAN_FIXED,
+             history: bool = False):
+        hist = torch.zeros((nsteps, FLUSI_NDIAG), dtype=torch.float64, device=self.dev) if history else None
+        p = flusi_step_params(nsteps, mean_mode, dt_fixed, cfl, dt_max, eta_cap, t_end,
+                              hist.data_ptr() if hist is not None else None)
+        flusi_step(self.handle, state, make_insect(insect), p)
+        return hist
+
+    def forces(self, state):
+        return flusi_forces(self.handle, state)
+
+    def velocity(self, state) -> torch.Tensor:
+        u = self.real(3)
+        flusi_state_velocity(self.handle, state, u)
+        return u
+
+    def uhat(self, state) -> torch.Tensor:
+        out = self.spec(3)
+        flusi_state_export_uhat(self.handle, state, out)
+        return out
+
+    def time(self, state):
+        return flusi_state_time(self.handle, state)

@@ -1,0 +1,245 @@
+// Register/LDS mixed-radix FFT machinery for gfx950.
+//
+// A workgroup transforms C independent columns of length N held in LDS.
+// Element n of column c lives at buf[n*SN + c*SC].  Each stage of radix R
+// (Stockham, decimation in time, auto-sorting) reads R elements with stride
+// N/R into registers, applies the inter-stage twiddles from an FP64-accurate
+// table, performs an R-point DFT in registers (R in {2,3,4,6,8,12,16}) and
+// writes the R results back in place after a barrier.  The output is in
+// natural order.  The forward transform uses exp(-2 pi i nk/N), the inverse
+// exp(+2 pi i nk/N), both unnormalized.
+#pragma once
+#include "common.hpp"
+
+namespace flusi {
+
+// ---------------------------------------------------------------------------
+// Radix plans (product = N)
+// ---------------------------------------------------------------------------
+__host__ __device__ constexpr int fft_nstages(int N) {
+    switch (N) {
+        case 16: return 1;
+        case 24: case 32: case 48: case 64: case 96: case 128: case 192: case 256: return 2;
+        case 384: case 512: case 768: case 1024: return 3;
+        default: return 0;
+    }
+}
+__host__ __device__ constexpr int fft_radix(int N, int s) {
+    switch (N) {
+        case 16: return 16;
+        case 24: return s == 0 ? 8 : 3;
+        case 32: return s == 0 ? 8 : 4;
+        case 48: return s == 0 ? 16 : 3;
+        case 64: return 8;
+        case 96: return s == 0 ? 8 : 12;
+        case 128: return s == 0 ? 8 : 16;
+        case 192: return s == 0 ? 16 : 12;
+        case 256: return 16;
+        case 384: return s == 0 ? 16 : (s == 1 ? 8 : 3);
+        case 512: return 8;
+        case 768: return s == 0 ? 16 : (s == 1 ? 16 : 3);
+        case 1024: return s == 0 ? 16 : (s == 1 ? 16 : 4);
+        default: return 1;
+    }
+}
+__host__ __device__ constexpr int fft_prefix(int N, int s) {
+    int p = 1;
+    for (int i = 0; i < s; ++i) p *= fft_radix(N, i);
+    return p;
+}
+__host__ __device__ constexpr bool fft_supported(int N) {
+    return fft_nstages(N) > 0 && fft_prefix(N, fft_nstages(N)) == N;
+}
+
+// ---------------------------------------------------------------------------
+// Exact small-radix twiddles: cos/sin of multiples of 2 pi / 48 (R | 48)
+// ---------------------------------------------------------------------------
+// cos(r * 7.5 deg) for the r that radices 2,3,4,6,8,12,16 need (r in 0..12)
+__host__ __device__ constexpr double cos_q(int r) {
+    switch (r) {
+        case 0: return 1.0;
+        case 3: return 0.92387953251128675612818318939678828682;   // 22.5 deg
+        case 4: return 0.86602540378443864676372317075293618347;   // 30 deg
+        case 6: return 0.70710678118654752440084436210484903928;   // 45 deg
+        case 8: return 0.5;                                        // 60 deg
+        case 9: return 0.38268343236508977172845998403039886676;   // 67.5 deg
+        case 12: return 0.0;                                       // 90 deg
+        default: return 2.0;  // not needed by any supported radix
+    }
+}
+// cos and sin of a * 7.5 deg, a in [0, 48)
+__host__ __device__ constexpr double cos48(int a) {
+    const int q = a / 12, r = a % 12;
+    return q == 0 ? cos_q(r) : q == 1 ? -cos_q(12 - r) : q == 2 ? -cos_q(r) : cos_q(12 - r);
+}
+__host__ __device__ constexpr double sin48(int a) {
+    const int q = a / 12, r = a % 12;
+    return q == 0 ? cos_q(12 - r) : q == 1 ? cos_q(r) : q == 2 ? -cos_q(12 - r) : -cos_q(r);
+}
+
+// v * exp(DIR * 2 pi i M / R) with DIR = -1 forward, +1 inverse; trivial angles
+// are applied as sign changes / swaps.
+template <int R, int M, int DIR, typename T>
+__device__ __forceinline__ cx<T> twc(cx<T> v) {
+    constexpr int a = ((M % R) * (48 / R)) % 48;
+    if constexpr (a == 0) {
+        return v;
+    } else if constexpr (a == 24) {
+        return {-v.x, -v.y};
+    } else if constexpr (a == 12) {
+        return DIR < 0 ? mul_mi(v) : mul_pi(v);
+    } else if constexpr (a == 36) {
+        return DIR < 0 ? mul_pi(v) : mul_mi(v);
+    } else {
+        constexpr double c = cos48(a);
+        constexpr double s = DIR < 0 ? -sin48(a) : sin48(a);
+        return cmul(v, cx<T>{T(c), T(s)});
+    }
+}
+
+// ---------------------------------------------------------------------------
+// R-point DFTs in registers
+// ---------------------------------------------------------------------------
+template <int R, int DIR, typename T>
+struct Dft;
+
+template <int DIR, typename T>
+struct Dft<1, DIR, T> {
+    __device__ __forceinline__ static void run(cx<T>*) {}
+};
+
+template <int DIR, typename T>
+struct Dft<2, DIR, T> {
+    __device__ __forceinline__ static void run(cx<T>* v) {
+        const cx<T> a = v[0], b = v[1];
+        v[0] = a + b;
+        v[1] = a - b;
+    }
+};
+
+template <int DIR, typename T>
+struct Dft<3, DIR, T> {
+    __device__ __forceinline__ static void run(cx<T>* v) {
+        constexpr T h = T(0.5);
+        constexpr T s3 = T(0.86602540378443864676372317075293618347);
+        const cx<T> s = v[1] + v[2];
+        const cx<T> d = v[1] - v[2];
+        const cx<T> m = v[0] - s * h;
+        // forward: X1 = m - i s3 d, X2 = m + i s3 d
+        const cx<T> r = (DIR < 0) ? mul_mi(d * s3) : mul_pi(d * s3);
+        v[0] = v[0] + s;
+        v[1] = m + r;
+        v[2] = m - r;
+    }
+};
+
+template <int DIR, typename T>
+struct Dft<4, DIR, T> {
+    __device__ __forceinline__ static void run(cx<T>* v) {
+        const cx<T> a = v[0] + v[2], b = v[0] - v[2];
+        const cx<T> c = v[1] + v[3], d = v[1] - v[3];
+        const cx<T> e = (DIR < 0) ? mul_mi(d) : mul_pi(d);
+        v[0] = a + c;
+        v[2] = a - c;
+        v[1] = b + e;
+        v[3] = b - e;
+    }
+};
+
+// R = P*Q: n = Q n1 + n2, k = k1 + P k2.
+template <int P, int Q, int DIR, typename T>
+struct DftPQ {
+    __device__ __forceinline__ static void run(cx<T>* v) {
+        constexpr int R = P * Q;
+        cx<T> y[Q][P];
+        static_for<Q>([&](auto n2c) {
+            constexpr int n2 = decltype(n2c)::value;
+            cx<T> a[P];
+            static_for<P>([&](auto n1c) { a[decltype(n1c)::value] = v[Q * decltype(n1c)::value + n2]; });
+            Dft<P, DIR, T>::run(a);
+            static_for<P>([&](auto k1c) {
+                constexpr int k1 = decltype(k1c)::value;
+                y[n2][k1] = twc<R, n2 * k1, DIR>(a[k1]);
+            });
+        });
+        static_for<P>([&](auto k1c) {
+            constexpr int k1 = decltype(k1c)::value;
+            cx<T> b[Q];
+            static_for<Q>([&](auto n2c) { b[decltype(n2c)::value] = y[decltype(n2c)::value][k1]; });
+            Dft<Q, DIR, T>::run(b);
+            static_for<Q>([&](auto k2c) { v[k1 + P * decltype(k2c)::value] = b[decltype(k2c)::value]; });
+        });
+    }
+};
+
+template <int DIR, typename T>
+struct Dft<6, DIR, T> : DftPQ<2, 3, DIR, T> {};
+template <int DIR, typename T>
+struct Dft<8, DIR, T> : DftPQ<2, 4, DIR, T> {};
+template <int DIR, typename T>
+struct Dft<12, DIR, T> : DftPQ<4, 3, DIR, T> {};
+template <int DIR, typename T>
+struct Dft<16, DIR, T> : DftPQ<4, 4, DIR, T> {};
+
+// ---------------------------------------------------------------------------
+// Columns in LDS
+// ---------------------------------------------------------------------------
+template <typename T, int N, int DIR, int C, int NT, int SN, int SC, int S>
+__device__ __forceinline__ void fft_stage(cx<T>* buf, const cx<T>* __restrict__ tw) {
+    constexpr int R = fft_radix(N, S);
+    constexpr int Ns = fft_prefix(N, S);
+    constexpr int NB = C * (N / R);
+    constexpr int PER = (NB + NT - 1) / NT;
+    constexpr int TWS = N / (Ns * R);
+    const int tid = threadIdx.x;
+    cx<T> v[PER][R];
+    static_for<PER>([&](auto ic) {
+        constexpr int i = decltype(ic)::value;
+        const int w = tid + i * NT;
+        if ((NB % NT == 0) || w < NB) {
+            const int c = w % C;
+            const int b = w / C;
+            static_for<R>([&](auto rc) {
+                constexpr int r = decltype(rc)::value;
+                v[i][r] = buf[(b + r * (N / R)) * SN + c * SC];
+            });
+            if constexpr (Ns > 1) {
+                const int k = b % Ns;
+                static_for<R - 1>([&](auto rc) {
+                    constexpr int r = decltype(rc)::value + 1;
+                    const cx<T> wv = tw[k * r * TWS];
+                    v[i][r] = (DIR < 0) ? cmul(v[i][r], wv) : cmulc(v[i][r], wv);
+                });
+            }
+            Dft<R, DIR, T>::run(v[i]);
+        }
+    });
+    __syncthreads();
+    static_for<PER>([&](auto ic) {
+        constexpr int i = decltype(ic)::value;
+        const int w = tid + i * NT;
+        if ((NB % NT == 0) || w < NB) {
+            const int c = w % C;
+            const int b = w / C;
+            const int k = b % Ns;
+            const int ob = (b / Ns) * Ns * R + k;
+            static_for<R>([&](auto rc) {
+                constexpr int r = decltype(rc)::value;
+                buf[(ob + r * Ns) * SN + c * SC] = v[i][r];
+            });
+        }
+    });
+    __syncthreads();
+}
+
+// Transform all C columns; starts with a barrier, ends with a barrier.
+template <typename T, int N, int DIR, int C, int NT, int SN, int SC>
+__device__ __forceinline__ void fft_lds(cx<T>* buf, const cx<T>* __restrict__ tw) {
+    static_assert(fft_supported(N), "unsupported FFT length");
+    __syncthreads();
+    static_for<fft_nstages(N)>([&](auto sc) {
+        fft_stage<T, N, DIR, C, NT, SN, SC, decltype(sc)::value>(buf, tw);
+    });
+}
+
+}  // namespace flusi

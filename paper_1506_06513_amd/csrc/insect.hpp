@@ -1,0 +1,225 @@
+// Insect kinematics and mask evaluation (FP64), Sec. 2.2 and Sec. 3.
+//
+// The kinematics block is evaluated once per time level by one thread and
+// read by every mask evaluation; the mask is evaluated pointwise inside the
+// physical-space pass (no chi / u_s arrays in HBM).
+#pragma once
+#include "common.hpp"
+#include "../../include/flusi.h"
+
+namespace flusi {
+
+// Per-time-level insect state in the global frame.
+struct Kin {
+    double Mb[9];      // M_body = Rx(psi) Ry(beta) Rz(gamma): x_b = Mb (x_g - xc)
+    double xc[3];      // body centre
+    double uc[3];      // body centre velocity
+    double omb[3];     // body angular velocity, body frame
+    double Mws[2][9];  // M_wing M_stroke for the left [0] and right [1] wing
+    double piv[2][3];  // pivots, body frame
+    double omw[2][3];  // wing angular velocities, body frame
+    double xref[3][3]; // torque reference points (global): body centre, left pivot, right pivot
+    double r2all;      // squared radius (about xc) outside which chi == 0 exactly
+    double thr;        // delta above which chi == 0 exactly
+    double h;          // smoothing half width
+    int body, wings, smooth, pad;
+};
+
+__host__ __device__ inline void mat_rx(double a, double* M) {
+    const double c = cos(a), s = sin(a);
+    M[0] = 1; M[1] = 0; M[2] = 0;
+    M[3] = 0; M[4] = c; M[5] = s;
+    M[6] = 0; M[7] = -s; M[8] = c;
+}
+__host__ __device__ inline void mat_ry(double a, double* M) {
+    const double c = cos(a), s = sin(a);
+    M[0] = c; M[1] = 0; M[2] = -s;
+    M[3] = 0; M[4] = 1; M[5] = 0;
+    M[6] = s; M[7] = 0; M[8] = c;
+}
+__host__ __device__ inline void mat_rz(double a, double* M) {
+    const double c = cos(a), s = sin(a);
+    M[0] = c; M[1] = s; M[2] = 0;
+    M[3] = -s; M[4] = c; M[5] = 0;
+    M[6] = 0; M[7] = 0; M[8] = 1;
+}
+__host__ __device__ inline void mat_mul(const double* A, const double* B, double* C) {
+    double t[9];
+    for (int i = 0; i < 3; ++i)
+        for (int j = 0; j < 3; ++j) t[3 * i + j] = A[3 * i] * B[j] + A[3 * i + 1] * B[3 + j] + A[3 * i + 2] * B[6 + j];
+    for (int i = 0; i < 9; ++i) C[i] = t[i];
+}
+__host__ __device__ inline void mat_vec(const double* A, const double* v, double* o) {
+    const double a = A[0] * v[0] + A[1] * v[1] + A[2] * v[2];
+    const double b = A[3] * v[0] + A[4] * v[1] + A[5] * v[2];
+    const double c = A[6] * v[0] + A[7] * v[1] + A[8] * v[2];
+    o[0] = a; o[1] = b; o[2] = c;
+}
+// A^T v
+__host__ __device__ inline void mat_tvec(const double* A, const double* v, double* o) {
+    const double a = A[0] * v[0] + A[3] * v[1] + A[6] * v[2];
+    const double b = A[1] * v[0] + A[4] * v[1] + A[7] * v[2];
+    const double c = A[2] * v[0] + A[5] * v[1] + A[8] * v[2];
+    o[0] = a; o[1] = b; o[2] = c;
+}
+__host__ __device__ inline void cross3(const double* a, const double* b, double* o) {
+    const double x = a[1] * b[2] - a[2] * b[1];
+    const double y = a[2] * b[0] - a[0] * b[2];
+    const double z = a[0] * b[1] - a[1] * b[0];
+    o[0] = x; o[1] = y; o[2] = z;
+}
+
+// Kinematics at time t (Sec. 3.1 and 3.3).  dx is the grid spacing.
+__host__ __device__ inline void compute_kin(const flusi_insect& in, double t, double dx, Kin& k) {
+    const double psi = in.psi + in.psi_dot * t;
+    const double beta = in.beta + in.beta_dot * t;
+    const double gam = in.gamma + in.gamma_dot * t;
+    double Rx_[9], Ry_[9], Rz_[9], T1[9];
+    mat_rx(psi, Rx_);
+    mat_ry(beta, Ry_);
+    mat_rz(gam, Rz_);
+    mat_mul(Rx_, Ry_, T1);
+    mat_mul(T1, Rz_, k.Mb);
+    // body angular velocity: Rz^T[(0,0,gd) + Ry^T[(0,bd,0) + Rx^T (pd,0,0)]], then to body frame
+    double v[3] = {in.psi_dot, 0.0, 0.0}, w[3];
+    mat_tvec(Rx_, v, w);
+    w[1] += in.beta_dot;
+    mat_tvec(Ry_, w, v);
+    v[2] += in.gamma_dot;
+    mat_tvec(Rz_, v, w);
+    mat_vec(k.Mb, w, k.omb);
+    for (int i = 0; i < 3; ++i) {
+        k.xc[i] = in.x_cntr[i];
+        k.uc[i] = in.u_cntr[i];
+        k.xref[0][i] = in.x_cntr[i];
+    }
+    k.body = in.body;
+    k.wings = in.wings;
+    k.smooth = in.smooth;
+    k.h = in.c_smth * dx;
+    // chi is exactly 0 beyond delta = h (cosine) or delta = 20 h (tanh rounds to 1)
+    k.thr = in.smooth == FLUSI_SMOOTH_TANH ? 20.0 * k.h : k.h;
+    double rall = 0.0;
+    if (in.body == FLUSI_BODY_SPHERE) rall = in.radius + k.thr;
+    if (in.body == FLUSI_BODY_ELLIPSOID) rall = 2.0 * (in.a + in.b) + k.thr;
+
+    const double om = 2.0 * M_PI * in.freq;
+    const double ph_phi = om * t + in.phi[2], ph_al = om * t + in.alpha[2], ph_th = om * t + in.theta[2];
+    const double phi0 = in.phi[0] + in.phi[1] * cos(ph_phi), dphi0 = -in.phi[1] * om * sin(ph_phi);
+    const double al0 = in.alpha[0] + in.alpha[1] * cos(ph_al), dal0 = -in.alpha[1] * om * sin(ph_al);
+    const double th = in.theta[0] + in.theta[1] * cos(ph_th), dth = -in.theta[1] * om * sin(ph_th);
+    for (int s = 0; s < 2; ++s) {
+        const double sg = s == 0 ? 1.0 : -1.0;  // right wing: alpha and phi mirrored
+        const double phi = sg * phi0, dphi = sg * dphi0, al = sg * al0, dal = sg * dal0;
+        double Ms[9], Mw[9], A[9], B[9], C[9];
+        mat_ry(in.eta_stroke, Ms);
+        if (s == 1) {
+            double Rpi[9];
+            mat_rx(M_PI, Rpi);
+            mat_mul(Rpi, Ms, Ms);
+        }
+        mat_ry(al, A);
+        mat_rz(-th, B);
+        mat_rx(phi, C);
+        mat_mul(A, B, Mw);
+        mat_mul(Mw, C, Mw);
+        mat_mul(Mw, Ms, k.Mws[s]);
+        // stroke-frame angular velocity: Rx^T(phi)[(dphi,0,0) + Rz^T(-th)[(0,0,-dth) + Ry^T(al)(0,dal,0)]]
+        double a1[3] = {0.0, dal, 0.0}, a2[3];
+        mat_tvec(A, a1, a2);
+        a2[2] -= dth;
+        mat_tvec(B, a2, a1);
+        a1[0] += dphi;
+        mat_tvec(C, a1, a2);
+        mat_tvec(Ms, a2, k.omw[s]);
+        const double* pv = s == 0 ? in.pivot_l : in.pivot_r;
+        for (int i = 0; i < 3; ++i) k.piv[s][i] = pv[i];
+        double pg[3];
+        mat_tvec(k.Mb, pv, pg);
+        for (int i = 0; i < 3; ++i) k.xref[1 + s][i] = in.x_cntr[i] + pg[i];
+        if (in.wings) {
+            const double mab = fmax(in.wing_A, in.wing_B);
+            const double e1 = mab + k.thr, e2 = 0.5 * in.wing_t + k.thr;
+            const double pn = sqrt(pv[0] * pv[0] + pv[1] * pv[1] + pv[2] * pv[2]);
+            rall = fmax(rall, pn + in.wing_B + sqrt(e1 * e1 + e2 * e2));
+        }
+    }
+    k.r2all = rall * rall;
+}
+
+__device__ __forceinline__ double chi_of(double delta, const Kin& k) {
+    if (k.smooth == FLUSI_SMOOTH_TANH) return 0.5 * (1.0 - tanh(delta / k.h));
+    if (delta <= -k.h) return 1.0;
+    if (delta >= k.h) return 0.0;
+    return 0.5 * (1.0 + cos(M_PI * (delta + k.h) / (2.0 * k.h)));
+}
+
+struct MaskPt {
+    double chi;
+    double us[3];
+    int colour;
+};
+
+// chi, u_s and colour at global point (x, y, z).
+__device__ __forceinline__ MaskPt eval_mask(const Kin& k, const flusi_insect& in, double x, double y, double z) {
+    MaskPt o;
+    o.chi = 0.0;
+    o.us[0] = o.us[1] = o.us[2] = 0.0;
+    o.colour = 0;
+    const double rel[3] = {x - k.xc[0], y - k.xc[1], z - k.xc[2]};
+    const double r2 = rel[0] * rel[0] + rel[1] * rel[1] + rel[2] * rel[2];
+    if (r2 > k.r2all) return o;
+    double xb[3];
+    mat_vec(k.Mb, rel, xb);
+    double best = 0.0;
+    int part = 0;
+    if (k.body == FLUSI_BODY_SPHERE) {
+        best = chi_of(sqrt(r2) - in.radius, k);
+    } else if (k.body == FLUSI_BODY_ELLIPSOID) {
+        const double q = xb[0] / in.a;
+        const double rad = sqrt(xb[1] * xb[1] + xb[2] * xb[2]);
+        const double d = fmax(rad - in.b * sqrt(fmax(0.0, 1.0 - q * q)), fabs(xb[0]) - in.a);
+        best = chi_of(d, k);
+    }
+    if (k.wings) {
+        const double mab = fmax(in.wing_A, in.wing_B);
+        for (int s = 0; s < 2; ++s) {
+            const double d0[3] = {xb[0] - k.piv[s][0], xb[1] - k.piv[s][1], xb[2] - k.piv[s][2]};
+            double xw[3];
+            mat_vec(k.Mws[s], d0, xw);
+            const double dz = fabs(xw[2]) - 0.5 * in.wing_t;
+            const double ey = xw[1] - in.wing_B;
+            const double r = sqrt(xw[0] * xw[0] + ey * ey);
+            if (dz >= k.thr || r - mab >= k.thr) continue;  // chi == 0 exactly
+            const double qa = xw[0] / in.wing_A, qb = ey / in.wing_B;
+            const double rho = sqrt(qa * qa + qb * qb);
+            const double inplane = r > 0.0 ? r - r / rho : -in.wing_A;
+            const double c = chi_of(fmax(dz, inplane), k);
+            if (c > best) {
+                best = c;
+                part = 1 + s;
+            }
+        }
+    }
+    if (best <= 0.0) return o;
+    o.chi = best;
+    o.colour = part + 1;
+    // u_b = u_cntr + Mb^T (omb x x_b)
+    double cr[3], ub[3];
+    cross3(k.omb, xb, cr);
+    mat_tvec(k.Mb, cr, ub);
+    for (int i = 0; i < 3; ++i) ub[i] += k.uc[i];
+    if (part == 0) {
+        o.us[0] = ub[0]; o.us[1] = ub[1]; o.us[2] = ub[2];
+    } else {
+        const int s = part - 1;
+        const double d0[3] = {xb[0] - k.piv[s][0], xb[1] - k.piv[s][1], xb[2] - k.piv[s][2]};
+        double uw[3];
+        cross3(k.omw[s], d0, cr);
+        mat_tvec(k.Mb, cr, uw);
+        o.us[0] = uw[0] + ub[0]; o.us[1] = uw[1] + ub[1]; o.us[2] = uw[2] + ub[2];
+    }
+    return o;
+}
+
+}  // namespace flusi
