@@ -1,0 +1,245 @@
+"""Benchmark of the pseudo-spectral penalized Navier-Stokes step on one MI355X.
+
+Workload (default): 128^3 periodic box L = 4, fixed sphere of radius 0.5 at the
+centre with a tanh mask of width 2 dx, mean inflow (1,0,0) plus seeded
+solenoidal noise of rms 1e-3 in |k| <= 8, nu = 0.01, C_eta = 1e-3, adaptive dt
+at CFL 0.1 (capped at C_eta/2).  One step = one pass of the whole hot path:
+mask on the fly, u x w and penalization, 2/3 rule, projection, IF-AB2 update,
+FP64 max|u| / force / energy reductions and the adaptive dt.
+
+Prints one JSON line.  `value` is FP32 Mpoint-steps/s (points x steps / s);
+the FP64 figure, each precision's error against the FP64 oracle, the roofline
+of the dominant kernel (live HIP-event timing over a timed region, algorithmic
+bytes from the pruned byte model) and the oracle's CPU throughput on a bounded
+sample are reported beside it.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "Mpoint-steps/s (AB2 RHS) FP32 vs FP64 at stated err; p50/p99 solve latency"
+HBM_PEAK_GBS = 8000.0
+
+
+def pass_bytes(n: int, cbytes: int, split_z: bool) -> dict:
+    """Algorithmic HBM bytes per launch of each pass of the pruned schedule.
+
+    K = (n-1)//3, KP = K+1 kept kx, M = 2K+1 kept ky and kz, Q = M*KP.
+    z-partials [6][n][Q], y-partials [6][n][n][KP], x-output [3][n][n][KP],
+    y-output [3][n][Q], state u_hat and previous right-hand side [3][M][Q] each.
+    z_pass is forward z + projection + AB2 (+ curl and inverse z when fused);
+    z_inverse is curl + inverse z from the state."""
+    K = (n - 1) // 3
+    KP, M = K + 1, 2 * K + 1
+    Q = M * KP
+    s = cbytes
+    nwg = n * n // max(2, 1 << int(math.log2(max(1, 1024 // n))))
+    zup = (3 * n * Q + 4 * 3 * M * Q) * s
+    return {
+        "z_inverse": (3 * M * Q + 6 * n * Q) * s,
+        "y_inverse": (6 * n * Q + 6 * n * n * KP) * s,
+        "x_pass": (6 * n * n * KP + 3 * n * n * KP) * s + nwg * 39 * 8,
+        "y_forward": (3 * n * n * KP + 3 * n * Q) * s + nwg * 39 * 8,
+        "z_pass": zup if split_z else zup + 6 * n * Q * s,
+    }
+
+
+def step_bytes(n: int, cbytes: int) -> int:
+    """Bytes the fused four-pass schedule must move per step (the algorithmic
+    model; a split z-pass re-reads u_hat, which is not counted)."""
+    b = pass_bytes(n, cbytes, split_z=False)
+    return b["y_inverse"] + b["x_pass"] + b["y_forward"] + b["z_pass"]
+
+
+def build_workload(name: str):
+    import workloads as W
+    if name == "sphere128":
+        wl = W.WORKLOADS["sphere128"]
+        n, L = wl["n"], wl["L"]
+        u0 = W.inflow_noise(n, L, seed=wl["seed"], rms=1e-3, kmax=8.0)
+        body = W.sphere_body(L)
+        desc = ("128^3 box L=4, sphere R=0.5 tanh mask 2dx, inflow (1,0,0) + solenoidal noise rms 1e-3 "
+                "|k|<=8 (seed 0), nu=0.01, C_eta=1e-3, adaptive dt CFL 0.1 capped at C_eta/2")
+        return dict(n=n, L=L, nu=wl["nu"], eta=wl["eta"], u0=u0, insect=body, cfl=0.1, dt_fixed=0.0,
+                    desc=desc, default_steps=wl["steps"])
+    if name == "insect256":
+        wl = W.WORKLOADS["insect256"]
+        n, L = wl["n"], wl["L"]
+        u0 = np.zeros((3, n, n, n))
+        body = W.model_insect(n, L)
+        desc = ("256^3 box L=4, ellipsoid body + two elliptic flapping wings (stroke +-70 deg, feathering "
+                "+-45 deg, f=1), mask rebuilt every step, nu=1/136, C_eta=2.5e-4, CFL 0.1, fluid at rest")
+        return dict(n=n, L=L, nu=wl["nu"], eta=wl["eta"], u0=u0, insect=body, cfl=0.1, dt_fixed=0.0,
+                    desc=desc, default_steps=200)
+    if name == "tg32":
+        wl = W.WORKLOADS["tg32"]
+        n = wl["n"]
+        return dict(n=n, L=wl["L"], nu=wl["nu"], eta=wl["eta"], u0=W.taylor_green(n), insect=None, cfl=0.0,
+                    dt_fixed=wl["dt_fixed"], desc="32^3 Taylor-Green, nu=0.01, dt=1e-3", default_steps=100)
+    raise SystemExit(f"unknown workload {name}")
+
+
+def gpu_run(F, torch, wl, dtype, steps, warmup):
+    P = F.Plan(wl["n"], wl["L"], wl["nu"], wl["eta"], dtype)
+    kw = dict(dt_fixed=wl["dt_fixed"], cfl=wl["cfl"], eta_cap=0.5, mean_mode=F.FLUSI_MEAN_FIXED)
+    u0 = torch.from_numpy(wl["u0"])
+    st = P.new_state(u0)
+    if warmup:
+        P.step(st, warmup, wl["insect"], **kw)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    t0 = time.perf_counter()
+    e0.record()
+    P.step(st, steps, wl["insect"], **kw)
+    e1.record()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    ev_ms = e0.elapsed_time(e1)
+    rc, diag = P.forces(st)
+    if rc != 0:
+        raise SystemExit(f"state stopped with status {rc}")
+    # second timed region with per-pass events (dominant-kernel roofline)
+    F.flusi_profile(P.handle, True)
+    P.step(st, steps, wl["insect"], **kw)
+    ms, cnt = F.flusi_pass_times(P.handle)
+    F.flusi_profile(P.handle, False)
+    torch.cuda.synchronize()
+    return dict(wall_s=wall, ev_ms=ev_ms, pass_ms=ms, pass_cnt=cnt, diag=diag)
+
+
+def oracle_sample(wl, budget_s=12.0, max_steps=30):
+    """Oracle throughput and final velocity on a bounded sample of the workload."""
+    import oracle as O
+    p = O.Params(wl["n"], wl["L"], wl["nu"], wl["eta"], O.MEAN_FIXED)
+    ins = O.Insect.from_dict(wl["insect"]) if wl["insect"] else None
+    ctl = O.StepControl(dt_fixed=wl["dt_fixed"], cfl=wl["cfl"] or 0.1, eta_cap=0.5)
+    st = O.init_state(p, wl["u0"])
+    st, _ = O.step(p, st, ctl, ins)  # first step (also warms scipy's plan cache)
+    t0 = time.perf_counter()
+    k = 0
+    while k < max_steps and (time.perf_counter() - t0) < budget_s:
+        st, _ = O.step(p, st, ctl, ins)
+        k += 1
+    dt = time.perf_counter() - t0
+    return dict(steps=k + 1, timed_steps=k, seconds=dt, cores=O.flusi_oracle._WORKERS,
+                u=O.velocity(p, st))
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=None)
+    ap.add_argument("--warmup", type=int, default=10)
+    ap.add_argument("--workload", default="sphere128", choices=["sphere128", "insect256", "tg32"])
+    ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="run only a plain device copy of 1 GiB (3 launches) to scale HBM counters")
+    a = ap.parse_args()
+    if a.copy_calibration:
+        import torch
+        x = torch.ones(1 << 28, dtype=torch.float32, device="cuda")
+        y = torch.empty_like(x)
+        for _ in range(3):
+            y.copy_(x)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes_read": x.numel() * 4, "copy_bytes_written": y.numel() * 4, "launches": 3}))
+        return
+    if a.gpus != 1:
+        print(f"bench.py: this build measures one GPU only (asked for {a.gpus}); the multi-GPU "
+              "decomposition is not part of it", file=sys.stderr)
+        raise SystemExit(2)
+
+    import torch
+    import paper_1506_06513_amd as F
+
+    wl = build_workload(a.workload)
+    steps = a.steps or wl["default_steps"]
+    n = wl["n"]
+    pts = float(n) ** 3
+    res = {}
+    for dtype in ("f32", "f64"):
+        res[dtype] = gpu_run(F, torch, wl, dtype, steps, a.warmup)
+
+    def mps(r):
+        return pts * steps / (r["ev_ms"] / 1e3) / 1e6
+
+    v32, v64 = mps(res["f32"]), mps(res["f64"])
+    # dominant kernel of the FP32 run
+    r = res["f32"]
+    names = list(F.PASS_NAMES)
+    split = r["pass_cnt"][names.index("z_inverse")] > 1
+    pb = pass_bytes(n, 8, split)
+    passes = {}
+    for i, nm in enumerate(names):
+        if r["pass_cnt"][i]:
+            avg = r["pass_ms"][i] / r["pass_cnt"][i]
+            passes[nm] = dict(avg_us=round(avg * 1e3, 3), launches=int(r["pass_cnt"][i]),
+                              bytes=int(pb.get(nm, 0)), gbs=round(pb.get(nm, 0) / (avg * 1e-3) / 1e9, 1))
+    step_names = ["y_inverse", "x_pass", "y_forward", "z_pass"] + (["z_inverse"] if split else [])
+    dom = max(step_names, key=lambda k: r["pass_ms"][names.index(k)])
+    d_avg_s = r["pass_ms"][names.index(dom)] / r["pass_cnt"][names.index(dom)] / 1e3
+    achieved = pb[dom] / d_avg_s / 1e9
+    sb = step_bytes(n, 8)
+    out = {
+        "metric": METRIC,
+        "value": round(v32, 2),
+        "unit": "Mpoint-steps/s",
+        "n_gpus": 1,
+        "steps": steps,
+        "warmup": a.warmup,
+        "ms_per_step": round(res["f32"]["ev_ms"] / steps, 5),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": a.workload, "description": wl["desc"], "grid": n},
+        "fp64": {"value": round(v64, 2), "unit": "Mpoint-steps/s",
+                 "ms_per_step": round(res["f64"]["ev_ms"] / steps, 5),
+                 "fp32_over_fp64": round(v32 / v64, 3)},
+        "roofline": {"bound": "hbm", "kernel": dom, "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None},
+        "step_roofline": {"bytes_per_step": sb, "bytes_per_point_step": round(sb / pts, 2),
+                          "achieved_gbs": round(sb / (res["f32"]["ev_ms"] / steps / 1e3) / 1e9, 1),
+                          "frac": round(sb / (res["f32"]["ev_ms"] / steps / 1e3) / 1e9 / HBM_PEAK_GBS, 4)},
+        "passes_f32": passes,
+        "wall_s": {k: round(v["wall_s"], 4) for k, v in res.items()},
+        "last_diag_f32": {"t": res["f32"]["diag"][0], "dt": res["f32"]["diag"][1],
+                          "umax": res["f32"]["diag"][2], "drag": res["f32"]["diag"][4]},
+    }
+    if not a.no_cpu:
+        cs = oracle_sample(wl)
+        cpu_v = pts * cs["timed_steps"] / cs["seconds"] / 1e6
+        out["cpu_baseline"] = {"value": round(cpu_v, 3), "unit": "Mpoint-steps/s", "cores": cs["cores"],
+                               "kind": "oracle",
+                               "sample": f"{cs['timed_steps']} steps of the same workload after 1 untimed step "
+                                         f"({cs['seconds']:.1f} s, NumPy/SciPy FP64)"}
+        # error of both precisions against the oracle after the same number of steps
+        errs = {}
+        for dtype in ("f32", "f64"):
+            P = F.Plan(n, wl["L"], wl["nu"], wl["eta"], dtype)
+            st = P.new_state(torch.from_numpy(wl["u0"]))
+            P.step(st, cs["steps"], wl["insect"], dt_fixed=wl["dt_fixed"], cfl=wl["cfl"], eta_cap=0.5)
+            u = P.velocity(st).double().cpu().numpy()
+            ou = cs["u"]
+            errs[dtype] = float(np.linalg.norm(u - ou) / np.linalg.norm(ou))
+            fl = u - u.mean(axis=(1, 2, 3), keepdims=True)
+            ofl = ou - ou.mean(axis=(1, 2, 3), keepdims=True)
+            errs[dtype + "_fluct"] = float(np.linalg.norm(fl - ofl) / np.linalg.norm(ofl))
+        out["err_vs_oracle"] = {"steps": cs["steps"], "rel_l2_f32": errs["f32"], "rel_l2_f64": errs["f64"],
+                                "rel_l2_fluct_f32": errs["f32_fluct"], "rel_l2_fluct_f64": errs["f64_fluct"]}
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

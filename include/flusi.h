@@ -198,6 +198,19 @@ int flusi_step(flusi_plan plan, void* state, const flusi_insect* ins, const flus
  * FLUSI_ENONFINITE if the state was stopped by a non-finite velocity. */
 int flusi_forces(flusi_plan plan, const void* state, double* out);
 
+/* Instrumentation.  While enabled, flusi_step brackets each pass it launches
+ * with HIP events on the plan's stream.  Passes: 0 inverse z of the state at
+ * the start of a call, 1 y-inverse, 2 x-pass (inverse x, source, forward x),
+ * 3 scalar reduction, 4 y-forward, 5 z-pass (forward z, projection, AB2,
+ * inverse z).  flusi_profile(plan, 1) clears the records and starts
+ * recording, flusi_profile(plan, 0) stops.  flusi_pass_times synchronizes the
+ * stream and returns, per pass, the summed event time in milliseconds and the
+ * number of launches recorded since the last flusi_profile(plan, 1); ms and
+ * launches are host arrays of FLUSI_NPASS entries (either may be NULL). */
+#define FLUSI_NPASS 6
+int flusi_profile(flusi_plan plan, int enable);
+int flusi_pass_times(flusi_plan plan, double* ms, long long* launches);
+
 #ifdef __cplusplus
 }
 #endif

@@ -33,6 +33,8 @@ FLUSI_BODY_NONE, FLUSI_BODY_SPHERE, FLUSI_BODY_ELLIPSOID = 0, 1, 2
 FLUSI_SMOOTH_COS, FLUSI_SMOOTH_TANH = 0, 1
 FLUSI_MEAN_FIXED, FLUSI_MEAN_FREE = 0, 1
 FLUSI_NDIAG = 22
+FLUSI_NPASS = 6
+PASS_NAMES = ("z_inverse", "y_inverse", "x_pass", "scalar", "y_forward", "z_pass")
 SUPPORTED_N = (16, 24, 32, 48, 64, 96, 128, 192, 256, 384, 512)
 
 
@@ -87,6 +89,8 @@ _SIGS = {
     "flusi_state_time": (ctypes.c_int, [_P, _P, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_longlong)]),
     "flusi_step": (ctypes.c_int, [_P, _P, ctypes.POINTER(flusi_insect), ctypes.POINTER(flusi_step_params)]),
     "flusi_forces": (ctypes.c_int, [_P, _P, ctypes.POINTER(ctypes.c_double)]),
+    "flusi_profile": (ctypes.c_int, [_P, ctypes.c_int]),
+    "flusi_pass_times": (ctypes.c_int, [_P, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_longlong)]),
 }
 
 _lib = None
@@ -210,6 +214,17 @@ def flusi_forces(plan, state):
     out = (ctypes.c_double * FLUSI_NDIAG)()
     rc = lib().flusi_forces(plan, _ptr(state), out)
     return rc, np.array(out[:])
+
+
+def flusi_profile(plan, enable: bool):
+    _check(lib().flusi_profile(plan, 1 if enable else 0))
+
+
+def flusi_pass_times(plan):
+    ms = (ctypes.c_double * FLUSI_NPASS)()
+    cnt = (ctypes.c_longlong * FLUSI_NPASS)()
+    _check(lib().flusi_pass_times(plan, ms, cnt))
+    return np.array(ms[:]), np.array(cnt[:], dtype=np.int64)
 
 
 # ----------------------------------------------------------------------------

@@ -1,12 +1,12 @@
 // Register/LDS mixed-radix FFT machinery for gfx950.
 //
-// A workgroup transforms C independent columns of length N held in LDS.
-// Element n of column c lives at buf[n*SN + c*SC].  Each stage of radix R
-// (Stockham, decimation in time, auto-sorting) reads R elements with stride
-// N/R into registers, applies the inter-stage twiddles from an FP64-accurate
-// table, performs an R-point DFT in registers (R in {2,3,4,6,8,12,16}) and
-// writes the R results back in place after a barrier.  The output is in
-// natural order.  The forward transform uses exp(-2 pi i nk/N), the inverse
+// A workgroup transforms columns of length N held in padded column-major LDS.
+// Each stage of radix R (Stockham, decimation in time, auto-sorting) reads R
+// elements with stride N/R into registers, applies the inter-stage twiddles
+// from an FP64-accurate table, performs an R-point DFT in registers (R in
+// {2,3,4,6,8,12,16}) and writes the R results back in place.  A column is
+// owned by one group of lanes of one wavefront for all stages, so the stages
+// synchronize at wavefront level only.  The output is in natural order.  The forward transform uses exp(-2 pi i nk/N), the inverse
 // exp(+2 pi i nk/N), both unnormalized.
 #pragma once
 #include "common.hpp"
@@ -14,13 +14,15 @@
 namespace flusi {
 
 // ---------------------------------------------------------------------------
-// Radix plans (product = N)
+// Radix plans (product = N).  Every radix of a plan divides E = fft_E(N), the
+// number of elements a lane holds, so that a column is always owned by the
+// same G = N/E lanes of one wavefront.
 // ---------------------------------------------------------------------------
 __host__ __device__ constexpr int fft_nstages(int N) {
     switch (N) {
         case 16: return 1;
-        case 24: case 32: case 48: case 64: case 96: case 128: case 192: case 256: return 2;
-        case 384: case 512: case 768: case 1024: return 3;
+        case 24: case 32: case 64: case 96: case 128: case 256: return 2;
+        case 48: case 192: case 384: case 512: case 768: case 1024: return 3;
         default: return 0;
     }
 }
@@ -29,26 +31,50 @@ __host__ __device__ constexpr int fft_radix(int N, int s) {
         case 16: return 16;
         case 24: return s == 0 ? 8 : 3;
         case 32: return s == 0 ? 8 : 4;
-        case 48: return s == 0 ? 16 : 3;
+        case 48: return s == 2 ? 3 : 4;
         case 64: return 8;
         case 96: return s == 0 ? 8 : 12;
         case 128: return s == 0 ? 8 : 16;
-        case 192: return s == 0 ? 16 : 12;
+        case 192: return s == 2 ? 3 : 8;
         case 256: return 16;
-        case 384: return s == 0 ? 16 : (s == 1 ? 8 : 3);
+        case 384: return s == 2 ? 6 : 8;
         case 512: return 8;
-        case 768: return s == 0 ? 16 : (s == 1 ? 16 : 3);
-        case 1024: return s == 0 ? 16 : (s == 1 ? 16 : 4);
+        case 768: return s == 2 ? 12 : 8;
+        case 1024: return s == 2 ? 4 : 16;
         default: return 1;
     }
 }
+// elements per lane (least common multiple of the radices)
+__host__ __device__ constexpr int fft_E(int N) {
+    switch (N) {
+        case 16: return 16;
+        case 24: return 24;
+        case 32: return 8;
+        case 48: return 12;
+        case 64: return 8;
+        case 96: return 24;
+        case 128: return 16;
+        case 192: return 24;
+        case 256: return 16;
+        case 384: return 24;
+        case 512: return 8;
+        case 768: return 24;
+        case 1024: return 16;
+        default: return 1;
+    }
+}
+// lanes per column
+__host__ __device__ constexpr int fft_G(int N) { return N / fft_E(N); }
 __host__ __device__ constexpr int fft_prefix(int N, int s) {
     int p = 1;
     for (int i = 0; i < s; ++i) p *= fft_radix(N, i);
     return p;
 }
 __host__ __device__ constexpr bool fft_supported(int N) {
-    return fft_nstages(N) > 0 && fft_prefix(N, fft_nstages(N)) == N;
+    if (fft_nstages(N) == 0 || fft_prefix(N, fft_nstages(N)) != N) return false;
+    for (int i = 0; i < fft_nstages(N); ++i)
+        if (fft_E(N) % fft_radix(N, i) != 0) return false;
+    return 64 % fft_G(N) == 0;
 }
 
 // ---------------------------------------------------------------------------
@@ -181,65 +207,90 @@ struct Dft<12, DIR, T> : DftPQ<4, 3, DIR, T> {};
 template <int DIR, typename T>
 struct Dft<16, DIR, T> : DftPQ<4, 4, DIR, T> {};
 
+// Padded column-major LDS: element n of column c at c*SC + n + n/16 (one pad
+// slot every 16 elements keeps the stride-R Stockham writes off a single bank).
+template <bool CM, int SN, int SC>
+__device__ __forceinline__ int lds_at(int n, int c) {
+    static_assert(CM, "only the column-major layout is used");
+    return c * SC + n + (n >> 4);
+}
+// column stride of a padded column-major buffer
+__host__ __device__ constexpr int cm_stride(int N) { return N + N / 16 + 1; }
+
 // ---------------------------------------------------------------------------
-// Columns in LDS
+// One column per group of G = N/E lanes of a wavefront, in padded column-major
+// LDS (element n at col[n + n/16]).  Lane l of the group handles butterflies
+// b = l + j*G of every stage, so a column never leaves its wavefront and the
+// stages only need wavefront-level ordering: LDS operations of one wavefront
+// complete in program order.  Callers stage data and block-synchronize before
+// and after.
 // ---------------------------------------------------------------------------
-template <typename T, int N, int DIR, int C, int NT, int SN, int SC, int S>
-__device__ __forceinline__ void fft_stage(cx<T>* buf, const cx<T>* __restrict__ tw) {
+__device__ __forceinline__ void wave_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+__device__ __forceinline__ int cpad(int n) { return n + (n >> 4); }
+
+template <typename T, int N, int DIR, int S>
+__device__ __forceinline__ void fft_col_stage(cx<T>* col, int l, const cx<T>* __restrict__ tw) {
+    constexpr int E = fft_E(N), G = N / E;
     constexpr int R = fft_radix(N, S);
     constexpr int Ns = fft_prefix(N, S);
-    constexpr int NB = C * (N / R);
-    constexpr int PER = (NB + NT - 1) / NT;
+    constexpr int NBC = N / R;
+    constexpr int J = E / R;  // butterflies per lane
     constexpr int TWS = N / (Ns * R);
-    const int tid = threadIdx.x;
-    cx<T> v[PER][R];
-    static_for<PER>([&](auto ic) {
-        constexpr int i = decltype(ic)::value;
-        const int w = tid + i * NT;
-        if ((NB % NT == 0) || w < NB) {
-            const int c = w % C;
-            const int b = w / C;
-            static_for<R>([&](auto rc) {
-                constexpr int r = decltype(rc)::value;
-                v[i][r] = buf[(b + r * (N / R)) * SN + c * SC];
-            });
-            if constexpr (Ns > 1) {
-                const int k = b % Ns;
-                static_for<R - 1>([&](auto rc) {
-                    constexpr int r = decltype(rc)::value + 1;
-                    const cx<T> wv = tw[k * r * TWS];
-                    v[i][r] = (DIR < 0) ? cmul(v[i][r], wv) : cmulc(v[i][r], wv);
-                });
-            }
-            Dft<R, DIR, T>::run(v[i]);
-        }
-    });
-    __syncthreads();
-    static_for<PER>([&](auto ic) {
-        constexpr int i = decltype(ic)::value;
-        const int w = tid + i * NT;
-        if ((NB % NT == 0) || w < NB) {
-            const int c = w % C;
-            const int b = w / C;
+    cx<T> v[J][R];
+    static_for<J>([&](auto jc) {
+        constexpr int j = decltype(jc)::value;
+        const int b = l + j * G;
+        static_for<R>([&](auto rc) {
+            constexpr int r = decltype(rc)::value;
+            v[j][r] = col[cpad(b + r * NBC)];
+        });
+        if constexpr (Ns > 1) {
             const int k = b % Ns;
-            const int ob = (b / Ns) * Ns * R + k;
-            static_for<R>([&](auto rc) {
-                constexpr int r = decltype(rc)::value;
-                buf[(ob + r * Ns) * SN + c * SC] = v[i][r];
+            static_for<R - 1>([&](auto rc) {
+                constexpr int r = decltype(rc)::value + 1;
+                const cx<T> wv = tw[k * r * TWS];
+                v[j][r] = (DIR < 0) ? cmul(v[j][r], wv) : cmulc(v[j][r], wv);
             });
         }
+        Dft<R, DIR, T>::run(v[j]);
     });
-    __syncthreads();
+    wave_sync();
+    static_for<J>([&](auto jc) {
+        constexpr int j = decltype(jc)::value;
+        const int b = l + j * G;
+        const int ob = (b / Ns) * Ns * R + b % Ns;
+        static_for<R>([&](auto rc) {
+            constexpr int r = decltype(rc)::value;
+            col[cpad(ob + r * Ns)] = v[j][r];
+        });
+    });
+    wave_sync();
 }
 
-// Transform all C columns; starts with a barrier, ends with a barrier.
-template <typename T, int N, int DIR, int C, int NT, int SN, int SC>
-__device__ __forceinline__ void fft_lds(cx<T>* buf, const cx<T>* __restrict__ tw) {
+template <typename T, int N, int DIR>
+__device__ __forceinline__ void fft_col(cx<T>* col, int l, const cx<T>* __restrict__ tw) {
     static_assert(fft_supported(N), "unsupported FFT length");
+    static_for<fft_nstages(N)>([&](auto sc) { fft_col_stage<T, N, DIR, decltype(sc)::value>(col, l, tw); });
+}
+
+// Transform columns 0..C-1 of a padded column-major buffer (column stride SC)
+// with NT threads; every lane group loops over its columns.
+template <typename T, int N, int DIR, int C, int NT, int SC>
+__device__ __forceinline__ void fft_cols(cx<T>* buf, const cx<T>* __restrict__ tw) {
+    constexpr int G = fft_G(N);
+    static_assert(NT % 64 == 0, "whole wavefronts");
+    const int l = threadIdx.x % G;
     __syncthreads();
-    static_for<fft_nstages(N)>([&](auto sc) {
-        fft_stage<T, N, DIR, C, NT, SN, SC, decltype(sc)::value>(buf, tw);
-    });
+    // all lanes of a wavefront run the same number of iterations
+    for (int c0 = 0; c0 < C; c0 += NT / G) {
+        const int c = c0 + threadIdx.x / G;
+        if (c < C) fft_col<T, N, DIR>(buf + c * SC, l, tw);
+    }
+    __syncthreads();
 }
 
 }  // namespace flusi

@@ -102,9 +102,11 @@ static int check_plan(flusi_plan p) {
     return FLUSI_OK;
 }
 static void free_plan(PlanData& d) {
-    void* ptrs[] = {d.tw, d.bufA, d.bufB, d.partial, d.partial2, d.counter, d.kin, d.pmax, d.spec, d.phys};
+    void* ptrs[] = {d.tw, d.bufA, d.bufB, d.partial, d.partial2, d.kin, d.ins_dev, d.pmax, d.spec, d.phys};
     for (void* q : ptrs)
         if (q) (void)hipFree(q);
+    for (hipEvent_t e : d.events) (void)hipEventDestroy(e);
+    d.events.clear();
     delete d.impl;
     d.impl = nullptr;
 }
@@ -152,14 +154,14 @@ int flusi_plan_create(int nx, int ny, int nz, double L, double nu, double eta, i
     ok = ok && hipMalloc(&d.bufB, d.szB) == hipSuccess;
     ok = ok && hipMalloc(&d.partial, (size_t)d.nwg_x * NV * sizeof(double)) == hipSuccess;
     ok = ok && hipMalloc(&d.partial2, (size_t)NRED_BLOCKS * NV * sizeof(double)) == hipSuccess;
-    ok = ok && hipMalloc(&d.counter, 256) == hipSuccess;
     ok = ok && hipMalloc(&d.kin, sizeof(Kin)) == hipSuccess;
+    ok = ok && hipMalloc(&d.ins_dev, sizeof(flusi_insect)) == hipSuccess;
     if (!ok) {
         free_plan(d);
         delete p;
         return set_error(FLUSI_ENOMEM, "device allocation for a %d^3 plan", nx);
     }
-    d.workspace = nx * cxb + d.szA + d.szB + (size_t)d.nwg_x * NV * 8 + NRED_BLOCKS * NV * 8 + 256 + sizeof(Kin);
+    d.workspace = nx * cxb + d.szA + d.szB + (size_t)d.nwg_x * NV * 8 + NRED_BLOCKS * NV * 8 + sizeof(Kin) + sizeof(flusi_insect);
     // FP64 twiddles exp(-2 pi i m / n); the FP32 table is rounded from them.
     std::vector<double> w(2 * nx);
     for (int m = 0; m < nx; ++m) {
@@ -176,7 +178,6 @@ int flusi_plan_create(int nx, int ny, int nz, double L, double nu, double eta, i
         for (int i = 0; i < 2 * nx; ++i) wf[i] = (float)w[i];
         e = hipMemcpy(d.tw, wf.data(), nx * cxb, hipMemcpyHostToDevice);
     }
-    if (e == hipSuccess) e = hipMemset(d.counter, 0, 256);
     if (e != hipSuccess) {
         free_plan(d);
         delete p;
@@ -266,8 +267,8 @@ int flusi_state_time(flusi_plan plan, const void* state, double* t, long long* n
     hipError_t e = hipMemcpyAsync(&h, state, sizeof(StateHdr), hipMemcpyDeviceToHost, plan->d.stream);
     if (e == hipSuccess) e = hipStreamSynchronize(plan->d.stream);
     if (e != hipSuccess) return set_error(FLUSI_EDEVICE, "state_time: %s", hipGetErrorString(e));
-    if (t) *t = h.t;
-    if (n) *n = h.n;
+    if (t) *t = h.slot[h.cur].t;
+    if (n) *n = h.slot[h.cur].n;
     return FLUSI_OK;
 }
 
@@ -290,6 +291,38 @@ int flusi_forces(flusi_plan plan, const void* state, double* out) {
     std::memcpy(out, h.diag, sizeof(h.diag));
     if (h.status == FLUSI_ENONFINITE) return set_error(FLUSI_ENONFINITE, "velocity became non-finite");
     if (h.status != 0) return set_error(h.status, "state stopped (status %d)", h.status);
+    return FLUSI_OK;
+}
+
+int flusi_profile(flusi_plan plan, int enable) {
+    if (int rc = check_plan(plan)) return rc;
+    PlanData& d = plan->d;
+    if (enable) {
+        d.prof_recs.clear();
+        d.ev_used = 0;
+    }
+    d.prof = enable != 0;
+    return FLUSI_OK;
+}
+
+int flusi_pass_times(flusi_plan plan, double* ms, long long* launches) {
+    if (int rc = check_plan(plan)) return rc;
+    PlanData& d = plan->d;
+    hipError_t e = hipStreamSynchronize(d.stream);
+    if (e != hipSuccess) return set_error(FLUSI_EDEVICE, "pass_times: %s", hipGetErrorString(e));
+    double acc[FLUSI_NPASS] = {0};
+    long long cnt[FLUSI_NPASS] = {0};
+    for (const auto& r : d.prof_recs) {
+        float t = 0.0f;
+        e = hipEventElapsedTime(&t, d.events[r.second], d.events[r.second + 1]);
+        if (e != hipSuccess) return set_error(FLUSI_EDEVICE, "pass_times: %s", hipGetErrorString(e));
+        acc[r.first] += t;
+        cnt[r.first] += 1;
+    }
+    for (int i = 0; i < FLUSI_NPASS; ++i) {
+        if (ms) ms[i] = acc[i];
+        if (launches) launches[i] = cnt[i];
+    }
     return FLUSI_OK;
 }
 

@@ -22,6 +22,8 @@ struct Kin {
     double r2all;      // squared radius (about xc) outside which chi == 0 exactly
     double thr;        // delta above which chi == 0 exactly
     double h;          // smoothing half width
+    double radius, ea, eb;       // sphere radius; ellipsoid semi-axes
+    double wA, wB, wt;           // elliptic wing: half chord, half span, thickness
     int body, wings, smooth, pad;
 };
 
@@ -96,6 +98,12 @@ __host__ __device__ inline void compute_kin(const flusi_insect& in, double t, do
     k.body = in.body;
     k.wings = in.wings;
     k.smooth = in.smooth;
+    k.radius = in.radius;
+    k.ea = in.a;
+    k.eb = in.b;
+    k.wA = in.wing_A;
+    k.wB = in.wing_B;
+    k.wt = in.wing_t;
     k.h = in.c_smth * dx;
     // chi is exactly 0 beyond delta = h (cosine) or delta = 20 h (tanh rounds to 1)
     k.thr = in.smooth == FLUSI_SMOOTH_TANH ? 20.0 * k.h : k.h;
@@ -147,76 +155,149 @@ __host__ __device__ inline void compute_kin(const flusi_insect& in, double t, do
     k.r2all = rall * rall;
 }
 
-__device__ __forceinline__ double chi_of(double delta, const Kin& k) {
-    if (k.smooth == FLUSI_SMOOTH_TANH) return 0.5 * (1.0 - tanh(delta / k.h));
-    if (delta <= -k.h) return 1.0;
-    if (delta >= k.h) return 0.0;
-    return 0.5 * (1.0 + cos(M_PI * (delta + k.h) / (2.0 * k.h)));
+// Copy of the kinematics in the precision the mask is evaluated in (FP64 for
+// the FP64 path; FP32 for the FP32 path, whose fields are FP32 anyway).
+template <typename TM>
+struct KinT {
+    TM Mb[9], xc[3], uc[3], omb[3], Mws[2][9], piv[2][3], omw[2][3], xref[3][3];
+    TM r2all, thr, h, radius, ea, eb, wA, wB, wt;
+    int body, wings, smooth, pad;
+};
+
+// FP32 tanh reaches 1 near 9.01 and FP64 tanh near 19.06: beyond these
+// multiples of h the tanh mask is exactly zero in that precision.
+template <typename TM>
+__device__ __forceinline__ TM tanh_cut() { return sizeof(TM) == 4 ? TM(10) : TM(20); }
+
+template <typename TM>
+__device__ inline void kin_cast(const Kin& a, KinT<TM>& b) {
+    for (int i = 0; i < 9; ++i) {
+        b.Mb[i] = TM(a.Mb[i]);
+        b.Mws[0][i] = TM(a.Mws[0][i]);
+        b.Mws[1][i] = TM(a.Mws[1][i]);
+    }
+    for (int i = 0; i < 3; ++i) {
+        b.xc[i] = TM(a.xc[i]); b.uc[i] = TM(a.uc[i]); b.omb[i] = TM(a.omb[i]);
+        for (int s = 0; s < 2; ++s) { b.piv[s][i] = TM(a.piv[s][i]); b.omw[s][i] = TM(a.omw[s][i]); }
+        for (int c = 0; c < 3; ++c) b.xref[c][i] = TM(a.xref[c][i]);
+    }
+    b.h = TM(a.h);
+    b.radius = TM(a.radius); b.ea = TM(a.ea); b.eb = TM(a.eb);
+    b.wA = TM(a.wA); b.wB = TM(a.wB); b.wt = TM(a.wt);
+    b.body = a.body; b.wings = a.wings; b.smooth = a.smooth; b.pad = 0;
+    // cull radius recomputed for the precision's own tanh cut-off
+    const double thr = a.smooth == FLUSI_SMOOTH_TANH ? (sizeof(TM) == 4 ? 10.0 : 20.0) * a.h : a.h;
+    b.thr = TM(thr);
+    double rall = 0.0;
+    if (a.body == FLUSI_BODY_SPHERE) rall = a.radius + thr;
+    if (a.body == FLUSI_BODY_ELLIPSOID) rall = 2.0 * (a.ea + a.eb) + thr;
+    if (a.wings) {
+        const double mab = fmax(a.wA, a.wB), e1 = mab + thr, e2 = 0.5 * a.wt + thr;
+        for (int s = 0; s < 2; ++s) {
+            const double pn = sqrt(a.piv[s][0] * a.piv[s][0] + a.piv[s][1] * a.piv[s][1] + a.piv[s][2] * a.piv[s][2]);
+            rall = fmax(rall, pn + a.wB + sqrt(e1 * e1 + e2 * e2));
+        }
+    }
+    // widen by a relative margin so the cull stays conservative after rounding
+    b.r2all = TM(rall * rall * (1.0 + 1e-5));
 }
 
+template <typename TM>
+__device__ __forceinline__ TM chi_of(TM delta, const KinT<TM>& k) {
+    if (k.smooth == FLUSI_SMOOTH_TANH) return TM(0.5) * (TM(1) - tanh(delta / k.h));
+    if (delta <= -k.h) return TM(1);
+    if (delta >= k.h) return TM(0);
+    return TM(0.5) * (TM(1) + cos(TM(M_PI) * (delta + k.h) / (TM(2) * k.h)));
+}
+
+template <typename TM>
 struct MaskPt {
-    double chi;
-    double us[3];
+    TM chi;
+    TM us[3];
     int colour;
 };
 
-// chi, u_s and colour at global point (x, y, z).
-__device__ __forceinline__ MaskPt eval_mask(const Kin& k, const flusi_insect& in, double x, double y, double z) {
-    MaskPt o;
-    o.chi = 0.0;
-    o.us[0] = o.us[1] = o.us[2] = 0.0;
+template <typename TM>
+__device__ __forceinline__ void mvec(const TM* A, const TM* v, TM* o) {
+    const TM a = A[0] * v[0] + A[1] * v[1] + A[2] * v[2];
+    const TM b = A[3] * v[0] + A[4] * v[1] + A[5] * v[2];
+    const TM c = A[6] * v[0] + A[7] * v[1] + A[8] * v[2];
+    o[0] = a; o[1] = b; o[2] = c;
+}
+template <typename TM>
+__device__ __forceinline__ void mtvec(const TM* A, const TM* v, TM* o) {
+    const TM a = A[0] * v[0] + A[3] * v[1] + A[6] * v[2];
+    const TM b = A[1] * v[0] + A[4] * v[1] + A[7] * v[2];
+    const TM c = A[2] * v[0] + A[5] * v[1] + A[8] * v[2];
+    o[0] = a; o[1] = b; o[2] = c;
+}
+template <typename TM>
+__device__ __forceinline__ void cross(const TM* a, const TM* b, TM* o) {
+    const TM x = a[1] * b[2] - a[2] * b[1];
+    const TM y = a[2] * b[0] - a[0] * b[2];
+    const TM z = a[0] * b[1] - a[1] * b[0];
+    o[0] = x; o[1] = y; o[2] = z;
+}
+
+// chi, u_s and colour at global point (x, y, z).  Reads only the kinematics
+// block (kept in LDS by the callers).
+template <typename TM>
+__device__ __forceinline__ MaskPt<TM> eval_mask(const KinT<TM>& k, TM x, TM y, TM z) {
+    MaskPt<TM> o;
+    o.chi = TM(0);
+    o.us[0] = o.us[1] = o.us[2] = TM(0);
     o.colour = 0;
-    const double rel[3] = {x - k.xc[0], y - k.xc[1], z - k.xc[2]};
-    const double r2 = rel[0] * rel[0] + rel[1] * rel[1] + rel[2] * rel[2];
+    const TM rel[3] = {x - k.xc[0], y - k.xc[1], z - k.xc[2]};
+    const TM r2 = rel[0] * rel[0] + rel[1] * rel[1] + rel[2] * rel[2];
     if (r2 > k.r2all) return o;
-    double xb[3];
-    mat_vec(k.Mb, rel, xb);
-    double best = 0.0;
+    TM xb[3];
+    mvec(k.Mb, rel, xb);
+    TM best = TM(0);
     int part = 0;
     if (k.body == FLUSI_BODY_SPHERE) {
-        best = chi_of(sqrt(r2) - in.radius, k);
+        best = chi_of(sqrt(r2) - k.radius, k);
     } else if (k.body == FLUSI_BODY_ELLIPSOID) {
-        const double q = xb[0] / in.a;
-        const double rad = sqrt(xb[1] * xb[1] + xb[2] * xb[2]);
-        const double d = fmax(rad - in.b * sqrt(fmax(0.0, 1.0 - q * q)), fabs(xb[0]) - in.a);
+        const TM q = xb[0] / k.ea;
+        const TM rad = sqrt(xb[1] * xb[1] + xb[2] * xb[2]);
+        const TM d = fmax(rad - k.eb * sqrt(fmax(TM(0), TM(1) - q * q)), fabs(xb[0]) - k.ea);
         best = chi_of(d, k);
     }
     if (k.wings) {
-        const double mab = fmax(in.wing_A, in.wing_B);
+        const TM mab = fmax(k.wA, k.wB);
         for (int s = 0; s < 2; ++s) {
-            const double d0[3] = {xb[0] - k.piv[s][0], xb[1] - k.piv[s][1], xb[2] - k.piv[s][2]};
-            double xw[3];
-            mat_vec(k.Mws[s], d0, xw);
-            const double dz = fabs(xw[2]) - 0.5 * in.wing_t;
-            const double ey = xw[1] - in.wing_B;
-            const double r = sqrt(xw[0] * xw[0] + ey * ey);
+            const TM d0[3] = {xb[0] - k.piv[s][0], xb[1] - k.piv[s][1], xb[2] - k.piv[s][2]};
+            TM xw[3];
+            mvec(k.Mws[s], d0, xw);
+            const TM dz = fabs(xw[2]) - TM(0.5) * k.wt;
+            const TM ey = xw[1] - k.wB;
+            const TM r = sqrt(xw[0] * xw[0] + ey * ey);
             if (dz >= k.thr || r - mab >= k.thr) continue;  // chi == 0 exactly
-            const double qa = xw[0] / in.wing_A, qb = ey / in.wing_B;
-            const double rho = sqrt(qa * qa + qb * qb);
-            const double inplane = r > 0.0 ? r - r / rho : -in.wing_A;
-            const double c = chi_of(fmax(dz, inplane), k);
+            const TM qa = xw[0] / k.wA, qb = ey / k.wB;
+            const TM rho = sqrt(qa * qa + qb * qb);
+            const TM inplane = r > TM(0) ? r - r / rho : -k.wA;
+            const TM c = chi_of(fmax(dz, inplane), k);
             if (c > best) {
                 best = c;
                 part = 1 + s;
             }
         }
     }
-    if (best <= 0.0) return o;
+    if (best <= TM(0)) return o;
     o.chi = best;
     o.colour = part + 1;
     // u_b = u_cntr + Mb^T (omb x x_b)
-    double cr[3], ub[3];
-    cross3(k.omb, xb, cr);
-    mat_tvec(k.Mb, cr, ub);
+    TM cr[3], ub[3];
+    cross(k.omb, xb, cr);
+    mtvec(k.Mb, cr, ub);
     for (int i = 0; i < 3; ++i) ub[i] += k.uc[i];
     if (part == 0) {
         o.us[0] = ub[0]; o.us[1] = ub[1]; o.us[2] = ub[2];
     } else {
         const int s = part - 1;
-        const double d0[3] = {xb[0] - k.piv[s][0], xb[1] - k.piv[s][1], xb[2] - k.piv[s][2]};
-        double uw[3];
-        cross3(k.omw[s], d0, cr);
-        mat_tvec(k.Mb, cr, uw);
+        const TM d0[3] = {xb[0] - k.piv[s][0], xb[1] - k.piv[s][1], xb[2] - k.piv[s][2]};
+        TM uw[3];
+        cross(k.omw[s], d0, cr);
+        mtvec(k.Mb, cr, uw);
         o.us[0] = uw[0] + ub[0]; o.us[1] = uw[1] + ub[1]; o.us[2] = uw[2] + ub[2];
     }
     return o;

@@ -21,43 +21,74 @@
 
 namespace flusi {
 
-constexpr int NT = 256;   // threads per workgroup of every pass
+constexpr int NT = 256;   // threads per workgroup of the y passes and the x-pass
 constexpr int NV = 39;    // reduction values per workgroup (see xpass)
 constexpr int NRED_BLOCKS = 64;
 
-// Columns per workgroup of the column passes: C*N ~ 4096 elements in LDS.
+// Columns per workgroup of the y passes: C*N ~ 4096 elements in LDS.
 __host__ __device__ constexpr int cols_of(int N) {
     int c = 4096 / N, p = 8;
     while (p * 2 <= c) p *= 2;
     return p;
 }
+// Columns and threads per workgroup of the z-pass (more, narrower workgroups:
+// the z-pass has only (2K+1)(K+1) columns).
+__host__ __device__ constexpr int cols_z(int N) { return N <= 24 ? 16 : 8; }
+__host__ __device__ constexpr int nt_z(int N) { return N <= 192 ? 128 : 256; }
 // Rows per workgroup of the x-pass (even): 3*RW*N ~ 3072 elements in LDS.
 __host__ __device__ constexpr int rows_x(int N) {
     int c = 1024 / N, p = 2;
     while (p * 2 <= c) p *= 2;
     return p;
 }
+__host__ __device__ constexpr int round_up(int a, int b) { return (a + b - 1) / b * b; }
+
+// Pruned-spectrum geometry.  Row pitches are padded to 128 bytes so that every
+// row of a pass starts on a cache line.
+template <typename T, int N>
+struct Geo {
+    static constexpr int K = kmax_of(N), KP = K + 1, M = 2 * K + 1, Q = M * KP;
+    static constexpr int AL = 128 / (int)sizeof(cx<T>);
+    static constexpr int KPp = round_up(KP, AL);  // pitch of [z][y][kx] rows
+    static constexpr int Qp = round_up(Q, AL);    // pitch of [z][ky'][kx] planes
+};
+
+// Workgroups are dispatched round-robin over the 8 XCDs (each with its own
+// L2).  Remap so that consecutive logical tiles, which share cache lines, run
+// on the same XCD.
+__device__ __forceinline__ int xcd_tile(int bid, int nb) {
+    const int x = bid & 7, s = bid >> 3;
+    const int per = nb >> 3, rem = nb & 7;
+    return x < rem ? x * (per + 1) + s : rem * (per + 1) + (x - rem) * per + s;
+}
 
 struct StepCtl {
     double dt_fixed, cfl, dt_max, eta_cap, t_end;
-    int masked, mean_mode;
+    int masked, mean_mode, kin_dynamic, pad;
 };
 
-// Device-resident per-state scalars (first 4 KiB of a state buffer).
-struct StateHdr {
-    double t;        // time of the current coefficients
+// Per-time-level scalars of a state.
+struct Slot {
+    double t;        // time of the coefficients
     double dt_prev;  // previous step size
     long long n;     // steps taken
     int have_prev;   // previous right-hand side stored
-    int status;      // 0 or FLUSI_ENONFINITE / FLUSI_EINVAL
     int have_I;      // previous solid-momentum integral stored
-    int active;      // coefficient block below is valid for this step
-    int first;       // this step is the first (Euler) step
-    int pad0;
-    double dt, dtp, b1, b2;  // coefficients of the current update
     double I_prev[3][6];
+};
+
+// Device-resident per-state scalars (first 4 KiB of a state buffer).  The time
+// level is double-buffered: during a step every workgroup reads slot[p] and a
+// single thread writes the next level into slot[1-p], so readers and the
+// writer never touch the same bytes.  `cur` names the current slot between
+// steps.
+struct StateHdr {
+    int status;      // 0, FLUSI_ENONFINITE or FLUSI_EINVAL
+    int cur;
+    int pad[2];
+    Slot slot[2];
     double diag[FLUSI_NDIAG];
-    Kin kin;         // kinematics at time t
+    Kin kin;         // kinematics at the current time level
 };
 static_assert(sizeof(StateHdr) <= 4096, "state header too large");
 constexpr size_t STATE_HDR_BYTES = 4096;
@@ -68,42 +99,82 @@ constexpr size_t STATE_HDR_BYTES = 4096;
 // the column sits at stride s.  PIN: the input holds only the 2K+1 kept
 // signed modes (pruned storage); POUT: only those are written.
 // ---------------------------------------------------------------------------
-template <typename T, int N, int DIR, bool PIN, bool POUT>
-__global__ __launch_bounds__(NT) void k_colfft(const cx<T>* in, cx<T>* out, int K, int Q, int KX,
+// Extra work carried by a column launch (kinds: 0 none, 1 first-level
+// reduction of the x-pass partial sums, 2 kinematics of time level p).
+struct ColExtra {
+    const double* partial;
+    double* partial2;
+    int nwg;
+    int p;
+    struct StateHdr* hdr;
+    const flusi_insect* ins;
+    double dx;
+};
+
+template <int NVAL>
+__device__ __forceinline__ void block_reduce_store(const double (&acc)[NVAL], double (*red)[NV], double* out);
+__device__ inline void reduce_level1(const double* __restrict__ partial, int nwg, double* __restrict__ partial2,
+                                     int b, double (*red)[NV]);
+__device__ inline void run_kin_extra(const ColExtra& ex);
+
+template <typename T, int N, int DIR, bool PIN, bool POUT, int EXTRA>
+__global__ __launch_bounds__(NT) void k_colfft(const cx<T>* in, cx<T>* out, int Q, int KX,
                                                long blk_in, long s_in, long blk_out, long s_out,
                                                long fs_in, long fs_out, const cx<T>* __restrict__ tw,
-                                               const int* status) {
+                                               const int* status, int nbx, int nf, ColExtra ex) {
     constexpr int C = cols_of(N);
-    static_assert(NT % C == 0 || C % NT == 0, "column mapping");
-    __shared__ cx<T> buf[C * N];
+    constexpr int K = kmax_of(N);
+    constexpr int SC = cm_stride(N);
+    constexpr int RS = NT / C;      // rows handled per sweep
+    constexpr int RPT = N / RS;     // rows per thread
+    static_assert(NT % C == 0 && N % RS == 0, "column mapping");
+    __shared__ cx<T> buf[C * SC];
     if (status && *status) return;
+    const int tile = xcd_tile(blockIdx.x, gridDim.x);
+    const int f = tile / nbx;
+    if (f >= nf) {
+        if constexpr (EXTRA == 1) {
+            __shared__ double red[NT / 64][NV];
+            if (tile - nf * nbx < NRED_BLOCKS) reduce_level1(ex.partial, ex.nwg, ex.partial2, tile - nf * nbx, red);
+        } else if constexpr (EXTRA == 2) {
+            if (tile == nf * nbx && threadIdx.x == 0) run_kin_extra(ex);
+        }
+        return;
+    }
     const int tid = threadIdx.x;
-    const int f = blockIdx.y;
     in += f * fs_in;
     out += f * fs_out;
-    const int c = tid % C;
-    const int q = blockIdx.x * C + c;
+    const int c = tid % C, r0 = tid / C;
+    const int q = (tile % nbx) * C + c;
     const bool ok = q < Q;
     const long bin = ok ? (long)(q / KX) * blk_in + q % KX : 0;
     const long bout = ok ? (long)(q / KX) * blk_out + q % KX : 0;
-    for (int n = tid / C; n < N; n += NT / C) {
-        cx<T> v = {T(0), T(0)};
+    cx<T> v[RPT];
+#pragma unroll
+    for (int i = 0; i < RPT; ++i) {
+        const int n = r0 + i * RS;
+        v[i] = cx<T>{T(0), T(0)};
         if (ok) {
             if constexpr (PIN) {
                 const int m = m_of_bin(n, N, K);
-                if (m >= 0) v = in[bin + m * s_in];
+                if (m >= 0) v[i] = in[bin + m * s_in];
             } else {
-                v = in[bin + n * s_in];
+                v[i] = in[bin + n * s_in];
             }
         }
-        buf[n * C + c] = v;
     }
-    fft_lds<T, N, DIR, C, NT, C, 1>(buf, tw);
-    const int nout = POUT ? 2 * K + 1 : N;
+#pragma unroll
+    for (int i = 0; i < RPT; ++i) buf[c * SC + cpad(r0 + i * RS)] = v[i];
+    fft_cols<T, N, DIR, C, NT, SC>(buf, tw);
     if (ok) {
-        for (int o = tid / C; o < nout; o += NT / C) {
-            const int n = POUT ? bin_of_m(o, N, K) : o;
-            out[bout + o * s_out] = buf[n * C + c];
+        constexpr int NOUT = POUT ? 2 * K + 1 : N;
+#pragma unroll
+        for (int i = 0; i < (NOUT + RS - 1) / RS; ++i) {
+            const int o = r0 + i * RS;
+            if (o < NOUT) {
+                const int n = POUT ? bin_of_m(o, N, K) : o;
+                out[bout + o * s_out] = buf[c * SC + cpad(n)];
+            }
         }
     }
 }
@@ -111,13 +182,36 @@ __global__ __launch_bounds__(NT) void k_colfft(const cx<T>* in, cx<T>* out, int 
 // ---------------------------------------------------------------------------
 // Deterministic workgroup reductions
 // ---------------------------------------------------------------------------
-__device__ __forceinline__ double wave_sum(double v) {
-    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+// Wave-wide FP64 reductions with DPP lane moves (no LDS traffic).  The result
+// is complete in lane 63; lanes whose DPP source is out of range add 0, which
+// is the identity for the sums and for the maxima of non-negative values used
+// here.  The combination order is fixed, so results are deterministic.
+template <int CTRL, int ROWM, int BANKM>
+__device__ __forceinline__ double dpp_move(double v) {
+    const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), CTRL, ROWM, BANKM, false);
+    const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), CTRL, ROWM, BANKM, false);
+    return __hiloint2double(hi, lo);
+}
+template <bool MAX>
+__device__ __forceinline__ double wave_reduce63(double v) {
+    auto op = [](double a, double b) { return MAX ? fmax(a, b) : a + b; };
+    v = op(v, dpp_move<0xb1, 0xf, 0xf>(v));   // quad_perm [1,0,3,2]
+    v = op(v, dpp_move<0x4e, 0xf, 0xf>(v));   // quad_perm [2,3,0,1]
+    v = op(v, dpp_move<0x114, 0xf, 0xe>(v));  // row_shr:4
+    v = op(v, dpp_move<0x118, 0xf, 0xc>(v));  // row_shr:8
+    v = op(v, dpp_move<0x142, 0xa, 0xf>(v));  // row_bcast:15
+    v = op(v, dpp_move<0x143, 0xc, 0xf>(v));  // row_bcast:31
     return v;
 }
+__device__ __forceinline__ double wave_sum(double v) {
+    v = wave_reduce63<false>(v);
+    return __hiloint2double(__builtin_amdgcn_readlane(__double2hiint(v), 63),
+                            __builtin_amdgcn_readlane(__double2loint(v), 63));
+}
 __device__ __forceinline__ double wave_max(double v) {
-    for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o, 64));
-    return v;
+    v = wave_reduce63<true>(v);
+    return __hiloint2double(__builtin_amdgcn_readlane(__double2hiint(v), 63),
+                            __builtin_amdgcn_readlane(__double2loint(v), 63));
 }
 
 // Reduce NV per-thread values (value 0 and 2 by max, the rest by sum) over the
@@ -127,7 +221,8 @@ __device__ __forceinline__ void block_reduce_store(const double (&acc)[NVAL], do
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
 #pragma unroll
     for (int v = 0; v < NVAL; ++v) {
-        const double r = (v == 0 || v == 2) ? wave_max(acc[v]) : wave_sum(acc[v]);
+        double r = 0.0;
+        if (__any(acc[v] != 0.0)) r = (v == 0 || v == 2) ? wave_max(acc[v]) : wave_sum(acc[v]);
         if (lane == 0) red[wv][v] = r;
     }
     __syncthreads();
@@ -155,123 +250,144 @@ __device__ __forceinline__ void block_reduce_store(const double (&acc)[NVAL], do
 template <typename T, int N, int NC>
 __global__ __launch_bounds__(NT) void k_xpass(const cx<T>* __restrict__ yin, cx<T>* __restrict__ xout,
                                               long fs_in, long fs_out, const cx<T>* __restrict__ tw,
-                                              const StateHdr* __restrict__ hdr, flusi_insect ins, double dx,
+                                              const StateHdr* __restrict__ hdr, double dx,
                                               double inv_eta, double* __restrict__ partial) {
-    constexpr int K = kmax_of(N), KP = K + 1;
+    using G = Geo<T, N>;
+    constexpr int K = G::K, KP = G::KP, KPp = G::KPp;
     constexpr int RW = rows_x(N);
-    constexpr int SC = N + 1;
+    constexpr int SC = cm_stride(N);
     constexpr int CI = 3 * RW, CF = 3 * RW / 2;
     constexpr int NVAL = 3 + 12 * NC;
-    constexpr int PP = (RW * N + NT - 1) / NT;
-    __shared__ cx<T> buf[CI * SC];
+
+    constexpr int LP = (RW * KP + NT - 1) / NT;
+    // inverse columns [0, CI), forward columns [CI, CI + CF)
+    __shared__ cx<T> buf[(CI + CF) * SC];
+    cx<T>* fbuf = buf + CI * SC;
     __shared__ double red[NT / 64][NV];
-    __shared__ Kin kin;
+    __shared__ KinT<T> kin;
     if (hdr->status) return;
     const int tid = threadIdx.x;
     const int row0 = blockIdx.x * RW;
     if constexpr (NC > 0) {
-        if (tid == 0) kin = hdr->kin;
+        if (tid == 0) kin_cast<T>(hdr->kin, kin);
     }
 
     // 1. pack three Hermitian pairs per row: Z = X + iY over the full x axis
-    for (int idx = tid; idx < CI * (N - 2 * K - 1); idx += NT) {
-        const int c = idx / (N - 2 * K - 1), n = K + 1 + idx % (N - 2 * K - 1);
-        buf[c * SC + n] = cx<T>{T(0), T(0)};
-    }
+    cx<T> la[3][LP], lb[3][LP];
 #pragma unroll
     for (int p = 0; p < 3; ++p) {
-        const cx<T>* A = yin + (2 * p) * fs_in + (long)row0 * KP;
-        const cx<T>* B = yin + (2 * p + 1) * fs_in + (long)row0 * KP;
-        for (int idx = tid; idx < RW * KP; idx += NT) {
-            const int r = idx / KP, k = idx % KP;
-            const cx<T> a = A[idx], b = B[idx];
-            cx<T>* col = buf + (3 * r + p) * SC;
-            if (k == 0) {
-                col[0] = cx<T>{a.x, b.x};
-            } else {
-                col[k] = cx<T>{a.x - b.y, a.y + b.x};
-                col[N - k] = cx<T>{a.x + b.y, b.x - a.y};
+        const cx<T>* A = yin + (2 * p) * fs_in + (long)row0 * KPp;
+        const cx<T>* B = yin + (2 * p + 1) * fs_in + (long)row0 * KPp;
+#pragma unroll
+        for (int i = 0; i < LP; ++i) {
+            const int idx = tid + i * NT;
+            if (idx < RW * KP) {
+                const int r = idx / KP, k = idx % KP;
+                la[p][i] = A[r * KPp + k];
+                lb[p][i] = B[r * KPp + k];
             }
         }
     }
-    fft_lds<T, N, +1, CI, NT, 1, SC>(buf, tw);
+    for (int idx = tid; idx < CI * (N - 2 * K - 1); idx += NT) {
+        const int c = idx / (N - 2 * K - 1), n = K + 1 + idx % (N - 2 * K - 1);
+        buf[lds_at<true, 1, SC>(n, c)] = cx<T>{T(0), T(0)};
+    }
+#pragma unroll
+    for (int p = 0; p < 3; ++p) {
+#pragma unroll
+        for (int i = 0; i < LP; ++i) {
+            const int idx = tid + i * NT;
+            if (idx < RW * KP) {
+                const int r = idx / KP, k = idx % KP;
+                const cx<T> a = la[p][i], b = lb[p][i];
+                const int cc = 3 * r + p;
+                if (k == 0) {
+                    buf[lds_at<true, 1, SC>(0, cc)] = cx<T>{a.x, b.x};
+                } else {
+                    buf[lds_at<true, 1, SC>(k, cc)] = cx<T>{a.x - b.y, a.y + b.x};
+                    buf[lds_at<true, 1, SC>(N - k, cc)] = cx<T>{a.x + b.y, b.x - a.y};
+                }
+            }
+        }
+    }
+    fft_cols<T, N, +1, CI, NT, SC>(buf, tw);
 
-    // 2. pointwise source and partial sums
+    // 2. pointwise source and partial sums, one point per iteration (the mask
+    //    code is large; a rolled loop keeps the register count down).  The
+    //    forward input goes to separate columns: column r holds (Nx, Ny) of row
+    //    r, column RW + r/2 holds Nz of rows (2q, 2q+1).
     double acc[NVAL];
 #pragma unroll
     for (int v = 0; v < NVAL; ++v) acc[v] = 0.0;
     const T s = T(1.0 / ((double)N * (double)N * (double)N));
-    T res[PP][3];
+#pragma unroll 1
+    for (int idx = tid; idx < RW * N; idx += NT) {
+        // keep the kinematics block in LDS: without this compiler barrier the
+        // ~60 loop-invariant FP64 values would be hoisted into registers
+        __asm__ volatile("" ::: "memory");
+        const int r = idx / N, i = idx % N;
+        const int row = row0 + r;
+        const cx<T> z0 = buf[lds_at<true, 1, SC>(i, 3 * r)];
+        const cx<T> z1 = buf[lds_at<true, 1, SC>(i, 3 * r + 1)];
+        const cx<T> z2 = buf[lds_at<true, 1, SC>(i, 3 * r + 2)];
+        const T ux = z0.x * s, uy = z0.y * s, uz = z1.x * s;
+        const T wx = z1.y * s, wy = z2.x * s, wz = z2.y * s;
+        T nx = uy * wz - uz * wy;
+        T ny = uz * wx - ux * wz;
+        T nz = ux * wy - uy * wx;
+        const double u2 = (double)ux * ux + (double)uy * uy + (double)uz * uz;
+        acc[0] = fmax(acc[0], u2);
+        acc[1] += u2;
+        if (!isfinite(u2)) acc[2] = 1.0;
+        if constexpr (NC > 0) {
+            const T xg = T(dx * i), yg = T(dx * (row % N)), zg = T(dx * (row / N));
+            const MaskPt<T> mp = eval_mask<T>(kin, xg, yg, zg);
+            if (mp.chi > T(0)) {
+                const T pen = mp.chi * T(inv_eta);
+                nx -= pen * (ux - mp.us[0]);
+                ny -= pen * (uy - mp.us[1]);
+                nz -= pen * (uz - mp.us[2]);
+                // FP64 partial sums from the working-precision mask values
+                const double ch = mp.chi, s0 = mp.us[0], s1 = mp.us[1], s2 = mp.us[2];
+                const double p0 = ch * ((double)ux - s0);
+                const double p1 = ch * ((double)uy - s1);
+                const double p2 = ch * ((double)uz - s2);
+                const double i0 = ch * s0, i1 = ch * s1, i2 = ch * s2;
+                // moments about the reference point of this part's colour; every
+                // accumulator index stays static (selects, no pointer into acc)
+                const int ci = mp.colour - 1;
+                const double xr0 = ci == 0 ? kin.xref[0][0] : (ci == 1 ? kin.xref[1][0] : kin.xref[2][0]);
+                const double xr1 = ci == 0 ? kin.xref[0][1] : (ci == 1 ? kin.xref[1][1] : kin.xref[2][1]);
+                const double xr2 = ci == 0 ? kin.xref[0][2] : (ci == 1 ? kin.xref[1][2] : kin.xref[2][2]);
+                const double rx = (double)xg - xr0, ry = (double)yg - xr1, rz = (double)zg - xr2;
+                const double val[12] = {p0, p1, p2,
+                                        ry * p2 - rz * p1, rz * p0 - rx * p2, rx * p1 - ry * p0,
+                                        i0, i1, i2,
+                                        ry * i2 - rz * i1, rz * i0 - rx * i2, rx * i1 - ry * i0};
+                static_for<NC>([&](auto cc) {
+                    constexpr int col = decltype(cc)::value;
+                    const bool mine = (NC == 1) || (ci == col);
 #pragma unroll
-    for (int j = 0; j < PP; ++j) {
-        const int idx = tid + j * NT;
-        if (idx < RW * N) {
-            const int r = idx / N, i = idx % N;
-            const int row = row0 + r;
-            const cx<T> z0 = buf[(3 * r) * SC + i], z1 = buf[(3 * r + 1) * SC + i], z2 = buf[(3 * r + 2) * SC + i];
-            const T ux = z0.x * s, uy = z0.y * s, uz = z1.x * s;
-            const T wx = z1.y * s, wy = z2.x * s, wz = z2.y * s;
-            T nx = uy * wz - uz * wy;
-            T ny = uz * wx - ux * wz;
-            T nz = ux * wy - uy * wx;
-            const double u2 = (double)ux * ux + (double)uy * uy + (double)uz * uz;
-            acc[0] = fmax(acc[0], u2);
-            acc[1] += u2;
-            if (!isfinite(u2)) acc[2] = 1.0;
-            if constexpr (NC > 0) {
-                const double xg = dx * i, yg = dx * (row % N), zg = dx * (row / N);
-                const MaskPt mp = eval_mask(kin, ins, xg, yg, zg);
-                if (mp.chi > 0.0) {
-                    const T pen = T(mp.chi * inv_eta);
-                    nx -= pen * (ux - T(mp.us[0]));
-                    ny -= pen * (uy - T(mp.us[1]));
-                    nz -= pen * (uz - T(mp.us[2]));
-                    const double p0 = mp.chi * ((double)ux - mp.us[0]);
-                    const double p1 = mp.chi * ((double)uy - mp.us[1]);
-                    const double p2 = mp.chi * ((double)uz - mp.us[2]);
-                    const double i0 = mp.chi * mp.us[0], i1 = mp.chi * mp.us[1], i2 = mp.chi * mp.us[2];
-                    static_for<NC>([&](auto cc) {
-                        constexpr int col = decltype(cc)::value;
-                        if (mp.colour == col + 1) {
-                            const double rx = xg - kin.xref[col][0], ry = yg - kin.xref[col][1], rz = zg - kin.xref[col][2];
-                            double* a = acc + 3 + 12 * col;
-                            a[0] += p0; a[1] += p1; a[2] += p2;
-                            a[3] += ry * p2 - rz * p1; a[4] += rz * p0 - rx * p2; a[5] += rx * p1 - ry * p0;
-                            a[6] += i0; a[7] += i1; a[8] += i2;
-                            a[9] += ry * i2 - rz * i1; a[10] += rz * i0 - rx * i2; a[11] += rx * i1 - ry * i0;
-                        }
-                    });
-                }
+                    for (int e = 0; e < 12; ++e) acc[3 + 12 * col + e] += mine ? val[e] : 0.0;
+                });
             }
-            res[j][0] = nx;
-            res[j][1] = ny;
-            res[j][2] = nz;
         }
+        fbuf[lds_at<true, 1, SC>(i, r)] = cx<T>{nx, ny};
+        reinterpret_cast<T*>(fbuf + lds_at<true, 1, SC>(i, RW + r / 2))[r & 1] = nz;
     }
-    __syncthreads();
-    // forward input: column r holds (Nx, Ny) of row r; column RW + r/2 holds Nz of rows (2q, 2q+1)
-#pragma unroll
-    for (int j = 0; j < PP; ++j) {
-        const int idx = tid + j * NT;
-        if (idx < RW * N) {
-            const int r = idx / N, i = idx % N;
-            buf[r * SC + i] = cx<T>{res[j][0], res[j][1]};
-            T* zc = reinterpret_cast<T*>(buf + (RW + r / 2) * SC + i);
-            zc[r & 1] = res[j][2];
-        }
-    }
-    fft_lds<T, N, -1, CF, NT, 1, SC>(buf, tw);
+    block_reduce_store<NVAL>(acc, red, partial + (long)blockIdx.x * NV);
+    fft_cols<T, N, -1, CF, NT, SC>(fbuf, tw);
 
     // 3. split the packed spectra and store kx = 0..K
 #pragma unroll
     for (int f = 0; f < 3; ++f) {
-        cx<T>* O = xout + f * fs_out + (long)row0 * KP;
+        cx<T>* O = xout + f * fs_out + (long)row0 * KPp;
         for (int idx = tid; idx < RW * KP; idx += NT) {
             const int r = idx / KP, k = idx % KP;
             const int colx = (f < 2) ? r : RW + r / 2;
             const bool second = (f == 1) || (f == 2 && (r & 1));
-            const cx<T> zk = buf[colx * SC + k];
-            const cx<T> zm = buf[colx * SC + ((N - k) % N)];
+            const cx<T> zk = fbuf[lds_at<true, 1, SC>(k, colx)];
+            const cx<T> zm = fbuf[lds_at<true, 1, SC>((N - k) % N, colx)];
             cx<T> v;
             if (!second) {
                 v = cx<T>{T(0.5) * (zk.x + zm.x), T(0.5) * (zk.y - zm.y)};
@@ -279,138 +395,171 @@ __global__ __launch_bounds__(NT) void k_xpass(const cx<T>* __restrict__ yin, cx<
                 const T dxr = zk.x - zm.x, dyi = zk.y + zm.y;  // zk - conj(zm)
                 v = cx<T>{T(0.5) * dyi, T(-0.5) * dxr};
             }
-            O[idx] = v;
+            O[r * KPp + k] = v;
         }
     }
-    block_reduce_store<NVAL>(acc, red, partial + (long)blockIdx.x * NV);
 }
 
 // ---------------------------------------------------------------------------
-// Scalar step: reduction of the x-pass partial sums (two fixed-order levels,
-// the last workgroup to finish does the second level), then dt, force,
-// torque, energy, AB2 weights, time advance and the kinematics of the new
-// time level.
+// Scalar work of a step.  The x-pass leaves NV partial sums per workgroup;
+// NRED_BLOCKS extra workgroups of the y-forward launch reduce fixed
+// contiguous chunks of them (first level); every z-pass workgroup reduces the
+// NRED_BLOCKS results in a fixed order (second level) and derives dt and the
+// AB2 weights itself, so all workgroups agree bit for bit.  Workgroup 0 of the
+// z-pass then writes the diagnostics and the next time level.
 // ---------------------------------------------------------------------------
-__device__ inline void finish_step(const double* tot, StateHdr* h, const flusi_insect& ins, const StepCtl& ctl,
-                                   double dx, double eta, double* history) {
+struct Coef {
+    double dt, dtp, b1, b2;
+    double umax, E;
+    int first, active, bad, pad;
+};
+
+__device__ inline Coef step_coef(const double* tot, const Slot& sl, StepCtl ctl, double dx, double eta) {
+    Coef c{};
     const double dV = dx * dx * dx;
-    const double umax = sqrt(tot[0]);
-    const double E = 0.5 * tot[1] * dV;
-    if (tot[2] != 0.0 || !isfinite(E) || !isfinite(umax)) {
-        h->status = FLUSI_ENONFINITE;
-        h->active = 0;
-        return;
+    c.umax = sqrt(tot[0]);
+    c.E = 0.5 * tot[1] * dV;
+    if (tot[2] != 0.0 || !isfinite(c.E) || !isfinite(c.umax)) {
+        c.bad = FLUSI_ENONFINITE;
+        return c;
     }
-    const double t = h->t;
     double dt;
     if (ctl.dt_fixed > 0.0) {
         dt = ctl.dt_fixed;
     } else {
-        dt = umax > 0.0 ? ctl.cfl * dx / umax : INFINITY;
+        dt = c.umax > 0.0 ? ctl.cfl * dx / c.umax : INFINITY;
         if (ctl.masked) dt = fmin(dt, ctl.eta_cap * eta);
         if (ctl.dt_max > 0.0) dt = fmin(dt, ctl.dt_max);
     }
-    if (ctl.t_end > 0.0 && t + dt > ctl.t_end) dt = ctl.t_end - t;
+    if (ctl.t_end > 0.0 && sl.t + dt > ctl.t_end) dt = ctl.t_end - sl.t;
     if (!isfinite(dt)) {
-        h->status = FLUSI_EINVAL;
-        h->active = 0;
-        return;
+        c.bad = FLUSI_EINVAL;
+        return c;
     }
-    double* d = h->diag;
-    d[0] = t;
-    d[1] = dt;
-    d[2] = umax;
-    d[3] = E;
-    for (int c = 0; c < 3; ++c) {
-        const double* a = tot + 3 + 12 * c;
-        for (int i = 0; i < 6; ++i) {
-            double v = a[i] * dV / eta;
-            if (h->have_I && h->dt_prev > 0.0) v += (a[6 + i] * dV - h->I_prev[c][i]) / h->dt_prev;
-            d[4 + 6 * c + i] = v;
-        }
-    }
-    if (history)
-        for (int i = 0; i < FLUSI_NDIAG; ++i) history[i] = d[i];
-    if (!(dt > 0.0)) {  // end time reached: leave the state as it is
-        h->active = 0;
-        return;
-    }
-    h->active = 1;
-    h->first = h->have_prev ? 0 : 1;
-    h->dt = dt;
-    h->dtp = h->dt_prev;
-    if (h->have_prev) {
-        const double r = dt / h->dt_prev;
-        h->b1 = 1.0 + 0.5 * r;
-        h->b2 = -0.5 * r;
+    c.dt = dt;
+    c.active = dt > 0.0;  // end time reached: leave the state as it is
+    c.first = sl.have_prev ? 0 : 1;
+    c.dtp = sl.dt_prev;
+    if (sl.have_prev) {
+        const double r = dt / sl.dt_prev;
+        c.b1 = 1.0 + 0.5 * r;
+        c.b2 = -0.5 * r;
     } else {
-        h->b1 = 1.0;
-        h->b2 = 0.0;
+        c.b1 = 1.0;
+        c.b2 = 0.0;
     }
-    if (ctl.masked) {
-        for (int c = 0; c < 3; ++c)
-            for (int i = 0; i < 6; ++i) h->I_prev[c][i] = tot[3 + 12 * c + 6 + i] * dV;
-        h->have_I = 1;
-    }
-    h->have_prev = 1;
-    h->dt_prev = dt;
-    h->t = t + dt;
-    h->n += 1;
-    if (ctl.masked) compute_kin(ins, h->t, dx, h->kin);
+    return c;
 }
 
-static __global__ __launch_bounds__(NT) void k_scalar(const double* __restrict__ partial, int nwg, double* partial2,
-                                               unsigned* counter, StateHdr* hdr, flusi_insect ins, StepCtl ctl,
-                                               double dx, double eta, double* history) {
-    __shared__ double red[NT / 64][NV];
-    __shared__ double tot[NV];
-    __shared__ unsigned ticket;
-    if (hdr->status) return;
+// Diagnostics of time level p and the next time level (one thread).
+__device__ inline void write_step(StateHdr* h, int p, const double* tot, const Coef& c, StepCtl ctl, double dx,
+                                  double eta, double* history) {
+    const Slot& sl = h->slot[p];
+    Slot& nx = h->slot[1 - p];
+    if (c.bad) {
+        h->status = c.bad;
+        return;
+    }
+    const double dV = dx * dx * dx;
+    double d[FLUSI_NDIAG];
+    d[0] = sl.t;
+    d[1] = c.dt;
+    d[2] = c.umax;
+    d[3] = c.E;
+    for (int k = 0; k < 3; ++k) {
+        const double* a = tot + 3 + 12 * k;
+        for (int i = 0; i < 6; ++i) {
+            double v = a[i] * dV / eta;
+            if (sl.have_I && sl.dt_prev > 0.0) v += (a[6 + i] * dV - sl.I_prev[k][i]) / sl.dt_prev;
+            d[4 + 6 * k + i] = v;
+        }
+    }
+    for (int i = 0; i < FLUSI_NDIAG; ++i) h->diag[i] = d[i];
+    if (history)
+        for (int i = 0; i < FLUSI_NDIAG; ++i) history[i] = d[i];
+    nx = sl;
+    if (c.active) {
+        if (ctl.masked) {
+            for (int k = 0; k < 3; ++k)
+                for (int i = 0; i < 6; ++i) nx.I_prev[k][i] = tot[3 + 12 * k + 6 + i] * dV;
+            nx.have_I = 1;
+        }
+        nx.have_prev = 1;
+        nx.dt_prev = c.dt;
+        nx.t = sl.t + c.dt;
+        nx.n = sl.n + 1;
+    }
+    h->cur = 1 - p;
+}
+
+// First level: workgroup b (< NRED_BLOCKS) reduces records [b*chunk, (b+1)*chunk).
+__device__ inline void reduce_level1(const double* __restrict__ partial, int nwg, double* __restrict__ partial2,
+                                     int b, double (*red)[NV]) {
     const int tid = threadIdx.x;
     const int chunk = (nwg + NRED_BLOCKS - 1) / NRED_BLOCKS;
-    const int lo = blockIdx.x * chunk, hi = min(nwg, lo + chunk);
+    const int lo = b * chunk, hi = min(nwg, lo + chunk);
     double acc[NV];
 #pragma unroll
     for (int v = 0; v < NV; ++v) acc[v] = 0.0;
     for (int w = lo + tid; w < hi; w += NT) {
-        const double* p = partial + (long)w * NV;
+        const double* q = partial + (long)w * NV;
 #pragma unroll
-        for (int v = 0; v < NV; ++v) acc[v] = (v == 0 || v == 2) ? fmax(acc[v], p[v]) : acc[v] + p[v];
+        for (int v = 0; v < NV; ++v) acc[v] = (v == 0 || v == 2) ? fmax(acc[v], q[v]) : acc[v] + q[v];
     }
-    block_reduce_store<NV>(acc, red, partial2 + (long)blockIdx.x * NV);
-    __threadfence();
+    block_reduce_store<NV>(acc, red, partial2 + (long)b * NV);
+}
+
+// Second level (whole workgroup, NTH threads): totals of the NRED_BLOCKS records.
+template <int NTH>
+__device__ inline void reduce_level2(const double* __restrict__ partial2, double* p2s, double* tot) {
+    const int tid = threadIdx.x;
+    constexpr int L2N = (NRED_BLOCKS * NV + NTH - 1) / NTH;
+    double tmp[L2N];
+#pragma unroll
+    for (int i = 0; i < L2N; ++i) {
+        const int e = tid + i * NTH;
+        tmp[i] = e < NRED_BLOCKS * NV ? partial2[e] : 0.0;
+    }
+#pragma unroll
+    for (int i = 0; i < L2N; ++i) {
+        const int e = tid + i * NTH;
+        if (e < NRED_BLOCKS * NV) p2s[e] = tmp[i];
+    }
     __syncthreads();
-    if (tid == 0) ticket = atomicAdd(counter, 1u);
-    __syncthreads();
-    if (ticket != NRED_BLOCKS - 1) return;
-    __threadfence();
-    if (tid < NV) {
-        double r = __hip_atomic_load(partial2 + tid, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    for (int v = tid; v < NV; v += NTH) {
+        double r = p2s[v];
         for (int b = 1; b < NRED_BLOCKS; ++b) {
-            const double x = __hip_atomic_load(partial2 + (long)b * NV + tid, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            r = (tid == 0 || tid == 2) ? fmax(r, x) : r + x;
+            const double x = p2s[b * NV + v];
+            r = (v == 0 || v == 2) ? fmax(r, x) : r + x;
         }
-        tot[tid] = r;
+        tot[v] = r;
     }
     __syncthreads();
-    if (tid == 0) {
-        finish_step(tot, hdr, ins, ctl, dx, eta, history);
-        atomicExch(counter, 0u);
+}
+
+// Start of a stepping call: make slot 0 current, keep a device copy of the
+// insect and evaluate the kinematics of the current time level.
+static __global__ void k_prologue(StateHdr* hdr, flusi_insect ins, flusi_insect* ins_dev, double dx, int masked) {
+    if (threadIdx.x == 0 && blockIdx.x == 0) {
+        if (hdr->cur == 1) {
+            hdr->slot[0] = hdr->slot[1];
+            hdr->cur = 0;
+        }
+        *ins_dev = ins;
+        if (masked) compute_kin(ins, hdr->slot[0].t, dx, hdr->kin);
     }
 }
 
-// Kinematics of the current time level of a state (start of each stepping call).
-static __global__ void k_prologue(StateHdr* hdr, flusi_insect ins, double dx) {
-    if (threadIdx.x == 0 && blockIdx.x == 0) compute_kin(ins, hdr->t, dx, hdr->kin);
+__device__ inline void run_kin_extra(const ColExtra& ex) {
+    compute_kin(*ex.ins, ex.hdr->slot[ex.p].t, ex.dx, ex.hdr->kin);
 }
 
 static __global__ void k_hdr_init(StateHdr* hdr, double t0) {
     if (threadIdx.x == 0 && blockIdx.x == 0) {
-        StateHdr h;
-        unsigned char* b = reinterpret_cast<unsigned char*>(&h);
+        unsigned char* b = reinterpret_cast<unsigned char*>(hdr);
         for (size_t i = 0; i < sizeof(StateHdr); ++i) b[i] = 0;
-        h.t = t0;
-        *hdr = h;
+        hdr->slot[0].t = t0;
+        hdr->cur = 0;
     }
 }
 
@@ -425,56 +574,96 @@ static __global__ void k_hdr_init(StateHdr* hdr, double t0) {
 enum { MODE_IMPORT = 0, MODE_STEP = 1, MODE_STEP_LAST = 2, MODE_INVERSE = 3 };
 
 template <typename T, int N, int MODE>
-__global__ __launch_bounds__(NT) void k_zpass(const cx<T>* __restrict__ yin, long fs_y, cx<T>* uhat, cx<T>* nold,
-                                              long fs_s, cx<T>* __restrict__ zout, long fs_z,
-                                              const cx<T>* __restrict__ tw, const StateHdr* __restrict__ hdr,
-                                              double kscale, double nu, int mean_mode) {
-    constexpr int K = kmax_of(N), KP = K + 1, M = 2 * K + 1, Q = M * KP;
-    constexpr int C = cols_of(N);
-    static_assert(NT % C == 0, "column mapping");
-    constexpr int PERM = (M * C + NT - 1) / NT;
-    __shared__ cx<T> buf[C * N];
+__global__ __launch_bounds__(nt_z(N)) void k_zpass(const cx<T>* __restrict__ yin, long fs_y, cx<T>* uhat,
+                                                   cx<T>* nold, long fs_s, cx<T>* __restrict__ zout, long fs_z,
+                                                   const cx<T>* __restrict__ tw, StateHdr* hdr, double kscale,
+                                                   double nu, int mean_mode, const double* __restrict__ partial2,
+                                                   int par, StepCtl ctl, double dx, double eta, double* history) {
+    using G = Geo<T, N>;
+    constexpr int K = G::K, KP = G::KP, M = G::M, Q = G::Q, Qp = G::Qp;
+    constexpr int C = cols_z(N), NTZ = nt_z(N);
+    constexpr int RS = NTZ / C;   // rows per sweep
+    constexpr int RPT = N / RS;   // rows per thread
+    static_assert(NTZ % C == 0 && N % RS == 0, "column mapping");
+    constexpr int PERM = (M + RS - 1) / RS;
+    constexpr int SC = cm_stride(N);
+    constexpr int BUFB = C * SC * (int)sizeof(cx<T>);
+    constexpr int REDB = NRED_BLOCKS * NV * 8;
+    __shared__ __align__(16) unsigned char smem[BUFB > REDB ? BUFB : REDB];
+    __shared__ double tot[NV];
+    __shared__ Coef cf;
+    cx<T>* buf = reinterpret_cast<cx<T>*>(smem);
     if (hdr->status) return;
     const int tid = threadIdx.x;
-    const int c = tid % C;
-    const int q = blockIdx.x * C + c;
+    const int c = tid % C, r0 = tid / C;
+    const int q = xcd_tile(blockIdx.x, gridDim.x) * C + c;
     const bool okq = q < Q;
     const int kxi = q % KP, myi = q / KP;
     const double kxv = kscale * kxi;
     const double kyv = kscale * j_of_m(myi, K);
 
     const bool step_mode = (MODE == MODE_STEP || MODE == MODE_STEP_LAST);
-    const bool active = step_mode ? (hdr->active != 0) : true;
+    if (step_mode) {
+        reduce_level2<NTZ>(partial2, reinterpret_cast<double*>(smem), tot);
+        if (tid == 0) {
+            cf = step_coef(tot, hdr->slot[par], ctl, dx, eta);
+            if (blockIdx.x == 0) write_step(hdr, par, tot, cf, ctl, dx, eta, history);
+        }
+        __syncthreads();
+        if (cf.bad) return;
+    }
+    const bool active = step_mode ? (cf.active != 0) : true;
     const bool do_fwd = (MODE == MODE_IMPORT) || (step_mode && active);
     const bool do_inv = (MODE == MODE_STEP) || (MODE == MODE_INVERSE);
 
+    // kept kz of this thread: m = r0 + i*RS, i < PERM
     cx<T> U[3][PERM];
     if (do_fwd) {
         cx<T> Nh[3][PERM];
 #pragma unroll
         for (int f = 0; f < 3; ++f) {
-            for (int n = tid / C; n < N; n += NT / C)
-                buf[n * C + c] = okq ? yin[f * fs_y + (long)n * Q + q] : cx<T>{T(0), T(0)};
-            fft_lds<T, N, -1, C, NT, C, 1>(buf, tw);
+            cx<T> v[RPT];
+#pragma unroll
+            for (int i = 0; i < RPT; ++i)
+                v[i] = okq ? yin[f * fs_y + (long)(r0 + i * RS) * Qp + q] : cx<T>{T(0), T(0)};
+#pragma unroll
+            for (int i = 0; i < RPT; ++i) buf[c * SC + cpad(r0 + i * RS)] = v[i];
+            fft_cols<T, N, -1, C, NTZ, SC>(buf, tw);
 #pragma unroll
             for (int i = 0; i < PERM; ++i) {
-                const int m = tid / C + i * (NT / C);
-                if (m < M) Nh[f][i] = buf[bin_of_m(m, N, K) * C + c];
+                const int m = r0 + i * RS;
+                if (m < M) Nh[f][i] = buf[c * SC + cpad(bin_of_m(m, N, K))];
             }
             __syncthreads();
         }
         double dt = 0, b1 = 0, b2 = 0, dtp = 0;
         int first = 1;
         if (step_mode) {
-            dt = hdr->dt;
-            b1 = hdr->b1;
-            b2 = hdr->b2;
-            dtp = hdr->dtp;
-            first = hdr->first;
+            dt = cf.dt;
+            b1 = cf.b1;
+            b2 = cf.b2;
+            dtp = cf.dtp;
+            first = cf.first;
+        }
+        // state loads first (independent of the projection arithmetic)
+        cx<T> uo[3][PERM], no[3][PERM];
+        if (MODE != MODE_IMPORT) {
+#pragma unroll
+            for (int i = 0; i < PERM; ++i) {
+                const int m = r0 + i * RS;
+                if (m < M && okq) {
+                    const long e = (long)m * Qp + q;
+#pragma unroll
+                    for (int f = 0; f < 3; ++f) {
+                        uo[f][i] = uhat[f * fs_s + e];
+                        no[f][i] = first ? cx<T>{T(0), T(0)} : nold[f * fs_s + e];
+                    }
+                }
+            }
         }
 #pragma unroll
         for (int i = 0; i < PERM; ++i) {
-            const int m = tid / C + i * (NT / C);
+            const int m = r0 + i * RS;
             if (m < M && okq) {
                 const double kzv = kscale * j_of_m(m, K);
                 const double k2 = kxv * kxv + kyv * kyv + kzv * kzv;
@@ -493,7 +682,7 @@ __global__ __launch_bounds__(NT) void k_zpass(const cx<T>* __restrict__ yin, lon
                     nr[0] = nr[1] = nr[2] = 0.0;
                     ni[0] = ni[1] = ni[2] = 0.0;
                 }
-                const long e = (long)m * Q + q;
+                const long e = (long)m * Qp + q;
                 if (MODE == MODE_IMPORT) {
 #pragma unroll
                     for (int f = 0; f < 3; ++f) {
@@ -502,22 +691,19 @@ __global__ __launch_bounds__(NT) void k_zpass(const cx<T>* __restrict__ yin, lon
                     }
                 } else {
                     const double e1 = exp(-nu * k2 * dt);
-                    const double e0 = first ? 0.0 : exp(-nu * k2 * dtp);
+                    const double c2 = first ? 0.0 : b2 * exp(-nu * k2 * dtp);
 #pragma unroll
                     for (int f = 0; f < 3; ++f) {
-                        const cx<T> uh = uhat[f * fs_s + e];
                         double ar, ai;
                         if (first) {
                             ar = nr[f];
                             ai = ni[f];
                         } else {
-                            const cx<T> no = nold[f * fs_s + e];
-                            const double c2 = b2 * e0;
-                            ar = b1 * nr[f] + c2 * (double)no.x;
-                            ai = b1 * ni[f] + c2 * (double)no.y;
+                            ar = b1 * nr[f] + c2 * (double)no[f][i].x;
+                            ai = b1 * ni[f] + c2 * (double)no[f][i].y;
                         }
-                        const double vr = e1 * ((double)uh.x + dt * ar);
-                        const double vi = e1 * ((double)uh.y + dt * ai);
+                        const double vr = e1 * ((double)uo[f][i].x + dt * ar);
+                        const double vi = e1 * ((double)uo[f][i].y + dt * ai);
                         U[f][i] = cx<T>{T(vr), T(vi)};
                         uhat[f * fs_s + e] = U[f][i];
                         nold[f * fs_s + e] = cx<T>{T(nr[f]), T(ni[f])};
@@ -528,9 +714,9 @@ __global__ __launch_bounds__(NT) void k_zpass(const cx<T>* __restrict__ yin, lon
     } else if (do_inv) {
 #pragma unroll
         for (int i = 0; i < PERM; ++i) {
-            const int m = tid / C + i * (NT / C);
+            const int m = r0 + i * RS;
             if (m < M && okq) {
-                const long e = (long)m * Q + q;
+                const long e = (long)m * Qp + q;
 #pragma unroll
                 for (int f = 0; f < 3; ++f) U[f][i] = uhat[f * fs_s + e];
             }
@@ -541,10 +727,10 @@ __global__ __launch_bounds__(NT) void k_zpass(const cx<T>* __restrict__ yin, lon
     const T kx = T(kxv), ky = T(kyv);
 #pragma unroll
     for (int g = 0; g < 6; ++g) {
-        for (int idx = tid; idx < C * (N - M); idx += NT) buf[(K + 1 + idx / C) * C + idx % C] = cx<T>{T(0), T(0)};
+        for (int idx = tid; idx < C * (N - M); idx += NTZ) buf[(idx % C) * SC + cpad(K + 1 + idx / C)] = cx<T>{T(0), T(0)};
 #pragma unroll
         for (int i = 0; i < PERM; ++i) {
-            const int m = tid / C + i * (NT / C);
+            const int m = r0 + i * RS;
             if (m < M) {
                 cx<T> v = {T(0), T(0)};
                 if (okq) {
@@ -559,12 +745,17 @@ __global__ __launch_bounds__(NT) void k_zpass(const cx<T>* __restrict__ yin, lon
                         v = mul_pi(a);
                     }
                 }
-                buf[bin_of_m(m, N, K) * C + c] = v;
+                buf[c * SC + cpad(bin_of_m(m, N, K))] = v;
             }
         }
-        fft_lds<T, N, +1, C, NT, C, 1>(buf, tw);
-        if (okq)
-            for (int n = tid / C; n < N; n += NT / C) zout[g * fs_z + (long)n * Q + q] = buf[n * C + c];
+        fft_cols<T, N, +1, C, NTZ, SC>(buf, tw);
+        if (okq) {
+            cx<T> o[RPT];
+#pragma unroll
+            for (int i = 0; i < RPT; ++i) o[i] = buf[c * SC + cpad(r0 + i * RS)];
+#pragma unroll
+            for (int i = 0; i < RPT; ++i) zout[g * fs_z + (long)(r0 + i * RS) * Qp + q] = o[i];
+        }
         __syncthreads();
     }
 }
@@ -576,9 +767,9 @@ __global__ __launch_bounds__(NT) void k_zpass(const cx<T>* __restrict__ yin, lon
 // ---------------------------------------------------------------------------
 template <typename T, int N>
 __global__ __launch_bounds__(NT) void k_x_r2c(const T* __restrict__ in, cx<T>* __restrict__ out, long nrows, int nkx,
-                                              const cx<T>* __restrict__ tw) {
+                                              int pitch, const cx<T>* __restrict__ tw) {
     constexpr int RW = 2 * rows_x(N);  // real rows per workgroup
-    constexpr int SC = N + 1;
+    constexpr int SC = cm_stride(N);
     constexpr int CP = RW / 2;
     __shared__ cx<T> buf[CP * SC];
     const int tid = threadIdx.x;
@@ -586,21 +777,21 @@ __global__ __launch_bounds__(NT) void k_x_r2c(const T* __restrict__ in, cx<T>* _
     for (int idx = tid; idx < RW * N; idx += NT) {
         const int r = idx / N, i = idx % N;
         const T v = (row0 + r < nrows) ? in[row0 * N + idx] : T(0);
-        reinterpret_cast<T*>(buf + (r / 2) * SC + i)[r & 1] = v;
+        reinterpret_cast<T*>(buf + lds_at<true, 1, SC>(i, r / 2))[r & 1] = v;
     }
-    fft_lds<T, N, -1, CP, NT, 1, SC>(buf, tw);
+    fft_cols<T, N, -1, CP, NT, SC>(buf, tw);
     for (int idx = tid; idx < RW * nkx; idx += NT) {
         const int r = idx / nkx, k = idx % nkx;
         if (row0 + r >= nrows) continue;
-        const cx<T> zk = buf[(r / 2) * SC + k];
-        const cx<T> zm = buf[(r / 2) * SC + ((N - k) % N)];
+        const cx<T> zk = buf[lds_at<true, 1, SC>(k, r / 2)];
+        const cx<T> zm = buf[lds_at<true, 1, SC>((N - k) % N, r / 2)];
         cx<T> v;
         if (!(r & 1)) {
             v = cx<T>{T(0.5) * (zk.x + zm.x), T(0.5) * (zk.y - zm.y)};
         } else {
             v = cx<T>{T(0.5) * (zk.y + zm.y), T(-0.5) * (zk.x - zm.x)};
         }
-        out[(row0 + r) * nkx + k] = v;
+        out[(row0 + r) * pitch + k] = v;
     }
 }
 
@@ -608,31 +799,30 @@ template <typename T, int N>
 __global__ __launch_bounds__(NT) void k_x_c2r(const cx<T>* __restrict__ in, T* __restrict__ out, long nrows, int nkx,
                                               T scale, const cx<T>* __restrict__ tw) {
     constexpr int RW = 2 * rows_x(N);
-    constexpr int SC = N + 1;
+    constexpr int SC = cm_stride(N);
     constexpr int CP = RW / 2;
     __shared__ cx<T> buf[CP * SC];
     const int tid = threadIdx.x;
     const long row0 = (long)blockIdx.x * RW;
-    for (int idx = tid; idx < CP * N; idx += NT) buf[(idx / N) * SC + idx % N] = cx<T>{T(0), T(0)};
+    for (int idx = tid; idx < CP * N; idx += NT) buf[lds_at<true, 1, SC>(idx % N, idx / N)] = cx<T>{T(0), T(0)};
     __syncthreads();
     for (int idx = tid; idx < CP * nkx; idx += NT) {
         const int p = idx / nkx, k = idx % nkx;
         const long ra = row0 + 2 * p, rb = ra + 1;
         const cx<T> a = ra < nrows ? in[ra * nkx + k] : cx<T>{T(0), T(0)};
         const cx<T> b = rb < nrows ? in[rb * nkx + k] : cx<T>{T(0), T(0)};
-        cx<T>* col = buf + p * SC;
         if (k == 0 || 2 * k == N) {
-            col[k] = cx<T>{a.x, b.x};
+            buf[lds_at<true, 1, SC>(k, p)] = cx<T>{a.x, b.x};
         } else {
-            col[k] = cx<T>{a.x - b.y, a.y + b.x};
-            col[N - k] = cx<T>{a.x + b.y, b.x - a.y};
+            buf[lds_at<true, 1, SC>(k, p)] = cx<T>{a.x - b.y, a.y + b.x};
+            buf[lds_at<true, 1, SC>(N - k, p)] = cx<T>{a.x + b.y, b.x - a.y};
         }
     }
-    fft_lds<T, N, +1, CP, NT, 1, SC>(buf, tw);
+    fft_cols<T, N, +1, CP, NT, SC>(buf, tw);
     for (int idx = tid; idx < RW * N; idx += NT) {
         const int r = idx / N, i = idx % N;
         if (row0 + r >= nrows) continue;
-        const cx<T> z = buf[(r / 2) * SC + i];
+        const cx<T> z = buf[lds_at<true, 1, SC>(i, r / 2)];
         out[row0 * N + idx] = ((r & 1) ? z.y : z.x) * scale;
     }
 }
@@ -727,13 +917,16 @@ __global__ void k_project_full(cx<T>* __restrict__ f3, int n, double kscale, int
 
 // Materialized mask (flusi_mask_insect).
 template <typename T>
-__global__ void k_mask(const Kin* __restrict__ kin, flusi_insect ins, int n, double dx, T* __restrict__ chi,
+__global__ void k_mask(const Kin* __restrict__ kin, int n, double dx, T* __restrict__ chi,
                        T* __restrict__ us, int16_t* __restrict__ colour) {
+    __shared__ KinT<T> kt;
+    if (threadIdx.x == 0) kin_cast<T>(*kin, kt);
+    __syncthreads();
     const long npts = (long)n * n * n;
     const long p = (long)blockIdx.x * blockDim.x + threadIdx.x;
     if (p >= npts) return;
     const int i = p % n, j = (p / n) % n, k = p / ((long)n * n);
-    const MaskPt mp = eval_mask(*kin, ins, dx * i, dx * j, dx * k);
+    const MaskPt<T> mp = eval_mask<T>(kt, T(dx * i), T(dx * j), T(dx * k));
     if (chi) chi[p] = T(mp.chi);
     if (us) {
         us[p] = T(mp.us[0]);
@@ -747,9 +940,9 @@ static __global__ void k_kin(Kin* kin, flusi_insect ins, double t, double dx) {
     if (threadIdx.x == 0 && blockIdx.x == 0) compute_kin(ins, t, dx, *kin);
 }
 
-// Pruned state spectrum [3][M][M][KP] -> full layout [3][n][n][n/2+1] (zeros elsewhere).
+// Pruned state spectrum [3][M][Qp] (q = my*KP + kx) -> full layout [3][n][n][n/2+1] (zeros elsewhere).
 template <typename T>
-__global__ void k_export_full(const cx<T>* __restrict__ st, cx<T>* __restrict__ out, int n, long fs_s) {
+__global__ void k_export_full(const cx<T>* __restrict__ st, cx<T>* __restrict__ out, int n, long fs_s, long Qp) {
     const int nkx = n / 2 + 1;
     const int K = kmax_of(n), KP = K + 1, M = 2 * K + 1;
     const long tot = (long)n * n * nkx;
@@ -759,7 +952,7 @@ __global__ void k_export_full(const cx<T>* __restrict__ st, cx<T>* __restrict__ 
     const int my = m_of_bin(iy, n, K), mz = m_of_bin(iz, n, K);
     const bool kept = ix <= K && my >= 0 && mz >= 0;
     for (int f = 0; f < 3; ++f)
-        out[f * tot + e] = kept ? st[f * fs_s + ((long)mz * M + my) * KP + ix] : cx<T>{T(0), T(0)};
+        out[f * tot + e] = kept ? st[f * fs_s + (long)mz * Qp + (long)my * KP + ix] : cx<T>{T(0), T(0)};
 }
 
 }  // namespace flusi

@@ -64,8 +64,8 @@ def test_tables_are_bit_exact(n):
     assert np.array_equal(keep.astype(bool), O.dealias_keep(O.signed_index(n), n))
 
 
-def _unambiguous(ins, g, t):
-    """Grid points where the largest part chi is not within 1e-9 of the next."""
+def _unambiguous(ins, g, t, gap=1e-9):
+    """Grid points where the largest part chi is not within `gap` of the next."""
     x, y, z = g.coords()
     xb = O.to_body(ins, t, np.stack([x, y, z]))
     chis = [O.chi_of_delta(O.delta_ellipsoid(xb[0], xb[1], xb[2], ins.a, ins.b), ins, g.dx)
@@ -81,7 +81,7 @@ def _unambiguous(ins, g, t):
     st = np.sort(np.stack(chis), axis=0)
     if st.shape[0] == 1:
         return np.ones(x.shape, bool)
-    return ~((st[-1] > 0) & (np.abs(st[-1] - st[-2]) < 1e-9))
+    return ~((st[-1] > 0) & (np.abs(st[-1] - st[-2]) < gap))
 
 
 @pytest.mark.parametrize("case", ["sphere", "insect"])
@@ -95,15 +95,18 @@ def test_mask_matches_oracle(case, dtype):
         chi_o, us_o, col_o = O.insect_mask(g, ins, t)
         P = F.Plan(n, L, 0.01, 1e-3, dtype)
         chi, us, col = P.mask(d, t)
-        tol = 1e-13 if dtype == "f64" else 1e-6
+        # FP32 geometry: lengths of order 1 carry ~1e-7 rounding, amplified by
+        # the mask slope ~1/h across the smoothing layer
+        tol = 1e-13 if dtype == "f64" else 3e-5
         assert np.max(np.abs(np_of(chi) - chi_o)) <= tol
         # colour and u_s are unique where one part clearly dominates and chi is not a
         # rounding-level tail value (0.5*(1 - tanh) far outside the body)
-        ok = _unambiguous(ins, g, t) & (chi_o > 1e-12)
+        # the FP32 path evaluates the geometry in FP32
+        ok = _unambiguous(ins, g, t, 1e-9 if dtype == "f64" else 1e-5) & (chi_o > (1e-12 if dtype == "f64" else 1e-6))
         gc, gchi = np_of(col), np_of(chi)
         assert np.array_equal(gc[ok], col_o[ok])
         assert np.all(gc[gchi == 0] == 0)
-        assert np.max(np.abs(np_of(us)[:, ok] - us_o[:, ok])) <= tol * 10
+        assert np.max(np.abs(np_of(us)[:, ok] - us_o[:, ok])) <= (tol * 10 if dtype == "f64" else 3e-5)
 
 
 @pytest.mark.parametrize("dtype", ["f64", "f32"])
