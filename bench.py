@@ -61,6 +61,44 @@ def step_bytes(n: int, cbytes: int) -> int:
     return b["y_inverse"] + b["x_pass"] + b["y_forward"] + b["z_pass"]
 
 
+def source_hash() -> str:
+    """Hash of the HIP sources; counter summaries are valid only for this hash."""
+    import glob
+    import hashlib
+    h = hashlib.sha256()
+    for f in sorted(glob.glob(os.path.join(ROOT, "paper_1506_06513_amd", "csrc", "*"))):
+        with open(f, "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def counter_traffic(workload: str, kernel_prefix: str):
+    """HBM bytes per launch (scaled FETCH_SIZE + WRITE_SIZE) of a kernel from
+    the committed rocprofv3 summary, or None when the summary is missing or
+    was taken on different kernel sources."""
+    path = os.path.join(ROOT, "profiles", f"{workload}.md")
+    if not os.path.exists(path):
+        return None
+    txt = open(path).read().splitlines()
+    if f"csrc_sha256: {source_hash()}" not in txt:
+        return None
+    for line in txt:
+        if line.startswith("traffic ") and line[len("traffic "):].startswith(kernel_prefix):
+            f, w = line.split()[-2:]
+            return int(f) + int(w)
+    return None
+
+
+def kernel_of_pass(pass_name: str, n: int, real: str, split: bool, nc: int) -> str:
+    return {
+        "z_pass": f"k_zpass<{real}, {n}, {2 if split else 1}>",
+        "z_inverse": f"k_zpass<{real}, {n}, 3>",
+        "x_pass": f"k_xpass<{real}, {n}, {nc}>",
+        "y_inverse": f"k_colfft<{real}, {n}, 1, true, false,",
+        "y_forward": f"k_colfft<{real}, {n}, -1, false, true, 1>",
+    }[pass_name]
+
+
 def build_workload(name: str):
     import workloads as W
     if name == "sphere128":
@@ -186,6 +224,8 @@ def main():
             passes[nm] = dict(avg_us=round(avg * 1e3, 3), launches=int(r["pass_cnt"][i]),
                               bytes=int(pb.get(nm, 0)), gbs=round(pb.get(nm, 0) / (avg * 1e-3) / 1e9, 1))
     step_names = ["y_inverse", "x_pass", "y_forward", "z_pass"] + (["z_inverse"] if split else [])
+    ins = wl["insect"]
+    nc = 0 if ins is None else (3 if ins.get("wings") else 1)
     dom = max(step_names, key=lambda k: r["pass_ms"][names.index(k)])
     d_avg_s = r["pass_ms"][names.index(dom)] / r["pass_cnt"][names.index(dom)] / 1e3
     achieved = pb[dom] / d_avg_s / 1e9
@@ -208,7 +248,9 @@ def main():
                  "ms_per_step": round(res["f64"]["ev_ms"] / steps, 5),
                  "fp32_over_fp64": round(v32 / v64, 3)},
         "roofline": {"bound": "hbm", "kernel": dom, "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
-                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None},
+                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+                     "traffic": counter_traffic(a.workload, kernel_of_pass(dom, n, "float", split, nc)),
+                     "algorithmic_bytes": int(pb[dom])},
         "step_roofline": {"bytes_per_step": sb, "bytes_per_point_step": round(sb / pts, 2),
                           "achieved_gbs": round(sb / (res["f32"]["ev_ms"] / steps / 1e3) / 1e9, 1),
                           "frac": round(sb / (res["f32"]["ev_ms"] / steps / 1e3) / 1e9 / HBM_PEAK_GBS, 4)},
