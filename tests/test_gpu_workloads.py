@@ -1,0 +1,177 @@
+"""Full-size workloads and edge cases of the HIP stepping path against the FP64
+oracle (needs an MI355X).
+
+Full sizes run a few steps (the oracle's cost grows as n^3 log n); the launch
+configuration is the one bench.py times (same plan, same flusi_step call)."""
+import math
+
+import numpy as np
+import pytest
+import torch
+
+import oracle as O
+import paper_1506_06513_amd as F
+import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+def rel_l2(a, b):
+    return float(np.linalg.norm((np.asarray(a) - np.asarray(b)).ravel()) / np.linalg.norm(np.asarray(b).ravel()))
+
+
+def np_of(t):
+    return t.detach().cpu().numpy()
+
+
+@pytest.fixture(autouse=True)
+def _announce(request):
+    print(f"\n[gpu case] {request.node.name}", flush=True)
+    yield
+    torch.cuda.synchronize()
+
+
+def _run_both(n, L, nu, eta, insect, u0, steps, dtype, **kw):
+    p = O.Params(n, L, nu, eta, O.MEAN_FIXED)
+    ins = O.Insect.from_dict(insect) if insect else None
+    ctl = O.StepControl(cfl=kw.get("cfl", 0.1), eta_cap=kw.get("eta_cap", 0.5), dt_fixed=kw.get("dt_fixed", 0.0),
+                        t_end=kw.get("t_end", math.inf) or math.inf)
+    ost, oh = O.run(p, u0, steps, ctl, ins)
+    P = F.Plan(n, L, nu, eta, dtype)
+    st = P.new_state(torch.from_numpy(u0))
+    h = np_of(P.step(st, steps, insect, history=True, cfl=ctl.cfl, eta_cap=ctl.eta_cap, dt_fixed=ctl.dt_fixed,
+                     t_end=kw.get("t_end", 0.0)))
+    return p, ost, oh, P, st, h
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+def test_sphere128_full_size(dtype):
+    wl = W.WORKLOADS["sphere128"]
+    n, L = wl["n"], wl["L"]
+    u0 = W.inflow_noise(n, L, seed=wl["seed"], rms=1e-3, kmax=8.0)
+    p, ost, oh, P, st, h = _run_both(n, L, wl["nu"], wl["eta"], W.sphere_body(L), u0, 8, dtype)
+    u = np_of(P.velocity(st))
+    ou = O.velocity(p, ost)
+    tol = 1e-11 if dtype == "f64" else 2e-5
+    assert rel_l2(u, ou) < tol
+    fl = lambda a: a - a.mean(axis=(1, 2, 3), keepdims=True)
+    assert rel_l2(fl(u), fl(ou)) < (1e-10 if dtype == "f64" else 1e-4)
+    oF = np.array([d["F"][0] for d in oh])
+    assert np.max(np.abs(h[:, 4:7] - oF)) <= (1e-10 if dtype == "f64" else 1e-4) * np.max(np.abs(oF))
+    assert np.allclose(h[:, 2], [d["umax"] for d in oh], rtol=1e-12 if dtype == "f64" else 1e-6)
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+def test_insect256_full_size_two_steps(dtype):
+    wl = W.WORKLOADS["insect256"]
+    n, L = wl["n"], wl["L"]
+    u0 = np.zeros((3, n, n, n))
+    p, ost, oh, P, st, h = _run_both(n, L, wl["nu"], wl["eta"], W.model_insect(n, L), u0, 2, dtype)
+    u = np_of(P.velocity(st))
+    ou = O.velocity(p, ost)
+    assert rel_l2(u, ou) < (1e-11 if dtype == "f64" else 2e-5)
+    for c in range(3):
+        oF = np.array([d["F"][c] for d in oh])
+        assert np.max(np.abs(h[:, 4 + 6 * c:7 + 6 * c] - oF)) <= (1e-9 if dtype == "f64" else 2e-3) * np.max(np.abs(oF))
+
+
+def test_fp32_sphere_100_steps_within_2e5():
+    n, L = 48, 4.0
+    u0 = W.inflow_noise(n, L, seed=0, rms=1e-3, kmax=8.0)
+    p, ost, oh, P, st, h = _run_both(n, L, 0.01, 1e-3, W.sphere_body(L), u0, 100, "f32")
+    assert rel_l2(np_of(P.velocity(st)), O.velocity(p, ost)) < 2e-5
+
+
+@pytest.mark.parametrize("n", [24, 192])
+def test_radix3_sizes_step(n):
+    # 24: three-stage radix-3 plans on every axis; 192: the split z-pass schedule
+    L = 2 * math.pi
+    u0 = W.random_bandlimited(n, 2, kmax=n / 4) * 0.3
+    p = O.Params(n, L, 0.05, 1.0, O.MEAN_FREE)
+    ost, oh = O.run(p, u0, 3, O.StepControl(dt_fixed=2e-3))
+    P = F.Plan(n, L, 0.05, 1.0, "f64")
+    st = P.new_state(torch.from_numpy(u0))
+    P.step(st, 3, None, dt_fixed=2e-3, mean_mode=F.FLUSI_MEAN_FREE)
+    assert rel_l2(np_of(P.velocity(st)), O.velocity(p, ost)) < 1e-12
+
+
+@pytest.mark.parametrize("n", [192, 256, 384, 512])
+def test_fft_large_sizes(n):
+    rng = np.random.default_rng(n)
+    f = rng.standard_normal((1, n, n, n))
+    P = F.Plan(n, 1.0, 0.0, 1.0, "f64")
+    fh = P.r2c(torch.from_numpy(f))
+    assert rel_l2(np_of(fh), O.r2c(f)) < 1e-13
+    assert rel_l2(np_of(P.c2r(fh)), f) < 1e-13
+
+
+def test_split_calls_equal_one_call_bitwise():
+    n, L = 48, 4.0
+    u0 = W.inflow_noise(n, L, seed=3, rms=0.05, kmax=8.0)
+    body = W.model_insect(n, L)
+    P = F.Plan(n, L, 0.01, 1e-3, "f64")
+    a = P.new_state(torch.from_numpy(u0))
+    b = P.new_state(torch.from_numpy(u0))
+    P.step(a, 20, body, cfl=0.1)
+    P.step(b, 7, body, cfl=0.1)
+    P.step(b, 13, body, cfl=0.1)
+    assert torch.equal(P.uhat(a), P.uhat(b))
+    assert P.time(a) == P.time(b)
+    assert np.array_equal(P.forces(a)[1], P.forces(b)[1])
+
+
+def test_runs_are_deterministic():
+    n, L = 64, 4.0
+    u0 = W.inflow_noise(n, L, seed=1, rms=1e-2, kmax=8.0)
+    out = []
+    for _ in range(2):
+        P = F.Plan(n, L, 0.01, 1e-3, "f32")
+        st = P.new_state(torch.from_numpy(u0))
+        h = P.step(st, 10, W.sphere_body(L), cfl=0.1, history=True)
+        out.append((P.uhat(st).clone(), h.clone()))
+    assert torch.equal(out[0][0], out[1][0]) and torch.equal(out[0][1], out[1][1])
+
+
+def test_t_end_lands_exactly_and_stops():
+    n, L = 32, 2 * math.pi
+    u0 = W.taylor_green(n)
+    P = F.Plan(n, L, 0.01, 1.0, "f64")
+    st = P.new_state(torch.from_numpy(u0))
+    h = np_of(P.step(st, 40, None, cfl=0.5, t_end=0.05, mean_mode=F.FLUSI_MEAN_FREE, history=True))
+    t, nsteps = P.time(st)
+    assert t == 0.05
+    # the same run on the oracle
+    p = O.Params(n, L, 0.01, 1.0, O.MEAN_FREE)
+    ost, oh = O.run(p, u0, nsteps, O.StepControl(cfl=0.5, t_end=0.05))
+    assert ost.t == pytest.approx(0.05, abs=1e-15)
+    assert rel_l2(np_of(P.velocity(st)), O.velocity(p, ost)) < 1e-12
+    # steps after t_end leave the state unchanged
+    uh = P.uhat(st).clone()
+    P.step(st, 3, None, cfl=0.5, t_end=0.05, mean_mode=F.FLUSI_MEAN_FREE)
+    assert torch.equal(uh, P.uhat(st)) and P.time(st)[0] == 0.05
+
+
+def test_nonfinite_velocity_stops_the_state():
+    n, L = 32, 4.0
+    u0 = W.inflow_noise(n, L, seed=0, rms=1e-3, kmax=8.0)
+    u0[1, 3, 4, 5] = np.nan
+    P = F.Plan(n, L, 0.01, 1e-3, "f32")
+    st = P.new_state(torch.from_numpy(u0))
+    P.step(st, 5, W.sphere_body(L), cfl=0.1)
+    rc, _ = P.forces(st)
+    assert rc == F.FLUSI_ENONFINITE
+    assert P.time(st) == (0.0, 0)
+    # a healthy state on the same plan is unaffected
+    st2 = P.new_state(torch.from_numpy(np.nan_to_num(u0)))
+    P.step(st2, 5, W.sphere_body(L), cfl=0.1)
+    assert P.forces(st2)[0] == 0
+
+
+def test_fixed_mean_holds_the_inflow():
+    n, L = 32, 4.0
+    u0 = W.inflow_noise(n, L, seed=0, rms=1e-3, kmax=8.0)
+    P = F.Plan(n, L, 0.01, 1e-3, "f64")
+    st = P.new_state(torch.from_numpy(u0))
+    P.step(st, 30, W.sphere_body(L), cfl=0.1, mean_mode=F.FLUSI_MEAN_FIXED)
+    m = np_of(P.velocity(st)).mean(axis=(1, 2, 3))
+    assert np.allclose(m, u0.mean(axis=(1, 2, 3)), atol=1e-13)
