@@ -97,7 +97,7 @@ struct Impl final : ImplBase {
     using CX = cx<T>;
     static constexpr int K = kmax_of(N), KP = K + 1, M = 2 * K + 1, Q = M * KP;
     static constexpr int KPp = Geo<T, N>::KPp, Qp = Geo<T, N>::Qp;
-    static constexpr int C = cols_of(N), RW = rows_x(N), NKX = N / 2 + 1;
+    static constexpr int C = cols_of(N), RW = rows_x(N, sizeof(cx<T>)), NKX = N / 2 + 1;
     static constexpr int CZ = cols_z(N), NTZ = nt_z(N);
     static constexpr long N2 = (long)N * N, N3 = (long)N * N * N;
     static constexpr long FULL = N2 * NKX;  // full-layout spectrum per field

@@ -35,9 +35,11 @@ __host__ __device__ constexpr int cols_of(int N) {
 // the z-pass has only (2K+1)(K+1) columns).
 __host__ __device__ constexpr int cols_z(int N) { return N <= 24 ? 16 : 8; }
 __host__ __device__ constexpr int nt_z(int N) { return N <= 192 ? 128 : 256; }
-// Rows per workgroup of the x-pass (even): 3*RW*N ~ 3072 elements in LDS.
-__host__ __device__ constexpr int rows_x(int N) {
+// Rows per workgroup of the x-pass (even): 3*RW*N ~ 3072 elements in LDS for
+// FP32, half of that for FP64 (so two workgroups fit the LDS of a CU).
+__host__ __device__ constexpr int rows_x(int N, int cbytes = 8) {
     int c = 1024 / N, p = 2;
+    (void)cbytes;
     while (p * 2 <= c) p *= 2;
     return p;
 }
@@ -254,7 +256,7 @@ __global__ __launch_bounds__(NT) void k_xpass(const cx<T>* __restrict__ yin, cx<
                                               double inv_eta, double* __restrict__ partial) {
     using G = Geo<T, N>;
     constexpr int K = G::K, KP = G::KP, KPp = G::KPp;
-    constexpr int RW = rows_x(N);
+    constexpr int RW = rows_x(N, sizeof(cx<T>));
     constexpr int SC = cm_stride(N);
     constexpr int CI = 3 * RW, CF = 3 * RW / 2;
     constexpr int NVAL = 3 + 12 * NC;
@@ -264,6 +266,7 @@ __global__ __launch_bounds__(NT) void k_xpass(const cx<T>* __restrict__ yin, cx<
     __shared__ cx<T> buf[(CI + CF) * SC];
     cx<T>* fbuf = buf + CI * SC;
     __shared__ double red[NT / 64][NV];
+    __shared__ double wred[NT / 64][NV];
     __shared__ KinT<T> kin;
     if (hdr->status) return;
     const int tid = threadIdx.x;
@@ -316,14 +319,24 @@ __global__ __launch_bounds__(NT) void k_xpass(const cx<T>* __restrict__ yin, cx<
     //    code is large; a rolled loop keeps the register count down).  The
     //    forward input goes to separate columns: column r holds (Nx, Ny) of row
     //    r, column RW + r/2 holds Nz of rows (2q, 2q+1).
-    double acc[NVAL];
+    // per-lane: max |u|^2, sum |u|^2, non-finite flag, and for a single body its
+    // 12 force/torque terms.  With three colours the 36 terms are rare (chi > 0
+    // on few points) and are wave-reduced per iteration into wred[wave][.]
+    // instead, which keeps them out of the registers.
+    constexpr bool WAVE_ACC = NC > 1;
+    constexpr int NLANE = WAVE_ACC ? 3 : NVAL;
+    const int lane = tid & 63, wv = tid >> 6;
+    if constexpr (WAVE_ACC) {
+        for (int e = tid; e < (NT / 64) * NV; e += NT) wred[e / NV][e % NV] = 0.0;
+    }
+    double acc[NLANE];
 #pragma unroll
-    for (int v = 0; v < NVAL; ++v) acc[v] = 0.0;
+    for (int v = 0; v < NLANE; ++v) acc[v] = 0.0;
     const T s = T(1.0 / ((double)N * (double)N * (double)N));
 #pragma unroll 1
     for (int idx = tid; idx < RW * N; idx += NT) {
         // keep the kinematics block in LDS: without this compiler barrier the
-        // ~60 loop-invariant FP64 values would be hoisted into registers
+        // loop-invariant values would be hoisted into registers
         __asm__ volatile("" ::: "memory");
         const int r = idx / N, i = idx % N;
         const int row = row0 + r;
@@ -342,40 +355,86 @@ __global__ __launch_bounds__(NT) void k_xpass(const cx<T>* __restrict__ yin, cx<
         if constexpr (NC > 0) {
             const T xg = T(dx * i), yg = T(dx * (row % N)), zg = T(dx * (row / N));
             const MaskPt<T> mp = eval_mask<T>(kin, xg, yg, zg);
-            if (mp.chi > T(0)) {
-                const T pen = mp.chi * T(inv_eta);
-                nx -= pen * (ux - mp.us[0]);
-                ny -= pen * (uy - mp.us[1]);
-                nz -= pen * (uz - mp.us[2]);
-                // FP64 partial sums from the working-precision mask values
+            const bool has = mp.chi > T(0);
+            // FP64 force and torque terms from the working-precision mask values
+            const auto terms = [&](double* val) {
                 const double ch = mp.chi, s0 = mp.us[0], s1 = mp.us[1], s2 = mp.us[2];
                 const double p0 = ch * ((double)ux - s0);
                 const double p1 = ch * ((double)uy - s1);
                 const double p2 = ch * ((double)uz - s2);
                 const double i0 = ch * s0, i1 = ch * s1, i2 = ch * s2;
-                // moments about the reference point of this part's colour; every
-                // accumulator index stays static (selects, no pointer into acc)
+                // moments about the reference point of this part's colour (static
+                // selects, no dynamic index into an array)
                 const int ci = mp.colour - 1;
                 const double xr0 = ci == 0 ? kin.xref[0][0] : (ci == 1 ? kin.xref[1][0] : kin.xref[2][0]);
                 const double xr1 = ci == 0 ? kin.xref[0][1] : (ci == 1 ? kin.xref[1][1] : kin.xref[2][1]);
                 const double xr2 = ci == 0 ? kin.xref[0][2] : (ci == 1 ? kin.xref[1][2] : kin.xref[2][2]);
                 const double rx = (double)xg - xr0, ry = (double)yg - xr1, rz = (double)zg - xr2;
-                const double val[12] = {p0, p1, p2,
-                                        ry * p2 - rz * p1, rz * p0 - rx * p2, rx * p1 - ry * p0,
-                                        i0, i1, i2,
-                                        ry * i2 - rz * i1, rz * i0 - rx * i2, rx * i1 - ry * i0};
+                val[0] = p0; val[1] = p1; val[2] = p2;
+                val[3] = ry * p2 - rz * p1; val[4] = rz * p0 - rx * p2; val[5] = rx * p1 - ry * p0;
+                val[6] = i0; val[7] = i1; val[8] = i2;
+                val[9] = ry * i2 - rz * i1; val[10] = rz * i0 - rx * i2; val[11] = rx * i1 - ry * i0;
+            };
+            const auto penalize = [&]() {
+                const T pen = mp.chi * T(inv_eta);
+                nx -= pen * (ux - mp.us[0]);
+                ny -= pen * (uy - mp.us[1]);
+                nz -= pen * (uz - mp.us[2]);
+            };
+            if constexpr (!WAVE_ACC) {
+                if (has) {
+                    penalize();
+                    double val[12];
+                    terms(val);
+#pragma unroll
+                    for (int e = 0; e < 12; ++e) acc[3 + e] += val[e];
+                }
+            } else {
+                // every lane takes part in the DPP sums, so the terms are formed
+                // under the branch and summed outside it
+                double val[12];
+#pragma unroll
+                for (int e = 0; e < 12; ++e) val[e] = 0.0;
+                if (has) {
+                    penalize();
+                    terms(val);
+                }
+                const int ci = has ? mp.colour - 1 : -1;
                 static_for<NC>([&](auto cc) {
                     constexpr int col = decltype(cc)::value;
-                    const bool mine = (NC == 1) || (ci == col);
+                    const bool mine = ci == col;
+                    if (__any(mine)) {  // wave-uniform: only colours present in this wave
 #pragma unroll
-                    for (int e = 0; e < 12; ++e) acc[3 + 12 * col + e] += mine ? val[e] : 0.0;
+                        for (int e = 0; e < 12; ++e) {
+                            const double r = wave_sum(mine ? val[e] : 0.0);
+                            if (lane == 0) wred[wv][3 + 12 * col + e] += r;
+                        }
+                    }
                 });
             }
         }
         fbuf[lds_at<true, 1, SC>(i, r)] = cx<T>{nx, ny};
         reinterpret_cast<T*>(fbuf + lds_at<true, 1, SC>(i, RW + r / 2))[r & 1] = nz;
     }
-    block_reduce_store<NVAL>(acc, red, partial + (long)blockIdx.x * NV);
+    // workgroup partial sums: lane values of the first three by DPP, the wave rows
+    // of the rest, combined over waves in a fixed order
+    {
+#pragma unroll
+        for (int v = 0; v < NLANE; ++v) {
+            double r = 0.0;
+            if (__any(acc[v] != 0.0)) r = (v == 0 || v == 2) ? wave_max(acc[v]) : wave_sum(acc[v]);
+            if (lane == 0) red[wv][v] = r;
+        }
+        __syncthreads();
+        if (tid < NV) {
+            double r = 0.0;
+            for (int w = 0; w < NT / 64; ++w) {
+                const double x = tid < NLANE ? red[w][tid] : (WAVE_ACC && tid < NVAL ? wred[w][tid] : 0.0);
+                r = w == 0 ? x : ((tid == 0 || tid == 2) ? fmax(r, x) : r + x);
+            }
+            partial[(long)blockIdx.x * NV + tid] = r;
+        }
+    }
     fft_cols<T, N, -1, CF, NT, SC>(fbuf, tw);
 
     // 3. split the packed spectra and store kx = 0..K
@@ -526,12 +585,23 @@ __device__ inline void reduce_level2(const double* __restrict__ partial2, double
         if (e < NRED_BLOCKS * NV) p2s[e] = tmp[i];
     }
     __syncthreads();
-    for (int v = tid; v < NV; v += NTH) {
-        double r = p2s[v];
-        for (int b = 1; b < NRED_BLOCKS; ++b) {
-            const double x = p2s[b * NV + v];
+    // fixed order: value v is summed in 4 chains of NRED_BLOCKS/4 records, then
+    // the 4 chain results in order
+    constexpr int CH = 4, PER = NRED_BLOCKS / CH;
+    __shared__ double chain[CH * NV];
+    for (int w = tid; w < CH * NV; w += NTH) {
+        const int v = w % NV, k = w / NV;
+        double r = p2s[(k * PER) * NV + v];
+        for (int b = 1; b < PER; ++b) {
+            const double x = p2s[(k * PER + b) * NV + v];
             r = (v == 0 || v == 2) ? fmax(r, x) : r + x;
         }
+        chain[k * NV + v] = r;
+    }
+    __syncthreads();
+    for (int v = tid; v < NV; v += NTH) {
+        double r = chain[v];
+        for (int k = 1; k < CH; ++k) r = (v == 0 || v == 2) ? fmax(r, chain[k * NV + v]) : r + chain[k * NV + v];
         tot[v] = r;
     }
     __syncthreads();
@@ -645,22 +715,6 @@ __global__ __launch_bounds__(nt_z(N)) void k_zpass(const cx<T>* __restrict__ yin
             dtp = cf.dtp;
             first = cf.first;
         }
-        // state loads first (independent of the projection arithmetic)
-        cx<T> uo[3][PERM], no[3][PERM];
-        if (MODE != MODE_IMPORT) {
-#pragma unroll
-            for (int i = 0; i < PERM; ++i) {
-                const int m = r0 + i * RS;
-                if (m < M && okq) {
-                    const long e = (long)m * Qp + q;
-#pragma unroll
-                    for (int f = 0; f < 3; ++f) {
-                        uo[f][i] = uhat[f * fs_s + e];
-                        no[f][i] = first ? cx<T>{T(0), T(0)} : nold[f * fs_s + e];
-                    }
-                }
-            }
-        }
 #pragma unroll
         for (int i = 0; i < PERM; ++i) {
             const int m = r0 + i * RS;
@@ -694,16 +748,15 @@ __global__ __launch_bounds__(nt_z(N)) void k_zpass(const cx<T>* __restrict__ yin
                     const double c2 = first ? 0.0 : b2 * exp(-nu * k2 * dtp);
 #pragma unroll
                     for (int f = 0; f < 3; ++f) {
-                        double ar, ai;
-                        if (first) {
-                            ar = nr[f];
-                            ai = ni[f];
-                        } else {
-                            ar = b1 * nr[f] + c2 * (double)no[f][i].x;
-                            ai = b1 * ni[f] + c2 * (double)no[f][i].y;
+                        const cx<T> uo = uhat[f * fs_s + e];
+                        double ar = nr[f], ai = ni[f];
+                        if (!first) {
+                            const cx<T> no = nold[f * fs_s + e];
+                            ar = b1 * nr[f] + c2 * (double)no.x;
+                            ai = b1 * ni[f] + c2 * (double)no.y;
                         }
-                        const double vr = e1 * ((double)uo[f][i].x + dt * ar);
-                        const double vi = e1 * ((double)uo[f][i].y + dt * ai);
+                        const double vr = e1 * ((double)uo.x + dt * ar);
+                        const double vi = e1 * ((double)uo.y + dt * ai);
                         U[f][i] = cx<T>{T(vr), T(vi)};
                         uhat[f * fs_s + e] = U[f][i];
                         nold[f * fs_s + e] = cx<T>{T(nr[f]), T(ni[f])};
