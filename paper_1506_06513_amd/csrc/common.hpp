@@ -12,6 +12,23 @@ struct cx {
     T x, y;
 };
 
+// Global-memory views.  A pointer read from memory (a launch table) is
+// generic, and generic accesses compile to flat instructions; these typed views
+// keep bulk accesses on global instructions.
+template <typename T>
+using glb = __attribute__((address_space(1))) T;
+template <typename T>
+__device__ __forceinline__ glb<T>* gview(T* p) { return (glb<T>*)p; }
+template <typename T>
+__device__ __forceinline__ const glb<T>* gview(const T* p) { return (const glb<T>*)p; }
+template <typename T>
+__device__ __forceinline__ cx<T> gld(const glb<cx<T>>* p, long i) { return cx<T>{p[i].x, p[i].y}; }
+template <typename T>
+__device__ __forceinline__ void gst(glb<cx<T>>* p, long i, cx<T> v) {
+    p[i].x = v.x;
+    p[i].y = v.y;
+}
+
 template <typename T>
 __device__ __forceinline__ cx<T> mk(T a, T b) { return cx<T>{a, b}; }
 template <typename T>

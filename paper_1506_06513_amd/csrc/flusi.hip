@@ -102,7 +102,7 @@ static int check_plan(flusi_plan p) {
     return FLUSI_OK;
 }
 static void free_plan(PlanData& d) {
-    void* ptrs[] = {d.tw, d.bufA, d.bufB, d.partial, d.partial2, d.kin, d.ins_dev, d.pmax, d.spec, d.phys};
+    void* ptrs[] = {d.tw, d.bufA, d.bufB, d.partial, d.partial2, d.kin, d.ins_dev, d.member_dev, d.pmax, d.spec, d.phys};
     for (void* q : ptrs)
         if (q) (void)hipFree(q);
     for (hipEvent_t e : d.events) (void)hipEventDestroy(e);
@@ -156,12 +156,14 @@ int flusi_plan_create(int nx, int ny, int nz, double L, double nu, double eta, i
     ok = ok && hipMalloc(&d.partial2, (size_t)NRED_BLOCKS * NV * sizeof(double)) == hipSuccess;
     ok = ok && hipMalloc(&d.kin, sizeof(Kin)) == hipSuccess;
     ok = ok && hipMalloc(&d.ins_dev, sizeof(flusi_insect)) == hipSuccess;
+    ok = ok && hipMalloc(&d.member_dev, sizeof(Member)) == hipSuccess;
+    d.split_z = impl->split_z_default();
     if (!ok) {
         free_plan(d);
         delete p;
         return set_error(FLUSI_ENOMEM, "device allocation for a %d^3 plan", nx);
     }
-    d.workspace = nx * cxb + d.szA + d.szB + (size_t)d.nwg_x * NV * 8 + NRED_BLOCKS * NV * 8 + sizeof(Kin) + sizeof(flusi_insect);
+    d.workspace = nx * cxb + d.szA + d.szB + (size_t)d.nwg_x * NV * 8 + NRED_BLOCKS * NV * 8 + sizeof(Kin) + sizeof(flusi_insect) + sizeof(Member);
     // FP64 twiddles exp(-2 pi i m / n); the FP32 table is rounded from them.
     std::vector<double> w(2 * nx);
     for (int m = 0; m < nx; ++m) {

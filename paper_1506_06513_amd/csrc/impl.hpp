@@ -25,6 +25,8 @@ struct PlanData {
     double* partial2 = nullptr;
     Kin* kin = nullptr;
     flusi_insect* ins_dev = nullptr;  // device copy of the insect of the current stepping call
+    Member* member_dev = nullptr;     // launch record of the plan's own calls
+    bool split_z = false;             // schedule: z-pass as update + inverse launches
     double* pmax = nullptr;
     int npmax = 0;
     void* spec = nullptr;  // lazily allocated full-layout scratch
@@ -42,15 +44,17 @@ struct PlanData {
 
 // Brackets one launch with a pair of events when profiling is on.
 struct PassScope {
-    PlanData& p;
+    PlanData* pp;
     int pass;
     size_t idx = 0;
-    PassScope(PlanData& pd, int ps) : p(pd), pass(ps) {
-        if (!p.prof) return;
+    PassScope(PlanData* pd, int ps) : pp(pd && pd->prof ? pd : nullptr), pass(ps) {
+        if (!pp) return;
+        PlanData& p = *pp;
         while (p.events.size() < p.ev_used + 2) {
             hipEvent_t e;
             if (hipEventCreate(&e) != hipSuccess) {
                 p.prof = false;
+                pp = nullptr;
                 return;
             }
             p.events.push_back(e);
@@ -60,11 +64,56 @@ struct PassScope {
         (void)hipEventRecord(p.events[idx], p.stream);
     }
     ~PassScope() {
-        if (!p.prof) return;
-        (void)hipEventRecord(p.events[idx + 1], p.stream);
-        p.prof_recs.emplace_back(pass, idx);
+        if (!pp) return;
+        (void)hipEventRecord(pp->events[idx + 1], pp->stream);
+        pp->prof_recs.emplace_back(pass, idx);
     }
 };
+
+// One batched stepping launch sequence: members of one (real type, size) that
+// advance together.  The device table is ordered by colour count (nc = 0,
+// then 1, then 3) so that each x-pass variant runs over a contiguous range.
+struct GroupRun {
+    const Member* mt = nullptr;
+    int nmem = 0;
+    int n_nc[3] = {0, 0, 0};  // members with nc = 0, 1, 3
+    bool any_dyn = false;
+    const void* tw = nullptr;
+    bool split_z = false;     // z-pass as update + inverse launches
+    hipStream_t stream = nullptr;
+    PlanData* prof = nullptr; // pass timing events, or null
+};
+
+inline int colour_count(const flusi_insect* ins) {
+    const bool masked = ins && (ins->body != FLUSI_BODY_NONE || ins->wings);
+    return masked ? (ins->wings ? 3 : 1) : 0;
+}
+inline int kin_dynamic(const flusi_insect* ins) {
+    return colour_count(ins) > 0 &&
+           (ins->wings || ins->psi_dot != 0.0 || ins->beta_dot != 0.0 || ins->gamma_dot != 0.0);
+}
+// Launch record of (plan, state) for a stepping call with parameters sp.
+inline Member make_member(const PlanData& p, void* st, const flusi_insect* ins, const flusi_step_params& sp) {
+    Member m{};
+    const int nc = colour_count(ins);
+    m.hdr = static_cast<StateHdr*>(st);
+    m.bufA = p.bufA;
+    m.bufB = p.bufB;
+    m.partial = p.partial;
+    m.partial2 = p.partial2;
+    m.ins = p.ins_dev;
+    m.history = sp.history;
+    m.dx = p.L / p.n;
+    m.ks = 2.0 * M_PI / p.L;
+    m.nu = p.nu;
+    m.eta = p.eta;
+    m.inv_eta = 1.0 / p.eta;
+    m.ctl = StepCtl{sp.dt_fixed, sp.cfl, sp.dt_max, sp.eta_cap, sp.t_end, nc > 0 ? 1 : 0, sp.mean_mode, kin_dynamic(ins), 0};
+    m.mean_mode = sp.mean_mode;
+    m.nc = nc;
+    m.dyn = kin_dynamic(ins);
+    return m;
+}
 enum { PASS_ZINV = 0, PASS_YINV = 1, PASS_X = 2, PASS_SCALAR = 3, PASS_YFWD = 4, PASS_Z = 5 };
 
 int set_error(int code, const char* fmt, ...);
@@ -84,6 +133,8 @@ struct ImplBase {
     virtual int export_uhat(PlanData&, const void*, void*) = 0;
     virtual int velocity(PlanData&, const void*, void*) = 0;
     virtual int step(PlanData&, void*, const flusi_insect*, const flusi_step_params&) = 0;
+    virtual int run_steps(const GroupRun&, int nsteps) = 0;
+    virtual bool split_z_default() const = 0;
 };
 
 inline int launch_check(const char* what) {
@@ -124,27 +175,27 @@ struct Impl final : ImplBase {
     static constexpr bool split_z() { return N >= 192; }
 
     // --- full-layout column passes ------------------------------------------------
-    // column launch over nf fields, 1D grid of nbx*nf (+ extra) workgroups
-    template <int DIR, bool PIN, bool POUT, int EXTRA>
+    // column transforms of nf fields, 1D grid of nbx*nf workgroups
+    template <int DIR, bool PIN, bool POUT>
     void colfft(PlanData& p, const CX* in, CX* out, int cols, int KX, long blk_in, long s_in, long blk_out,
-                long s_out, long fs_in, long fs_out, int nf, const int* status, const ColExtra& ex, int nextra) {
+                long s_out, long fs_in, long fs_out, int nf) {
         const int nbx = (cols + C - 1) / C;
-        k_colfft<T, N, DIR, PIN, POUT, EXTRA><<<(unsigned)(nbx * nf + nextra), NT, 0, p.stream>>>(
-            in, out, cols, KX, blk_in, s_in, blk_out, s_out, fs_in, fs_out, tw(p), status, nbx, nf, ex);
+        k_colfft<T, N, DIR, PIN, POUT><<<(unsigned)(nbx * nf), NT, 0, p.stream>>>(
+            in, out, cols, KX, blk_in, s_in, blk_out, s_out, fs_in, fs_out, tw(p), nbx);
     }
     void y_full(PlanData& p, const CX* in, CX* out, int nf, int dir) {
         const int cols = N * NKX;
         if (dir < 0)
-            colfft<-1, false, false, 0>(p, in, out, cols, NKX, N * NKX, NKX, N * NKX, NKX, FULL, FULL, nf, nullptr, {}, 0);
+            colfft<-1, false, false>(p, in, out, cols, NKX, N * NKX, NKX, N * NKX, NKX, FULL, FULL, nf);
         else
-            colfft<+1, false, false, 0>(p, in, out, cols, NKX, N * NKX, NKX, N * NKX, NKX, FULL, FULL, nf, nullptr, {}, 0);
+            colfft<+1, false, false>(p, in, out, cols, NKX, N * NKX, NKX, N * NKX, NKX, FULL, FULL, nf);
     }
     void z_full(PlanData& p, const CX* in, CX* out, int nf, int dir) {
         const int cols = N * NKX;
         if (dir < 0)
-            colfft<-1, false, false, 0>(p, in, out, cols, cols, 0, cols, 0, cols, FULL, FULL, nf, nullptr, {}, 0);
+            colfft<-1, false, false>(p, in, out, cols, cols, 0, cols, 0, cols, FULL, FULL, nf);
         else
-            colfft<+1, false, false, 0>(p, in, out, cols, cols, 0, cols, 0, cols, FULL, FULL, nf, nullptr, {}, 0);
+            colfft<+1, false, false>(p, in, out, cols, cols, 0, cols, 0, cols, FULL, FULL, nf);
     }
     void x_r2c(PlanData& p, const T* in, CX* out, long nrows, int nkx, int pitch) {
         constexpr int RR = 2 * RW;
@@ -230,50 +281,98 @@ struct Impl final : ImplBase {
         return FLUSI_OK;
     }
 
-    // --- pruned stepping schedule ------------------------------------------------
-    // y-inverse of the 6 z-partial fields; with kin set, one extra workgroup
-    // evaluates the kinematics of time level `par`
-    void y_inverse(PlanData& p, const int* status, const ColExtra* kin) {
-        const int cols = N * KP;
-        const CX* a = static_cast<const CX*>(p.bufA);
-        CX* b = static_cast<CX*>(p.bufB);
-        if (kin)
-            colfft<+1, true, false, 2>(p, a, b, cols, KP, Qp, KP, (long)N * KPp, KPp, (long)N * Qp, N2 * KPp, 6, status,
-                                       *kin, 1);
-        else
-            colfft<+1, true, false, 0>(p, a, b, cols, KP, Qp, KP, (long)N * KPp, KPp, (long)N * Qp, N2 * KPp, 6, status,
-                                       {}, 0);
+    // --- pruned stepping schedule over a member table ------------------------------
+    static constexpr int NBY_INV = (N * KP + C - 1) / C * 6;  // y-inverse tiles per member
+    static constexpr int NBY_FWD = (N * KP + C - 1) / C * 3;  // y-forward tiles per member
+    static constexpr int NBZ = (Q + CZ - 1) / CZ;             // z-pass tiles per member
+    static constexpr int NWG = (int)(N2 / RW);                // x-pass workgroups per member
+
+    // y-inverse of the 6 z-partial fields; with kin set, one extra workgroup per
+    // member evaluates the kinematics of time level par
+    static void y_inverse(const GroupRun& g, bool kin, int par) {
+        const CX* w = static_cast<const CX*>(g.tw);
+        if (kin) {
+            const int per = NBY_INV + 1;
+            k_ypass<T, N, +1, 2><<<(unsigned)(per * g.nmem), NT, 0, g.stream>>>(g.mt, per, w, par);
+        } else {
+            k_ypass<T, N, +1, 0><<<(unsigned)(NBY_INV * g.nmem), NT, 0, g.stream>>>(g.mt, NBY_INV, w, par);
+        }
     }
-    // y-forward of nf fields; with red set, NRED_BLOCKS extra workgroups do the
-    // first-level reduction of the x-pass partial sums
-    void y_forward(PlanData& p, const int* status, int nf, const ColExtra* red) {
-        const int cols = N * KP;
-        const CX* a = static_cast<const CX*>(p.bufA);
-        CX* b = static_cast<CX*>(p.bufB);
-        if (red)
-            colfft<-1, false, true, 1>(p, a, b, cols, KP, (long)N * KPp, KPp, Qp, KP, N2 * KPp, (long)N * Qp, nf, status,
-                                       *red, NRED_BLOCKS);
-        else
-            colfft<-1, false, true, 0>(p, a, b, cols, KP, (long)N * KPp, KPp, Qp, KP, N2 * KPp, (long)N * Qp, nf, status,
-                                       {}, 0);
+    // y-forward of 3 fields; with red set, NRED_BLOCKS extra workgroups per member
+    // do the first-level reduction of the x-pass sums
+    static void y_forward(const GroupRun& g, bool red) {
+        const CX* w = static_cast<const CX*>(g.tw);
+        if (red) {
+            const int per = NBY_FWD + NRED_BLOCKS;
+            k_ypass<T, N, -1, 1><<<(unsigned)(per * g.nmem), NT, 0, g.stream>>>(g.mt, per, w, 0);
+        } else {
+            k_ypass<T, N, -1, 0><<<(unsigned)(NBY_FWD * g.nmem), NT, 0, g.stream>>>(g.mt, NBY_FWD, w, 0);
+        }
+    }
+    static void xpass(const GroupRun& g) {
+        const CX* w = static_cast<const CX*>(g.tw);
+        const Member* mt = g.mt;
+        if (g.n_nc[0]) k_xpass<T, N, 0><<<(unsigned)(NWG * g.n_nc[0]), NT, 0, g.stream>>>(mt, w);
+        mt += g.n_nc[0];
+        if (g.n_nc[1]) k_xpass<T, N, 1><<<(unsigned)(NWG * g.n_nc[1]), NT, 0, g.stream>>>(mt, w);
+        mt += g.n_nc[1];
+        if (g.n_nc[2]) k_xpass<T, N, 3><<<(unsigned)(NWG * g.n_nc[2]), NT, 0, g.stream>>>(mt, w);
     }
     template <int MODE>
-    void zpass(PlanData& p, void* st, int mean_mode, int par = 0, const StepCtl* ctl = nullptr,
-               double* history = nullptr) {
-        const unsigned nb = (Q + CZ - 1) / CZ;
-        StepCtl c{};
-        if (ctl) c = *ctl;
-        k_zpass<T, N, MODE><<<nb, NTZ, 0, p.stream>>>(static_cast<const CX*>(p.bufB), (long)N * Qp, st_uhat(st),
-                                                      st_nold(st), st_fs(), static_cast<CX*>(p.bufA), (long)N * Qp,
-                                                      tw(p), static_cast<StateHdr*>(st), 2.0 * M_PI / p.L, p.nu,
-                                                      mean_mode, p.partial2, par, c, p.L / N, p.eta, history);
+    static void zpass(const GroupRun& g, int par = 0, int s = 0) {
+        k_zpass<T, N, MODE><<<(unsigned)(NBZ * g.nmem), NTZ, 0, g.stream>>>(g.mt, static_cast<const CX*>(g.tw), par, s);
+    }
+
+    bool split_z_default() const override { return split_z(); }
+
+    int run_steps(const GroupRun& g, int nsteps) override {
+        if (g.nmem <= 0 || nsteps <= 0) return FLUSI_OK;
+        k_prologue<<<(unsigned)((g.nmem + 63) / 64), 64, 0, g.stream>>>(g.mt, g.nmem);
+        {
+            PassScope ps(g.prof, PASS_ZINV);
+            zpass<MODE_INVERSE>(g);
+        }
+        for (int s = 0; s < nsteps; ++s) {
+            const int par = s & 1;
+            {
+                PassScope ps(g.prof, PASS_YINV);
+                y_inverse(g, g.any_dyn, par);
+            }
+            {
+                PassScope ps(g.prof, PASS_X);
+                xpass(g);
+            }
+            {
+                PassScope ps(g.prof, PASS_YFWD);
+                y_forward(g, true);
+            }
+            {
+                PassScope ps(g.prof, PASS_Z);
+                if (s + 1 < nsteps && !g.split_z) zpass<MODE_STEP>(g, par, s);
+                else zpass<MODE_STEP_LAST>(g, par, s);
+            }
+            if (s + 1 < nsteps && g.split_z) {
+                PassScope ps(g.prof, PASS_ZINV);
+                zpass<MODE_INVERSE>(g);
+            }
+        }
+        return launch_check("step");
     }
 
     int state_init(PlanData& p, void* st, const void* u0, double t0) override {
+        flusi_step_params sp{};
+        sp.mean_mode = FLUSI_MEAN_FREE;
+        const Member m = make_member(p, st, nullptr, sp);
+        k_member_set<<<1, 64, 0, p.stream>>>(p.member_dev, m, flusi_insect{});
         k_hdr_init<<<1, 64, 0, p.stream>>>(static_cast<StateHdr*>(st), t0);
         x_r2c(p, static_cast<const T*>(u0), static_cast<CX*>(p.bufA), 3 * N2, KP, KPp);
-        y_forward(p, nullptr, 3, nullptr);
-        zpass<MODE_IMPORT>(p, st, FLUSI_MEAN_FREE);
+        GroupRun g;
+        g.mt = p.member_dev;
+        g.nmem = 1;
+        g.tw = p.tw;
+        g.stream = p.stream;
+        y_forward(g, false);
+        zpass<MODE_IMPORT>(g);
         return launch_check("state_init");
     }
 
@@ -293,56 +392,18 @@ struct Impl final : ImplBase {
     }
 
     int step(PlanData& p, void* st, const flusi_insect* ins, const flusi_step_params& sp) override {
-        StateHdr* hdr = static_cast<StateHdr*>(st);
-        const int* status = &hdr->status;
-        flusi_insect in{};
-        const bool masked = ins && (ins->body != FLUSI_BODY_NONE || ins->wings);
-        if (masked) in = *ins;
-        const int nc = masked ? (in.wings ? 3 : 1) : 0;
-        const double dx = p.L / N;
-        const bool dyn = masked && (in.wings || in.psi_dot != 0.0 || in.beta_dot != 0.0 || in.gamma_dot != 0.0);
-        StepCtl ctl{sp.dt_fixed, sp.cfl, sp.dt_max, sp.eta_cap, sp.t_end, masked ? 1 : 0, sp.mean_mode, dyn ? 1 : 0, 0};
-        k_prologue<<<1, 64, 0, p.stream>>>(hdr, in, p.ins_dev, dx, masked ? 1 : 0);
-        {
-            PassScope ps(p, PASS_ZINV);
-            zpass<MODE_INVERSE>(p, st, sp.mean_mode);
-        }
-        const unsigned nwg = (unsigned)nwg_x();
-        ColExtra red{p.partial, p.partial2, (int)nwg, 0, hdr, p.ins_dev, dx};
-        for (int s = 0; s < sp.nsteps; ++s) {
-            const int par = s & 1;
-            {
-                PassScope ps(p, PASS_YINV);
-                ColExtra kin{nullptr, nullptr, 0, par, hdr, p.ins_dev, dx};
-                y_inverse(p, status, dyn ? &kin : nullptr);
-            }
-            {
-                PassScope ps(p, PASS_X);
-                const CX* yin = static_cast<const CX*>(p.bufB);
-                CX* xo = static_cast<CX*>(p.bufA);
-                if (nc == 0)
-                    k_xpass<T, N, 0><<<nwg, NT, 0, p.stream>>>(yin, xo, N2 * KPp, N2 * KPp, tw(p), hdr, dx, 1.0 / p.eta, p.partial);
-                else if (nc == 1)
-                    k_xpass<T, N, 1><<<nwg, NT, 0, p.stream>>>(yin, xo, N2 * KPp, N2 * KPp, tw(p), hdr, dx, 1.0 / p.eta, p.partial);
-                else
-                    k_xpass<T, N, 3><<<nwg, NT, 0, p.stream>>>(yin, xo, N2 * KPp, N2 * KPp, tw(p), hdr, dx, 1.0 / p.eta, p.partial);
-            }
-            {
-                PassScope ps(p, PASS_YFWD);
-                y_forward(p, status, 3, &red);
-            }
-            double* hist = sp.history ? sp.history + (long)s * FLUSI_NDIAG : nullptr;
-            {
-                PassScope ps(p, PASS_Z);
-                if (s + 1 < sp.nsteps && !split_z()) zpass<MODE_STEP>(p, st, sp.mean_mode, par, &ctl, hist);
-                else zpass<MODE_STEP_LAST>(p, st, sp.mean_mode, par, &ctl, hist);
-            }
-            if (s + 1 < sp.nsteps && split_z()) {
-                PassScope ps(p, PASS_ZINV);
-                zpass<MODE_INVERSE>(p, st, sp.mean_mode);
-            }
-        }
-        return launch_check("step");
+        const Member m = make_member(p, st, ins, sp);
+        k_member_set<<<1, 64, 0, p.stream>>>(p.member_dev, m, m.nc > 0 ? *ins : flusi_insect{});
+        GroupRun g;
+        g.mt = p.member_dev;
+        g.nmem = 1;
+        g.n_nc[m.nc == 0 ? 0 : (m.nc == 1 ? 1 : 2)] = 1;
+        g.any_dyn = m.dyn != 0;
+        g.tw = p.tw;
+        g.split_z = p.split_z;
+        g.stream = p.stream;
+        g.prof = &p;
+        return run_steps(g, sp.nsteps);
     }
 };
 

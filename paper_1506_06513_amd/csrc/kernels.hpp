@@ -95,59 +95,49 @@ struct StateHdr {
 static_assert(sizeof(StateHdr) <= 4096, "state header too large");
 constexpr size_t STATE_HDR_BYTES = 4096;
 
+// Launch record of one simulation (device memory).  The stepping kernels take
+// a table of these and work on every member of the table in one launch: the
+// 1D grid holds `per` workgroups per member, member = tile / per.  A single
+// plan is a table of one.
+struct Member {
+    StateHdr* hdr;              // state: header, then the fields (pruned layout)
+    void* bufA;                 // z-partials (inverse) / x-pass output
+    void* bufB;                 // y-partials (inverse) / y-forward output
+    double* partial;            // NV sums per x-pass workgroup
+    double* partial2;           // NV sums per first-level reduction workgroup
+    const flusi_insect* ins;    // device copy of the body description
+    double* history;            // FLUSI_NDIAG values per step of a call, or null
+    double dx, ks, nu, eta, inv_eta;
+    StepCtl ctl;
+    int mean_mode;
+    int nc;                     // colours of the mask: 0 (none), 1 (body), 3 (body + wings)
+    int dyn;                    // kinematics change with time
+    int pad;
+};
+
+__device__ inline void reduce_level1(const double* __restrict__ partial, int nwg, double* __restrict__ partial2,
+                                     int b, double (*red)[NV]);
+__device__ inline void kin_of_level(const Member& m, int p);
+
 // ---------------------------------------------------------------------------
-// Generic column FFT along y or z.
+// Column FFT along y or z of one tile of C columns.
 // Column q (q < Q) of a field starts at (q / KX) * blk + q % KX; element e of
 // the column sits at stride s.  PIN: the input holds only the 2K+1 kept
 // signed modes (pruned storage); POUT: only those are written.
 // ---------------------------------------------------------------------------
-// Extra work carried by a column launch (kinds: 0 none, 1 first-level
-// reduction of the x-pass partial sums, 2 kinematics of time level p).
-struct ColExtra {
-    const double* partial;
-    double* partial2;
-    int nwg;
-    int p;
-    struct StateHdr* hdr;
-    const flusi_insect* ins;
-    double dx;
-};
-
-template <int NVAL>
-__device__ __forceinline__ void block_reduce_store(const double (&acc)[NVAL], double (*red)[NV], double* out);
-__device__ inline void reduce_level1(const double* __restrict__ partial, int nwg, double* __restrict__ partial2,
-                                     int b, double (*red)[NV]);
-__device__ inline void run_kin_extra(const ColExtra& ex);
-
-template <typename T, int N, int DIR, bool PIN, bool POUT, int EXTRA>
-__global__ __launch_bounds__(NT) void k_colfft(const cx<T>* in, cx<T>* out, int Q, int KX,
-                                               long blk_in, long s_in, long blk_out, long s_out,
-                                               long fs_in, long fs_out, const cx<T>* __restrict__ tw,
-                                               const int* status, int nbx, int nf, ColExtra ex) {
+template <typename T, int N, int DIR, bool PIN, bool POUT>
+__device__ __forceinline__ void colfft_tile(const glb<cx<T>>* __restrict__ in, glb<cx<T>>* __restrict__ out, int Q, int KX,
+                                            long blk_in, long s_in, long blk_out, long s_out, int tile,
+                                            const cx<T>* __restrict__ tw, cx<T>* buf) {
     constexpr int C = cols_of(N);
     constexpr int K = kmax_of(N);
     constexpr int SC = cm_stride(N);
     constexpr int RS = NT / C;      // rows handled per sweep
     constexpr int RPT = N / RS;     // rows per thread
     static_assert(NT % C == 0 && N % RS == 0, "column mapping");
-    __shared__ cx<T> buf[C * SC];
-    if (status && *status) return;
-    const int tile = xcd_tile(blockIdx.x, gridDim.x);
-    const int f = tile / nbx;
-    if (f >= nf) {
-        if constexpr (EXTRA == 1) {
-            __shared__ double red[NT / 64][NV];
-            if (tile - nf * nbx < NRED_BLOCKS) reduce_level1(ex.partial, ex.nwg, ex.partial2, tile - nf * nbx, red);
-        } else if constexpr (EXTRA == 2) {
-            if (tile == nf * nbx && threadIdx.x == 0) run_kin_extra(ex);
-        }
-        return;
-    }
     const int tid = threadIdx.x;
-    in += f * fs_in;
-    out += f * fs_out;
     const int c = tid % C, r0 = tid / C;
-    const int q = (tile % nbx) * C + c;
+    const int q = tile * C + c;
     const bool ok = q < Q;
     const long bin = ok ? (long)(q / KX) * blk_in + q % KX : 0;
     const long bout = ok ? (long)(q / KX) * blk_out + q % KX : 0;
@@ -159,9 +149,9 @@ __global__ __launch_bounds__(NT) void k_colfft(const cx<T>* in, cx<T>* out, int 
         if (ok) {
             if constexpr (PIN) {
                 const int m = m_of_bin(n, N, K);
-                if (m >= 0) v[i] = in[bin + m * s_in];
+                if (m >= 0) v[i] = gld(in, bin + m * s_in);
             } else {
-                v[i] = in[bin + n * s_in];
+                v[i] = gld(in, bin + n * s_in);
             }
         }
     }
@@ -175,10 +165,64 @@ __global__ __launch_bounds__(NT) void k_colfft(const cx<T>* in, cx<T>* out, int 
             const int o = r0 + i * RS;
             if (o < NOUT) {
                 const int n = POUT ? bin_of_m(o, N, K) : o;
-                out[bout + o * s_out] = buf[c * SC + cpad(n)];
+                gst(out, bout + o * s_out, buf[c * SC + cpad(n)]);
             }
         }
     }
+}
+
+// Column transforms of nf fields given by pointers (full-layout utilities):
+// 1D grid of nbx * nf workgroups.
+template <typename T, int N, int DIR, bool PIN, bool POUT>
+__global__ __launch_bounds__(NT) void k_colfft(const cx<T>* in, cx<T>* out, int Q, int KX, long blk_in, long s_in,
+                                               long blk_out, long s_out, long fs_in, long fs_out,
+                                               const cx<T>* __restrict__ tw, int nbx) {
+    __shared__ cx<T> buf[cols_of(N) * cm_stride(N)];
+    const int tile = xcd_tile(blockIdx.x, gridDim.x);
+    const int f = tile / nbx;
+    colfft_tile<T, N, DIR, PIN, POUT>(gview(in) + f * fs_in, gview(out) + f * fs_out, Q, KX, blk_in, s_in, blk_out, s_out,
+                                      tile % nbx, tw, buf);
+}
+
+// y passes of the stepping schedule over a member table.
+//   DIR = +1 (y-inverse): 6 z-partial fields bufA [f][z][ky'][kx] (pitch Qp per
+//            z) -> bufB [f][z][y][kx] (pitch KPp per y)
+//   DIR = -1 (y-forward): 3 fields bufA [f][z][y][kx] -> bufB [f][z][ky'][kx]
+// Each member has nbx*nf column tiles followed by the extra workgroups:
+//   EXTRA 1: NRED_BLOCKS workgroups reduce the x-pass sums (first level)
+//   EXTRA 2: one workgroup evaluates the kinematics of time level p
+template <typename T, int N, int DIR, int EXTRA>
+__global__ __launch_bounds__(NT) void k_ypass(const Member* __restrict__ mt, int per, const cx<T>* __restrict__ tw,
+                                              int p) {
+    using G = Geo<T, N>;
+    constexpr int KP = G::KP, KPp = G::KPp, Qp = G::Qp;
+    constexpr int C = cols_of(N);
+    constexpr int nbx = (N * KP + C - 1) / C;
+    constexpr int nf = DIR > 0 ? 6 : 3;
+    __shared__ cx<T> buf[C * cm_stride(N)];
+    const int lin = xcd_tile(blockIdx.x, gridDim.x);
+    const Member& m = mt[lin / per];
+    const int tile = lin % per;
+    if (*gview(&m.hdr->status)) return;
+    const int f = tile / nbx;
+    if (f >= nf) {
+        if constexpr (EXTRA == 1) {
+            __shared__ double red[NT / 64][NV];
+            const int nwg = (int)((long)N * N / rows_x(N, sizeof(cx<T>)));
+            if (tile - nf * nbx < NRED_BLOCKS) reduce_level1(m.partial, nwg, m.partial2, tile - nf * nbx, red);
+        } else if constexpr (EXTRA == 2) {
+            if (tile == nf * nbx && threadIdx.x == 0 && m.dyn) kin_of_level(m, p);
+        }
+        return;
+    }
+    const glb<cx<T>>* A = gview(static_cast<const cx<T>*>(m.bufA));
+    glb<cx<T>>* B = gview(static_cast<cx<T>*>(m.bufB));
+    if constexpr (DIR > 0)
+        colfft_tile<T, N, +1, true, false>(A + f * (long)N * Qp, B + f * (long)N * N * KPp, N * KP, KP, Qp, KP,
+                                           (long)N * KPp, KPp, tile % nbx, tw, buf);
+    else
+        colfft_tile<T, N, -1, false, true>(A + f * (long)N * N * KPp, B + f * (long)N * Qp, N * KP, KP,
+                                           (long)N * KPp, KPp, Qp, KP, tile % nbx, tw, buf);
 }
 
 // ---------------------------------------------------------------------------
@@ -235,7 +279,7 @@ __device__ __forceinline__ void block_reduce_store(const double (&acc)[NVAL], do
             r = red[0][t];
             for (int w = 1; w < NT / 64; ++w) r = (t == 0 || t == 2) ? fmax(r, red[w][t]) : r + red[w][t];
         }
-        out[t] = r;
+        gview(out)[t] = r;
     }
 }
 
@@ -249,14 +293,21 @@ __device__ __forceinline__ void block_reduce_store(const double (&acc)[NVAL], do
 //   [3 + 12 c + 9..11] sum (x - x_ref) x chi u_s
 // NC: number of colours accumulated (0 no mask, 1 single body, 3 insect).
 // ---------------------------------------------------------------------------
+// Member table: N*N/RW workgroups per member, y-partials in bufB, output in bufA.
 template <typename T, int N, int NC>
-__global__ __launch_bounds__(NT) void k_xpass(const cx<T>* __restrict__ yin, cx<T>* __restrict__ xout,
-                                              long fs_in, long fs_out, const cx<T>* __restrict__ tw,
-                                              const StateHdr* __restrict__ hdr, double dx,
-                                              double inv_eta, double* __restrict__ partial) {
+__global__ __launch_bounds__(NT) void k_xpass(const Member* __restrict__ mt, const cx<T>* __restrict__ tw) {
     using G = Geo<T, N>;
     constexpr int K = G::K, KP = G::KP, KPp = G::KPp;
     constexpr int RW = rows_x(N, sizeof(cx<T>));
+    constexpr int NWG = N * N / RW;
+    constexpr long fs_in = (long)N * N * KPp, fs_out = (long)N * N * KPp;
+    const Member& m = mt[blockIdx.x / NWG];
+    const StateHdr* __restrict__ hdr = m.hdr;
+    const glb<cx<T>>* __restrict__ yin = gview(static_cast<const cx<T>*>(m.bufB));
+    glb<cx<T>>* __restrict__ xout = gview(static_cast<cx<T>*>(m.bufA));
+    const double dx = m.dx, inv_eta = m.inv_eta;
+    glb<double>* __restrict__ partial = gview(m.partial);
+    const int wg = blockIdx.x % NWG;
     constexpr int SC = cm_stride(N);
     constexpr int CI = 3 * RW, CF = 3 * RW / 2;
     constexpr int NVAL = 3 + 12 * NC;
@@ -268,9 +319,9 @@ __global__ __launch_bounds__(NT) void k_xpass(const cx<T>* __restrict__ yin, cx<
     __shared__ double red[NT / 64][NV];
     __shared__ double wred[NT / 64][NV];
     __shared__ KinT<T> kin;
-    if (hdr->status) return;
+    if (*gview(&hdr->status)) return;
     const int tid = threadIdx.x;
-    const int row0 = blockIdx.x * RW;
+    const int row0 = wg * RW;
     if constexpr (NC > 0) {
         if (tid == 0) kin_cast<T>(hdr->kin, kin);
     }
@@ -279,15 +330,15 @@ __global__ __launch_bounds__(NT) void k_xpass(const cx<T>* __restrict__ yin, cx<
     cx<T> la[3][LP], lb[3][LP];
 #pragma unroll
     for (int p = 0; p < 3; ++p) {
-        const cx<T>* A = yin + (2 * p) * fs_in + (long)row0 * KPp;
-        const cx<T>* B = yin + (2 * p + 1) * fs_in + (long)row0 * KPp;
+        const glb<cx<T>>* A = yin + (2 * p) * fs_in + (long)row0 * KPp;
+        const glb<cx<T>>* B = yin + (2 * p + 1) * fs_in + (long)row0 * KPp;
 #pragma unroll
         for (int i = 0; i < LP; ++i) {
             const int idx = tid + i * NT;
             if (idx < RW * KP) {
                 const int r = idx / KP, k = idx % KP;
-                la[p][i] = A[r * KPp + k];
-                lb[p][i] = B[r * KPp + k];
+                la[p][i] = gld(A, r * KPp + k);
+                lb[p][i] = gld(B, r * KPp + k);
             }
         }
     }
@@ -432,7 +483,7 @@ __global__ __launch_bounds__(NT) void k_xpass(const cx<T>* __restrict__ yin, cx<
                 const double x = tid < NLANE ? red[w][tid] : (WAVE_ACC && tid < NVAL ? wred[w][tid] : 0.0);
                 r = w == 0 ? x : ((tid == 0 || tid == 2) ? fmax(r, x) : r + x);
             }
-            partial[(long)blockIdx.x * NV + tid] = r;
+            partial[(long)wg * NV + tid] = r;
         }
     }
     fft_cols<T, N, -1, CF, NT, SC>(fbuf, tw);
@@ -440,7 +491,7 @@ __global__ __launch_bounds__(NT) void k_xpass(const cx<T>* __restrict__ yin, cx<
     // 3. split the packed spectra and store kx = 0..K
 #pragma unroll
     for (int f = 0; f < 3; ++f) {
-        cx<T>* O = xout + f * fs_out + (long)row0 * KPp;
+        glb<cx<T>>* O = xout + f * fs_out + (long)row0 * KPp;
         for (int idx = tid; idx < RW * KP; idx += NT) {
             const int r = idx / KP, k = idx % KP;
             const int colx = (f < 2) ? r : RW + r / 2;
@@ -454,7 +505,7 @@ __global__ __launch_bounds__(NT) void k_xpass(const cx<T>* __restrict__ yin, cx<
                 const T dxr = zk.x - zm.x, dyi = zk.y + zm.y;  // zk - conj(zm)
                 v = cx<T>{T(0.5) * dyi, T(-0.5) * dxr};
             }
-            O[r * KPp + k] = v;
+            gst(O, r * KPp + k, v);
         }
     }
 }
@@ -561,7 +612,7 @@ __device__ inline void reduce_level1(const double* __restrict__ partial, int nwg
 #pragma unroll
     for (int v = 0; v < NV; ++v) acc[v] = 0.0;
     for (int w = lo + tid; w < hi; w += NT) {
-        const double* q = partial + (long)w * NV;
+        const glb<double>* q = gview(partial) + (long)w * NV;
 #pragma unroll
         for (int v = 0; v < NV; ++v) acc[v] = (v == 0 || v == 2) ? fmax(acc[v], q[v]) : acc[v] + q[v];
     }
@@ -577,7 +628,7 @@ __device__ inline void reduce_level2(const double* __restrict__ partial2, double
 #pragma unroll
     for (int i = 0; i < L2N; ++i) {
         const int e = tid + i * NTH;
-        tmp[i] = e < NRED_BLOCKS * NV ? partial2[e] : 0.0;
+        tmp[i] = e < NRED_BLOCKS * NV ? gview(partial2)[e] : 0.0;
     }
 #pragma unroll
     for (int i = 0; i < L2N; ++i) {
@@ -607,21 +658,33 @@ __device__ inline void reduce_level2(const double* __restrict__ partial2, double
     __syncthreads();
 }
 
-// Start of a stepping call: make slot 0 current, keep a device copy of the
-// insect and evaluate the kinematics of the current time level.
-static __global__ void k_prologue(StateHdr* hdr, flusi_insect ins, flusi_insect* ins_dev, double dx, int masked) {
+// Start of a stepping call, one thread per member: make slot 0 current and
+// evaluate the kinematics of the current time level.
+static __global__ void k_prologue(const Member* __restrict__ mt, int nmem) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= nmem) return;
+    const Member& m = mt[i];
+    StateHdr* hdr = m.hdr;
+    if (hdr->cur == 1) {
+        hdr->slot[0] = hdr->slot[1];
+        hdr->cur = 0;
+    }
+    if (m.nc > 0) compute_kin(*m.ins, hdr->slot[0].t, m.dx, hdr->kin);
+}
+
+// Writes the launch record of a single plan (and the device copy of its body
+// description) ahead of the kernels that read it, in stream order.
+static __global__ void k_member_set(Member* dst, Member v, flusi_insect ins) {
     if (threadIdx.x == 0 && blockIdx.x == 0) {
-        if (hdr->cur == 1) {
-            hdr->slot[0] = hdr->slot[1];
-            hdr->cur = 0;
-        }
-        *ins_dev = ins;
-        if (masked) compute_kin(ins, hdr->slot[0].t, dx, hdr->kin);
+        *dst = v;
+        if (v.nc > 0) *const_cast<flusi_insect*>(v.ins) = ins;
     }
 }
 
-__device__ inline void run_kin_extra(const ColExtra& ex) {
-    compute_kin(*ex.ins, ex.hdr->slot[ex.p].t, ex.dx, ex.hdr->kin);
+// Kinematics of time level p (one thread).  compute_kin stays a call: inlined,
+// its FP64 working set would set the register count of the whole y-pass.
+__device__ inline void kin_of_level(const Member& m, int p) {
+    compute_kin(*m.ins, m.hdr->slot[p].t, m.dx, m.hdr->kin);
 }
 
 static __global__ void k_hdr_init(StateHdr* hdr, double t0) {
@@ -643,15 +706,29 @@ static __global__ void k_hdr_init(StateHdr* hdr, double t0) {
 // ---------------------------------------------------------------------------
 enum { MODE_IMPORT = 0, MODE_STEP = 1, MODE_STEP_LAST = 2, MODE_INVERSE = 3 };
 
+// Member table: ceil(Q/C) workgroups per member.  par: slot of the current
+// time level; s: step index within the call (row of the history).
 template <typename T, int N, int MODE>
-__global__ __launch_bounds__(nt_z(N)) void k_zpass(const cx<T>* __restrict__ yin, long fs_y, cx<T>* uhat,
-                                                   cx<T>* nold, long fs_s, cx<T>* __restrict__ zout, long fs_z,
-                                                   const cx<T>* __restrict__ tw, StateHdr* hdr, double kscale,
-                                                   double nu, int mean_mode, const double* __restrict__ partial2,
-                                                   int par, StepCtl ctl, double dx, double eta, double* history) {
+__global__ __launch_bounds__(nt_z(N)) void k_zpass(const Member* __restrict__ mt, const cx<T>* __restrict__ tw,
+                                                   int par, int s) {
     using G = Geo<T, N>;
     constexpr int K = G::K, KP = G::KP, M = G::M, Q = G::Q, Qp = G::Qp;
     constexpr int C = cols_z(N), NTZ = nt_z(N);
+    constexpr int NBZ = (Q + C - 1) / C;
+    // state fields: [uhat 3][nold 3], each padded to 256 bytes
+    constexpr long fs_s = (((long)M * Qp * (long)sizeof(cx<T>) + 255) / 256 * 256) / (long)sizeof(cx<T>);
+    constexpr long fs_y = (long)N * Qp, fs_z = (long)N * Qp;
+    const int lin = xcd_tile(blockIdx.x, gridDim.x);
+    const Member& mb = mt[lin / NBZ];
+    const int tile = lin % NBZ;
+    StateHdr* hdr = mb.hdr;
+    glb<cx<T>>* uhat = gview(reinterpret_cast<cx<T>*>(reinterpret_cast<char*>(hdr) + STATE_HDR_BYTES));
+    glb<cx<T>>* nold = uhat + 3 * fs_s;
+    const glb<cx<T>>* __restrict__ yin = gview(static_cast<const cx<T>*>(mb.bufB));
+    glb<cx<T>>* __restrict__ zout = gview(static_cast<cx<T>*>(mb.bufA));
+    const double kscale = mb.ks, nu = mb.nu, dx = mb.dx, eta = mb.eta;
+    const int mean_mode = mb.mean_mode;
+    const double* __restrict__ partial2 = mb.partial2;
     constexpr int RS = NTZ / C;   // rows per sweep
     constexpr int RPT = N / RS;   // rows per thread
     static_assert(NTZ % C == 0 && N % RS == 0, "column mapping");
@@ -663,10 +740,10 @@ __global__ __launch_bounds__(nt_z(N)) void k_zpass(const cx<T>* __restrict__ yin
     __shared__ double tot[NV];
     __shared__ Coef cf;
     cx<T>* buf = reinterpret_cast<cx<T>*>(smem);
-    if (hdr->status) return;
+    if (*gview(&hdr->status)) return;
     const int tid = threadIdx.x;
     const int c = tid % C, r0 = tid / C;
-    const int q = xcd_tile(blockIdx.x, gridDim.x) * C + c;
+    const int q = tile * C + c;
     const bool okq = q < Q;
     const int kxi = q % KP, myi = q / KP;
     const double kxv = kscale * kxi;
@@ -676,8 +753,9 @@ __global__ __launch_bounds__(nt_z(N)) void k_zpass(const cx<T>* __restrict__ yin
     if (step_mode) {
         reduce_level2<NTZ>(partial2, reinterpret_cast<double*>(smem), tot);
         if (tid == 0) {
-            cf = step_coef(tot, hdr->slot[par], ctl, dx, eta);
-            if (blockIdx.x == 0) write_step(hdr, par, tot, cf, ctl, dx, eta, history);
+            cf = step_coef(tot, hdr->slot[par], mb.ctl, dx, eta);
+            if (tile == 0)
+                write_step(hdr, par, tot, cf, mb.ctl, dx, eta, mb.history ? mb.history + (long)s * FLUSI_NDIAG : nullptr);
         }
         __syncthreads();
         if (cf.bad) return;
@@ -695,7 +773,7 @@ __global__ __launch_bounds__(nt_z(N)) void k_zpass(const cx<T>* __restrict__ yin
             cx<T> v[RPT];
 #pragma unroll
             for (int i = 0; i < RPT; ++i)
-                v[i] = okq ? yin[f * fs_y + (long)(r0 + i * RS) * Qp + q] : cx<T>{T(0), T(0)};
+                v[i] = okq ? gld(yin, f * fs_y + (long)(r0 + i * RS) * Qp + q) : cx<T>{T(0), T(0)};
 #pragma unroll
             for (int i = 0; i < RPT; ++i) buf[c * SC + cpad(r0 + i * RS)] = v[i];
             fft_cols<T, N, -1, C, NTZ, SC>(buf, tw);
@@ -741,25 +819,25 @@ __global__ __launch_bounds__(nt_z(N)) void k_zpass(const cx<T>* __restrict__ yin
 #pragma unroll
                     for (int f = 0; f < 3; ++f) {
                         U[f][i] = cx<T>{T(nr[f]), T(ni[f])};
-                        uhat[f * fs_s + e] = U[f][i];
+                        gst(uhat, f * fs_s + e, U[f][i]);
                     }
                 } else {
                     const double e1 = exp(-nu * k2 * dt);
                     const double c2 = first ? 0.0 : b2 * exp(-nu * k2 * dtp);
 #pragma unroll
                     for (int f = 0; f < 3; ++f) {
-                        const cx<T> uo = uhat[f * fs_s + e];
+                        const cx<T> uo = gld(uhat, f * fs_s + e);
                         double ar = nr[f], ai = ni[f];
                         if (!first) {
-                            const cx<T> no = nold[f * fs_s + e];
+                            const cx<T> no = gld(nold, f * fs_s + e);
                             ar = b1 * nr[f] + c2 * (double)no.x;
                             ai = b1 * ni[f] + c2 * (double)no.y;
                         }
                         const double vr = e1 * ((double)uo.x + dt * ar);
                         const double vi = e1 * ((double)uo.y + dt * ai);
                         U[f][i] = cx<T>{T(vr), T(vi)};
-                        uhat[f * fs_s + e] = U[f][i];
-                        nold[f * fs_s + e] = cx<T>{T(nr[f]), T(ni[f])};
+                        gst(uhat, f * fs_s + e, U[f][i]);
+                        gst(nold, f * fs_s + e, cx<T>{T(nr[f]), T(ni[f])});
                     }
                 }
             }
@@ -771,7 +849,7 @@ __global__ __launch_bounds__(nt_z(N)) void k_zpass(const cx<T>* __restrict__ yin
             if (m < M && okq) {
                 const long e = (long)m * Qp + q;
 #pragma unroll
-                for (int f = 0; f < 3; ++f) U[f][i] = uhat[f * fs_s + e];
+                for (int f = 0; f < 3; ++f) U[f][i] = gld(uhat, f * fs_s + e);
             }
         }
     }
@@ -807,7 +885,7 @@ __global__ __launch_bounds__(nt_z(N)) void k_zpass(const cx<T>* __restrict__ yin
 #pragma unroll
             for (int i = 0; i < RPT; ++i) o[i] = buf[c * SC + cpad(r0 + i * RS)];
 #pragma unroll
-            for (int i = 0; i < RPT; ++i) zout[g * fs_z + (long)(r0 + i * RS) * Qp + q] = o[i];
+            for (int i = 0; i < RPT; ++i) gst(zout, g * fs_z + (long)(r0 + i * RS) * Qp + q, o[i]);
         }
         __syncthreads();
     }
