@@ -51,8 +51,11 @@ listed in the design notes of the repository):
       the wing frame is M_wing M_stroke Omega_w^(b), and the wing velocity in
       the global frame is M_body^T M_stroke^T M_wing^T (Omega^(w) x x_w).
   Parts combine by the maximum of chi; u_s and colour come from the argmax
-      part (ties -> lowest colour).  Colours: 0 fluid, 1 body, 2 left wing,
-      3 right wing.
+      part, where a later part wins only if its chi exceeds the best so far
+      by more than the relative tie tolerance TIE_REL (ties, including
+      values equal up to rounding such as both wings on the mirror plane of a
+      symmetric insect, go to the lowest colour).  Colours: 0 fluid, 1 body,
+      2 left wing, 3 right wing.
   Force on the solid: F = (1/C_eta) sum chi (u - u_s) dV + (I^n - I^{n-1})/dt_{n-1}
       with I = sum chi u_s dV (no unsteady term at the first step); torques
       about the body centre (body) or the wing pivot (wings).
@@ -401,6 +404,25 @@ def to_body(ins: Insect, t: float, xg):
     return _apply(M_body(ins, t), xg - xc)
 
 
+# Relative tolerance under which two part values count as a tie.
+TIE_REL = 1e-9
+
+
+def part_of_max(stack: np.ndarray) -> np.ndarray:
+    """Index of the part that supplies u_s and the colour at each point.
+
+    Parts are taken in colour order; a later part replaces the current one only
+    if its chi is larger by more than TIE_REL relative, so ties (up to rounding)
+    resolve to the lowest colour."""
+    part = np.zeros(stack.shape[1:], dtype=np.int64)
+    best = stack[0].copy()
+    for p in range(1, stack.shape[0]):
+        take = stack[p] > best * (1.0 + TIE_REL)
+        part[take] = p
+        best = np.where(take, stack[p], best)
+    return part
+
+
 def insect_mask(g: Grid, ins: Insect, t: float):
     """chi, u_s [3] and colour on every grid point at time t  [Alg. 1 step (a)]."""
     n = g.n
@@ -434,7 +456,7 @@ def insect_mask(g: Grid, ins: Insect, t: float):
         uss += [np.zeros((3, n, n, n))] * 2
 
     stack = np.stack(chis)
-    part = np.argmax(stack, axis=0)             # first maximum -> lowest colour on ties
+    part = part_of_max(stack)
     chi = np.max(stack, axis=0)
     us = np.zeros((3, n, n, n))
     for p in range(3):

@@ -181,3 +181,34 @@ def test_model_insect_mirror_symmetry():
     u = O.velocity(p, st)
     mirrored = u[:, :, (-np.arange(n)) % n, :] * np.array([1, -1, 1])[:, None, None, None]
     assert np.max(np.abs(mirrored - u)) <= 1e-12 * np.max(np.abs(u))
+
+
+def test_part_choice_ties_go_to_the_lowest_colour():
+    # a later part wins only by more than the relative tie tolerance
+    st = np.array([[1.0, 1.0, 0.0, 0.0, 0.2],
+                   [1.0 + 1e-12, 1.0 + 1e-6, 0.0, 0.0, 0.2 * (1 + 1e-10)],
+                   [0.5, 0.5, 0.0, 1e-3, 0.2 * (1 - 1e-10)]])
+    assert O.part_of_max(st).tolist() == [0, 1, 0, 2, 0]
+
+
+def test_mirror_plane_points_take_the_left_wing():
+    # at 48^3 the wing roots reach the mid-plane y = L/2 (a grid plane): both
+    # wings give the same chi there up to rounding, so colour 2 (left) and the
+    # left wing velocity must be chosen
+    n, L = 48, 4.0
+    g = O.Grid(n, L)
+    ins = O.Insect.from_dict(W.model_insect(n, L))
+    t = 0.1
+    chi, us, col = O.insect_mask(g, ins, t)
+    x, y, z = g.coords()
+    xb = O.to_body(ins, t, np.stack([x, y, z]))
+    wl = [O.chi_of_delta(O.delta_elliptic_wing(*O.wing_frame(ins, t, s, xb), ins.wing_A, ins.wing_B, ins.wing_t),
+                         ins, g.dx) for s in ("l", "r")]
+    j = n // 2
+    both = (wl[0][:, j, :] > 1e-6) & (wl[1][:, j, :] > 1e-6)
+    assert both.sum() > 0
+    assert np.allclose(wl[0][:, j, :][both], wl[1][:, j, :][both], rtol=1e-12, atol=0)
+    wing_pts = both & (col[:, j, :] > 1)
+    assert wing_pts.sum() > 0 and np.all(col[:, j, :][wing_pts] == 2)
+    ul = O.wing_velocity(ins, t, "l", xb)
+    assert np.allclose(us[:, :, j, :][:, wing_pts], ul[:, :, j, :][:, wing_pts], rtol=0, atol=1e-14)
