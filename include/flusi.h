@@ -211,6 +211,48 @@ int flusi_forces(flusi_plan plan, const void* state, double* out);
 int flusi_profile(flusi_plan plan, int enable);
 int flusi_pass_times(flusi_plan plan, double* ms, long long* launches);
 
+/* ------------------------------------------------------------------------
+ * Ensembles: many independent simulations advanced together.
+ *
+ * A member is a (plan, state) pair with its body and step controls; plans
+ * may differ in n, L, nu and eta but share the ensemble's dtype, and a plan
+ * belongs to at most one member (its scratch buffers are the member's).
+ * Members of equal n form a size group.  flusi_ensemble_step launches each
+ * pass of Algorithm 1 once per size group over all of its members (one
+ * workgroup grid spanning every member), with the size groups on parallel
+ * streams forked from the ensemble's stream.  Each member follows exactly the
+ * arithmetic of flusi_step on its own plan, so results are bitwise equal to
+ * stepping the members one by one with the same schedule.
+ *
+ * Ownership: the ensemble keeps the plan and state pointers (it owns
+ * neither); destroy the ensemble before them.  Adding or removing members
+ * invalidates captured graphs (they are rebuilt on the next call).
+ * ------------------------------------------------------------------------ */
+typedef struct flusi_ensemble_s* flusi_ensemble;
+
+/* Empty ensemble for plans of the given dtype.  Errors: EINVAL, ENOMEM. */
+int flusi_ensemble_create(int dtype, flusi_ensemble* out);
+/* Synchronizes the ensemble's streams and frees its tables and graphs. */
+int flusi_ensemble_destroy(flusi_ensemble e);
+/* Stream (hipStream_t) on which flusi_ensemble_step is ordered. */
+int flusi_ensemble_set_stream(flusi_ensemble e, void* stream);
+/* Adds a member.  ins: body (NULL: no mask), copied; p: step controls as for
+ * flusi_step (p->nsteps is ignored; p->history, when set, receives one record
+ * per step of each flusi_ensemble_step call, row s for step s of the call).
+ * *id receives a member index that stays valid until the member is removed.
+ * Errors: EINVAL (dtype mismatch, plan already a member, bad controls). */
+int flusi_ensemble_add(flusi_ensemble e, flusi_plan plan, void* state, const flusi_insect* ins,
+                       const flusi_step_params* p, int* id);
+/* Removes member id (its state is left as it is). */
+int flusi_ensemble_remove(flusi_ensemble e, int id);
+/* Number of members and of size groups. */
+int flusi_ensemble_size(flusi_ensemble e, int* members, int* groups);
+/* Advances every member by nsteps steps (Algorithm 1, as flusi_step).
+ * use_graph != 0: the whole call (all groups, all steps) is captured once per
+ * distinct nsteps into a hipGraph and replayed on later calls.  No host
+ * synchronization. */
+int flusi_ensemble_step(flusi_ensemble e, int nsteps, int use_graph);
+
 #ifdef __cplusplus
 }
 #endif

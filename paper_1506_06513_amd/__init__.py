@@ -91,6 +91,14 @@ _SIGS = {
     "flusi_forces": (ctypes.c_int, [_P, _P, ctypes.POINTER(ctypes.c_double)]),
     "flusi_profile": (ctypes.c_int, [_P, ctypes.c_int]),
     "flusi_pass_times": (ctypes.c_int, [_P, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_longlong)]),
+    "flusi_ensemble_create": (ctypes.c_int, [ctypes.c_int, ctypes.POINTER(_P)]),
+    "flusi_ensemble_destroy": (ctypes.c_int, [_P]),
+    "flusi_ensemble_set_stream": (ctypes.c_int, [_P, _P]),
+    "flusi_ensemble_add": (ctypes.c_int, [_P, _P, _P, ctypes.POINTER(flusi_insect), ctypes.POINTER(flusi_step_params),
+                                          ctypes.POINTER(ctypes.c_int)]),
+    "flusi_ensemble_remove": (ctypes.c_int, [_P, ctypes.c_int]),
+    "flusi_ensemble_size": (ctypes.c_int, [_P, ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_int)]),
+    "flusi_ensemble_step": (ctypes.c_int, [_P, ctypes.c_int, ctypes.c_int]),
 }
 
 _lib = None
@@ -227,6 +235,42 @@ def flusi_pass_times(plan):
     return np.array(ms[:]), np.array(cnt[:], dtype=np.int64)
 
 
+def flusi_ensemble_create(dtype: int):
+    h = _P()
+    _check(lib().flusi_ensemble_create(dtype, ctypes.byref(h)))
+    return h
+
+
+def flusi_ensemble_destroy(ens):
+    _check(lib().flusi_ensemble_destroy(ens))
+
+
+def flusi_ensemble_set_stream(ens, stream):
+    _check(lib().flusi_ensemble_set_stream(ens, _P(stream)))
+
+
+def flusi_ensemble_add(ens, plan, state, ins: flusi_insect | None, params: flusi_step_params) -> int:
+    i = ctypes.c_int(-1)
+    _check(lib().flusi_ensemble_add(ens, plan, _ptr(state), ctypes.byref(ins) if ins is not None else None,
+                                    ctypes.byref(params), ctypes.byref(i)))
+    return i.value
+
+
+def flusi_ensemble_remove(ens, member: int):
+    _check(lib().flusi_ensemble_remove(ens, member))
+
+
+def flusi_ensemble_size(ens):
+    m = ctypes.c_int()
+    g = ctypes.c_int()
+    _check(lib().flusi_ensemble_size(ens, ctypes.byref(m), ctypes.byref(g)))
+    return m.value, g.value
+
+
+def flusi_ensemble_step(ens, nsteps: int, use_graph: bool):
+    _check(lib().flusi_ensemble_step(ens, nsteps, 1 if use_graph else 0))
+
+
 # ----------------------------------------------------------------------------
 # Conveniences
 # ----------------------------------------------------------------------------
@@ -348,3 +392,50 @@ class Plan:
 
     def time(self, state):
         return flusi_state_time(self.handle, state)
+
+
+def step_params(nsteps: int = 0, dt_fixed: float = 0.0, cfl: float = 0.1, dt_max: float = 0.0, eta_cap: float = 0.5,
+                t_end: float = 0.0, mean_mode: int = FLUSI_MEAN_FIXED, history=None) -> flusi_step_params:
+    return flusi_step_params(nsteps, mean_mode, dt_fixed, cfl, dt_max, eta_cap, t_end,
+                             _ptr(history) if history is not None else None)
+
+
+class Ensemble:
+    """Many (plan, state) members advanced together by flusi_ensemble_step.
+
+    Keeps references to the member plans and states so that they outlive the
+    ensemble."""
+
+    def __init__(self, dtype: str = "f32"):
+        self.dtype = dtype
+        self.handle = flusi_ensemble_create(FLUSI_F64 if dtype == "f64" else FLUSI_F32)
+        self._keep = {}
+        flusi_ensemble_set_stream(self.handle, torch.cuda.current_stream().cuda_stream)
+
+    def add(self, plan: Plan, state: torch.Tensor, insect: dict | None = None, history=None, **controls) -> int:
+        p = step_params(0, history=history, **controls)
+        i = flusi_ensemble_add(self.handle, plan.handle, state, make_insect(insect), p)
+        self._keep[i] = (plan, state, history)
+        return i
+
+    def remove(self, member: int):
+        flusi_ensemble_remove(self.handle, member)
+        self._keep.pop(member, None)
+
+    def size(self):
+        return flusi_ensemble_size(self.handle)
+
+    def step(self, nsteps: int, graph: bool = False):
+        flusi_ensemble_step(self.handle, nsteps, graph)
+
+    def close(self):
+        if self.handle is not None:
+            flusi_ensemble_destroy(self.handle)
+            self.handle = None
+            self._keep.clear()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

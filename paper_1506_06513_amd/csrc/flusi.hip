@@ -1,8 +1,10 @@
 // C ABI of the pseudo-spectral penalized Navier-Stokes library (see include/flusi.h).
+#include <algorithm>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <map>
 #include <new>
 #include <vector>
 
@@ -325,6 +327,263 @@ int flusi_pass_times(flusi_plan plan, double* ms, long long* launches) {
         if (ms) ms[i] = acc[i];
         if (launches) launches[i] = cnt[i];
     }
+    return FLUSI_OK;
+}
+
+}  // extern "C"
+
+// ---------------------------------------------------------------------------
+// Ensembles
+// ---------------------------------------------------------------------------
+namespace flusi {
+struct EnsMember {
+    flusi_plan plan = nullptr;
+    void* state = nullptr;
+    bool has_ins = false;
+    flusi_insect ins{};
+    flusi_step_params sp{};
+    bool used = false;
+};
+struct EnsGroup {
+    int n = 0;
+    ImplBase* impl = nullptr;
+    Member* dev = nullptr;  // device member table
+    GroupRun run;
+    hipEvent_t done = nullptr;
+};
+}  // namespace flusi
+
+struct flusi_ensemble_s {
+    int dtype = 0;
+    hipStream_t ext = nullptr;   // caller's stream
+    hipStream_t own = nullptr;   // ordering/capture stream of the ensemble
+    hipEvent_t ev_in = nullptr, ev_out = nullptr, fork = nullptr;
+    std::vector<flusi::EnsMember> members;
+    std::vector<flusi::EnsGroup> groups;
+    std::vector<hipStream_t> pool;  // one stream per size group
+    std::map<int, hipGraphExec_t> graphs;
+    bool dirty = true;
+};
+
+namespace flusi {
+static void ens_clear_groups(flusi_ensemble e) {
+    for (auto& g : e->groups) {
+        if (g.dev) (void)hipFree(g.dev);
+        if (g.done) (void)hipEventDestroy(g.done);
+    }
+    e->groups.clear();
+    for (auto& kv : e->graphs) (void)hipGraphExecDestroy(kv.second);
+    e->graphs.clear();
+}
+
+// Groups the members by grid size, orders each group by colour count and
+// uploads the launch tables (synchronous; outside the stepping hot path).
+static int ens_rebuild(flusi_ensemble e) {
+    if (!e->dirty) return FLUSI_OK;
+    hipError_t err = hipStreamSynchronize(e->own);
+    if (err != hipSuccess) return set_error(FLUSI_EDEVICE, "ensemble: %s", hipGetErrorString(err));
+    ens_clear_groups(e);
+    std::map<int, std::vector<int>> by_n;
+    for (int i = 0; i < (int)e->members.size(); ++i)
+        if (e->members[i].used) by_n[e->members[i].plan->d.n].push_back(i);
+    for (auto& kv : by_n) {
+        std::vector<int>& ids = kv.second;
+        auto nc_of = [&](int i) { return colour_count(e->members[i].has_ins ? &e->members[i].ins : nullptr); };
+        std::stable_sort(ids.begin(), ids.end(), [&](int a, int b) { return nc_of(a) < nc_of(b); });
+        EnsGroup g;
+        g.n = kv.first;
+        const PlanData& p0 = e->members[ids[0]].plan->d;
+        g.impl = p0.impl;
+        std::vector<Member> host;
+        for (int i : ids) {
+            EnsMember& m = e->members[i];
+            PlanData& pd = m.plan->d;
+            const flusi_insect* ins = m.has_ins ? &m.ins : nullptr;
+            if (ins) {
+                err = hipMemcpy(pd.ins_dev, ins, sizeof(flusi_insect), hipMemcpyHostToDevice);
+                if (err != hipSuccess) return set_error(FLUSI_EDEVICE, "ensemble: %s", hipGetErrorString(err));
+            }
+            const Member rec = make_member(pd, m.state, ins, m.sp);
+            host.push_back(rec);
+            const int nc = rec.nc;
+            g.run.n_nc[nc == 0 ? 0 : (nc == 1 ? 1 : 2)] += 1;
+            g.run.any_dyn = g.run.any_dyn || rec.dyn;
+        }
+        if (hipMalloc(&g.dev, host.size() * sizeof(Member)) != hipSuccess)
+            return set_error(FLUSI_ENOMEM, "ensemble: member table");
+        err = hipMemcpy(g.dev, host.data(), host.size() * sizeof(Member), hipMemcpyHostToDevice);
+        if (err == hipSuccess) err = hipEventCreateWithFlags(&g.done, hipEventDisableTiming);
+        if (err != hipSuccess) {
+            (void)hipFree(g.dev);
+            return set_error(FLUSI_EDEVICE, "ensemble: %s", hipGetErrorString(err));
+        }
+        g.run.mt = g.dev;
+        g.run.nmem = (int)host.size();
+        g.run.tw = p0.tw;
+        g.run.split_z = p0.split_z;
+        e->groups.push_back(g);
+    }
+    while (e->pool.size() < e->groups.size()) {
+        hipStream_t st;
+        err = hipStreamCreateWithFlags(&st, hipStreamNonBlocking);
+        if (err != hipSuccess) return set_error(FLUSI_EDEVICE, "ensemble: %s", hipGetErrorString(err));
+        e->pool.push_back(st);
+    }
+    e->dirty = false;
+    return FLUSI_OK;
+}
+
+// Enqueues nsteps of every group on e->own (forking one stream per group).
+static int ens_launch(flusi_ensemble e, int nsteps) {
+    if (e->groups.size() == 1) {
+        GroupRun r = e->groups[0].run;
+        r.stream = e->own;
+        return e->groups[0].impl->run_steps(r, nsteps);
+    }
+    hipError_t err = hipEventRecord(e->fork, e->own);
+    for (size_t i = 0; i < e->groups.size() && err == hipSuccess; ++i) {
+        EnsGroup& g = e->groups[i];
+        err = hipStreamWaitEvent(e->pool[i], e->fork, 0);
+        if (err != hipSuccess) break;
+        GroupRun r = g.run;
+        r.stream = e->pool[i];
+        if (int rc = g.impl->run_steps(r, nsteps)) return rc;
+        err = hipEventRecord(g.done, e->pool[i]);
+        if (err == hipSuccess) err = hipStreamWaitEvent(e->own, g.done, 0);
+    }
+    if (err != hipSuccess) return set_error(FLUSI_EDEVICE, "ensemble step: %s", hipGetErrorString(err));
+    return FLUSI_OK;
+}
+}  // namespace flusi
+
+extern "C" {
+
+int flusi_ensemble_create(int dtype, flusi_ensemble* out) {
+    if (!out) return set_error(FLUSI_EINVAL, "out is NULL");
+    *out = nullptr;
+    if (dtype != FLUSI_F32 && dtype != FLUSI_F64) return set_error(FLUSI_EINVAL, "dtype must be FLUSI_F32 or FLUSI_F64");
+    flusi_ensemble e = new (std::nothrow) flusi_ensemble_s();
+    if (!e) return set_error(FLUSI_ENOMEM, "host allocation");
+    e->dtype = dtype;
+    hipError_t err = hipStreamCreateWithFlags(&e->own, hipStreamNonBlocking);
+    if (err == hipSuccess) err = hipEventCreateWithFlags(&e->ev_in, hipEventDisableTiming);
+    if (err == hipSuccess) err = hipEventCreateWithFlags(&e->ev_out, hipEventDisableTiming);
+    if (err == hipSuccess) err = hipEventCreateWithFlags(&e->fork, hipEventDisableTiming);
+    if (err != hipSuccess) {
+        flusi_ensemble_destroy(e);
+        return set_error(FLUSI_EDEVICE, "ensemble_create: %s", hipGetErrorString(err));
+    }
+    *out = e;
+    return FLUSI_OK;
+}
+
+int flusi_ensemble_destroy(flusi_ensemble e) {
+    if (!e) return FLUSI_OK;
+    if (e->own) (void)hipStreamSynchronize(e->own);
+    ens_clear_groups(e);
+    for (hipStream_t s : e->pool) (void)hipStreamDestroy(s);
+    if (e->ev_in) (void)hipEventDestroy(e->ev_in);
+    if (e->ev_out) (void)hipEventDestroy(e->ev_out);
+    if (e->fork) (void)hipEventDestroy(e->fork);
+    if (e->own) (void)hipStreamDestroy(e->own);
+    delete e;
+    return FLUSI_OK;
+}
+
+int flusi_ensemble_set_stream(flusi_ensemble e, void* stream) {
+    if (!e) return set_error(FLUSI_EINVAL, "null ensemble");
+    e->ext = static_cast<hipStream_t>(stream);
+    return FLUSI_OK;
+}
+
+int flusi_ensemble_add(flusi_ensemble e, flusi_plan plan, void* state, const flusi_insect* ins,
+                       const flusi_step_params* p, int* id) {
+    if (!e) return set_error(FLUSI_EINVAL, "null ensemble");
+    if (int rc = check_plan(plan)) return rc;
+    if (!state || !p) return set_error(FLUSI_EINVAL, "ensemble_add: null pointer");
+    if (plan->d.dtype != e->dtype) return set_error(FLUSI_EINVAL, "ensemble_add: plan dtype differs from the ensemble's");
+    if (!(p->dt_fixed > 0.0) && !(p->cfl > 0.0)) return set_error(FLUSI_EINVAL, "ensemble_add: need dt_fixed > 0 or cfl > 0");
+    for (const auto& m : e->members)
+        if (m.used && m.plan == plan) return set_error(FLUSI_EINVAL, "ensemble_add: plan is already a member");
+    EnsMember m;
+    m.plan = plan;
+    m.state = state;
+    m.has_ins = colour_count(ins) > 0;
+    if (m.has_ins) m.ins = *ins;
+    m.sp = *p;
+    m.sp.nsteps = 0;
+    m.used = true;
+    int slot = -1;
+    for (int i = 0; i < (int)e->members.size(); ++i)
+        if (!e->members[i].used) {
+            slot = i;
+            break;
+        }
+    if (slot < 0) {
+        slot = (int)e->members.size();
+        e->members.push_back(m);
+    } else {
+        e->members[slot] = m;
+    }
+    e->dirty = true;
+    if (id) *id = slot;
+    return FLUSI_OK;
+}
+
+int flusi_ensemble_remove(flusi_ensemble e, int id) {
+    if (!e) return set_error(FLUSI_EINVAL, "null ensemble");
+    if (id < 0 || id >= (int)e->members.size() || !e->members[id].used)
+        return set_error(FLUSI_EINVAL, "ensemble_remove: no member %d", id);
+    e->members[id].used = false;
+    e->dirty = true;
+    return FLUSI_OK;
+}
+
+int flusi_ensemble_size(flusi_ensemble e, int* members, int* groups) {
+    if (!e) return set_error(FLUSI_EINVAL, "null ensemble");
+    if (int rc = ens_rebuild(e)) return rc;
+    int n = 0;
+    for (const auto& m : e->members) n += m.used ? 1 : 0;
+    if (members) *members = n;
+    if (groups) *groups = (int)e->groups.size();
+    return FLUSI_OK;
+}
+
+int flusi_ensemble_step(flusi_ensemble e, int nsteps, int use_graph) {
+    if (!e) return set_error(FLUSI_EINVAL, "null ensemble");
+    if (nsteps < 0) return set_error(FLUSI_EINVAL, "ensemble_step: nsteps < 0");
+    if (int rc = ens_rebuild(e)) return rc;
+    if (nsteps == 0 || e->groups.empty()) return FLUSI_OK;
+    hipError_t err = hipEventRecord(e->ev_in, e->ext);
+    if (err == hipSuccess) err = hipStreamWaitEvent(e->own, e->ev_in, 0);
+    if (err != hipSuccess) return set_error(FLUSI_EDEVICE, "ensemble_step: %s", hipGetErrorString(err));
+    if (use_graph) {
+        auto it = e->graphs.find(nsteps);
+        if (it == e->graphs.end()) {
+            err = hipStreamBeginCapture(e->own, hipStreamCaptureModeThreadLocal);
+            if (err != hipSuccess) return set_error(FLUSI_EDEVICE, "ensemble capture: %s", hipGetErrorString(err));
+            const int rc = ens_launch(e, nsteps);
+            hipGraph_t graph = nullptr;
+            err = hipStreamEndCapture(e->own, &graph);
+            if (rc) {
+                if (graph) (void)hipGraphDestroy(graph);
+                return rc;
+            }
+            if (err != hipSuccess) return set_error(FLUSI_EDEVICE, "ensemble capture: %s", hipGetErrorString(err));
+            hipGraphExec_t exec = nullptr;
+            err = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+            (void)hipGraphDestroy(graph);
+            if (err != hipSuccess) return set_error(FLUSI_EDEVICE, "ensemble graph: %s", hipGetErrorString(err));
+            it = e->graphs.emplace(nsteps, exec).first;
+        }
+        err = hipGraphLaunch(it->second, e->own);
+        if (err != hipSuccess) return set_error(FLUSI_EDEVICE, "ensemble graph launch: %s", hipGetErrorString(err));
+    } else {
+        if (int rc = ens_launch(e, nsteps)) return rc;
+    }
+    err = hipEventRecord(e->ev_out, e->own);
+    if (err == hipSuccess) err = hipStreamWaitEvent(e->ext, e->ev_out, 0);
+    if (err != hipSuccess) return set_error(FLUSI_EDEVICE, "ensemble_step: %s", hipGetErrorString(err));
     return FLUSI_OK;
 }
 

@@ -239,28 +239,27 @@ __device__ __forceinline__ void cross(const TM* a, const TM* b, TM* o) {
     o[0] = x; o[1] = y; o[2] = z;
 }
 
-// chi, u_s and colour at global point (x, y, z).  Reads only the kinematics
-// block (kept in LDS by the callers).
+// Relative tolerance under which two part values count as a tie: a later part
+// replaces the current one only if its chi is larger by more than this, so ties
+// (including values equal up to rounding, e.g. both wings on the mirror plane
+// of a symmetric insect) go to the lowest colour.
+constexpr double TIE_REL = 1e-9;
+
+// chi of each part (body, left wing, right wing; 0 where absent or culled) and
+// the body-frame coordinates of the point.
 template <typename TM>
-__device__ __forceinline__ MaskPt<TM> eval_mask(const KinT<TM>& k, TM x, TM y, TM z) {
-    MaskPt<TM> o;
-    o.chi = TM(0);
-    o.us[0] = o.us[1] = o.us[2] = TM(0);
-    o.colour = 0;
+__device__ __forceinline__ void part_chis(const KinT<TM>& k, TM x, TM y, TM z, TM (&c)[3], TM (&xb)[3]) {
+    c[0] = c[1] = c[2] = TM(0);
     const TM rel[3] = {x - k.xc[0], y - k.xc[1], z - k.xc[2]};
     const TM r2 = rel[0] * rel[0] + rel[1] * rel[1] + rel[2] * rel[2];
-    if (r2 > k.r2all) return o;
-    TM xb[3];
     mvec(k.Mb, rel, xb);
-    TM best = TM(0);
-    int part = 0;
     if (k.body == FLUSI_BODY_SPHERE) {
-        best = chi_of(sqrt(r2) - k.radius, k);
+        c[0] = chi_of(sqrt(r2) - k.radius, k);
     } else if (k.body == FLUSI_BODY_ELLIPSOID) {
         const TM q = xb[0] / k.ea;
         const TM rad = sqrt(xb[1] * xb[1] + xb[2] * xb[2]);
         const TM d = fmax(rad - k.eb * sqrt(fmax(TM(0), TM(1) - q * q)), fabs(xb[0]) - k.ea);
-        best = chi_of(d, k);
+        c[0] = chi_of(d, k);
     }
     if (k.wings) {
         const TM mab = fmax(k.wA, k.wB);
@@ -275,15 +274,63 @@ __device__ __forceinline__ MaskPt<TM> eval_mask(const KinT<TM>& k, TM x, TM y, T
             const TM qa = xw[0] / k.wA, qb = ey / k.wB;
             const TM rho = sqrt(qa * qa + qb * qb);
             const TM inplane = r > TM(0) ? r - r / rho : -k.wA;
-            const TM c = chi_of(fmax(dz, inplane), k);
-            if (c > best) {
-                best = c;
-                part = 1 + s;
-            }
+            const TM cw = chi_of(fmax(dz, inplane), k);
+            if (s == 0) c[1] = cw;
+            else c[2] = cw;
         }
     }
-    if (best <= TM(0)) return o;
-    o.chi = best;
+}
+
+// Part that supplies u_s and the colour (parts in colour order, ties to the
+// lowest).
+template <typename TV>
+__device__ __forceinline__ int part_of_max(const TV (&c)[3]) {
+    int part = 0;
+    TV best = c[0];
+    if (c[1] > best * TV(1.0 + TIE_REL)) {
+        part = 1;
+        best = c[1];
+    }
+    if (c[2] > best * TV(1.0 + TIE_REL)) part = 2;
+    return part;
+}
+
+// Part choice in FP64 at a point where two parts overlap.  Out of line: the
+// FP64 geometry is rare and would otherwise set the register count of the
+// FP32 kernels that call eval_mask.
+__device__ __attribute__((noinline)) int part_of_max64(const KinT<double>* k64, double x, double y, double z) {
+    double c64[3], xb64[3];
+    part_chis(*k64, x, y, z, c64, xb64);
+    return part_of_max(c64);
+}
+
+// chi, u_s and colour at the grid point with global coordinates (x, y, z).
+// Reads only the kinematics blocks (kept in LDS by the callers).  With TM =
+// float, k64 (the FP64 kinematics) decides the part wherever two parts
+// overlap, so the integer part choice is taken in FP64 as in the FP64 path.
+template <typename TM>
+__device__ __forceinline__ MaskPt<TM> eval_mask(const KinT<TM>& k, double x, double y, double z,
+                                                const KinT<double>* k64) {
+    MaskPt<TM> o;
+    o.chi = TM(0);
+    o.us[0] = o.us[1] = o.us[2] = TM(0);
+    o.colour = 0;
+    const TM xt = TM(x), yt = TM(y), zt = TM(z);
+    {
+        const TM r0 = xt - k.xc[0], r1 = yt - k.xc[1], r2c = zt - k.xc[2];
+        if (r0 * r0 + r1 * r1 + r2c * r2c > k.r2all) return o;
+    }
+    TM c[3], xb[3];
+    part_chis(k, xt, yt, zt, c, xb);
+    const TM chimax = fmax(c[0], fmax(c[1], c[2]));
+    if (chimax <= TM(0)) return o;
+    int part;
+    if (k64 != nullptr && (int(c[0] > TM(0)) + int(c[1] > TM(0)) + int(c[2] > TM(0))) >= 2) {
+        part = part_of_max64(k64, x, y, z);
+    } else {
+        part = part_of_max(c);
+    }
+    o.chi = chimax;
     o.colour = part + 1;
     // u_b = u_cntr + Mb^T (omb x x_b)
     TM cr[3], ub[3];

@@ -15,6 +15,8 @@
 // moment_of_love), Sec. 2.4 (Fourier discretization, 2/3 rule, AB2 with
 // integrating factor), Algorithm 1.
 #pragma once
+#include <type_traits>
+
 #include "common.hpp"
 #include "fft.hpp"
 #include "insect.hpp"
@@ -319,11 +321,17 @@ __global__ __launch_bounds__(NT) void k_xpass(const Member* __restrict__ mt, con
     __shared__ double red[NT / 64][NV];
     __shared__ double wred[NT / 64][NV];
     __shared__ KinT<T> kin;
+    // FP64 kinematics for the part choice where parts overlap (FP32 runs)
+    constexpr bool K64 = NC > 1 && sizeof(T) < 8;
+    __shared__ typename std::conditional<K64, KinT<double>, char>::type kin64;
     if (*gview(&hdr->status)) return;
     const int tid = threadIdx.x;
     const int row0 = wg * RW;
     if constexpr (NC > 0) {
         if (tid == 0) kin_cast<T>(hdr->kin, kin);
+    }
+    if constexpr (K64) {
+        if (tid == 64) kin_cast<double>(hdr->kin, kin64);
     }
 
     // 1. pack three Hermitian pairs per row: Z = X + iY over the full x axis
@@ -404,8 +412,10 @@ __global__ __launch_bounds__(NT) void k_xpass(const Member* __restrict__ mt, con
         acc[1] += u2;
         if (!isfinite(u2)) acc[2] = 1.0;
         if constexpr (NC > 0) {
-            const T xg = T(dx * i), yg = T(dx * (row % N)), zg = T(dx * (row / N));
-            const MaskPt<T> mp = eval_mask<T>(kin, xg, yg, zg);
+            const double xg = dx * i, yg = dx * (row % N), zg = dx * (row / N);
+            const KinT<double>* k64 = nullptr;
+            if constexpr (K64) k64 = &kin64;
+            const MaskPt<T> mp = eval_mask<T>(kin, xg, yg, zg, k64);
             const bool has = mp.chi > T(0);
             // FP64 force and torque terms from the working-precision mask values
             const auto terms = [&](double* val) {
@@ -420,7 +430,7 @@ __global__ __launch_bounds__(NT) void k_xpass(const Member* __restrict__ mt, con
                 const double xr0 = ci == 0 ? kin.xref[0][0] : (ci == 1 ? kin.xref[1][0] : kin.xref[2][0]);
                 const double xr1 = ci == 0 ? kin.xref[0][1] : (ci == 1 ? kin.xref[1][1] : kin.xref[2][1]);
                 const double xr2 = ci == 0 ? kin.xref[0][2] : (ci == 1 ? kin.xref[1][2] : kin.xref[2][2]);
-                const double rx = (double)xg - xr0, ry = (double)yg - xr1, rz = (double)zg - xr2;
+                const double rx = xg - xr0, ry = yg - xr1, rz = zg - xr2;
                 val[0] = p0; val[1] = p1; val[2] = p2;
                 val[3] = ry * p2 - rz * p1; val[4] = rz * p0 - rx * p2; val[5] = rx * p1 - ry * p0;
                 val[6] = i0; val[7] = i1; val[8] = i2;
@@ -1051,13 +1061,20 @@ template <typename T>
 __global__ void k_mask(const Kin* __restrict__ kin, int n, double dx, T* __restrict__ chi,
                        T* __restrict__ us, int16_t* __restrict__ colour) {
     __shared__ KinT<T> kt;
+    constexpr bool K64 = sizeof(T) < 8;
+    __shared__ typename std::conditional<K64, KinT<double>, char>::type k64s;
     if (threadIdx.x == 0) kin_cast<T>(*kin, kt);
+    if constexpr (K64) {
+        if (threadIdx.x == 64) kin_cast<double>(*kin, k64s);
+    }
     __syncthreads();
     const long npts = (long)n * n * n;
     const long p = (long)blockIdx.x * blockDim.x + threadIdx.x;
     if (p >= npts) return;
     const int i = p % n, j = (p / n) % n, k = p / ((long)n * n);
-    const MaskPt<T> mp = eval_mask<T>(kt, T(dx * i), T(dx * j), T(dx * k));
+    const KinT<double>* k64 = nullptr;
+    if constexpr (K64) k64 = &k64s;
+    const MaskPt<T> mp = eval_mask<T>(kt, dx * i, dx * j, dx * k, k64);
     if (chi) chi[p] = T(mp.chi);
     if (us) {
         us[p] = T(mp.us[0]);
