@@ -212,6 +212,41 @@ int flusi_profile(flusi_plan plan, int enable);
 int flusi_pass_times(flusi_plan plan, double* ms, long long* launches);
 
 /* ------------------------------------------------------------------------
+ * Schedules and the autotuner.
+ *
+ * Each stepping pass (y-inverse, x-pass, y-forward, z-pass) exists in two
+ * tile variants: 0 (default) and 1 (y passes: half the columns per
+ * workgroup; x-pass: half the rows; z-pass: more threads per column).  The
+ * z-pass runs either as one launch (update, curl and inverse z) or as two
+ * (update, then curl + inverse z).  The velocity field does not depend on
+ * the schedule (every variant performs the same operations per value); the
+ * x-pass variant changes only the summation order of the FP64 diagnostic
+ * integrals (energy, force, torque), at round-off level.
+ * ------------------------------------------------------------------------ */
+typedef struct {
+    int y_inverse;   /* tile variant, 0 or 1 */
+    int x_pass;
+    int y_forward;
+    int z_pass;
+    int split_z;     /* 1: z-pass as update + inverse launches, 0: one launch */
+    int reserved[3]; /* zero */
+} flusi_schedule;
+
+/* Schedule used by this plan's flusi_step calls (and by an ensemble size
+ * group whose first member is this plan).  Errors: EINVAL (variant not 0/1). */
+int flusi_plan_get_schedule(flusi_plan plan, flusi_schedule* out);
+int flusi_plan_set_schedule(flusi_plan plan, const flusi_schedule* s);
+
+/* Times every variant of every pass over reps steps (after 2 warm-up steps)
+ * on a scratch copy of `state` with body ins and controls p, keeps the
+ * fastest variant per pass, then the faster of the one- and two-launch
+ * z-pass, and makes that the plan's schedule (also returned in *out, which
+ * may be NULL).  The state itself is not modified.  Synchronous.  Errors:
+ * EINVAL, ENOMEM, EDEVICE. */
+int flusi_autotune(flusi_plan plan, const void* state, const flusi_insect* ins, const flusi_step_params* p,
+                   int reps, flusi_schedule* out);
+
+/* ------------------------------------------------------------------------
  * Ensembles: many independent simulations advanced together.
  *
  * A member is a (plan, state) pair with its body and step controls; plans
@@ -252,6 +287,11 @@ int flusi_ensemble_size(flusi_ensemble e, int* members, int* groups);
  * distinct nsteps into a hipGraph and replayed on later calls.  No host
  * synchronization. */
 int flusi_ensemble_step(flusi_ensemble e, int nsteps, int use_graph);
+/* Autotunes every size group as a whole (all of its members in each timed
+ * launch, as flusi_ensemble_step runs them) on scratch copies of the member
+ * states, and stores the chosen schedule in the group's first plan.  Member
+ * states are not modified.  Synchronous. */
+int flusi_ensemble_autotune(flusi_ensemble e, int reps);
 
 #ifdef __cplusplus
 }

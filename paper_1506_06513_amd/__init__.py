@@ -69,6 +69,14 @@ class flusi_step_params(ctypes.Structure):
     ]
 
 
+class flusi_schedule(ctypes.Structure):
+    _fields_ = [("y_inverse", ctypes.c_int), ("x_pass", ctypes.c_int), ("y_forward", ctypes.c_int),
+                ("z_pass", ctypes.c_int), ("split_z", ctypes.c_int), ("reserved", ctypes.c_int * 3)]
+
+    def as_dict(self) -> dict:
+        return {k: int(getattr(self, k)) for k in ("y_inverse", "x_pass", "y_forward", "z_pass", "split_z")}
+
+
 _P = ctypes.c_void_p
 _SIGS = {
     "flusi_last_error": (ctypes.c_char_p, []),
@@ -91,6 +99,11 @@ _SIGS = {
     "flusi_forces": (ctypes.c_int, [_P, _P, ctypes.POINTER(ctypes.c_double)]),
     "flusi_profile": (ctypes.c_int, [_P, ctypes.c_int]),
     "flusi_pass_times": (ctypes.c_int, [_P, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_longlong)]),
+    "flusi_plan_get_schedule": (ctypes.c_int, [_P, ctypes.POINTER(flusi_schedule)]),
+    "flusi_plan_set_schedule": (ctypes.c_int, [_P, ctypes.POINTER(flusi_schedule)]),
+    "flusi_autotune": (ctypes.c_int, [_P, _P, ctypes.POINTER(flusi_insect), ctypes.POINTER(flusi_step_params),
+                                      ctypes.c_int, ctypes.POINTER(flusi_schedule)]),
+    "flusi_ensemble_autotune": (ctypes.c_int, [_P, ctypes.c_int]),
     "flusi_ensemble_create": (ctypes.c_int, [ctypes.c_int, ctypes.POINTER(_P)]),
     "flusi_ensemble_destroy": (ctypes.c_int, [_P]),
     "flusi_ensemble_set_stream": (ctypes.c_int, [_P, _P]),
@@ -233,6 +246,34 @@ def flusi_pass_times(plan):
     cnt = (ctypes.c_longlong * FLUSI_NPASS)()
     _check(lib().flusi_pass_times(plan, ms, cnt))
     return np.array(ms[:]), np.array(cnt[:], dtype=np.int64)
+
+
+def flusi_plan_get_schedule(plan) -> flusi_schedule:
+    s = flusi_schedule()
+    _check(lib().flusi_plan_get_schedule(plan, ctypes.byref(s)))
+    return s
+
+
+def flusi_plan_set_schedule(plan, sched: flusi_schedule):
+    _check(lib().flusi_plan_set_schedule(plan, ctypes.byref(sched)))
+
+
+def flusi_autotune(plan, state, ins: flusi_insect | None, params: flusi_step_params, reps: int) -> flusi_schedule:
+    s = flusi_schedule()
+    _check(lib().flusi_autotune(plan, _ptr(state), ctypes.byref(ins) if ins is not None else None,
+                                ctypes.byref(params), reps, ctypes.byref(s)))
+    return s
+
+
+def flusi_ensemble_autotune(ens, reps: int):
+    _check(lib().flusi_ensemble_autotune(ens, reps))
+
+
+def make_schedule(d: dict) -> flusi_schedule:
+    s = flusi_schedule()
+    for k, v in d.items():
+        setattr(s, k, int(v))
+    return s
 
 
 def flusi_ensemble_create(dtype: int):
@@ -380,6 +421,17 @@ class Plan:
     def forces(self, state):
         return flusi_forces(self.handle, state)
 
+    def schedule(self) -> dict:
+        return flusi_plan_get_schedule(self.handle).as_dict()
+
+    def set_schedule(self, sched: dict):
+        cur = self.schedule()
+        cur.update(sched)
+        flusi_plan_set_schedule(self.handle, make_schedule(cur))
+
+    def autotune(self, state, insect: dict | None = None, reps: int = 10, **controls) -> dict:
+        return flusi_autotune(self.handle, state, make_insect(insect), step_params(0, **controls), reps).as_dict()
+
     def velocity(self, state) -> torch.Tensor:
         u = self.real(3)
         flusi_state_velocity(self.handle, state, u)
@@ -427,6 +479,9 @@ class Ensemble:
 
     def step(self, nsteps: int, graph: bool = False):
         flusi_ensemble_step(self.handle, nsteps, graph)
+
+    def autotune(self, reps: int = 5):
+        flusi_ensemble_autotune(self.handle, reps)
 
     def close(self):
         if self.handle is not None:

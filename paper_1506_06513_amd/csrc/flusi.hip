@@ -112,6 +112,112 @@ static void free_plan(PlanData& d) {
     delete d.impl;
     d.impl = nullptr;
 }
+static int sched_check(const flusi_schedule& s) {
+    const int v[5] = {s.y_inverse, s.x_pass, s.y_forward, s.z_pass, s.split_z};
+    for (int x : v)
+        if (x != 0 && x != 1) return set_error(FLUSI_EINVAL, "schedule entries must be 0 or 1");
+    return FLUSI_OK;
+}
+static Sched sched_from(const flusi_schedule& s) {
+    Sched d;
+    d.y_inverse = s.y_inverse;
+    d.x_pass = s.x_pass;
+    d.y_forward = s.y_forward;
+    d.z_pass = s.z_pass;
+    d.split_z = s.split_z;
+    return d;
+}
+static flusi_schedule sched_to(const Sched& d) {
+    flusi_schedule s{};
+    s.y_inverse = d.y_inverse;
+    s.x_pass = d.x_pass;
+    s.y_forward = d.y_forward;
+    s.z_pass = d.z_pass;
+    s.split_z = d.split_z;
+    return s;
+}
+
+// Average time per launch of each stepping pass over reps steps of g with
+// schedule sc (prof: plan whose event pool records the passes).
+static int time_passes(ImplBase* impl, GroupRun g, const Sched& sc, PlanData& prof, int reps, double* avg_ms) {
+    g.sched = sc;
+    g.prof = nullptr;
+    if (int rc = impl->run_steps(g, 2)) return rc;
+    const bool was = prof.prof;
+    prof.prof = true;
+    prof.prof_recs.clear();
+    prof.ev_used = 0;
+    g.prof = &prof;
+    int rc = impl->run_steps(g, reps);
+    prof.prof = was;
+    if (rc) return rc;
+    hipError_t e = hipStreamSynchronize(g.stream);
+    if (e != hipSuccess) return set_error(FLUSI_EDEVICE, "autotune: %s", hipGetErrorString(e));
+    double acc[FLUSI_NPASS] = {0};
+    int cnt[FLUSI_NPASS] = {0};
+    for (const auto& r : prof.prof_recs) {
+        float t = 0.0f;
+        e = hipEventElapsedTime(&t, prof.events[r.second], prof.events[r.second + 1]);
+        if (e != hipSuccess) return set_error(FLUSI_EDEVICE, "autotune: %s", hipGetErrorString(e));
+        acc[r.first] += t;
+        cnt[r.first] += 1;
+    }
+    prof.prof_recs.clear();
+    prof.ev_used = 0;
+    for (int i = 0; i < FLUSI_NPASS; ++i) avg_ms[i] = cnt[i] ? acc[i] / cnt[i] : 0.0;
+    return FLUSI_OK;
+}
+
+// Whole-step time (ms per step) of g with schedule sc.
+static int time_steps(ImplBase* impl, GroupRun g, const Sched& sc, int reps, double* ms_per_step) {
+    g.sched = sc;
+    g.prof = nullptr;
+    if (int rc = impl->run_steps(g, 2)) return rc;
+    hipEvent_t a, b;
+    if (hipEventCreate(&a) != hipSuccess) return set_error(FLUSI_EDEVICE, "autotune: event");
+    if (hipEventCreate(&b) != hipSuccess) {
+        (void)hipEventDestroy(a);
+        return set_error(FLUSI_EDEVICE, "autotune: event");
+    }
+    hipError_t e = hipEventRecord(a, g.stream);
+    int rc = e == hipSuccess ? impl->run_steps(g, reps) : FLUSI_OK;
+    if (e == hipSuccess && !rc) e = hipEventRecord(b, g.stream);
+    if (e == hipSuccess && !rc) e = hipEventSynchronize(b);
+    float t = 0.0f;
+    if (e == hipSuccess && !rc) e = hipEventElapsedTime(&t, a, b);
+    (void)hipEventDestroy(a);
+    (void)hipEventDestroy(b);
+    if (rc) return rc;
+    if (e != hipSuccess) return set_error(FLUSI_EDEVICE, "autotune: %s", hipGetErrorString(e));
+    *ms_per_step = t / reps;
+    return FLUSI_OK;
+}
+
+// Chooses the fastest variant per pass, then one- or two-launch z-pass.
+static int tune_group(ImplBase* impl, const GroupRun& g, PlanData& prof, int reps, Sched* out) {
+    double t[2][FLUSI_NPASS];
+    Sched base = impl->default_sched();
+    for (int v = 0; v < 2; ++v) {
+        Sched sc = base;
+        sc.y_inverse = sc.x_pass = sc.y_forward = sc.z_pass = v;
+        if (int rc = time_passes(impl, g, sc, prof, reps, t[v])) return rc;
+    }
+    Sched best = base;
+    best.y_inverse = t[1][PASS_YINV] < t[0][PASS_YINV] ? 1 : 0;
+    best.x_pass = t[1][PASS_X] < t[0][PASS_X] ? 1 : 0;
+    best.y_forward = t[1][PASS_YFWD] < t[0][PASS_YFWD] ? 1 : 0;
+    best.z_pass = t[1][PASS_Z] + t[1][PASS_ZINV] < t[0][PASS_Z] + t[0][PASS_ZINV] ? 1 : 0;
+    double ms[2];
+    for (int sp = 0; sp < 2; ++sp) {
+        Sched sc = best;
+        sc.split_z = sp;
+        if (int rc = time_steps(impl, g, sc, reps, &ms[sp])) return rc;
+    }
+    best.split_z = ms[1] < ms[0] ? 1 : 0;
+    *out = best;
+    return FLUSI_OK;
+}
+
 }  // namespace flusi
 
 using namespace flusi;
@@ -159,7 +265,7 @@ int flusi_plan_create(int nx, int ny, int nz, double L, double nu, double eta, i
     ok = ok && hipMalloc(&d.kin, sizeof(Kin)) == hipSuccess;
     ok = ok && hipMalloc(&d.ins_dev, sizeof(flusi_insect)) == hipSuccess;
     ok = ok && hipMalloc(&d.member_dev, sizeof(Member)) == hipSuccess;
-    d.split_z = impl->split_z_default();
+    d.sched = impl->default_sched();
     if (!ok) {
         free_plan(d);
         delete p;
@@ -298,6 +404,60 @@ int flusi_forces(flusi_plan plan, const void* state, double* out) {
     return FLUSI_OK;
 }
 
+int flusi_plan_get_schedule(flusi_plan plan, flusi_schedule* out) {
+    if (int rc = check_plan(plan)) return rc;
+    if (!out) return set_error(FLUSI_EINVAL, "get_schedule: out is NULL");
+    *out = sched_to(plan->d.sched);
+    return FLUSI_OK;
+}
+
+int flusi_plan_set_schedule(flusi_plan plan, const flusi_schedule* s) {
+    if (int rc = check_plan(plan)) return rc;
+    if (!s) return set_error(FLUSI_EINVAL, "set_schedule: schedule is NULL");
+    if (int rc = sched_check(*s)) return rc;
+    plan->d.sched = sched_from(*s);
+    return FLUSI_OK;
+}
+
+int flusi_autotune(flusi_plan plan, const void* state, const flusi_insect* ins, const flusi_step_params* p, int reps,
+                   flusi_schedule* out) {
+    if (int rc = check_plan(plan)) return rc;
+    if (!state || !p) return set_error(FLUSI_EINVAL, "autotune: null pointer");
+    if (reps < 1) return set_error(FLUSI_EINVAL, "autotune: reps < 1");
+    if (!(p->dt_fixed > 0.0) && !(p->cfl > 0.0)) return set_error(FLUSI_EINVAL, "autotune: need dt_fixed > 0 or cfl > 0");
+    PlanData& d = plan->d;
+    const size_t sb = d.impl->state_bytes();
+    void* tmp = nullptr;
+    if (hipMalloc(&tmp, sb) != hipSuccess) return set_error(FLUSI_ENOMEM, "autotune: scratch state");
+    hipError_t e = hipMemcpyAsync(tmp, state, sb, hipMemcpyDeviceToDevice, d.stream);
+    flusi_step_params sp = *p;
+    sp.history = nullptr;
+    const Member m = make_member(d, tmp, ins, sp);
+    if (e == hipSuccess) {
+        k_member_set<<<1, 64, 0, d.stream>>>(d.member_dev, m, m.nc > 0 ? *ins : flusi_insect{});
+        e = hipGetLastError();
+    }
+    int rc = FLUSI_OK;
+    if (e != hipSuccess) rc = set_error(FLUSI_EDEVICE, "autotune: %s", hipGetErrorString(e));
+    Sched best;
+    if (!rc) {
+        GroupRun g;
+        g.mt = d.member_dev;
+        g.nmem = 1;
+        g.n_nc[m.nc == 0 ? 0 : (m.nc == 1 ? 1 : 2)] = 1;
+        g.any_dyn = m.dyn != 0;
+        g.tw = d.tw;
+        g.stream = d.stream;
+        rc = tune_group(d.impl, g, d, reps, &best);
+    }
+    (void)hipStreamSynchronize(d.stream);
+    (void)hipFree(tmp);
+    if (rc) return rc;
+    d.sched = best;
+    if (out) *out = sched_to(best);
+    return FLUSI_OK;
+}
+
 int flusi_profile(flusi_plan plan, int enable) {
     if (int rc = check_plan(plan)) return rc;
     PlanData& d = plan->d;
@@ -347,6 +507,7 @@ struct EnsMember {
 struct EnsGroup {
     int n = 0;
     ImplBase* impl = nullptr;
+    flusi_plan p0 = nullptr;  // member plan that holds the group's schedule
     Member* dev = nullptr;  // device member table
     GroupRun run;
     hipEvent_t done = nullptr;
@@ -392,7 +553,8 @@ static int ens_rebuild(flusi_ensemble e) {
         std::stable_sort(ids.begin(), ids.end(), [&](int a, int b) { return nc_of(a) < nc_of(b); });
         EnsGroup g;
         g.n = kv.first;
-        const PlanData& p0 = e->members[ids[0]].plan->d;
+        g.p0 = e->members[ids[0]].plan;
+        const PlanData& p0 = g.p0->d;
         g.impl = p0.impl;
         std::vector<Member> host;
         for (int i : ids) {
@@ -420,7 +582,7 @@ static int ens_rebuild(flusi_ensemble e) {
         g.run.mt = g.dev;
         g.run.nmem = (int)host.size();
         g.run.tw = p0.tw;
-        g.run.split_z = p0.split_z;
+        g.run.sched = p0.sched;
         e->groups.push_back(g);
     }
     while (e->pool.size() < e->groups.size()) {
@@ -584,6 +746,64 @@ int flusi_ensemble_step(flusi_ensemble e, int nsteps, int use_graph) {
     err = hipEventRecord(e->ev_out, e->own);
     if (err == hipSuccess) err = hipStreamWaitEvent(e->ext, e->ev_out, 0);
     if (err != hipSuccess) return set_error(FLUSI_EDEVICE, "ensemble_step: %s", hipGetErrorString(err));
+    return FLUSI_OK;
+}
+
+int flusi_ensemble_autotune(flusi_ensemble e, int reps) {
+    if (!e) return set_error(FLUSI_EINVAL, "null ensemble");
+    if (reps < 1) return set_error(FLUSI_EINVAL, "ensemble_autotune: reps < 1");
+    if (int rc = ens_rebuild(e)) return rc;
+    hipError_t err = hipStreamSynchronize(e->own);
+    if (err != hipSuccess) return set_error(FLUSI_EDEVICE, "ensemble_autotune: %s", hipGetErrorString(err));
+    for (auto& g : e->groups) {
+        // member records of the group, pointing at scratch copies of the states
+        std::vector<Member> host(g.run.nmem);
+        err = hipMemcpy(host.data(), g.dev, host.size() * sizeof(Member), hipMemcpyDeviceToHost);
+        if (err != hipSuccess) return set_error(FLUSI_EDEVICE, "ensemble_autotune: %s", hipGetErrorString(err));
+        std::vector<void*> copies;
+        Member* dev = nullptr;
+        int rc = FLUSI_OK;
+        const size_t sb = g.impl->state_bytes();
+        for (auto& m : host) {
+            void* c = nullptr;
+            if (hipMalloc(&c, sb) != hipSuccess) {
+                rc = set_error(FLUSI_ENOMEM, "ensemble_autotune: scratch states");
+                break;
+            }
+            copies.push_back(c);
+            err = hipMemcpy(c, m.hdr, sb, hipMemcpyDeviceToDevice);
+            if (err != hipSuccess) {
+                rc = set_error(FLUSI_EDEVICE, "ensemble_autotune: %s", hipGetErrorString(err));
+                break;
+            }
+            m.hdr = static_cast<StateHdr*>(c);
+            m.history = nullptr;
+        }
+        if (!rc && hipMalloc(&dev, host.size() * sizeof(Member)) != hipSuccess)
+            rc = set_error(FLUSI_ENOMEM, "ensemble_autotune: member table");
+        if (!rc) {
+            err = hipMemcpy(dev, host.data(), host.size() * sizeof(Member), hipMemcpyHostToDevice);
+            if (err != hipSuccess) rc = set_error(FLUSI_EDEVICE, "ensemble_autotune: %s", hipGetErrorString(err));
+        }
+        Sched best;
+        if (!rc) {
+            GroupRun r = g.run;
+            r.mt = dev;
+            r.stream = e->own;
+            // the group's first plan holds the schedule and lends its event pool
+            rc = tune_group(g.impl, r, g.p0->d, reps, &best);
+            if (!rc) {
+                g.p0->d.sched = best;
+                g.run.sched = best;
+            }
+        }
+        (void)hipStreamSynchronize(e->own);
+        for (void* c : copies) (void)hipFree(c);
+        if (dev) (void)hipFree(dev);
+        if (rc) return rc;
+    }
+    for (auto& kv : e->graphs) (void)hipGraphExecDestroy(kv.second);
+    e->graphs.clear();
     return FLUSI_OK;
 }
 

@@ -10,6 +10,13 @@ namespace flusi {
 
 struct ImplBase;
 
+// Schedule of the stepping passes: tile variant (0 or 1) of each pass and
+// whether the z-pass runs as one launch or as update + inverse launches.
+struct Sched {
+    int y_inverse = 0, x_pass = 0, y_forward = 0, z_pass = 0;
+    int split_z = 0;
+};
+
 // Plan contents shared with the launchers.
 struct PlanData {
     int n = 0, dtype = 0;
@@ -26,7 +33,7 @@ struct PlanData {
     Kin* kin = nullptr;
     flusi_insect* ins_dev = nullptr;  // device copy of the insect of the current stepping call
     Member* member_dev = nullptr;     // launch record of the plan's own calls
-    bool split_z = false;             // schedule: z-pass as update + inverse launches
+    Sched sched;                      // schedule of the plan's own stepping calls
     double* pmax = nullptr;
     int npmax = 0;
     void* spec = nullptr;  // lazily allocated full-layout scratch
@@ -42,12 +49,14 @@ struct PlanData {
     std::vector<std::pair<int, size_t>> prof_recs;
 };
 
-// Brackets one launch with a pair of events when profiling is on.
+// Brackets one launch on stream st with a pair of events when profiling is on
+// (records kept in the plan).
 struct PassScope {
     PlanData* pp;
     int pass;
+    hipStream_t st;
     size_t idx = 0;
-    PassScope(PlanData* pd, int ps) : pp(pd && pd->prof ? pd : nullptr), pass(ps) {
+    PassScope(PlanData* pd, int ps, hipStream_t s) : pp(pd && pd->prof ? pd : nullptr), pass(ps), st(s) {
         if (!pp) return;
         PlanData& p = *pp;
         while (p.events.size() < p.ev_used + 2) {
@@ -61,11 +70,11 @@ struct PassScope {
         }
         idx = p.ev_used;
         p.ev_used += 2;
-        (void)hipEventRecord(p.events[idx], p.stream);
+        (void)hipEventRecord(p.events[idx], st);
     }
     ~PassScope() {
         if (!pp) return;
-        (void)hipEventRecord(pp->events[idx + 1], pp->stream);
+        (void)hipEventRecord(pp->events[idx + 1], st);
         pp->prof_recs.emplace_back(pass, idx);
     }
 };
@@ -79,7 +88,7 @@ struct GroupRun {
     int n_nc[3] = {0, 0, 0};  // members with nc = 0, 1, 3
     bool any_dyn = false;
     const void* tw = nullptr;
-    bool split_z = false;     // z-pass as update + inverse launches
+    Sched sched;
     hipStream_t stream = nullptr;
     PlanData* prof = nullptr; // pass timing events, or null
 };
@@ -134,7 +143,7 @@ struct ImplBase {
     virtual int velocity(PlanData&, const void*, void*) = 0;
     virtual int step(PlanData&, void*, const flusi_insect*, const flusi_step_params&) = 0;
     virtual int run_steps(const GroupRun&, int nsteps) = 0;
-    virtual bool split_z_default() const = 0;
+    virtual Sched default_sched() const = 0;
 };
 
 inline int launch_check(const char* what) {
@@ -149,7 +158,7 @@ struct Impl final : ImplBase {
     static constexpr int K = kmax_of(N), KP = K + 1, M = 2 * K + 1, Q = M * KP;
     static constexpr int KPp = Geo<T, N>::KPp, Qp = Geo<T, N>::Qp;
     static constexpr int C = cols_of(N), RW = rows_x(N, sizeof(cx<T>)), NKX = N / 2 + 1;
-    static constexpr int CZ = cols_z(N), NTZ = nt_z(N);
+    static constexpr int CZ = cols_z(N);
     static constexpr long N2 = (long)N * N, N3 = (long)N * N * N;
     static constexpr long FULL = N2 * NKX;  // full-layout spectrum per field
 
@@ -161,7 +170,9 @@ struct Impl final : ImplBase {
         const size_t a = 6ul * N2 * KPp, b = 3ul * N * Qp;
         return a > b ? a : b;
     }
-    int nwg_x() const override { return (int)(N2 / RW); }
+    // x-pass workgroups per member, largest over the tile variants (sizes the
+    // partial-sum buffer)
+    int nwg_x() const override { return (int)(N2 / rows_x(N, sizeof(cx<T>), 1)); }
     static size_t field_bytes() { return (size_t)M * Qp * sizeof(CX); }
     size_t state_bytes() const override { return STATE_HDR_BYTES + 6 * ((field_bytes() + 255) / 256 * 256); }
 
@@ -282,77 +293,102 @@ struct Impl final : ImplBase {
     }
 
     // --- pruned stepping schedule over a member table ------------------------------
-    static constexpr int NBY_INV = (N * KP + C - 1) / C * 6;  // y-inverse tiles per member
-    static constexpr int NBY_FWD = (N * KP + C - 1) / C * 3;  // y-forward tiles per member
-    static constexpr int NBZ = (Q + CZ - 1) / CZ;             // z-pass tiles per member
-    static constexpr int NWG = (int)(N2 / RW);                // x-pass workgroups per member
+    template <int V>
+    static constexpr int nby(int nf) { return (N * KP + cols_of(N, V) - 1) / cols_of(N, V) * nf; }
+    template <int V>
+    static constexpr int nwg(int) { return (int)(N2 / rows_x(N, sizeof(cx<T>), V)); }
+    static constexpr int NBZ = (Q + CZ - 1) / CZ;  // z-pass tiles per member
+    static int nwg_of(int v) { return v ? nwg<1>(0) : nwg<0>(0); }
 
     // y-inverse of the 6 z-partial fields; with kin set, one extra workgroup per
     // member evaluates the kinematics of time level par
-    static void y_inverse(const GroupRun& g, bool kin, int par) {
+    template <int V>
+    static void y_inverse_v(const GroupRun& g, bool kin, int par) {
         const CX* w = static_cast<const CX*>(g.tw);
-        if (kin) {
-            const int per = NBY_INV + 1;
-            k_ypass<T, N, +1, 2><<<(unsigned)(per * g.nmem), NT, 0, g.stream>>>(g.mt, per, w, par);
-        } else {
-            k_ypass<T, N, +1, 0><<<(unsigned)(NBY_INV * g.nmem), NT, 0, g.stream>>>(g.mt, NBY_INV, w, par);
-        }
+        constexpr int nb = nby<V>(6);
+        if (kin)
+            k_ypass<T, N, +1, 2, V><<<(unsigned)((nb + 1) * g.nmem), NT, 0, g.stream>>>(g.mt, nb + 1, w, par, 0);
+        else
+            k_ypass<T, N, +1, 0, V><<<(unsigned)(nb * g.nmem), NT, 0, g.stream>>>(g.mt, nb, w, par, 0);
+    }
+    static void y_inverse(const GroupRun& g, bool kin, int par) {
+        if (g.sched.y_inverse) y_inverse_v<1>(g, kin, par);
+        else y_inverse_v<0>(g, kin, par);
     }
     // y-forward of 3 fields; with red set, NRED_BLOCKS extra workgroups per member
     // do the first-level reduction of the x-pass sums
-    static void y_forward(const GroupRun& g, bool red) {
+    template <int V>
+    static void y_forward_v(const GroupRun& g, bool red) {
         const CX* w = static_cast<const CX*>(g.tw);
-        if (red) {
-            const int per = NBY_FWD + NRED_BLOCKS;
-            k_ypass<T, N, -1, 1><<<(unsigned)(per * g.nmem), NT, 0, g.stream>>>(g.mt, per, w, 0);
-        } else {
-            k_ypass<T, N, -1, 0><<<(unsigned)(NBY_FWD * g.nmem), NT, 0, g.stream>>>(g.mt, NBY_FWD, w, 0);
-        }
+        constexpr int nb = nby<V>(3);
+        if (red)
+            k_ypass<T, N, -1, 1, V><<<(unsigned)((nb + NRED_BLOCKS) * g.nmem), NT, 0, g.stream>>>(
+                g.mt, nb + NRED_BLOCKS, w, 0, nwg_of(g.sched.x_pass));
+        else
+            k_ypass<T, N, -1, 0, V><<<(unsigned)(nb * g.nmem), NT, 0, g.stream>>>(g.mt, nb, w, 0, 0);
     }
-    static void xpass(const GroupRun& g) {
+    static void y_forward(const GroupRun& g, bool red) {
+        if (g.sched.y_forward) y_forward_v<1>(g, red);
+        else y_forward_v<0>(g, red);
+    }
+    template <int V>
+    static void xpass_v(const GroupRun& g) {
         const CX* w = static_cast<const CX*>(g.tw);
         const Member* mt = g.mt;
-        if (g.n_nc[0]) k_xpass<T, N, 0><<<(unsigned)(NWG * g.n_nc[0]), NT, 0, g.stream>>>(mt, w);
+        constexpr int nw = nwg<V>(0);
+        if (g.n_nc[0]) k_xpass<T, N, 0, V><<<(unsigned)(nw * g.n_nc[0]), NT, 0, g.stream>>>(mt, w);
         mt += g.n_nc[0];
-        if (g.n_nc[1]) k_xpass<T, N, 1><<<(unsigned)(NWG * g.n_nc[1]), NT, 0, g.stream>>>(mt, w);
+        if (g.n_nc[1]) k_xpass<T, N, 1, V><<<(unsigned)(nw * g.n_nc[1]), NT, 0, g.stream>>>(mt, w);
         mt += g.n_nc[1];
-        if (g.n_nc[2]) k_xpass<T, N, 3><<<(unsigned)(NWG * g.n_nc[2]), NT, 0, g.stream>>>(mt, w);
+        if (g.n_nc[2]) k_xpass<T, N, 3, V><<<(unsigned)(nw * g.n_nc[2]), NT, 0, g.stream>>>(mt, w);
+    }
+    static void xpass(const GroupRun& g) {
+        if (g.sched.x_pass) xpass_v<1>(g);
+        else xpass_v<0>(g);
     }
     template <int MODE>
     static void zpass(const GroupRun& g, int par = 0, int s = 0) {
-        k_zpass<T, N, MODE><<<(unsigned)(NBZ * g.nmem), NTZ, 0, g.stream>>>(g.mt, static_cast<const CX*>(g.tw), par, s);
+        const CX* w = static_cast<const CX*>(g.tw);
+        if (g.sched.z_pass)
+            k_zpass<T, N, MODE, 1><<<(unsigned)(NBZ * g.nmem), nt_z(N, 1), 0, g.stream>>>(g.mt, w, par, s);
+        else
+            k_zpass<T, N, MODE, 0><<<(unsigned)(NBZ * g.nmem), nt_z(N, 0), 0, g.stream>>>(g.mt, w, par, s);
     }
 
-    bool split_z_default() const override { return split_z(); }
+    Sched default_sched() const override {
+        Sched d;
+        d.split_z = split_z() ? 1 : 0;
+        return d;
+    }
 
     int run_steps(const GroupRun& g, int nsteps) override {
         if (g.nmem <= 0 || nsteps <= 0) return FLUSI_OK;
         k_prologue<<<(unsigned)((g.nmem + 63) / 64), 64, 0, g.stream>>>(g.mt, g.nmem);
         {
-            PassScope ps(g.prof, PASS_ZINV);
+            PassScope ps(g.prof, PASS_ZINV, g.stream);
             zpass<MODE_INVERSE>(g);
         }
         for (int s = 0; s < nsteps; ++s) {
             const int par = s & 1;
             {
-                PassScope ps(g.prof, PASS_YINV);
+                PassScope ps(g.prof, PASS_YINV, g.stream);
                 y_inverse(g, g.any_dyn, par);
             }
             {
-                PassScope ps(g.prof, PASS_X);
+                PassScope ps(g.prof, PASS_X, g.stream);
                 xpass(g);
             }
             {
-                PassScope ps(g.prof, PASS_YFWD);
+                PassScope ps(g.prof, PASS_YFWD, g.stream);
                 y_forward(g, true);
             }
             {
-                PassScope ps(g.prof, PASS_Z);
-                if (s + 1 < nsteps && !g.split_z) zpass<MODE_STEP>(g, par, s);
+                PassScope ps(g.prof, PASS_Z, g.stream);
+                if (s + 1 < nsteps && !g.sched.split_z) zpass<MODE_STEP>(g, par, s);
                 else zpass<MODE_STEP_LAST>(g, par, s);
             }
-            if (s + 1 < nsteps && g.split_z) {
-                PassScope ps(g.prof, PASS_ZINV);
+            if (s + 1 < nsteps && g.sched.split_z) {
+                PassScope ps(g.prof, PASS_ZINV, g.stream);
                 zpass<MODE_INVERSE>(g);
             }
         }
@@ -400,7 +436,7 @@ struct Impl final : ImplBase {
         g.n_nc[m.nc == 0 ? 0 : (m.nc == 1 ? 1 : 2)] = 1;
         g.any_dyn = m.dyn != 0;
         g.tw = p.tw;
-        g.split_z = p.split_z;
+        g.sched = p.sched;
         g.stream = p.stream;
         g.prof = &p;
         return run_steps(g, sp.nsteps);

@@ -27,23 +27,33 @@ constexpr int NT = 256;   // threads per workgroup of the y passes and the x-pas
 constexpr int NV = 39;    // reduction values per workgroup (see xpass)
 constexpr int NRED_BLOCKS = 64;
 
-// Columns per workgroup of the y passes: C*N ~ 4096 elements in LDS.
-__host__ __device__ constexpr int cols_of(int N) {
+// Tile shapes.  Each stepping pass has two variants that compute the same
+// values (V = 0 the default, V = 1 the alternative); a schedule picks one per
+// pass (see the autotuner).
+// Columns per workgroup of the y passes: C*N ~ 4096 elements in LDS (V = 0),
+// half of that (V = 1).
+__host__ __device__ constexpr int cols_of(int N, int V = 0) {
     int c = 4096 / N, p = 8;
     while (p * 2 <= c) p *= 2;
-    return p;
+    return V ? p / 2 : p;
 }
 // Columns and threads per workgroup of the z-pass (more, narrower workgroups:
-// the z-pass has only (2K+1)(K+1) columns).
+// the z-pass has only (2K+1)(K+1) columns).  V = 1 uses more threads per
+// column (fewer rows per thread): twice as many, or three times as many
+// where twice would not divide the column.
 __host__ __device__ constexpr int cols_z(int N) { return N <= 24 ? 16 : 8; }
-__host__ __device__ constexpr int nt_z(int N) { return N <= 192 ? 128 : 256; }
-// Rows per workgroup of the x-pass (even): 3*RW*N ~ 3072 elements in LDS for
-// FP32, half of that for FP64 (so two workgroups fit the LDS of a CU).
-__host__ __device__ constexpr int rows_x(int N, int cbytes = 8) {
+__host__ __device__ constexpr int nt_z(int N, int V = 0) {
+    const int t0 = N <= 192 ? 128 : 256;
+    if (!V) return t0;
+    return N % (2 * t0 / cols_z(N)) == 0 ? 2 * t0 : 3 * t0;
+}
+// Rows per workgroup of the x-pass (even): 3*RW*N ~ 3072 elements in LDS
+// (V = 0), half of that (V = 1, at least 2 rows).
+__host__ __device__ constexpr int rows_x(int N, int cbytes = 8, int V = 0) {
     int c = 1024 / N, p = 2;
     (void)cbytes;
     while (p * 2 <= c) p *= 2;
-    return p;
+    return V && p > 2 ? p / 2 : p;
 }
 __host__ __device__ constexpr int round_up(int a, int b) { return (a + b - 1) / b * b; }
 
@@ -127,11 +137,10 @@ __device__ inline void kin_of_level(const Member& m, int p);
 // the column sits at stride s.  PIN: the input holds only the 2K+1 kept
 // signed modes (pruned storage); POUT: only those are written.
 // ---------------------------------------------------------------------------
-template <typename T, int N, int DIR, bool PIN, bool POUT>
+template <typename T, int N, int DIR, bool PIN, bool POUT, int C>
 __device__ __forceinline__ void colfft_tile(const glb<cx<T>>* __restrict__ in, glb<cx<T>>* __restrict__ out, int Q, int KX,
                                             long blk_in, long s_in, long blk_out, long s_out, int tile,
                                             const cx<T>* __restrict__ tw, cx<T>* buf) {
-    constexpr int C = cols_of(N);
     constexpr int K = kmax_of(N);
     constexpr int SC = cm_stride(N);
     constexpr int RS = NT / C;      // rows handled per sweep
@@ -182,7 +191,7 @@ __global__ __launch_bounds__(NT) void k_colfft(const cx<T>* in, cx<T>* out, int 
     __shared__ cx<T> buf[cols_of(N) * cm_stride(N)];
     const int tile = xcd_tile(blockIdx.x, gridDim.x);
     const int f = tile / nbx;
-    colfft_tile<T, N, DIR, PIN, POUT>(gview(in) + f * fs_in, gview(out) + f * fs_out, Q, KX, blk_in, s_in, blk_out, s_out,
+    colfft_tile<T, N, DIR, PIN, POUT, cols_of(N)>(gview(in) + f * fs_in, gview(out) + f * fs_out, Q, KX, blk_in, s_in, blk_out, s_out,
                                       tile % nbx, tw, buf);
 }
 
@@ -193,12 +202,13 @@ __global__ __launch_bounds__(NT) void k_colfft(const cx<T>* in, cx<T>* out, int 
 // Each member has nbx*nf column tiles followed by the extra workgroups:
 //   EXTRA 1: NRED_BLOCKS workgroups reduce the x-pass sums (first level)
 //   EXTRA 2: one workgroup evaluates the kinematics of time level p
-template <typename T, int N, int DIR, int EXTRA>
+// nwg: x-pass workgroups per member (records of the first-level reduction).
+template <typename T, int N, int DIR, int EXTRA, int V>
 __global__ __launch_bounds__(NT) void k_ypass(const Member* __restrict__ mt, int per, const cx<T>* __restrict__ tw,
-                                              int p) {
+                                              int p, int nwg) {
     using G = Geo<T, N>;
     constexpr int KP = G::KP, KPp = G::KPp, Qp = G::Qp;
-    constexpr int C = cols_of(N);
+    constexpr int C = cols_of(N, V);
     constexpr int nbx = (N * KP + C - 1) / C;
     constexpr int nf = DIR > 0 ? 6 : 3;
     __shared__ cx<T> buf[C * cm_stride(N)];
@@ -210,7 +220,6 @@ __global__ __launch_bounds__(NT) void k_ypass(const Member* __restrict__ mt, int
     if (f >= nf) {
         if constexpr (EXTRA == 1) {
             __shared__ double red[NT / 64][NV];
-            const int nwg = (int)((long)N * N / rows_x(N, sizeof(cx<T>)));
             if (tile - nf * nbx < NRED_BLOCKS) reduce_level1(m.partial, nwg, m.partial2, tile - nf * nbx, red);
         } else if constexpr (EXTRA == 2) {
             if (tile == nf * nbx && threadIdx.x == 0 && m.dyn) kin_of_level(m, p);
@@ -220,10 +229,10 @@ __global__ __launch_bounds__(NT) void k_ypass(const Member* __restrict__ mt, int
     const glb<cx<T>>* A = gview(static_cast<const cx<T>*>(m.bufA));
     glb<cx<T>>* B = gview(static_cast<cx<T>*>(m.bufB));
     if constexpr (DIR > 0)
-        colfft_tile<T, N, +1, true, false>(A + f * (long)N * Qp, B + f * (long)N * N * KPp, N * KP, KP, Qp, KP,
+        colfft_tile<T, N, +1, true, false, C>(A + f * (long)N * Qp, B + f * (long)N * N * KPp, N * KP, KP, Qp, KP,
                                            (long)N * KPp, KPp, tile % nbx, tw, buf);
     else
-        colfft_tile<T, N, -1, false, true>(A + f * (long)N * N * KPp, B + f * (long)N * Qp, N * KP, KP,
+        colfft_tile<T, N, -1, false, true, C>(A + f * (long)N * N * KPp, B + f * (long)N * Qp, N * KP, KP,
                                            (long)N * KPp, KPp, Qp, KP, tile % nbx, tw, buf);
 }
 
@@ -296,11 +305,11 @@ __device__ __forceinline__ void block_reduce_store(const double (&acc)[NVAL], do
 // NC: number of colours accumulated (0 no mask, 1 single body, 3 insect).
 // ---------------------------------------------------------------------------
 // Member table: N*N/RW workgroups per member, y-partials in bufB, output in bufA.
-template <typename T, int N, int NC>
+template <typename T, int N, int NC, int V>
 __global__ __launch_bounds__(NT) void k_xpass(const Member* __restrict__ mt, const cx<T>* __restrict__ tw) {
     using G = Geo<T, N>;
     constexpr int K = G::K, KP = G::KP, KPp = G::KPp;
-    constexpr int RW = rows_x(N, sizeof(cx<T>));
+    constexpr int RW = rows_x(N, sizeof(cx<T>), V);
     constexpr int NWG = N * N / RW;
     constexpr long fs_in = (long)N * N * KPp, fs_out = (long)N * N * KPp;
     const Member& m = mt[blockIdx.x / NWG];
@@ -718,12 +727,12 @@ enum { MODE_IMPORT = 0, MODE_STEP = 1, MODE_STEP_LAST = 2, MODE_INVERSE = 3 };
 
 // Member table: ceil(Q/C) workgroups per member.  par: slot of the current
 // time level; s: step index within the call (row of the history).
-template <typename T, int N, int MODE>
-__global__ __launch_bounds__(nt_z(N)) void k_zpass(const Member* __restrict__ mt, const cx<T>* __restrict__ tw,
-                                                   int par, int s) {
+template <typename T, int N, int MODE, int V>
+__global__ __launch_bounds__(nt_z(N, V)) void k_zpass(const Member* __restrict__ mt, const cx<T>* __restrict__ tw,
+                                                      int par, int s) {
     using G = Geo<T, N>;
     constexpr int K = G::K, KP = G::KP, M = G::M, Q = G::Q, Qp = G::Qp;
-    constexpr int C = cols_z(N), NTZ = nt_z(N);
+    constexpr int C = cols_z(N), NTZ = nt_z(N, V);
     constexpr int NBZ = (Q + C - 1) / C;
     // state fields: [uhat 3][nold 3], each padded to 256 bytes
     constexpr long fs_s = (((long)M * Qp * (long)sizeof(cx<T>) + 255) / 256 * 256) / (long)sizeof(cx<T>);
