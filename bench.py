@@ -31,7 +31,7 @@ METRIC = "Mpoint-steps/s (AB2 RHS) FP32 vs FP64 at stated err; p50/p99 solve lat
 HBM_PEAK_GBS = 8000.0
 
 
-def pass_bytes(n: int, cbytes: int, split_z: bool) -> dict:
+def pass_bytes(n: int, cbytes: int, split_z: bool, x_variant: int = 0) -> dict:
     """Algorithmic HBM bytes per launch of each pass of the pruned schedule.
 
     K = (n-1)//3, KP = K+1 kept kx, M = 2K+1 kept ky and kz, Q = M*KP.
@@ -43,7 +43,10 @@ def pass_bytes(n: int, cbytes: int, split_z: bool) -> dict:
     KP, M = K + 1, 2 * K + 1
     Q = M * KP
     s = cbytes
-    nwg = n * n // max(2, 1 << int(math.log2(max(1, 1024 // n))))
+    rows = max(2, 1 << int(math.log2(max(1, 1024 // n))))
+    if x_variant and rows > 2:
+        rows //= 2
+    nwg = n * n // rows
     zup = (3 * n * Q + 4 * 3 * M * Q) * s
     return {
         "z_inverse": (3 * M * Q + 6 * n * Q) * s,
@@ -89,13 +92,15 @@ def counter_traffic(workload: str, kernel_prefix: str):
     return None
 
 
-def kernel_of_pass(pass_name: str, n: int, real: str, split: bool, nc: int) -> str:
+def kernel_of_pass(pass_name: str, n: int, real: str, sched: dict, nc: int, dyn: bool) -> str:
+    """Kernel name (as rocprofv3 prints it) of a pass under a schedule."""
+    split = sched["split_z"]
     return {
-        "z_pass": f"k_zpass<{real}, {n}, {2 if split else 1}>",
-        "z_inverse": f"k_zpass<{real}, {n}, 3>",
-        "x_pass": f"k_xpass<{real}, {n}, {nc}>",
-        "y_inverse": f"k_colfft<{real}, {n}, 1, true, false,",
-        "y_forward": f"k_colfft<{real}, {n}, -1, false, true, 1>",
+        "z_pass": f"k_zpass<{real}, {n}, {2 if split else 1}, {sched['z_pass']}>",
+        "z_inverse": f"k_zpass<{real}, {n}, 3, {sched['z_pass']}>",
+        "x_pass": f"k_xpass<{real}, {n}, {nc}, {sched['x_pass']}>",
+        "y_inverse": f"k_ypass<{real}, {n}, 1, {2 if dyn else 0}, {sched['y_inverse']}>",
+        "y_forward": f"k_ypass<{real}, {n}, -1, 1, {sched['y_forward']}>",
     }[pass_name]
 
 
@@ -127,13 +132,14 @@ def build_workload(name: str):
     raise SystemExit(f"unknown workload {name}")
 
 
-def gpu_run(F, torch, wl, dtype, steps, warmup):
+def gpu_run(F, torch, wl, dtype, steps, warmup, tune=True):
     P = F.Plan(wl["n"], wl["L"], wl["nu"], wl["eta"], dtype)
     kw = dict(dt_fixed=wl["dt_fixed"], cfl=wl["cfl"], eta_cap=0.5, mean_mode=F.FLUSI_MEAN_FIXED)
     u0 = torch.from_numpy(wl["u0"])
     st = P.new_state(u0)
     if warmup:
         P.step(st, warmup, wl["insect"], **kw)
+    sched = P.autotune(st, wl["insect"], reps=10, **kw) if tune else P.schedule()
     torch.cuda.synchronize()
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     t0 = time.perf_counter()
@@ -152,10 +158,10 @@ def gpu_run(F, torch, wl, dtype, steps, warmup):
     ms, cnt = F.flusi_pass_times(P.handle)
     F.flusi_profile(P.handle, False)
     torch.cuda.synchronize()
-    return dict(wall_s=wall, ev_ms=ev_ms, pass_ms=ms, pass_cnt=cnt, diag=diag)
+    return dict(wall_s=wall, ev_ms=ev_ms, pass_ms=ms, pass_cnt=cnt, diag=diag, schedule=sched)
 
 
-def ensemble_run(F, torch, count=48, steps=200, chunk=20, seed=1):
+def ensemble_run(F, torch, count=48, steps=200, chunk=20, seed=1, tune=True):
     """Batched ensemble (seeded insects on mixed grids, FP32): one graph of
     `chunk` steps for all members, replayed steps/chunk times in the timed
     region; then the same members stepped one by one for comparison."""
@@ -169,6 +175,11 @@ def ensemble_run(F, torch, count=48, steps=200, chunk=20, seed=1):
         ens.add(P, st, sp["insect"], cfl=0.1)
         members.append((P, st, sp))
     nmem, ngroups = ens.size()
+    if tune:
+        ens.autotune(reps=5)
+    scheds = {}
+    for P, st, sp in members:
+        scheds.setdefault(str(sp["n"]), P.schedule())
     ens.step(chunk, graph=True)  # capture + warm-up
     torch.cuda.synchronize()
     pts = sum(float(sp["n"]) ** 3 for sp in specs)
@@ -202,6 +213,7 @@ def ensemble_run(F, torch, count=48, steps=200, chunk=20, seed=1):
             "ms": round(ms, 3), "point_steps": pts * done, "dtype": "f32",
             "one_by_one": {"value": round(v_solo, 2), "steps": chunk, "ms": round(ms_solo, 3)},
             "batching_speedup": round(v / v_solo, 3),
+            "schedules": scheds if tune else "default",
             "description": f"{count} seeded insects (grids {{64,96,128,192}}, Re 50-500, C_eta 1e-4..1e-3, "
                            f"stroke 50-80 deg; seed {seed}), fluid at rest, CFL 0.1"}
 
@@ -231,6 +243,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--workload", default="sphere128", choices=["sphere128", "insect256", "tg32", "ensemble48"])
     ap.add_argument("--no-ensemble", action="store_true", help="skip the batched-ensemble figure")
+    ap.add_argument("--no-autotune", action="store_true", help="time the default schedules")
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="run only a plain device copy of 1 GiB (3 launches) to scale HBM counters")
@@ -253,7 +266,7 @@ def main():
     import paper_1506_06513_amd as F
 
     if a.workload == "ensemble48":
-        e = ensemble_run(F, torch, steps=a.steps or 200)
+        e = ensemble_run(F, torch, steps=a.steps or 200, tune=not a.no_autotune)
         print(json.dumps({"metric": METRIC, "value": e["value"], "unit": e["unit"], "n_gpus": 1,
                           "steps": e["steps"], "warmup": e["graph_chunk"], "ms_per_step": round(e["ms"] / e["steps"], 5),
                           "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
@@ -267,7 +280,7 @@ def main():
     pts = float(n) ** 3
     res = {}
     for dtype in ("f32", "f64"):
-        res[dtype] = gpu_run(F, torch, wl, dtype, steps, a.warmup)
+        res[dtype] = gpu_run(F, torch, wl, dtype, steps, a.warmup, tune=not a.no_autotune)
 
     def mps(r):
         return pts * steps / (r["ev_ms"] / 1e3) / 1e6
@@ -277,7 +290,7 @@ def main():
     r = res["f32"]
     names = list(F.PASS_NAMES)
     split = r["pass_cnt"][names.index("z_inverse")] > 1
-    pb = pass_bytes(n, 8, split)
+    pb = pass_bytes(n, 8, split, r["schedule"]["x_pass"])
     passes = {}
     for i, nm in enumerate(names):
         if r["pass_cnt"][i]:
@@ -310,18 +323,21 @@ def main():
                  "fp32_over_fp64": round(v32 / v64, 3)},
         "roofline": {"bound": "hbm", "kernel": dom, "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-                     "traffic": counter_traffic(a.workload, kernel_of_pass(dom, n, "float", split, nc)),
+                     "traffic": counter_traffic(a.workload, kernel_of_pass(dom, n, "float", r["schedule"], nc,
+                                                                           dyn=bool(ins and ins.get("wings")))),
                      "algorithmic_bytes": int(pb[dom])},
         "step_roofline": {"bytes_per_step": sb, "bytes_per_point_step": round(sb / pts, 2),
                           "achieved_gbs": round(sb / (res["f32"]["ev_ms"] / steps / 1e3) / 1e9, 1),
                           "frac": round(sb / (res["f32"]["ev_ms"] / steps / 1e3) / 1e9 / HBM_PEAK_GBS, 4)},
         "passes_f32": passes,
+        "schedule": {"f32": res["f32"]["schedule"], "f64": res["f64"]["schedule"],
+                     "chosen_by": "autotune" if not a.no_autotune else "default"},
         "wall_s": {k: round(v["wall_s"], 4) for k, v in res.items()},
         "last_diag_f32": {"t": res["f32"]["diag"][0], "dt": res["f32"]["diag"][1],
                           "umax": res["f32"]["diag"][2], "drag": res["f32"]["diag"][4]},
     }
     if not a.no_ensemble and a.workload == "sphere128":
-        out["ensemble48"] = ensemble_run(F, torch)
+        out["ensemble48"] = ensemble_run(F, torch, tune=not a.no_autotune)
     if not a.no_cpu:
         cs = oracle_sample(wl)
         cpu_v = pts * cs["timed_steps"] / cs["seconds"] / 1e6

@@ -308,9 +308,12 @@ __device__ __attribute__((noinline)) int part_of_max64(const KinT<double>* k64, 
 // Reads only the kinematics blocks (kept in LDS by the callers).  With TM =
 // float, k64 (the FP64 kinematics) decides the part wherever two parts
 // overlap, so the integer part choice is taken in FP64 as in the FP64 path.
+//
+// defer != nullptr: where two parts overlap, set *defer and return an empty
+// point instead of deciding (the caller revisits such points with k64).
 template <typename TM>
 __device__ __forceinline__ MaskPt<TM> eval_mask(const KinT<TM>& k, double x, double y, double z,
-                                                const KinT<double>* k64) {
+                                                const KinT<double>* k64, bool* defer = nullptr) {
     MaskPt<TM> o;
     o.chi = TM(0);
     o.us[0] = o.us[1] = o.us[2] = TM(0);
@@ -325,7 +328,12 @@ __device__ __forceinline__ MaskPt<TM> eval_mask(const KinT<TM>& k, double x, dou
     const TM chimax = fmax(c[0], fmax(c[1], c[2]));
     if (chimax <= TM(0)) return o;
     int part;
-    if (k64 != nullptr && (int(c[0] > TM(0)) + int(c[1] > TM(0)) + int(c[2] > TM(0))) >= 2) {
+    const bool overlap = (int(c[0] > TM(0)) + int(c[1] > TM(0)) + int(c[2] > TM(0))) >= 2;
+    if (overlap && defer != nullptr) {
+        *defer = true;
+        return o;
+    }
+    if (overlap && k64 != nullptr) {
         part = part_of_max64(k64, x, y, z);
     } else {
         part = part_of_max(c);

@@ -103,6 +103,8 @@ struct StateHdr {
     Slot slot[2];
     double diag[FLUSI_NDIAG];
     Kin kin;         // kinematics at the current time level
+    KinT<float> kf;  // the same, prepared for the FP32 mask evaluation
+    KinT<double> kd; // ... and for the FP64 one
 };
 static_assert(sizeof(StateHdr) <= 4096, "state header too large");
 constexpr size_t STATE_HDR_BYTES = 4096;
@@ -333,15 +335,26 @@ __global__ __launch_bounds__(NT) void k_xpass(const Member* __restrict__ mt, con
     // FP64 kinematics for the part choice where parts overlap (FP32 runs)
     constexpr bool K64 = NC > 1 && sizeof(T) < 8;
     __shared__ typename std::conditional<K64, KinT<double>, char>::type kin64;
+    __shared__ unsigned char amb[K64 ? RW * N : 1];  // point flagged for the FP64 part decision
+    __shared__ int amb_any;
     if (*gview(&hdr->status)) return;
     const int tid = threadIdx.x;
     const int row0 = wg * RW;
-    if constexpr (NC > 0) {
-        if (tid == 0) kin_cast<T>(hdr->kin, kin);
-    }
     if constexpr (K64) {
-        if (tid == 64) kin_cast<double>(hdr->kin, kin64);
+        for (int e = tid; e < RW * N; e += NT) amb[e] = 0;
+        if (tid == 0) amb_any = 0;
     }
+    // kinematics blocks prepared once per time level (state header) -> LDS
+    const auto lds_copy = [&](const void* src, void* dst, int bytes) {
+        const glb<unsigned>* a = gview(static_cast<const unsigned*>(src));
+        unsigned* b = static_cast<unsigned*>(dst);
+        for (int e = tid; e < bytes / 4; e += NT) b[e] = a[e];
+    };
+    if constexpr (NC > 0) {
+        if constexpr (sizeof(T) < 8) lds_copy(&hdr->kf, &kin, (int)sizeof(KinT<T>));
+        else lds_copy(&hdr->kd, &kin, (int)sizeof(KinT<T>));
+    }
+    if constexpr (K64) lds_copy(&hdr->kd, &kin64, (int)sizeof(KinT<double>));
 
     // 1. pack three Hermitian pairs per row: Z = X + iY over the full x axis
     cx<T> la[3][LP], lb[3][LP];
@@ -401,8 +414,14 @@ __global__ __launch_bounds__(NT) void k_xpass(const Member* __restrict__ mt, con
 #pragma unroll
     for (int v = 0; v < NLANE; ++v) acc[v] = 0.0;
     const T s = T(1.0 / ((double)N * (double)N * (double)N));
-#pragma unroll 1
-    for (int idx = tid; idx < RW * N; idx += NT) {
+    const KinT<double>* k64p = nullptr;
+    if constexpr (K64) k64p = &kin64;
+    // One grid point.  PH = 0: main sweep (with K64, points where two parts
+    // overlap are only flagged); PH = 1: the flagged points again, with the
+    // part decided in FP64 (the grid-sum terms of u were taken in the sweep).
+    // act = false: the lane only takes part in the wave sums.
+    const auto point = [&](int idx, bool act, auto phase) {
+        constexpr int PH = decltype(phase)::value;
         // keep the kinematics block in LDS: without this compiler barrier the
         // loop-invariant values would be hoisted into registers
         __asm__ volatile("" ::: "memory");
@@ -416,15 +435,32 @@ __global__ __launch_bounds__(NT) void k_xpass(const Member* __restrict__ mt, con
         T nx = uy * wz - uz * wy;
         T ny = uz * wx - ux * wz;
         T nz = ux * wy - uy * wx;
-        const double u2 = (double)ux * ux + (double)uy * uy + (double)uz * uz;
-        acc[0] = fmax(acc[0], u2);
-        acc[1] += u2;
-        if (!isfinite(u2)) acc[2] = 1.0;
+        if constexpr (PH == 0) {
+            const double u2 = (double)ux * ux + (double)uy * uy + (double)uz * uz;
+            acc[0] = fmax(acc[0], u2);
+            acc[1] += u2;
+            if (!isfinite(u2)) acc[2] = 1.0;
+        }
         if constexpr (NC > 0) {
             const double xg = dx * i, yg = dx * (row % N), zg = dx * (row / N);
-            const KinT<double>* k64 = nullptr;
-            if constexpr (K64) k64 = &kin64;
-            const MaskPt<T> mp = eval_mask<T>(kin, xg, yg, zg, k64);
+            MaskPt<T> mp;
+            mp.chi = T(0);
+            mp.us[0] = mp.us[1] = mp.us[2] = T(0);
+            mp.colour = 0;
+            if (act) {
+                if constexpr (PH == 1) {
+                    mp = eval_mask<T>(kin, xg, yg, zg, k64p);
+                } else if constexpr (K64) {
+                    bool defer = false;
+                    mp = eval_mask<T>(kin, xg, yg, zg, nullptr, &defer);
+                    if (defer) {
+                        amb[idx] = 1;
+                        amb_any = 1;
+                    }
+                } else {
+                    mp = eval_mask<T>(kin, xg, yg, zg, nullptr);
+                }
+            }
             const bool has = mp.chi > T(0);
             // FP64 force and torque terms from the working-precision mask values
             const auto terms = [&](double* val) {
@@ -483,8 +519,21 @@ __global__ __launch_bounds__(NT) void k_xpass(const Member* __restrict__ mt, con
                 });
             }
         }
-        fbuf[lds_at<true, 1, SC>(i, r)] = cx<T>{nx, ny};
-        reinterpret_cast<T*>(fbuf + lds_at<true, 1, SC>(i, RW + r / 2))[r & 1] = nz;
+        if (act) {
+            fbuf[lds_at<true, 1, SC>(i, r)] = cx<T>{nx, ny};
+            reinterpret_cast<T*>(fbuf + lds_at<true, 1, SC>(i, RW + r / 2))[r & 1] = nz;
+        }
+    };
+#pragma unroll 1
+    for (int idx = tid; idx < RW * N; idx += NT) point(idx, true, std::integral_constant<int, 0>{});
+    if constexpr (K64) {
+        // points where two parts overlap, in a fixed order (deterministic sums);
+        // every lane runs the same number of iterations for the wave sums
+        __syncthreads();
+        if (amb_any) {
+#pragma unroll 1
+            for (int idx = tid; idx < RW * N; idx += NT) point(idx, amb[idx] != 0, std::integral_constant<int, 1>{});
+        }
     }
     // workgroup partial sums: lane values of the first three by DPP, the wave rows
     // of the rest, combined over waves in a fixed order
@@ -677,6 +726,13 @@ __device__ inline void reduce_level2(const double* __restrict__ partial2, double
     __syncthreads();
 }
 
+// Mask-evaluation blocks of the current kinematics (one thread), read by every
+// x-pass workgroup.
+__device__ __attribute__((noinline)) void kin_prepare(StateHdr* h) {
+    kin_cast<float>(h->kin, h->kf);
+    kin_cast<double>(h->kin, h->kd);
+}
+
 // Start of a stepping call, one thread per member: make slot 0 current and
 // evaluate the kinematics of the current time level.
 static __global__ void k_prologue(const Member* __restrict__ mt, int nmem) {
@@ -688,7 +744,10 @@ static __global__ void k_prologue(const Member* __restrict__ mt, int nmem) {
         hdr->slot[0] = hdr->slot[1];
         hdr->cur = 0;
     }
-    if (m.nc > 0) compute_kin(*m.ins, hdr->slot[0].t, m.dx, hdr->kin);
+    if (m.nc > 0) {
+        compute_kin(*m.ins, hdr->slot[0].t, m.dx, hdr->kin);
+        kin_prepare(hdr);
+    }
 }
 
 // Writes the launch record of a single plan (and the device copy of its body
@@ -704,6 +763,7 @@ static __global__ void k_member_set(Member* dst, Member v, flusi_insect ins) {
 // its FP64 working set would set the register count of the whole y-pass.
 __device__ inline void kin_of_level(const Member& m, int p) {
     compute_kin(*m.ins, m.hdr->slot[p].t, m.dx, m.hdr->kin);
+    kin_prepare(m.hdr);
 }
 
 static __global__ void k_hdr_init(StateHdr* hdr, double t0) {
