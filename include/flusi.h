@@ -128,6 +128,11 @@ int flusi_plan_create(int nx, int ny, int nz, double L, double nu, double eta, i
                       flusi_plan* out);
 int flusi_plan_destroy(flusi_plan plan);
 
+/* Device bytes a plan of this size and dtype allocates at creation
+ * (workspace) and that one state occupies, without allocating anything.
+ * Errors: EINVAL, EUNSUPPORTED. */
+int flusi_sizes(int n, int dtype, size_t* workspace_bytes, size_t* state_bytes);
+
 /* All further launches of this plan go to `stream` (a hipStream_t). */
 int flusi_set_stream(flusi_plan plan, void* stream);
 
@@ -292,6 +297,69 @@ int flusi_ensemble_step(flusi_ensemble e, int nsteps, int use_graph);
  * states, and stores the chosen schedule in the group's first plan.  Member
  * states are not modified.  Synchronous. */
 int flusi_ensemble_autotune(flusi_ensemble e, int reps);
+
+/* ------------------------------------------------------------------------
+ * Serving: a request loop with continuous batching.
+ *
+ * A server owns a worker thread, an ensemble and the device memory of the
+ * requests it has admitted.  Submitted requests queue in arrival order; the
+ * worker admits the oldest waiting requests while their device footprint
+ * (plan workspace + state + velocity-export scratch + output field) fits the
+ * HBM budget, advances every admitted request together (all grid sizes in
+ * one ensemble step, size groups on parallel streams) in chunks of at most
+ * max_chunk steps, never past any request's last step, and retires a request
+ * as soon as its steps are done: its final velocity and diagnostics are
+ * copied to host memory and its device memory is freed, which admits the
+ * next waiting requests.  A request's result is bitwise the same as stepping
+ * it alone with flusi_step (same plan parameters, body, controls and steps).
+ * Latency = completion time - submit time (host steady clock).
+ * ------------------------------------------------------------------------ */
+typedef struct flusi_server_s* flusi_server;
+
+typedef struct {
+    int n;                 /* grid points per axis */
+    int has_insect;        /* 0: no mask; otherwise `ins` is used */
+    double L, nu, eta;     /* box side, viscosity, C_eta */
+    flusi_insect ins;
+    flusi_step_params p;   /* controls; p.nsteps = steps of the request; p.history is ignored */
+    const void* u0;        /* HOST pointer to the initial velocity [3][n][n][n] of the server's real
+                              type (copied by flusi_server_submit), or NULL: fluid at rest */
+} flusi_request;
+
+typedef struct {
+    long long submitted, completed, failed, waiting, active;
+    double p50_ms, p99_ms, max_ms;  /* latency over completed requests */
+    double point_steps;             /* sum of n^3 * steps over completed requests */
+    double busy_s;                  /* first submit to last completion */
+    double mpoint_steps_per_s;      /* point_steps / busy_s / 1e6 */
+    size_t peak_bytes;              /* largest admitted footprint sum */
+    int peak_active;                /* most requests on the device at once */
+    int reserved;
+} flusi_server_stats;
+
+/* Footprint a request of grid n occupies while admitted (bytes). */
+size_t flusi_request_bytes(int n, int dtype);
+/* Server for requests of one dtype; hbm_budget: device bytes the admitted
+ * requests may occupy together; max_chunk >= 1: steps per batch iteration.
+ * Starts the worker thread on the current device.  Errors: EINVAL, EDEVICE. */
+int flusi_server_create(int dtype, size_t hbm_budget, int max_chunk, flusi_server* out);
+/* Stops the worker (after the request in flight of each batch iteration) and
+ * frees every request and result. */
+int flusi_server_destroy(flusi_server s);
+/* Queues a request (thread-safe; copies r and the initial field) and returns
+ * its id.  Errors: EINVAL (bad parameters), EUNSUPPORTED (grid size), ENOMEM
+ * (footprint larger than the whole budget). */
+int flusi_server_submit(flusi_server s, const flusi_request* r, long long* id);
+/* Waits up to timeout_ms (< 0: no limit) for request id to finish.  Then
+ * copies its final velocity [3][n][n][n] to u_host (may be NULL), its last
+ * diagnostics record (FLUSI_NDIAG doubles) to diag (may be NULL) and its
+ * latency in ms to latency_ms (may be NULL), forgets the request and returns
+ * its status (FLUSI_OK, FLUSI_ENONFINITE, ...).  Returns 1 on time-out (the
+ * request stays).  Errors: EINVAL (unknown id). */
+int flusi_server_wait(flusi_server s, long long id, double timeout_ms, void* u_host, double* diag,
+                      double* latency_ms);
+/* Counters and latency percentiles so far. */
+int flusi_server_stats_get(flusi_server s, flusi_server_stats* out);
 
 #ifdef __cplusplus
 }

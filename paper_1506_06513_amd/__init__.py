@@ -77,6 +77,24 @@ class flusi_schedule(ctypes.Structure):
         return {k: int(getattr(self, k)) for k in ("y_inverse", "x_pass", "y_forward", "z_pass", "split_z")}
 
 
+class flusi_request(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int), ("has_insect", ctypes.c_int),
+                ("L", ctypes.c_double), ("nu", ctypes.c_double), ("eta", ctypes.c_double),
+                ("ins", flusi_insect), ("p", flusi_step_params), ("u0", ctypes.c_void_p)]
+
+
+class flusi_server_stats(ctypes.Structure):
+    _fields_ = [("submitted", ctypes.c_longlong), ("completed", ctypes.c_longlong), ("failed", ctypes.c_longlong),
+                ("waiting", ctypes.c_longlong), ("active", ctypes.c_longlong),
+                ("p50_ms", ctypes.c_double), ("p99_ms", ctypes.c_double), ("max_ms", ctypes.c_double),
+                ("point_steps", ctypes.c_double), ("busy_s", ctypes.c_double),
+                ("mpoint_steps_per_s", ctypes.c_double), ("peak_bytes", ctypes.c_size_t),
+                ("peak_active", ctypes.c_int), ("reserved", ctypes.c_int)]
+
+    def as_dict(self) -> dict:
+        return {k: (getattr(self, k)) for k, _ in self._fields_ if k != "reserved"}
+
+
 _P = ctypes.c_void_p
 _SIGS = {
     "flusi_last_error": (ctypes.c_char_p, []),
@@ -104,6 +122,15 @@ _SIGS = {
     "flusi_autotune": (ctypes.c_int, [_P, _P, ctypes.POINTER(flusi_insect), ctypes.POINTER(flusi_step_params),
                                       ctypes.c_int, ctypes.POINTER(flusi_schedule)]),
     "flusi_ensemble_autotune": (ctypes.c_int, [_P, ctypes.c_int]),
+    "flusi_sizes": (ctypes.c_int, [ctypes.c_int, ctypes.c_int, ctypes.POINTER(ctypes.c_size_t),
+                                   ctypes.POINTER(ctypes.c_size_t)]),
+    "flusi_request_bytes": (ctypes.c_size_t, [ctypes.c_int, ctypes.c_int]),
+    "flusi_server_create": (ctypes.c_int, [ctypes.c_int, ctypes.c_size_t, ctypes.c_int, ctypes.POINTER(_P)]),
+    "flusi_server_destroy": (ctypes.c_int, [_P]),
+    "flusi_server_submit": (ctypes.c_int, [_P, ctypes.POINTER(flusi_request), ctypes.POINTER(ctypes.c_longlong)]),
+    "flusi_server_wait": (ctypes.c_int, [_P, ctypes.c_longlong, ctypes.c_double, _P, ctypes.POINTER(ctypes.c_double),
+                                         ctypes.POINTER(ctypes.c_double)]),
+    "flusi_server_stats_get": (ctypes.c_int, [_P, ctypes.POINTER(flusi_server_stats)]),
     "flusi_ensemble_create": (ctypes.c_int, [ctypes.c_int, ctypes.POINTER(_P)]),
     "flusi_ensemble_destroy": (ctypes.c_int, [_P]),
     "flusi_ensemble_set_stream": (ctypes.c_int, [_P, _P]),
@@ -274,6 +301,47 @@ def make_schedule(d: dict) -> flusi_schedule:
     for k, v in d.items():
         setattr(s, k, int(v))
     return s
+
+
+def flusi_sizes(n: int, dtype: int):
+    w = ctypes.c_size_t()
+    st = ctypes.c_size_t()
+    _check(lib().flusi_sizes(n, dtype, ctypes.byref(w), ctypes.byref(st)))
+    return w.value, st.value
+
+
+def flusi_request_bytes(n: int, dtype: int) -> int:
+    return int(lib().flusi_request_bytes(n, dtype))
+
+
+def flusi_server_create(dtype: int, hbm_budget: int, max_chunk: int):
+    h = _P()
+    _check(lib().flusi_server_create(dtype, hbm_budget, max_chunk, ctypes.byref(h)))
+    return h
+
+
+def flusi_server_destroy(srv):
+    _check(lib().flusi_server_destroy(srv))
+
+
+def flusi_server_submit(srv, req: flusi_request) -> int:
+    i = ctypes.c_longlong()
+    _check(lib().flusi_server_submit(srv, ctypes.byref(req), ctypes.byref(i)))
+    return i.value
+
+
+def flusi_server_wait(srv, rid: int, timeout_ms: float, u_host, diag: bool = True):
+    """Returns (status, diag array, latency ms); status 1 = timed out."""
+    d = (ctypes.c_double * FLUSI_NDIAG)()
+    lat = ctypes.c_double()
+    rc = lib().flusi_server_wait(srv, rid, timeout_ms, u_host, d, ctypes.byref(lat))
+    return rc, np.array(d[:]), lat.value
+
+
+def flusi_server_stats_get(srv) -> dict:
+    st = flusi_server_stats()
+    _check(lib().flusi_server_stats_get(srv, ctypes.byref(st)))
+    return st.as_dict()
 
 
 def flusi_ensemble_create(dtype: int):
@@ -488,6 +556,63 @@ class Ensemble:
             flusi_ensemble_destroy(self.handle)
             self.handle = None
             self._keep.clear()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Server:
+    """Request loop with continuous batching (flusi_server_*).
+
+    submit() copies the request (and its initial field) and returns an id;
+    wait() returns (status, u [3][n][n][n] as numpy, diagnostics, latency ms)."""
+
+    def __init__(self, dtype: str = "f32", hbm_budget: int | None = None, max_chunk: int = 20):
+        self.dtype = dtype
+        self.np_dt = np.float64 if dtype == "f64" else np.float32
+        if hbm_budget is None:
+            free, _ = torch.cuda.mem_get_info()
+            hbm_budget = int(free * 0.8)
+        self.budget = hbm_budget
+        self.handle = flusi_server_create(FLUSI_F64 if dtype == "f64" else FLUSI_F32, hbm_budget, max_chunk)
+        self._n = {}
+
+    def submit(self, n: int, L: float, nu: float, eta: float, steps: int, insect: dict | None = None,
+               u0: np.ndarray | None = None, **controls) -> int:
+        r = flusi_request()
+        r.n, r.L, r.nu, r.eta = n, L, nu, eta
+        ins = make_insect(insect)
+        r.has_insect = 1 if ins is not None else 0
+        if ins is not None:
+            r.ins = ins
+        r.p = step_params(steps, **controls)
+        keep = None
+        if u0 is not None:
+            keep = np.ascontiguousarray(u0, dtype=self.np_dt)
+            assert keep.shape == (3, n, n, n)
+            r.u0 = keep.ctypes.data
+        rid = flusi_server_submit(self.handle, r)
+        self._n[rid] = n
+        return rid
+
+    def wait(self, rid: int, timeout_ms: float = -1.0, want_u: bool = True):
+        n = self._n[rid]
+        u = np.empty((3, n, n, n), dtype=self.np_dt) if want_u else None
+        rc, diag, lat = flusi_server_wait(self.handle, rid, timeout_ms, u.ctypes.data if want_u else None)
+        if rc != 1:
+            self._n.pop(rid, None)
+        return rc, u, diag, lat
+
+    def stats(self) -> dict:
+        return flusi_server_stats_get(self.handle)
+
+    def close(self):
+        if self.handle is not None:
+            flusi_server_destroy(self.handle)
+            self.handle = None
 
     def __del__(self):
         try:

@@ -48,7 +48,8 @@ def _run(cmd):
 def build(jobs: int | None = None, out: str = LIB, verbose: bool = False) -> str:
     jobs = jobs or min(16, os.cpu_count() or 1)
     with tempfile.TemporaryDirectory(prefix="flusi_build_") as tmp:
-        units = [(os.path.join(CSRC, "flusi.hip"), [], os.path.join(tmp, "flusi.o"))]
+        units = [(os.path.join(CSRC, "flusi.hip"), [], os.path.join(tmp, "flusi.o")),
+                 (os.path.join(CSRC, "server.hip"), [], os.path.join(tmp, "server.o"))]
         for n in sizes():
             units.append((os.path.join(CSRC, "inst.hip"), [f"-DFLUSI_N={n}"],
                           os.path.join(tmp, f"inst_{n}.o")))

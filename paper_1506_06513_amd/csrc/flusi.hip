@@ -306,6 +306,20 @@ int flusi_plan_destroy(flusi_plan plan) {
     return FLUSI_OK;
 }
 
+int flusi_sizes(int n, int dtype, size_t* workspace_bytes, size_t* state_bytes) {
+    if (dtype != FLUSI_F32 && dtype != FLUSI_F64) return set_error(FLUSI_EINVAL, "dtype must be FLUSI_F32 or FLUSI_F64");
+    ImplBase* impl = make_impl(n, dtype);
+    if (!impl) return set_error(FLUSI_EUNSUPPORTED, "grid size %d not supported", n);
+    const size_t cxb = dtype == FLUSI_F32 ? 8 : 16;
+    if (workspace_bytes)
+        *workspace_bytes = n * cxb + impl->bufA_elems() * cxb + impl->bufB_elems() * cxb +
+                           (size_t)impl->nwg_x() * NV * 8 + NRED_BLOCKS * NV * 8 + sizeof(Kin) + sizeof(flusi_insect) +
+                           sizeof(Member);
+    if (state_bytes) *state_bytes = impl->state_bytes();
+    delete impl;
+    return FLUSI_OK;
+}
+
 int flusi_set_stream(flusi_plan plan, void* stream) {
     if (int rc = check_plan(plan)) return rc;
     plan->d.stream = static_cast<hipStream_t>(stream);

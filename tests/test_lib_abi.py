@@ -44,3 +44,16 @@ def test_insect_struct_from_dict():
     assert s.body == F.FLUSI_BODY_ELLIPSOID and s.wings == 1 and s.smooth == F.FLUSI_SMOOTH_COS
     assert abs(s.wing_t - 4 * 4.0 / 256) < 1e-15
     assert list(s.pivot_r) == [0.0, -0.15, 0.0]
+
+
+def test_size_queries_need_no_device():
+    # footprints are computed on the host from the grid size alone
+    for n in F.SUPPORTED_N:
+        ws, sb = F.flusi_sizes(n, F.FLUSI_F32)
+        ws64, sb64 = F.flusi_sizes(n, F.FLUSI_F64)
+        assert 0 < sb < ws and ws64 > ws and sb64 > sb
+        assert F.flusi_request_bytes(n, F.FLUSI_F32) > ws + sb
+    with pytest.raises(F.FlusiError) as e:
+        F.flusi_sizes(100, F.FLUSI_F32)
+    assert e.value.code == F.FLUSI_EUNSUPPORTED
+    assert F.flusi_request_bytes(100, F.FLUSI_F32) == 0
