@@ -218,6 +218,50 @@ def ensemble_run(F, torch, count=48, steps=200, chunk=20, seed=1, tune=True):
                            f"stroke 50-80 deg; seed {seed}), fluid at rest, CFL 0.1"}
 
 
+def serve_run(F, torch, count=120, seed=2, budget_gib=32.0, chunk=20, big_n=512, big_steps=2000):
+    """Serving stream: requests submitted at their Poisson arrival times to a
+    flusi server (FP32, HBM budget budget_gib); latency from submit to result."""
+    import workloads as W
+    reqs = W.serve_stream(count, seed=seed, big_n=big_n, big_steps=big_steps)
+    big = [r for r in reqs if r["turbulent"]][0]
+    t_ic = time.perf_counter()
+    big_u0 = W.turbulent_inflow(big["n"], big["L"], seed=big["seed"], intensity=0.1, kmax=32.0).astype(np.float32)
+    t_ic = time.perf_counter() - t_ic
+    free, _ = torch.cuda.mem_get_info()
+    budget = int(min(free * 0.8, budget_gib * (1 << 30)))
+    srv = F.Server("f32", hbm_budget=budget, max_chunk=chunk)
+    ids = []
+    t0 = time.perf_counter()
+    for r in reqs:
+        now = time.perf_counter() - t0
+        if r["arrival"] > now:
+            time.sleep(r["arrival"] - now)
+        ids.append(srv.submit(r["n"], r["L"], r["nu"], r["eta"], r["steps"], r["insect"],
+                              big_u0 if r["turbulent"] else None, cfl=0.1))
+    res = [srv.wait(i, want_u=False) for i in ids]
+    wall = time.perf_counter() - t0
+    st = srv.stats()
+    srv.close()
+    bad = [r["id"] for r, x in zip(reqs, res) if x[0] != 0]
+    if bad:
+        raise SystemExit(f"serving: requests {bad} failed")
+    grids = {}
+    for r in reqs:
+        grids[r["n"]] = grids.get(r["n"], 0) + 1
+    return {"p50_ms": round(st["p50_ms"], 2), "p99_ms": round(st["p99_ms"], 2), "max_ms": round(st["max_ms"], 2),
+            "value": round(st["mpoint_steps_per_s"], 2), "unit": "Mpoint-steps/s",
+            "requests": count, "completed": st["completed"], "grids": {str(k): v for k, v in sorted(grids.items())},
+            "large_request_latency_ms": round(res[big["id"]][3], 2),
+            "peak_active": st["peak_active"], "peak_bytes": st["peak_bytes"], "hbm_budget_bytes": budget,
+            "max_chunk": chunk, "arrival_span_s": round(reqs[-1]["arrival"], 2), "wall_s": round(wall, 2),
+            "busy_s": round(st["busy_s"], 2), "point_steps": st["point_steps"], "dtype": "f32",
+            "initial_field_s": round(t_ic, 1),
+            "description": f"{count} requests, Poisson arrivals mean 4/s (seed {seed}): one {big['n']}^3 insect "
+                           f"in k^-5/3 turbulent inflow (intensity 0.1, |k| 1-32, {big['steps']} steps), the rest "
+                           f"insects on {{64,96,128,192}}^3 (Re 50-500, C_eta 1e-4..1e-3, 200 steps, at rest); "
+                           f"FP32 with FP64 reductions; admitted by footprint within the HBM budget"}
+
+
 def oracle_sample(wl, budget_s=12.0, max_steps=30):
     """Oracle throughput and final velocity on a bounded sample of the workload."""
     import oracle as O
@@ -241,7 +285,9 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=None)
     ap.add_argument("--warmup", type=int, default=10)
-    ap.add_argument("--workload", default="sphere128", choices=["sphere128", "insect256", "tg32", "ensemble48"])
+    ap.add_argument("--workload", default="sphere128",
+                    choices=["sphere128", "insect256", "tg32", "ensemble48", "serve"])
+    ap.add_argument("--no-serve", action="store_true", help="skip the serving-stream figure")
     ap.add_argument("--no-ensemble", action="store_true", help="skip the batched-ensemble figure")
     ap.add_argument("--no-autotune", action="store_true", help="time the default schedules")
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
@@ -272,6 +318,15 @@ def main():
                           "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
                           "data": "synthetic", "config": {"workload": "ensemble48", "description": e["description"]},
                           "ensemble": e}), flush=True)
+        return
+
+    if a.workload == "serve":
+        sv = serve_run(F, torch)
+        print(json.dumps({"metric": METRIC, "value": sv["value"], "unit": sv["unit"], "n_gpus": 1,
+                          "steps": None, "warmup": 0, "ms_per_step": None, "higher_is_better": True,
+                          "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+                          "config": {"workload": "serve", "description": sv["description"]},
+                          "p50_ms": sv["p50_ms"], "p99_ms": sv["p99_ms"], "serving": sv}), flush=True)
         return
 
     wl = build_workload(a.workload)
@@ -338,6 +393,8 @@ def main():
     }
     if not a.no_ensemble and a.workload == "sphere128":
         out["ensemble48"] = ensemble_run(F, torch, tune=not a.no_autotune)
+    if not a.no_serve and a.workload == "sphere128":
+        out["serving"] = serve_run(F, torch)
     if not a.no_cpu:
         cs = oracle_sample(wl)
         cpu_v = pts * cs["timed_steps"] / cs["seconds"] / 1e6

@@ -423,10 +423,11 @@ def part_of_max(stack: np.ndarray) -> np.ndarray:
     return part
 
 
-def insect_mask(g: Grid, ins: Insect, t: float):
-    """chi, u_s [3] and colour on every grid point at time t  [Alg. 1 step (a)]."""
-    n = g.n
-    x, y, z = g.coords()
+def mask_at(ins: Insect, t: float, dx: float, x, y, z):
+    """chi, u_s [3] and colour at points with global coordinates x, y, z (arrays
+    of one shape), smoothing width set by the grid spacing dx  [Alg. 1 step (a)]."""
+    x, y, z = (np.asarray(v, dtype=np.float64) for v in (x, y, z))
+    shp = x.shape
     xg = np.stack([x, y, z])
     xb = to_body(ins, t, xg)
     ub = body_velocity(ins, t, xb)
@@ -435,36 +436,42 @@ def insect_mask(g: Grid, ins: Insect, t: float):
     if ins.body == "sphere":
         xc = np.asarray(ins.x_cntr, dtype=np.float64)
         d = np.sqrt((x - xc[0]) ** 2 + (y - xc[1]) ** 2 + (z - xc[2]) ** 2) - ins.radius
-        chis.append(chi_of_delta(d, ins, g.dx))
+        chis.append(chi_of_delta(d, ins, dx))
         uss.append(ub)
     elif ins.body == "ellipsoid":
         d = delta_ellipsoid(xb[0], xb[1], xb[2], ins.a, ins.b)
-        chis.append(chi_of_delta(d, ins, g.dx))
+        chis.append(chi_of_delta(d, ins, dx))
         uss.append(ub)
     else:
-        chis.append(np.zeros((n, n, n)))
-        uss.append(np.zeros((3, n, n, n)))
+        chis.append(np.zeros(shp))
+        uss.append(np.zeros((3,) + shp))
 
     if ins.wings:
         for side in ("l", "r"):
             xw = wing_frame(ins, t, side, xb)
             d = delta_elliptic_wing(xw[0], xw[1], xw[2], ins.wing_A, ins.wing_B, ins.wing_t)
-            chis.append(chi_of_delta(d, ins, g.dx))
+            chis.append(chi_of_delta(d, ins, dx))
             uss.append(wing_velocity(ins, t, side, xb))
     else:
-        chis += [np.zeros((n, n, n))] * 2
-        uss += [np.zeros((3, n, n, n))] * 2
+        chis += [np.zeros(shp)] * 2
+        uss += [np.zeros((3,) + shp)] * 2
 
     stack = np.stack(chis)
     part = part_of_max(stack)
     chi = np.max(stack, axis=0)
-    us = np.zeros((3, n, n, n))
+    us = np.zeros((3,) + shp)
     for p in range(3):
         sel = part == p
         us[:, sel] = uss[p][:, sel]
     colour = np.where(chi > 0.0, part + 1, 0).astype(np.int16)
     us = us * (chi > 0.0)
     return chi, us, colour
+
+
+def insect_mask(g: Grid, ins: Insect, t: float):
+    """chi, u_s [3] and colour on every grid point at time t  [Alg. 1 step (a)]."""
+    x, y, z = g.coords()
+    return mask_at(ins, t, g.dx, x, y, z)
 
 
 def reference_points(ins: Insect, t: float) -> np.ndarray:

@@ -175,3 +175,57 @@ def test_fixed_mean_holds_the_inflow():
     P.step(st, 30, W.sphere_body(L), cfl=0.1, mean_mode=F.FLUSI_MEAN_FIXED)
     m = np_of(P.velocity(st)).mean(axis=(1, 2, 3))
     assert np.allclose(m, u0.mean(axis=(1, 2, 3)), atol=1e-13)
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+def test_taylor_green_512_closed_form(dtype):
+    # the 2D Taylor-Green vortex decays as exp(-2 nu t) exactly under the
+    # method (u x w is a gradient); at 512^3 this pins the FFTs, curl,
+    # projection and IF-AB2 at the largest grid of the serving stream
+    n, nu, dt, steps = 512, 0.01, 1e-3, 3
+    u0 = torch.from_numpy(W.taylor_green(n))
+    P = F.Plan(n, 2 * math.pi, nu, 1.0, dtype)
+    st = P.new_state(u0)
+    P.step(st, steps, None, dt_fixed=dt, mean_mode=F.FLUSI_MEAN_FREE)
+    u = P.velocity(st).double()
+    ref = u0.to(u.device) * math.exp(-2 * nu * dt * steps)
+    err = float(torch.linalg.vector_norm(u - ref) / torch.linalg.vector_norm(ref))
+    assert err < (1e-13 if dtype == "f64" else 2e-6)
+
+
+def test_insect512_fp32_matches_fp64_and_sampled_mask_matches_oracle():
+    n, L = 512, 4.0
+    wl = W.WORKLOADS["insect256"]
+    body = W.model_insect(n, L)
+    vel = {}
+    for dtype in ("f64", "f32"):
+        P = F.Plan(n, L, wl["nu"], wl["eta"], dtype)
+        st = P.new_state(torch.zeros((3, n, n, n), dtype=P.rdt, device="cuda"))
+        P.step(st, 2, body, cfl=0.1)
+        assert P.forces(st)[0] == 0
+        vel[dtype] = P.velocity(st).double()
+        if dtype == "f64":
+            # sampled points of the materialized 512^3 mask against the oracle
+            t = 0.3
+            chi, us, col = P.mask(body, t)
+            inside = torch.nonzero(chi.reshape(-1) > 0).reshape(-1)
+            g = torch.Generator(device="cpu").manual_seed(0)
+            pick = inside[torch.randint(0, inside.numel(), (20000,), generator=g).to(inside.device)]
+            anywhere = torch.randint(0, n ** 3, (20000,), generator=g).to(inside.device)
+            idx = torch.cat([pick, anywhere])
+            k, j, i = idx // (n * n), (idx // n) % n, idx % n
+            dx = L / n
+            oc, ous, ocol = O.mask_at(O.Insect.from_dict(body), t, dx, (i * dx).cpu().numpy(),
+                                      (j * dx).cpu().numpy(), (k * dx).cpu().numpy())
+            gc = chi.reshape(-1)[idx].cpu().numpy()
+            gu = us.reshape(3, -1)[:, idx].cpu().numpy()
+            gk = col.reshape(-1)[idx].cpu().numpy()
+            assert np.max(np.abs(gc - oc)) <= 1e-13
+            assert np.max(np.abs(gu - ous)) <= 1e-12
+            sel = oc > 1e-12
+            assert np.array_equal(gk[sel], ocol[sel])
+            del chi, us, col
+        del P, st
+        torch.cuda.empty_cache()
+    d = torch.linalg.vector_norm(vel["f32"] - vel["f64"]) / torch.linalg.vector_norm(vel["f64"])
+    assert float(d) < 2e-5

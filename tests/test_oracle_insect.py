@@ -212,3 +212,17 @@ def test_mirror_plane_points_take_the_left_wing():
     assert wing_pts.sum() > 0 and np.all(col[:, j, :][wing_pts] == 2)
     ul = O.wing_velocity(ins, t, "l", xb)
     assert np.allclose(us[:, :, j, :][:, wing_pts], ul[:, :, j, :][:, wing_pts], rtol=0, atol=1e-14)
+
+
+def test_pointwise_mask_equals_the_grid_mask():
+    n, L = 32, 4.0
+    g = O.Grid(n, L)
+    ins = O.Insect.from_dict(W.model_insect(n, L))
+    chi, us, col = O.insect_mask(g, ins, 0.2)
+    rng = np.random.default_rng(0)
+    idx = rng.integers(0, n, size=(3, 500))
+    x, y, z = (idx[2] * g.dx, idx[1] * g.dx, idx[0] * g.dx)
+    c2, u2, k2 = O.mask_at(ins, 0.2, g.dx, x, y, z)
+    assert np.array_equal(c2, chi[idx[0], idx[1], idx[2]])
+    assert np.array_equal(u2, us[:, idx[0], idx[1], idx[2]])
+    assert np.array_equal(k2, col[idx[0], idx[1], idx[2]])

@@ -19,12 +19,18 @@ near 0.1, stroke amplitude 140 deg, Re 100-500, C_eta 1e-4..1e-3):
              nu = 1/136, C_eta = 2.5e-4, CFL 0.1, fluid at rest.
   ensemble   insect simulations on {64,96,128,192}^3 with seeded Re, C_eta
              and stroke amplitude.
+  serve      Poisson-arrival request stream (mean 4 per s): one 512^3 insect
+             in isotropic k^(-5/3) turbulent inflow (intensity 0.1,
+             1 <= |k| <= 32, 2000 steps) arriving second, and ensemble-like
+             insect requests (200 steps, fluid at rest).
 """
 from __future__ import annotations
 
 import math
+import os
 
 import numpy as np
+import scipy.fft
 
 DEG = math.pi / 180.0
 
@@ -72,7 +78,7 @@ def _random_solenoidal(n: int, seed: int, kmin: float, kmax: float, slope: float
         amp = np.sqrt(kk ** slope / kk ** 2)
     phase = np.exp(2j * math.pi * rng.random(shape))
     coef = a / norm * amp * phase * shell
-    return np.fft.irfftn(coef, s=(n, n, n), axes=(1, 2, 3))
+    return scipy.fft.irfftn(coef, s=(n, n, n), axes=(1, 2, 3), workers=os.cpu_count())
 
 
 def inflow_noise(n: int, L: float, seed: int, rms: float = 1e-3, kmax: float = 8.0,
@@ -156,4 +162,28 @@ def ensemble_members(count: int = 48, seed: int = 1, grids=(64, 96, 128, 192), L
         phim = float(rng.uniform(50.0, 80.0)) * DEG
         out.append(dict(id=i, n=n, L=L, nu=1.0 / re, eta=eta, phi_m=phim,
                         insect=model_insect(n, L, phi_m=phim)))
+    return out
+
+
+def serve_stream(count: int = 120, seed: int = 2, rate: float = 4.0, big_n: int = 512, big_steps: int = 2000,
+                 small_steps: int = 200, L: float = 4.0):
+    """Request list of the serving workload with arrival times in seconds.
+
+    Arrivals: Poisson process of the given mean rate (first arrival at 0).
+    Request 1 is the large insect in turbulent inflow (its initial field is
+    `turbulent_inflow(big_n, L, seed)`, built by the caller); the others are
+    drawn like the ensemble members and start from rest."""
+    rng = np.random.default_rng(seed + 1000)
+    gaps = rng.exponential(1.0 / rate, size=count)
+    arrivals = np.concatenate([[0.0], np.cumsum(gaps[1:])])
+    small = ensemble_members(count - 1, seed=seed, L=L)
+    out = []
+    for i in range(count):
+        if i == 1:
+            out.append(dict(id=i, arrival=float(arrivals[i]), n=big_n, L=L, nu=1.0 / 136.0, eta=2.5e-4,
+                            steps=big_steps, insect=model_insect(big_n, L), turbulent=True, seed=seed))
+        else:
+            m = small[i if i == 0 else i - 1]
+            out.append(dict(id=i, arrival=float(arrivals[i]), n=m["n"], L=L, nu=m["nu"], eta=m["eta"],
+                            steps=small_steps, insect=m["insect"], turbulent=False))
     return out
