@@ -11,7 +11,13 @@ Prints one JSON line.  `value` is FP32 Mpoint-steps/s (points x steps / s);
 the FP64 figure, each precision's error against the FP64 oracle, the roofline
 of the dominant kernel (live HIP-event timing over a timed region, algorithmic
 bytes from the pruned byte model) and the oracle's CPU throughput on a bounded
-sample are reported beside it.
+sample are reported beside it.  Schedules are autotuned before the timed
+region (--no-autotune: defaults).  The default run adds two sub-objects:
+`ensemble48` (48 seeded insect simulations on mixed grids advanced by batched
+launches replayed from a hipGraph, against the same members stepped one by one)
+and `serving` (a Poisson-arrival request stream with a 512^3 insect: p50/p99
+latency and throughput).  --workload selects insect256, tg32, ensemble48 or
+serve as the main line instead.
 """
 from __future__ import annotations
 
