@@ -261,7 +261,7 @@ int flusi_plan_create(int nx, int ny, int nz, double L, double nu, double eta, i
     ok = ok && hipMalloc(&d.bufA, d.szA) == hipSuccess;
     ok = ok && hipMalloc(&d.bufB, d.szB) == hipSuccess;
     ok = ok && hipMalloc(&d.partial, (size_t)d.nwg_x * NV * sizeof(double)) == hipSuccess;
-    ok = ok && hipMalloc(&d.partial2, (size_t)NRED_BLOCKS * NV * sizeof(double)) == hipSuccess;
+    ok = ok && hipMalloc(&d.partial2, (size_t)NRED_MAX * NV * sizeof(double)) == hipSuccess;
     ok = ok && hipMalloc(&d.kin, sizeof(Kin)) == hipSuccess;
     ok = ok && hipMalloc(&d.ins_dev, sizeof(flusi_insect)) == hipSuccess;
     ok = ok && hipMalloc(&d.member_dev, sizeof(Member)) == hipSuccess;
@@ -271,7 +271,7 @@ int flusi_plan_create(int nx, int ny, int nz, double L, double nu, double eta, i
         delete p;
         return set_error(FLUSI_ENOMEM, "device allocation for a %d^3 plan", nx);
     }
-    d.workspace = nx * cxb + d.szA + d.szB + (size_t)d.nwg_x * NV * 8 + NRED_BLOCKS * NV * 8 + sizeof(Kin) + sizeof(flusi_insect) + sizeof(Member);
+    d.workspace = nx * cxb + d.szA + d.szB + (size_t)d.nwg_x * NV * 8 + NRED_MAX * NV * 8 + sizeof(Kin) + sizeof(flusi_insect) + sizeof(Member);
     // FP64 twiddles exp(-2 pi i m / n); the FP32 table is rounded from them.
     std::vector<double> w(2 * nx);
     for (int m = 0; m < nx; ++m) {
@@ -313,7 +313,7 @@ int flusi_sizes(int n, int dtype, size_t* workspace_bytes, size_t* state_bytes) 
     const size_t cxb = dtype == FLUSI_F32 ? 8 : 16;
     if (workspace_bytes)
         *workspace_bytes = n * cxb + impl->bufA_elems() * cxb + impl->bufB_elems() * cxb +
-                           (size_t)impl->nwg_x() * NV * 8 + NRED_BLOCKS * NV * 8 + sizeof(Kin) + sizeof(flusi_insect) +
+                           (size_t)impl->nwg_x() * NV * 8 + NRED_MAX * NV * 8 + sizeof(Kin) + sizeof(flusi_insect) +
                            sizeof(Member);
     if (state_bytes) *state_bytes = impl->state_bytes();
     delete impl;

@@ -300,30 +300,26 @@ struct Impl final : ImplBase {
     static constexpr int NBZ = (Q + CZ - 1) / CZ;  // z-pass tiles per member
     static int nwg_of(int v) { return v ? nwg<1>(0) : nwg<0>(0); }
 
-    // y-inverse of the 6 z-partial fields; with kin set, one extra workgroup per
-    // member evaluates the kinematics of time level par
+    // y-inverse of the 6 z-partial fields
     template <int V>
-    static void y_inverse_v(const GroupRun& g, bool kin, int par) {
+    static void y_inverse_v(const GroupRun& g) {
         const CX* w = static_cast<const CX*>(g.tw);
         constexpr int nb = nby<V>(6);
-        if (kin)
-            k_ypass<T, N, +1, 2, V><<<(unsigned)((nb + 1) * g.nmem), NT, 0, g.stream>>>(g.mt, nb + 1, w, par, 0);
-        else
-            k_ypass<T, N, +1, 0, V><<<(unsigned)(nb * g.nmem), NT, 0, g.stream>>>(g.mt, nb, w, par, 0);
+        k_ypass<T, N, +1, 0, V><<<(unsigned)(nb * g.nmem), NT, 0, g.stream>>>(g.mt, nb, w, 0, 0);
     }
-    static void y_inverse(const GroupRun& g, bool kin, int par) {
-        if (g.sched.y_inverse) y_inverse_v<1>(g, kin, par);
-        else y_inverse_v<0>(g, kin, par);
+    static void y_inverse(const GroupRun& g) {
+        if (g.sched.y_inverse) y_inverse_v<1>(g);
+        else y_inverse_v<0>(g);
     }
-    // y-forward of 3 fields; with red set, NRED_BLOCKS extra workgroups per member
+    // y-forward of 3 fields; with red set, nred_of(N) extra workgroups per member
     // do the first-level reduction of the x-pass sums
     template <int V>
     static void y_forward_v(const GroupRun& g, bool red) {
         const CX* w = static_cast<const CX*>(g.tw);
         constexpr int nb = nby<V>(3);
         if (red)
-            k_ypass<T, N, -1, 1, V><<<(unsigned)((nb + NRED_BLOCKS) * g.nmem), NT, 0, g.stream>>>(
-                g.mt, nb + NRED_BLOCKS, w, 0, nwg_of(g.sched.x_pass));
+            k_ypass<T, N, -1, 1, V><<<(unsigned)((nb + nred_of(N)) * g.nmem), NT, 0, g.stream>>>(
+                g.mt, nb + nred_of(N), w, 0, nwg_of(g.sched.x_pass));
         else
             k_ypass<T, N, -1, 0, V><<<(unsigned)(nb * g.nmem), NT, 0, g.stream>>>(g.mt, nb, w, 0, 0);
     }
@@ -370,9 +366,11 @@ struct Impl final : ImplBase {
         }
         for (int s = 0; s < nsteps; ++s) {
             const int par = s & 1;
+            // kinematics of this time level (the prologue covers the first)
+            if (g.any_dyn && s > 0) k_kin_level<<<(unsigned)((g.nmem + 63) / 64), 64, 0, g.stream>>>(g.mt, g.nmem, par);
             {
                 PassScope ps(g.prof, PASS_YINV, g.stream);
-                y_inverse(g, g.any_dyn, par);
+                y_inverse(g);
             }
             {
                 PassScope ps(g.prof, PASS_X, g.stream);

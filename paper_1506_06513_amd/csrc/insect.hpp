@@ -72,7 +72,7 @@ __host__ __device__ inline void cross3(const double* a, const double* b, double*
 }
 
 // Kinematics at time t (Sec. 3.1 and 3.3).  dx is the grid spacing.
-__host__ __device__ inline void compute_kin(const flusi_insect& in, double t, double dx, Kin& k) {
+__host__ __device__ __forceinline__ void compute_kin(const flusi_insect& in, double t, double dx, Kin& k) {
     const double psi = in.psi + in.psi_dot * t;
     const double beta = in.beta + in.beta_dot * t;
     const double gam = in.gamma + in.gamma_dot * t;

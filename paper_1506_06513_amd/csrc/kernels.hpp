@@ -25,7 +25,7 @@ namespace flusi {
 
 constexpr int NT = 256;   // threads per workgroup of the y passes and the x-pass
 constexpr int NV = 39;    // reduction values per workgroup (see xpass)
-constexpr int NRED_BLOCKS = 64;
+constexpr int NRED_MAX = 64;  // most first-level reduction workgroups per member
 
 // Tile shapes.  Each stepping pass has two variants that compute the same
 // values (V = 0 the default, V = 1 the alternative); a schedule picks one per
@@ -56,6 +56,13 @@ __host__ __device__ constexpr int rows_x(int N, int cbytes = 8, int V = 0) {
     return V && p > 2 ? p / 2 : p;
 }
 __host__ __device__ constexpr int round_up(int a, int b) { return (a + b - 1) / b * b; }
+// First-level reduction workgroups per member: every z-pass workgroup reads
+// their NV-value records, so small grids use few; large grids (many x-pass
+// records) use more so that the first level stays shorter than the y-forward.
+__host__ __device__ constexpr int nred_of(int N) {
+    const int n = N * N / rows_x(N) / 128;
+    return n < 16 ? 16 : (n > NRED_MAX ? NRED_MAX : n);
+}
 
 // Pruned-spectrum geometry.  Row pitches are padded to 128 bytes so that every
 // row of a pass starts on a cache line.
@@ -129,9 +136,9 @@ struct Member {
     int pad;
 };
 
+template <int NRED>
 __device__ inline void reduce_level1(const double* __restrict__ partial, int nwg, double* __restrict__ partial2,
                                      int b, double (*red)[NV]);
-__device__ inline void kin_of_level(const Member& m, int p);
 
 // ---------------------------------------------------------------------------
 // Column FFT along y or z of one tile of C columns.
@@ -202,8 +209,7 @@ __global__ __launch_bounds__(NT) void k_colfft(const cx<T>* in, cx<T>* out, int 
 //            z) -> bufB [f][z][y][kx] (pitch KPp per y)
 //   DIR = -1 (y-forward): 3 fields bufA [f][z][y][kx] -> bufB [f][z][ky'][kx]
 // Each member has nbx*nf column tiles followed by the extra workgroups:
-//   EXTRA 1: NRED_BLOCKS workgroups reduce the x-pass sums (first level)
-//   EXTRA 2: one workgroup evaluates the kinematics of time level p
+//   EXTRA 1: nred_of(N) workgroups reduce the x-pass sums (first level)
 // nwg: x-pass workgroups per member (records of the first-level reduction).
 template <typename T, int N, int DIR, int EXTRA, int V>
 __global__ __launch_bounds__(NT) void k_ypass(const Member* __restrict__ mt, int per, const cx<T>* __restrict__ tw,
@@ -222,9 +228,7 @@ __global__ __launch_bounds__(NT) void k_ypass(const Member* __restrict__ mt, int
     if (f >= nf) {
         if constexpr (EXTRA == 1) {
             __shared__ double red[NT / 64][NV];
-            if (tile - nf * nbx < NRED_BLOCKS) reduce_level1(m.partial, nwg, m.partial2, tile - nf * nbx, red);
-        } else if constexpr (EXTRA == 2) {
-            if (tile == nf * nbx && threadIdx.x == 0 && m.dyn) kin_of_level(m, p);
+            if (tile - nf * nbx < nred_of(N)) reduce_level1<nred_of(N)>(m.partial, nwg, m.partial2, tile - nf * nbx, red);
         }
         return;
     }
@@ -580,9 +584,9 @@ __global__ __launch_bounds__(NT) void k_xpass(const Member* __restrict__ mt, con
 
 // ---------------------------------------------------------------------------
 // Scalar work of a step.  The x-pass leaves NV partial sums per workgroup;
-// NRED_BLOCKS extra workgroups of the y-forward launch reduce fixed
+// nred_of(N) extra workgroups of the y-forward launch reduce fixed
 // contiguous chunks of them (first level); every z-pass workgroup reduces the
-// NRED_BLOCKS results in a fixed order (second level) and derives dt and the
+// nred_of(N) results in a fixed order (second level) and derives dt and the
 // AB2 weights itself, so all workgroups agree bit for bit.  Workgroup 0 of the
 // z-pass then writes the diagnostics and the next time level.
 // ---------------------------------------------------------------------------
@@ -670,43 +674,65 @@ __device__ inline void write_step(StateHdr* h, int p, const double* tot, const C
     h->cur = 1 - p;
 }
 
-// First level: workgroup b (< NRED_BLOCKS) reduces records [b*chunk, (b+1)*chunk).
+// First level: workgroup b (< NRED) reduces the x-pass records
+// [b*chunk, (b+1)*chunk) ([workgroup][NV]).  Each wave reads whole records
+// (one coalesced load of NV doubles) and lane v accumulates value v; the four
+// waves take every fourth record and are combined in a fixed order.
+template <int NRED>
 __device__ inline void reduce_level1(const double* __restrict__ partial, int nwg, double* __restrict__ partial2,
                                      int b, double (*red)[NV]) {
-    const int tid = threadIdx.x;
-    const int chunk = (nwg + NRED_BLOCKS - 1) / NRED_BLOCKS;
+    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+    constexpr int NW = NT / 64;
+    const int chunk = (nwg + NRED - 1) / NRED;
     const int lo = b * chunk, hi = min(nwg, lo + chunk);
-    double acc[NV];
+    const bool is_max = lane == 0 || lane == 2;
+    const glb<double>* P = gview(partial);
+    double acc = 0.0;
+    if (lane < NV) {
+        int w = lo + wv;
+        constexpr int UN = 8;  // records in flight per wave
+#pragma unroll 1
+        for (; w + (UN - 1) * NW < hi; w += UN * NW) {
+            double x[UN];
 #pragma unroll
-    for (int v = 0; v < NV; ++v) acc[v] = 0.0;
-    for (int w = lo + tid; w < hi; w += NT) {
-        const glb<double>* q = gview(partial) + (long)w * NV;
+            for (int u = 0; u < UN; ++u) x[u] = P[(long)(w + u * NW) * NV + lane];
 #pragma unroll
-        for (int v = 0; v < NV; ++v) acc[v] = (v == 0 || v == 2) ? fmax(acc[v], q[v]) : acc[v] + q[v];
+            for (int u = 0; u < UN; ++u) acc = is_max ? fmax(acc, x[u]) : acc + x[u];
+        }
+        for (; w < hi; w += NW) {
+            const double x = P[(long)w * NV + lane];
+            acc = is_max ? fmax(acc, x) : acc + x;
+        }
+        red[wv][lane] = acc;
     }
-    block_reduce_store<NV>(acc, red, partial2 + (long)b * NV);
+    __syncthreads();
+    if (tid < NV) {
+        double r = red[0][tid];
+        for (int k = 1; k < NW; ++k) r = (tid == 0 || tid == 2) ? fmax(r, red[k][tid]) : r + red[k][tid];
+        gview(partial2)[(long)b * NV + tid] = r;
+    }
 }
 
-// Second level (whole workgroup, NTH threads): totals of the NRED_BLOCKS records.
-template <int NTH>
+// Second level (whole workgroup, NTH threads): totals of the NRED records.
+template <int NTH, int NRED>
 __device__ inline void reduce_level2(const double* __restrict__ partial2, double* p2s, double* tot) {
     const int tid = threadIdx.x;
-    constexpr int L2N = (NRED_BLOCKS * NV + NTH - 1) / NTH;
+    constexpr int L2N = (NRED * NV + NTH - 1) / NTH;
     double tmp[L2N];
 #pragma unroll
     for (int i = 0; i < L2N; ++i) {
         const int e = tid + i * NTH;
-        tmp[i] = e < NRED_BLOCKS * NV ? gview(partial2)[e] : 0.0;
+        tmp[i] = e < NRED * NV ? gview(partial2)[e] : 0.0;
     }
 #pragma unroll
     for (int i = 0; i < L2N; ++i) {
         const int e = tid + i * NTH;
-        if (e < NRED_BLOCKS * NV) p2s[e] = tmp[i];
+        if (e < NRED * NV) p2s[e] = tmp[i];
     }
     __syncthreads();
-    // fixed order: value v is summed in 4 chains of NRED_BLOCKS/4 records, then
+    // fixed order: value v is summed in 4 chains of NRED/4 records, then
     // the 4 chain results in order
-    constexpr int CH = 4, PER = NRED_BLOCKS / CH;
+    constexpr int CH = 4, PER = NRED / CH;
     __shared__ double chain[CH * NV];
     for (int w = tid; w < CH * NV; w += NTH) {
         const int v = w % NV, k = w / NV;
@@ -726,16 +752,27 @@ __device__ inline void reduce_level2(const double* __restrict__ partial2, double
     __syncthreads();
 }
 
-// Mask-evaluation blocks of the current kinematics (one thread), read by every
-// x-pass workgroup.
-__device__ __attribute__((noinline)) void kin_prepare(StateHdr* h) {
-    kin_cast<float>(h->kin, h->kf);
-    kin_cast<double>(h->kin, h->kd);
+// Kinematics of member m at time t and its mask-evaluation blocks (one
+// thread).  Everything is computed in registers from a register copy of the
+// body description and stored once: interleaving loads of the description and
+// stores of the block in global memory would serialize on memory round trips.
+__device__ __forceinline__ void kin_update(const Member& m, double t) {
+    const flusi_insect in = *m.ins;
+    Kin k;
+    compute_kin(in, t, m.dx, k);
+    KinT<float> kf;
+    KinT<double> kd;
+    kin_cast<float>(k, kf);
+    kin_cast<double>(k, kd);
+    StateHdr* h = m.hdr;
+    h->kin = k;
+    h->kf = kf;
+    h->kd = kd;
 }
 
 // Start of a stepping call, one thread per member: make slot 0 current and
 // evaluate the kinematics of the current time level.
-static __global__ void k_prologue(const Member* __restrict__ mt, int nmem) {
+static __global__ __launch_bounds__(64) void k_prologue(const Member* __restrict__ mt, int nmem) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= nmem) return;
     const Member& m = mt[i];
@@ -744,10 +781,16 @@ static __global__ void k_prologue(const Member* __restrict__ mt, int nmem) {
         hdr->slot[0] = hdr->slot[1];
         hdr->cur = 0;
     }
-    if (m.nc > 0) {
-        compute_kin(*m.ins, hdr->slot[0].t, m.dx, hdr->kin);
-        kin_prepare(hdr);
-    }
+    if (m.nc > 0) kin_update(m, hdr->slot[0].t);
+}
+
+// Kinematics of time level p of every member whose kinematics change with
+// time (one thread per member), before the pass that reads them.
+static __global__ __launch_bounds__(64) void k_kin_level(const Member* __restrict__ mt, int nmem, int p) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= nmem) return;
+    const Member& m = mt[i];
+    if (m.dyn && !m.hdr->status) kin_update(m, m.hdr->slot[p].t);
 }
 
 // Writes the launch record of a single plan (and the device copy of its body
@@ -757,13 +800,6 @@ static __global__ void k_member_set(Member* dst, Member v, flusi_insect ins) {
         *dst = v;
         if (v.nc > 0) *const_cast<flusi_insect*>(v.ins) = ins;
     }
-}
-
-// Kinematics of time level p (one thread).  compute_kin stays a call: inlined,
-// its FP64 working set would set the register count of the whole y-pass.
-__device__ inline void kin_of_level(const Member& m, int p) {
-    compute_kin(*m.ins, m.hdr->slot[p].t, m.dx, m.hdr->kin);
-    kin_prepare(m.hdr);
 }
 
 static __global__ void k_hdr_init(StateHdr* hdr, double t0) {
@@ -814,7 +850,7 @@ __global__ __launch_bounds__(nt_z(N, V)) void k_zpass(const Member* __restrict__
     constexpr int PERM = (M + RS - 1) / RS;
     constexpr int SC = cm_stride(N);
     constexpr int BUFB = C * SC * (int)sizeof(cx<T>);
-    constexpr int REDB = NRED_BLOCKS * NV * 8;
+    constexpr int REDB = nred_of(N) * NV * 8;
     __shared__ __align__(16) unsigned char smem[BUFB > REDB ? BUFB : REDB];
     __shared__ double tot[NV];
     __shared__ Coef cf;
@@ -829,8 +865,18 @@ __global__ __launch_bounds__(nt_z(N, V)) void k_zpass(const Member* __restrict__
     const double kyv = kscale * j_of_m(myi, K);
 
     const bool step_mode = (MODE == MODE_STEP || MODE == MODE_STEP_LAST);
+    // forward input: field f+1 is loaded while field f is transformed; field 0
+    // is in flight together with the reduction loads
+    constexpr bool FWD = (MODE == MODE_IMPORT) || step_mode;
+    cx<T> vn[FWD ? RPT : 1];
+    const auto load_field = [&](int f) {
+#pragma unroll
+        for (int i = 0; i < RPT; ++i)
+            vn[i] = okq ? gld(yin, f * fs_y + (long)(r0 + i * RS) * Qp + q) : cx<T>{T(0), T(0)};
+    };
+    if constexpr (FWD) load_field(0);
     if (step_mode) {
-        reduce_level2<NTZ>(partial2, reinterpret_cast<double*>(smem), tot);
+        reduce_level2<NTZ, nred_of(N)>(partial2, reinterpret_cast<double*>(smem), tot);
         if (tid == 0) {
             cf = step_coef(tot, hdr->slot[par], mb.ctl, dx, eta);
             if (tile == 0)
@@ -849,12 +895,9 @@ __global__ __launch_bounds__(nt_z(N, V)) void k_zpass(const Member* __restrict__
         cx<T> Nh[3][PERM];
 #pragma unroll
         for (int f = 0; f < 3; ++f) {
-            cx<T> v[RPT];
 #pragma unroll
-            for (int i = 0; i < RPT; ++i)
-                v[i] = okq ? gld(yin, f * fs_y + (long)(r0 + i * RS) * Qp + q) : cx<T>{T(0), T(0)};
-#pragma unroll
-            for (int i = 0; i < RPT; ++i) buf[c * SC + cpad(r0 + i * RS)] = v[i];
+            for (int i = 0; i < RPT; ++i) buf[c * SC + cpad(r0 + i * RS)] = vn[i];
+            if (f < 2) load_field(f + 1);
             fft_cols<T, N, -1, C, NTZ, SC>(buf, tw);
 #pragma unroll
             for (int i = 0; i < PERM; ++i) {
