@@ -83,6 +83,14 @@ __device__ __forceinline__ int xcd_tile(int bid, int nb) {
     return x < rem ? x * (per + 1) + s : rem * (per + 1) + (x - rem) * per + s;
 }
 
+// Twiddle table of a workgroup's FFTs staged in LDS (every butterfly stage
+// reads it; LDS latency instead of cache latency).  Visible after the barrier
+// that opens the first column transform.
+template <typename T, int N>
+__device__ __forceinline__ void stage_twiddles(cx<T>* tws, const cx<T>* __restrict__ tw, int nthreads) {
+    for (int e = threadIdx.x; e < N; e += nthreads) tws[e] = tw[e];
+}
+
 struct StepCtl {
     double dt_fixed, cfl, dt_max, eta_cap, t_end;
     int masked, mean_mode, kin_dynamic, pad;
@@ -232,14 +240,16 @@ __global__ __launch_bounds__(NT) void k_ypass(const Member* __restrict__ mt, int
         }
         return;
     }
+    __shared__ cx<T> tws[N];
+    stage_twiddles<T, N>(tws, tw, NT);
     const glb<cx<T>>* A = gview(static_cast<const cx<T>*>(m.bufA));
     glb<cx<T>>* B = gview(static_cast<cx<T>*>(m.bufB));
     if constexpr (DIR > 0)
         colfft_tile<T, N, +1, true, false, C>(A + f * (long)N * Qp, B + f * (long)N * N * KPp, N * KP, KP, Qp, KP,
-                                           (long)N * KPp, KPp, tile % nbx, tw, buf);
+                                           (long)N * KPp, KPp, tile % nbx, tws, buf);
     else
         colfft_tile<T, N, -1, false, true, C>(A + f * (long)N * N * KPp, B + f * (long)N * Qp, N * KP, KP,
-                                           (long)N * KPp, KPp, Qp, KP, tile % nbx, tw, buf);
+                                           (long)N * KPp, KPp, Qp, KP, tile % nbx, tws, buf);
 }
 
 // ---------------------------------------------------------------------------
@@ -333,7 +343,10 @@ __global__ __launch_bounds__(NT) void k_xpass(const Member* __restrict__ mt, con
     // inverse columns [0, CI), forward columns [CI, CI + CF)
     __shared__ cx<T> buf[(CI + CF) * SC];
     cx<T>* fbuf = buf + CI * SC;
-    __shared__ double red[NT / 64][NV];
+    // per-wave sums: with three colours the wave rows wred also take the three
+    // lane-reduced values (slots 0..2 are free there), which saves the LDS of red
+    constexpr bool WAVE_ACC = NC > 1;
+    __shared__ double red[WAVE_ACC ? 1 : NT / 64][NV];
     __shared__ double wred[NT / 64][NV];
     __shared__ KinT<T> kin;
     // FP64 kinematics for the part choice where parts overlap (FP32 runs)
@@ -341,9 +354,18 @@ __global__ __launch_bounds__(NT) void k_xpass(const Member* __restrict__ mt, con
     __shared__ typename std::conditional<K64, KinT<double>, char>::type kin64;
     __shared__ unsigned char amb[K64 ? RW * N : 1];  // point flagged for the FP64 part decision
     __shared__ int amb_any;
+    // twiddles from LDS unless the table would cost a workgroup per CU (FP64,
+    // full-size tile: the tile alone is just under half of the 160 KiB)
+    constexpr bool TWL = !(sizeof(T) == 8 && V == 0);
+    __shared__ cx<T> tws[TWL ? N : 1];
     if (*gview(&hdr->status)) return;
     const int tid = threadIdx.x;
     const int row0 = wg * RW;
+    const cx<T>* twx = tw;
+    if constexpr (TWL) {
+        stage_twiddles<T, N>(tws, tw, NT);
+        twx = tws;
+    }
     if constexpr (K64) {
         for (int e = tid; e < RW * N; e += NT) amb[e] = 0;
         if (tid == 0) amb_any = 0;
@@ -398,7 +420,7 @@ __global__ __launch_bounds__(NT) void k_xpass(const Member* __restrict__ mt, con
             }
         }
     }
-    fft_cols<T, N, +1, CI, NT, SC>(buf, tw);
+    fft_cols<T, N, +1, CI, NT, SC>(buf, twx);
 
     // 2. pointwise source and partial sums, one point per iteration (the mask
     //    code is large; a rolled loop keeps the register count down).  The
@@ -408,7 +430,6 @@ __global__ __launch_bounds__(NT) void k_xpass(const Member* __restrict__ mt, con
     // 12 force/torque terms.  With three colours the 36 terms are rare (chi > 0
     // on few points) and are wave-reduced per iteration into wred[wave][.]
     // instead, which keeps them out of the registers.
-    constexpr bool WAVE_ACC = NC > 1;
     constexpr int NLANE = WAVE_ACC ? 3 : NVAL;
     const int lane = tid & 63, wv = tid >> 6;
     if constexpr (WAVE_ACC) {
@@ -546,19 +567,23 @@ __global__ __launch_bounds__(NT) void k_xpass(const Member* __restrict__ mt, con
         for (int v = 0; v < NLANE; ++v) {
             double r = 0.0;
             if (__any(acc[v] != 0.0)) r = (v == 0 || v == 2) ? wave_max(acc[v]) : wave_sum(acc[v]);
-            if (lane == 0) red[wv][v] = r;
+            if (lane == 0) {
+                if constexpr (WAVE_ACC) wred[wv][v] = r;
+                else red[wv][v] = r;
+            }
         }
         __syncthreads();
         if (tid < NV) {
             double r = 0.0;
             for (int w = 0; w < NT / 64; ++w) {
-                const double x = tid < NLANE ? red[w][tid] : (WAVE_ACC && tid < NVAL ? wred[w][tid] : 0.0);
+                double x = 0.0;
+                if (tid < NVAL) x = WAVE_ACC ? wred[w][tid] : red[w][tid];
                 r = w == 0 ? x : ((tid == 0 || tid == 2) ? fmax(r, x) : r + x);
             }
             partial[(long)wg * NV + tid] = r;
         }
     }
-    fft_cols<T, N, -1, CF, NT, SC>(fbuf, tw);
+    fft_cols<T, N, -1, CF, NT, SC>(fbuf, twx);
 
     // 3. split the packed spectra and store kx = 0..K
 #pragma unroll
@@ -854,9 +879,11 @@ __global__ __launch_bounds__(nt_z(N, V)) void k_zpass(const Member* __restrict__
     __shared__ __align__(16) unsigned char smem[BUFB > REDB ? BUFB : REDB];
     __shared__ double tot[NV];
     __shared__ Coef cf;
+    __shared__ cx<T> tws[N];
     cx<T>* buf = reinterpret_cast<cx<T>*>(smem);
     if (*gview(&hdr->status)) return;
     const int tid = threadIdx.x;
+    stage_twiddles<T, N>(tws, tw, NTZ);
     const int c = tid % C, r0 = tid / C;
     const int q = tile * C + c;
     const bool okq = q < Q;
@@ -898,7 +925,7 @@ __global__ __launch_bounds__(nt_z(N, V)) void k_zpass(const Member* __restrict__
 #pragma unroll
             for (int i = 0; i < RPT; ++i) buf[c * SC + cpad(r0 + i * RS)] = vn[i];
             if (f < 2) load_field(f + 1);
-            fft_cols<T, N, -1, C, NTZ, SC>(buf, tw);
+            fft_cols<T, N, -1, C, NTZ, SC>(buf, tws);
 #pragma unroll
             for (int i = 0; i < PERM; ++i) {
                 const int m = r0 + i * RS;
@@ -1001,7 +1028,7 @@ __global__ __launch_bounds__(nt_z(N, V)) void k_zpass(const Member* __restrict__
                 buf[c * SC + cpad(bin_of_m(m, N, K))] = v;
             }
         }
-        fft_cols<T, N, +1, C, NTZ, SC>(buf, tw);
+        fft_cols<T, N, +1, C, NTZ, SC>(buf, tws);
         if (okq) {
             cx<T> o[RPT];
 #pragma unroll
