@@ -161,6 +161,9 @@ template <typename TM>
 struct KinT {
     TM Mb[9], xc[3], uc[3], omb[3], Mws[2][9], piv[2][3], omw[2][3], xref[3][3];
     TM r2all, thr, h, radius, ea, eb, wA, wB, wt;
+    TM r2b;          // squared radius about xc outside which the body's chi == 0
+    TM wc[2][3];     // wing ellipse centres (global frame)
+    TM r2w;          // squared radius about wc outside which a wing's chi == 0
     int body, wings, smooth, pad;
 };
 
@@ -188,17 +191,29 @@ __device__ inline void kin_cast(const Kin& a, KinT<TM>& b) {
     // cull radius recomputed for the precision's own tanh cut-off
     const double thr = a.smooth == FLUSI_SMOOTH_TANH ? (sizeof(TM) == 4 ? 10.0 : 20.0) * a.h : a.h;
     b.thr = TM(thr);
-    double rall = 0.0;
-    if (a.body == FLUSI_BODY_SPHERE) rall = a.radius + thr;
-    if (a.body == FLUSI_BODY_ELLIPSOID) rall = 2.0 * (a.ea + a.eb) + thr;
-    if (a.wings) {
-        const double mab = fmax(a.wA, a.wB), e1 = mab + thr, e2 = 0.5 * a.wt + thr;
-        for (int s = 0; s < 2; ++s) {
-            const double pn = sqrt(a.piv[s][0] * a.piv[s][0] + a.piv[s][1] * a.piv[s][1] + a.piv[s][2] * a.piv[s][2]);
-            rall = fmax(rall, pn + a.wB + sqrt(e1 * e1 + e2 * e2));
-        }
+    // Culls (chi == 0 exactly beyond them), widened by a relative margin so they
+    // stay conservative after rounding:
+    //  body: sphere delta = |r| - R; ellipsoid: if |r|^2 > (a+thr)^2 + (b+thr)^2
+    //        then |x_b| > a + thr or rho > b + thr, and either way delta > thr
+    //  wing: the in-plane ellipse radius is at most max(A, B), so beyond a
+    //        distance sqrt((max(A,B)+thr)^2 + (t/2+thr)^2) from the ellipse
+    //        centre either r - R > thr or |z_w| - t/2 > thr
+    double rb2 = 0.0;
+    if (a.body == FLUSI_BODY_SPHERE) rb2 = (a.radius + thr) * (a.radius + thr);
+    if (a.body == FLUSI_BODY_ELLIPSOID) rb2 = (a.ea + thr) * (a.ea + thr) + (a.eb + thr) * (a.eb + thr);
+    b.r2b = TM(rb2 * (1.0 + 1e-5));
+    double rall = sqrt(rb2);
+    const double e1 = fmax(a.wA, a.wB) + thr, e2 = 0.5 * a.wt + thr;
+    const double rw = sqrt(e1 * e1 + e2 * e2);
+    b.r2w = TM(rw * rw * (1.0 + 1e-5));
+    for (int s = 0; s < 2; ++s) {
+        // ellipse centre (0, B, 0) of the wing frame: body frame piv + (M_wing M_stroke)^T (0, B, 0)
+        double cb[3], cg[3];
+        for (int i = 0; i < 3; ++i) cb[i] = a.piv[s][i] + a.Mws[s][3 + i] * a.wB;
+        mat_tvec(a.Mb, cb, cg);
+        for (int i = 0; i < 3; ++i) b.wc[s][i] = TM(a.xc[i] + cg[i]);
+        if (a.wings) rall = fmax(rall, sqrt(cg[0] * cg[0] + cg[1] * cg[1] + cg[2] * cg[2]) + rw);
     }
-    // widen by a relative margin so the cull stays conservative after rounding
     b.r2all = TM(rall * rall * (1.0 + 1e-5));
 }
 
@@ -253,7 +268,9 @@ __device__ __forceinline__ void part_chis(const KinT<TM>& k, TM x, TM y, TM z, T
     const TM rel[3] = {x - k.xc[0], y - k.xc[1], z - k.xc[2]};
     const TM r2 = rel[0] * rel[0] + rel[1] * rel[1] + rel[2] * rel[2];
     mvec(k.Mb, rel, xb);
-    if (k.body == FLUSI_BODY_SPHERE) {
+    if (r2 > k.r2b) {
+        // outside the body's cull sphere: chi_body == 0
+    } else if (k.body == FLUSI_BODY_SPHERE) {
         c[0] = chi_of(sqrt(r2) - k.radius, k);
     } else if (k.body == FLUSI_BODY_ELLIPSOID) {
         const TM q = xb[0] / k.ea;
@@ -264,6 +281,8 @@ __device__ __forceinline__ void part_chis(const KinT<TM>& k, TM x, TM y, TM z, T
     if (k.wings) {
         const TM mab = fmax(k.wA, k.wB);
         for (int s = 0; s < 2; ++s) {
+            const TM g0 = x - k.wc[s][0], g1 = y - k.wc[s][1], g2 = z - k.wc[s][2];
+            if (g0 * g0 + g1 * g1 + g2 * g2 > k.r2w) continue;  // outside the wing's cull sphere: chi == 0
             const TM d0[3] = {xb[0] - k.piv[s][0], xb[1] - k.piv[s][1], xb[2] - k.piv[s][2]};
             TM xw[3];
             mvec(k.Mws[s], d0, xw);
