@@ -445,12 +445,29 @@ __global__ __launch_bounds__(NT) void k_xpass(const Member* __restrict__ mt, con
     // overlap are only flagged); PH = 1: the flagged points again, with the
     // part decided in FP64 (the grid-sum terms of u were taken in the sweep).
     // act = false: the lane only takes part in the wave sums.
+    // Sweep index g -> (row r, x index i).  Each wave takes a compact patch of
+    // PR rows x PX points (PR*PX = 64) rather than 64 points of one row, so the
+    // lanes that need the mask's geometry tend to share waves.
+    constexpr int PR = (RW >= 4 && N % 16 == 0) ? 4 : ((RW >= 2 && N % 32 == 0) ? 2 : 1);
+    constexpr int PX = 64 / PR;
+    const auto decode = [](int g, int& r, int& i) {
+        if constexpr (PR == 1) {
+            r = g / N;
+            i = g % N;
+        } else {
+            const int lane_ = g & 63, p = g >> 6;
+            constexpr int NPX = N / PX;
+            r = (p / NPX) * PR + lane_ / PX;
+            i = (p % NPX) * PX + lane_ % PX;
+        }
+    };
     const auto point = [&](int idx, bool act, auto phase) {
         constexpr int PH = decltype(phase)::value;
         // keep the kinematics block in LDS: without this compiler barrier the
         // loop-invariant values would be hoisted into registers
         __asm__ volatile("" ::: "memory");
-        const int r = idx / N, i = idx % N;
+        int r, i;
+        decode(idx, r, i);
         const int row = row0 + r;
         const cx<T> z0 = buf[lds_at<true, 1, SC>(i, 3 * r)];
         const cx<T> z1 = buf[lds_at<true, 1, SC>(i, 3 * r + 1)];
