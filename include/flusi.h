@@ -219,9 +219,10 @@ int flusi_pass_times(flusi_plan plan, double* ms, long long* launches);
 /* ------------------------------------------------------------------------
  * Schedules and the autotuner.
  *
- * Each stepping pass (y-inverse, x-pass, y-forward, z-pass) exists in two
- * tile variants: 0 (default) and 1 (y passes: half the columns per
- * workgroup; x-pass: half the rows; z-pass: more threads per column).  The
+ * Each stepping pass (y-inverse, x-pass, y-forward, z-pass) exists in three
+ * tile variants: 0 (default), 1 and 2 (y passes: a half / a quarter of the
+ * columns per workgroup; x-pass: a half / a quarter of the rows, at least two;
+ * z-pass: two or three / four or six times the threads per column).  The
  * z-pass runs either as one launch (update, curl and inverse z) or as two
  * (update, then curl + inverse z).  The velocity field does not depend on
  * the schedule (every variant performs the same operations per value); the
@@ -229,7 +230,7 @@ int flusi_pass_times(flusi_plan plan, double* ms, long long* launches);
  * integrals (energy, force, torque), at round-off level.
  * ------------------------------------------------------------------------ */
 typedef struct {
-    int y_inverse;   /* tile variant, 0 or 1 */
+    int y_inverse;   /* tile variant, 0, 1 or 2 */
     int x_pass;
     int y_forward;
     int z_pass;
@@ -238,7 +239,8 @@ typedef struct {
 } flusi_schedule;
 
 /* Schedule used by this plan's flusi_step calls (and by an ensemble size
- * group whose first member is this plan).  Errors: EINVAL (variant not 0/1). */
+ * group whose first member is this plan).  Errors: EINVAL (variant out of
+ * range, split_z not 0/1). */
 int flusi_plan_get_schedule(flusi_plan plan, flusi_schedule* out);
 int flusi_plan_set_schedule(flusi_plan plan, const flusi_schedule* s);
 

@@ -113,9 +113,10 @@ static void free_plan(PlanData& d) {
     d.impl = nullptr;
 }
 static int sched_check(const flusi_schedule& s) {
-    const int v[5] = {s.y_inverse, s.x_pass, s.y_forward, s.z_pass, s.split_z};
+    const int v[4] = {s.y_inverse, s.x_pass, s.y_forward, s.z_pass};
     for (int x : v)
-        if (x != 0 && x != 1) return set_error(FLUSI_EINVAL, "schedule entries must be 0 or 1");
+        if (x < 0 || x >= NVARIANT) return set_error(FLUSI_EINVAL, "tile variants must be in [0, %d)", NVARIANT);
+    if (s.split_z != 0 && s.split_z != 1) return set_error(FLUSI_EINVAL, "split_z must be 0 or 1");
     return FLUSI_OK;
 }
 static Sched sched_from(const flusi_schedule& s) {
@@ -195,18 +196,25 @@ static int time_steps(ImplBase* impl, GroupRun g, const Sched& sc, int reps, dou
 
 // Chooses the fastest variant per pass, then one- or two-launch z-pass.
 static int tune_group(ImplBase* impl, const GroupRun& g, PlanData& prof, int reps, Sched* out) {
-    double t[2][FLUSI_NPASS];
+    double t[NVARIANT][FLUSI_NPASS];
     Sched base = impl->default_sched();
-    for (int v = 0; v < 2; ++v) {
+    for (int v = 0; v < NVARIANT; ++v) {
         Sched sc = base;
         sc.y_inverse = sc.x_pass = sc.y_forward = sc.z_pass = v;
         if (int rc = time_passes(impl, g, sc, prof, reps, t[v])) return rc;
     }
+    // fastest variant per pass (the z-pass with its inverse launch when split)
+    auto pick = [&](auto cost) {
+        int b = 0;
+        for (int v = 1; v < NVARIANT; ++v)
+            if (cost(v) < cost(b)) b = v;
+        return b;
+    };
     Sched best = base;
-    best.y_inverse = t[1][PASS_YINV] < t[0][PASS_YINV] ? 1 : 0;
-    best.x_pass = t[1][PASS_X] < t[0][PASS_X] ? 1 : 0;
-    best.y_forward = t[1][PASS_YFWD] < t[0][PASS_YFWD] ? 1 : 0;
-    best.z_pass = t[1][PASS_Z] + t[1][PASS_ZINV] < t[0][PASS_Z] + t[0][PASS_ZINV] ? 1 : 0;
+    best.y_inverse = pick([&](int v) { return t[v][PASS_YINV]; });
+    best.x_pass = pick([&](int v) { return t[v][PASS_X]; });
+    best.y_forward = pick([&](int v) { return t[v][PASS_YFWD]; });
+    best.z_pass = pick([&](int v) { return t[v][PASS_Z] + t[v][PASS_ZINV]; });
     double ms[2];
     for (int sp = 0; sp < 2; ++sp) {
         Sched sc = best;

@@ -10,7 +10,7 @@ namespace flusi {
 
 struct ImplBase;
 
-// Schedule of the stepping passes: tile variant (0 or 1) of each pass and
+// Schedule of the stepping passes: tile variant (0 .. NVARIANT-1) of each pass and
 // whether the z-pass runs as one launch or as update + inverse launches.
 struct Sched {
     int y_inverse = 0, x_pass = 0, y_forward = 0, z_pass = 0;
@@ -172,7 +172,7 @@ struct Impl final : ImplBase {
     }
     // x-pass workgroups per member, largest over the tile variants (sizes the
     // partial-sum buffer)
-    int nwg_x() const override { return (int)(N2 / rows_x(N, sizeof(cx<T>), 1)); }
+    int nwg_x() const override { return (int)(N2 / rows_x(N, sizeof(cx<T>), NVARIANT - 1)); }
     static size_t field_bytes() { return (size_t)M * Qp * sizeof(CX); }
     size_t state_bytes() const override { return STATE_HDR_BYTES + 6 * ((field_bytes() + 255) / 256 * 256); }
 
@@ -298,7 +298,7 @@ struct Impl final : ImplBase {
     template <int V>
     static constexpr int nwg(int) { return (int)(N2 / rows_x(N, sizeof(cx<T>), V)); }
     static constexpr int NBZ = (Q + CZ - 1) / CZ;  // z-pass tiles per member
-    static int nwg_of(int v) { return v ? nwg<1>(0) : nwg<0>(0); }
+    static int nwg_of(int v) { return v == 2 ? nwg<2>(0) : (v == 1 ? nwg<1>(0) : nwg<0>(0)); }
 
     // y-inverse of the 6 z-partial fields
     template <int V>
@@ -308,7 +308,8 @@ struct Impl final : ImplBase {
         k_ypass<T, N, +1, 0, V><<<(unsigned)(nb * g.nmem), NT, 0, g.stream>>>(g.mt, nb, w, 0, 0);
     }
     static void y_inverse(const GroupRun& g) {
-        if (g.sched.y_inverse) y_inverse_v<1>(g);
+        if (g.sched.y_inverse == 2) y_inverse_v<2>(g);
+        else if (g.sched.y_inverse == 1) y_inverse_v<1>(g);
         else y_inverse_v<0>(g);
     }
     // y-forward of 3 fields; with red set, nred_of(N) extra workgroups per member
@@ -324,7 +325,8 @@ struct Impl final : ImplBase {
             k_ypass<T, N, -1, 0, V><<<(unsigned)(nb * g.nmem), NT, 0, g.stream>>>(g.mt, nb, w, 0, 0);
     }
     static void y_forward(const GroupRun& g, bool red) {
-        if (g.sched.y_forward) y_forward_v<1>(g, red);
+        if (g.sched.y_forward == 2) y_forward_v<2>(g, red);
+        else if (g.sched.y_forward == 1) y_forward_v<1>(g, red);
         else y_forward_v<0>(g, red);
     }
     template <int V>
@@ -339,13 +341,16 @@ struct Impl final : ImplBase {
         if (g.n_nc[2]) k_xpass<T, N, 3, V><<<(unsigned)(nw * g.n_nc[2]), NT, 0, g.stream>>>(mt, w);
     }
     static void xpass(const GroupRun& g) {
-        if (g.sched.x_pass) xpass_v<1>(g);
+        if (g.sched.x_pass == 2) xpass_v<2>(g);
+        else if (g.sched.x_pass == 1) xpass_v<1>(g);
         else xpass_v<0>(g);
     }
     template <int MODE>
     static void zpass(const GroupRun& g, int par = 0, int s = 0) {
         const CX* w = static_cast<const CX*>(g.tw);
-        if (g.sched.z_pass)
+        if (g.sched.z_pass == 2)
+            k_zpass<T, N, MODE, 2><<<(unsigned)(NBZ * g.nmem), nt_z(N, 2), 0, g.stream>>>(g.mt, w, par, s);
+        else if (g.sched.z_pass == 1)
             k_zpass<T, N, MODE, 1><<<(unsigned)(NBZ * g.nmem), nt_z(N, 1), 0, g.stream>>>(g.mt, w, par, s);
         else
             k_zpass<T, N, MODE, 0><<<(unsigned)(NBZ * g.nmem), nt_z(N, 0), 0, g.stream>>>(g.mt, w, par, s);

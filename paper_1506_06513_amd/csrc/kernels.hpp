@@ -27,33 +27,40 @@ constexpr int NT = 256;   // threads per workgroup of the y passes and the x-pas
 constexpr int NV = 39;    // reduction values per workgroup (see xpass)
 constexpr int NRED_MAX = 64;  // most first-level reduction workgroups per member
 
-// Tile shapes.  Each stepping pass has two variants that compute the same
-// values (V = 0 the default, V = 1 the alternative); a schedule picks one per
-// pass (see the autotuner).
+// Tile shapes.  Each stepping pass has NVARIANT shapes that compute the same
+// values (V = 0 the default); a schedule picks one per pass (see the
+// autotuner).
+constexpr int NVARIANT = 3;
 // Columns per workgroup of the y passes: C*N ~ 4096 elements in LDS (V = 0),
-// half of that (V = 1).
+// a half (V = 1) or a quarter (V = 2) of that.
 __host__ __device__ constexpr int cols_of(int N, int V = 0) {
     int c = 4096 / N, p = 8;
     while (p * 2 <= c) p *= 2;
-    return V ? p / 2 : p;
+    return p >> V;
 }
 // Columns and threads per workgroup of the z-pass (more, narrower workgroups:
-// the z-pass has only (2K+1)(K+1) columns).  V = 1 uses more threads per
-// column (fewer rows per thread): twice as many, or three times as many
-// where twice would not divide the column.
+// the z-pass has only (2K+1)(K+1) columns).  V = 1 and 2 use more threads per
+// column (fewer rows per thread): the smallest multiple of the V = 0 count
+// among {2, 3} (V = 1) or {4, 6} (V = 2) whose rows per sweep divide the
+// column, at most 1024 threads; otherwise the previous variant's count.
 __host__ __device__ constexpr int cols_z(int N) { return N <= 24 ? 16 : 8; }
 __host__ __device__ constexpr int nt_z(int N, int V = 0) {
     const int t0 = N <= 192 ? 128 : 256;
-    if (!V) return t0;
-    return N % (2 * t0 / cols_z(N)) == 0 ? 2 * t0 : 3 * t0;
+    const int C = cols_z(N);
+    const auto fits = [&](int t) { return t <= 1024 && N % (t / C) == 0; };
+    const int t1 = fits(2 * t0) ? 2 * t0 : 3 * t0;
+    if (V == 0) return t0;
+    if (V == 1) return t1;
+    return fits(4 * t0) ? 4 * t0 : (fits(6 * t0) ? 6 * t0 : t1);
 }
 // Rows per workgroup of the x-pass (even): 3*RW*N ~ 3072 elements in LDS
-// (V = 0), half of that (V = 1, at least 2 rows).
+// (V = 0), a half (V = 1) or a quarter (V = 2) of that, at least 2 rows.
 __host__ __device__ constexpr int rows_x(int N, int cbytes = 8, int V = 0) {
     int c = 1024 / N, p = 2;
     (void)cbytes;
     while (p * 2 <= c) p *= 2;
-    return V && p > 2 ? p / 2 : p;
+    p >>= V;
+    return p < 2 ? 2 : p;
 }
 __host__ __device__ constexpr int round_up(int a, int b) { return (a + b - 1) / b * b; }
 // First-level reduction workgroups per member: every z-pass workgroup reads

@@ -29,7 +29,8 @@ def _case(n, body):
 
 
 SCHEDULES = [dict(zip(KEYS, v)) for v in
-             ((1, 1, 1, 1, 0), (1, 1, 1, 1, 1), (0, 1, 0, 1, 0), (1, 0, 1, 0, 1), (0, 0, 0, 0, 1))]
+             ((1, 1, 1, 1, 0), (1, 1, 1, 1, 1), (0, 1, 0, 1, 0), (1, 0, 1, 0, 1), (0, 0, 0, 0, 1),
+              (2, 2, 2, 2, 0), (2, 0, 1, 2, 1), (0, 2, 2, 1, 0))]
 
 
 @pytest.mark.parametrize("n,body,dtype", [(24, "insect", "f64"), (48, "sphere", "f32"), (96, "insect", "f32"),
@@ -56,7 +57,7 @@ def test_velocity_is_independent_of_the_schedule(n, body, dtype):
 def test_bad_schedule_is_rejected():
     P = F.Plan(32, 4.0, 0.01, 1e-3, "f32")
     with pytest.raises(F.FlusiError) as e:
-        P.set_schedule({"x_pass": 2})
+        P.set_schedule({"x_pass": 3})
     assert e.value.code == F.FLUSI_EINVAL
 
 
@@ -71,7 +72,7 @@ def test_autotune_leaves_the_state_and_sets_a_schedule(dtype):
     sc = P.autotune(st, ins, reps=4, cfl=0.1)
     torch.cuda.synchronize()
     assert torch.equal(st, before)
-    assert set(sc) == set(KEYS) and all(v in (0, 1) for v in sc.values())
+    assert set(sc) == set(KEYS) and all(v in (0, 1, 2) for v in sc.values()) and sc["split_z"] in (0, 1)
     assert P.schedule() == sc
     # stepping with the tuned schedule matches the default schedule
     Q = F.Plan(n, L, 1 / 136, 5e-4, dtype)
