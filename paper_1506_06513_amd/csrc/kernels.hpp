@@ -320,7 +320,7 @@ __device__ __forceinline__ void block_reduce_store(const double (&acc)[NVAL], do
 // ---------------------------------------------------------------------------
 // x-pass: inverse x, pointwise source with the mask, FP64 partial sums,
 // forward x.  Reduction values per workgroup:
-//   [0] max |u|^2, [1] sum |u|^2, [2] non-finite flag,
+//   [0] max |u|^2, [1] sum |u|^2 (non-finite values propagate into it), [2] 0,
 //   [3 + 12 c + 0..2]  sum chi (u - u_s)            (colour c+1)
 //   [3 + 12 c + 3..5]  sum (x - x_ref) x chi (u - u_s)
 //   [3 + 12 c + 6..8]  sum chi u_s
@@ -486,9 +486,10 @@ __global__ __launch_bounds__(NT) void k_xpass(const Member* __restrict__ mt, con
         T nz = ux * wy - uy * wx;
         if constexpr (PH == 0) {
             const double u2 = (double)ux * ux + (double)uy * uy + (double)uz * uz;
+            // a non-finite value reaches the FP64 sum acc[1] (NaN and Inf
+            // propagate through additions), which the step checks; slot 2 stays 0
             acc[0] = fmax(acc[0], u2);
             acc[1] += u2;
-            if (!isfinite(u2)) acc[2] = 1.0;
         }
         if constexpr (NC > 0) {
             const double xg = dx * i, yg = dx * (row % N), zg = dx * (row / N);
