@@ -7,7 +7,8 @@ fusion or pruning, and it shares no code with the HIP library.
 What it computes (paper section / equation in brackets):
 
 * the volume-penalized Navier-Stokes equations in rotational form
-  [Sec. 2.1, eq. PNST_org_momentum] without the sponge term,
+  [Sec. 2.1, eq. PNST_org_momentum], with the optional vorticity sponge
+  [Sec. 2.3],
 * Fourier pseudo-spectral discretization: derivatives as multiplication by
   i*k, products in physical space, the 2/3 rule always on [Sec. 2.4],
 * the pressure handled by the projection of Algorithm 1 step (d) [Alg. 1],
@@ -37,6 +38,10 @@ listed in the design notes of the repository):
       right-hand side to zero (the mean velocity stays at its initial value),
       FREE keeps it.
   Nonlinear term on the right-hand side: u x w (= -w x u).
+  Vorticity sponge: -(1/C_sp) curl (chi_sp w)/Laplacian read as the
+      Biot-Savart damping of the vorticity, i.e. -(1/C_sp) (i k x W_hat)/|k|^2
+      with W = chi_sp w (the printed sign with the Laplacian -|k|^2 would
+      amplify); chi_sp = 1 in layers at the top end of chosen axes, sharp.
   AB2-IF with variable step: AB2 on v = exp(nu|k|^2 t) u_hat with the
       variable-step weights b1 = 1 + r/2, b2 = -r/2, r = dt_n/dt_{n-1};
       the first step is integrating-factor Euler.
@@ -493,6 +498,37 @@ class Params:
     nu: float
     eta: float
     mean_mode: int = MEAN_FIXED
+    c_sp: float = 0.0                      # vorticity sponge constant C_sp (0: no sponge)
+    sponge: tuple = (0.0, 0.0, 0.0)        # sponge layer thickness per axis (0: none on that axis)
+
+
+def sponge_mask(g: Grid, thickness) -> np.ndarray:
+    """chi_sp on the grid: 1 where, for an axis a with thickness d_a > 0, the
+    coordinate x_a lies in the top layer [L - d_a, L) of the periodic box
+    (upstream of the seam), 0 elsewhere  [Sec. 2.3, wake removal]."""
+    x, y, z = g.coords()
+    chi = np.zeros_like(x)
+    for c, d in zip((x, y, z), thickness):
+        if d > 0.0:
+            chi = np.where(c >= g.L - d, 1.0, chi)
+    return chi
+
+
+def sponge_hat(g: Grid, w: np.ndarray, chi_sp: np.ndarray, c_sp: float) -> np.ndarray:
+    """Vorticity sponge term in Fourier space  [Sec. 2.1 eq. PNST_org_momentum,
+    Sec. 2.3]: -(1/C_sp) (i k x W_hat)/|k|^2 with W = chi_sp * w, zero at k = 0.
+
+    The Biot-Savart form of damping the vorticity by chi_sp/C_sp: with
+    chi_sp = 1 it equals -u_hat/C_sp for a divergence-free u, i.e. damping at
+    the rate 1/C_sp; it is divergence-free and leaves the mean flow alone."""
+    wh = r2c(chi_sp * w)
+    kx, ky, kz = g.k_vectors(derivative=True)
+    k2 = kx * kx + ky * ky + kz * kz
+    with np.errstate(invalid="ignore", divide="ignore"):
+        f = np.where(k2 > 0.0, -1.0 / (c_sp * np.where(k2 > 0.0, k2, 1.0)), 0.0)
+    return np.stack([1j * (ky * wh[2] - kz * wh[1]) * f,
+                     1j * (kz * wh[0] - kx * wh[2]) * f,
+                     1j * (kx * wh[1] - ky * wh[0]) * f])
 
 
 def physical_fields(g: Grid, uh: np.ndarray):
@@ -515,7 +551,10 @@ def rhs_hat(p: Params, g: Grid, uh, chi, us):
         nphys = source_physical(u, w, 0.0, 0.0, p.eta)
     else:
         nphys = source_physical(u, w, chi, us, p.eta)
-    nh = r2c(nphys) * g.dealias()
+    nh = r2c(nphys)
+    if p.c_sp > 0.0 and any(d > 0.0 for d in p.sponge):
+        nh = nh + sponge_hat(g, w, sponge_mask(g, p.sponge), p.c_sp)
+    nh = nh * g.dealias()
     nh = project(g, nh)
     if p.mean_mode == MEAN_FIXED:
         nh[:, 0, 0, 0] = 0.0
@@ -616,7 +655,10 @@ def step(p: Params, st: State, ctl: StepControl, ins: Insect | None, fixed_mask=
     dt = choose_dt(ctl, umax, g.dx, p.eta, masked, st.t)               # (b)
     nphys = source_physical(u, w, 0.0 if chi is None else chi,
                             0.0 if us is None else us, p.eta)          # (c)
-    nh = project(g, r2c(nphys) * g.dealias())                          # (d)
+    nh = r2c(nphys)
+    if p.c_sp > 0.0 and any(d > 0.0 for d in p.sponge):
+        nh = nh + sponge_hat(g, w, sponge_mask(g, p.sponge), p.c_sp)  # (c), sponge
+    nh = project(g, nh * g.dealias())                                  # (d)
     if p.mean_mode == MEAN_FIXED:
         nh[:, 0, 0, 0] = 0.0
     diag = {"t": st.t, "dt": dt, "umax": umax,
