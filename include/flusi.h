@@ -133,6 +133,19 @@ int flusi_plan_destroy(flusi_plan plan);
  * Errors: EINVAL, EUNSUPPORTED. */
 int flusi_sizes(int n, int dtype, size_t* workspace_bytes, size_t* state_bytes);
 
+/* Vorticity sponge (Sec. 2.3, wake removal; the sponge term of eq.
+ * PNST_org_momentum) for every later step of this plan: the right-hand side
+ * gains -(1/C_sp) (i k x W_hat)/|k|^2 with W = chi_sp * w, the Biot-Savart form
+ * of damping the vorticity at rate chi_sp/C_sp (divergence-free, zero at
+ * k = 0).  chi_sp = 1 where x_a >= L - thickness[a] for an axis a with
+ * thickness[a] > 0 (a layer at the top end of that axis, just upstream of the
+ * periodic seam), 0 elsewhere.  c_sp <= 0 or all thicknesses 0 switch it off.
+ * thickness is a host array of 3 doubles (may be NULL: off).  Switching it
+ * on enlarges the plan's scratch (6 instead of 3 forward fields; synchronizes
+ * the plan's stream).  Not used by flusi_rhs.  Errors: EINVAL (thickness < 0
+ * or > L), ENOMEM. */
+int flusi_plan_set_sponge(flusi_plan plan, double c_sp, const double* thickness);
+
 /* All further launches of this plan go to `stream` (a hipStream_t). */
 int flusi_set_stream(flusi_plan plan, void* stream);
 

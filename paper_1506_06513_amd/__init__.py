@@ -117,6 +117,7 @@ _SIGS = {
     "flusi_forces": (ctypes.c_int, [_P, _P, ctypes.POINTER(ctypes.c_double)]),
     "flusi_profile": (ctypes.c_int, [_P, ctypes.c_int]),
     "flusi_pass_times": (ctypes.c_int, [_P, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_longlong)]),
+    "flusi_plan_set_sponge": (ctypes.c_int, [_P, ctypes.c_double, ctypes.POINTER(ctypes.c_double)]),
     "flusi_plan_get_schedule": (ctypes.c_int, [_P, ctypes.POINTER(flusi_schedule)]),
     "flusi_plan_set_schedule": (ctypes.c_int, [_P, ctypes.POINTER(flusi_schedule)]),
     "flusi_autotune": (ctypes.c_int, [_P, _P, ctypes.POINTER(flusi_insect), ctypes.POINTER(flusi_step_params),
@@ -273,6 +274,11 @@ def flusi_pass_times(plan):
     cnt = (ctypes.c_longlong * FLUSI_NPASS)()
     _check(lib().flusi_pass_times(plan, ms, cnt))
     return np.array(ms[:]), np.array(cnt[:], dtype=np.int64)
+
+
+def flusi_plan_set_sponge(plan, c_sp: float, thickness=None):
+    th = (ctypes.c_double * 3)(*[float(v) for v in thickness]) if thickness is not None else None
+    _check(lib().flusi_plan_set_sponge(plan, c_sp, th))
 
 
 def flusi_plan_get_schedule(plan) -> flusi_schedule:
@@ -488,6 +494,10 @@ class Plan:
 
     def forces(self, state):
         return flusi_forces(self.handle, state)
+
+    def set_sponge(self, c_sp: float, thickness=(0.0, 0.0, 0.0)):
+        """Vorticity sponge (layers at the top end of the axes with thickness > 0)."""
+        flusi_plan_set_sponge(self.handle, c_sp, thickness)
 
     def schedule(self) -> dict:
         return flusi_plan_get_schedule(self.handle).as_dict()

@@ -328,6 +328,35 @@ int flusi_sizes(int n, int dtype, size_t* workspace_bytes, size_t* state_bytes) 
     return FLUSI_OK;
 }
 
+int flusi_plan_set_sponge(flusi_plan plan, double c_sp, const double* thickness) {
+    if (int rc = check_plan(plan)) return rc;
+    PlanData& d = plan->d;
+    double th[3] = {0.0, 0.0, 0.0};
+    if (thickness)
+        for (int a = 0; a < 3; ++a) {
+            if (!(thickness[a] >= 0.0) || thickness[a] > d.L)
+                return set_error(FLUSI_EINVAL, "set_sponge: thickness must be in [0, L]");
+            th[a] = thickness[a];
+        }
+    const bool on = c_sp > 0.0 && (th[0] > 0.0 || th[1] > 0.0 || th[2] > 0.0);
+    if (on) {
+        const size_t cxb = d.dtype == FLUSI_F32 ? 8 : 16;
+        const size_t need = d.impl->bufA_elems_sponge() * cxb;
+        if (need > d.szA) {
+            void* nb = nullptr;
+            (void)hipStreamSynchronize(d.stream);
+            if (hipMalloc(&nb, need) != hipSuccess) return set_error(FLUSI_ENOMEM, "set_sponge: scratch");
+            (void)hipFree(d.bufA);
+            d.workspace += need - d.szA;
+            d.bufA = nb;
+            d.szA = need;
+        }
+    }
+    d.c_sp = on ? c_sp : 0.0;
+    for (int a = 0; a < 3; ++a) d.sp_thick[a] = on ? th[a] : 0.0;
+    return FLUSI_OK;
+}
+
 int flusi_set_stream(flusi_plan plan, void* stream) {
     if (int rc = check_plan(plan)) return rc;
     plan->d.stream = static_cast<hipStream_t>(stream);
@@ -466,7 +495,7 @@ int flusi_autotune(flusi_plan plan, const void* state, const flusi_insect* ins, 
         GroupRun g;
         g.mt = d.member_dev;
         g.nmem = 1;
-        g.n_nc[m.nc == 0 ? 0 : (m.nc == 1 ? 1 : 2)] = 1;
+        g.n_nc[m.sponge][colour_slot(m.nc)] = 1;
         g.any_dyn = m.dyn != 0;
         g.tw = d.tw;
         g.stream = d.stream;
@@ -571,8 +600,12 @@ static int ens_rebuild(flusi_ensemble e) {
         if (e->members[i].used) by_n[e->members[i].plan->d.n].push_back(i);
     for (auto& kv : by_n) {
         std::vector<int>& ids = kv.second;
-        auto nc_of = [&](int i) { return colour_count(e->members[i].has_ins ? &e->members[i].ins : nullptr); };
-        std::stable_sort(ids.begin(), ids.end(), [&](int a, int b) { return nc_of(a) < nc_of(b); });
+        // order: without sponge, then with; within each, by colour count
+        auto key = [&](int i) {
+            const int nc = colour_count(e->members[i].has_ins ? &e->members[i].ins : nullptr);
+            return (sponge_on(e->members[i].plan->d) ? 8 : 0) + nc;
+        };
+        std::stable_sort(ids.begin(), ids.end(), [&](int a, int b) { return key(a) < key(b); });
         EnsGroup g;
         g.n = kv.first;
         g.p0 = e->members[ids[0]].plan;
@@ -589,8 +622,7 @@ static int ens_rebuild(flusi_ensemble e) {
             }
             const Member rec = make_member(pd, m.state, ins, m.sp);
             host.push_back(rec);
-            const int nc = rec.nc;
-            g.run.n_nc[nc == 0 ? 0 : (nc == 1 ? 1 : 2)] += 1;
+            g.run.n_nc[rec.sponge][colour_slot(rec.nc)] += 1;
             g.run.any_dyn = g.run.any_dyn || rec.dyn;
         }
         if (hipMalloc(&g.dev, host.size() * sizeof(Member)) != hipSuccess)

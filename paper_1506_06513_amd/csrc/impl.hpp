@@ -34,6 +34,8 @@ struct PlanData {
     flusi_insect* ins_dev = nullptr;  // device copy of the insect of the current stepping call
     Member* member_dev = nullptr;     // launch record of the plan's own calls
     Sched sched;                      // schedule of the plan's own stepping calls
+    double c_sp = 0.0;                // vorticity sponge constant (0: off)
+    double sp_thick[3] = {0.0, 0.0, 0.0};  // sponge layer thickness per axis
     double* pmax = nullptr;
     int npmax = 0;
     void* spec = nullptr;  // lazily allocated full-layout scratch
@@ -80,12 +82,13 @@ struct PassScope {
 };
 
 // One batched stepping launch sequence: members of one (real type, size) that
-// advance together.  The device table is ordered by colour count (nc = 0,
-// then 1, then 3) so that each x-pass variant runs over a contiguous range.
+// advance together.  The device table is ordered by sponge flag, then colour
+// count (nc = 0, then 1, then 3), so that each x-pass variant runs over a
+// contiguous range.
 struct GroupRun {
     const Member* mt = nullptr;
     int nmem = 0;
-    int n_nc[3] = {0, 0, 0};  // members with nc = 0, 1, 3
+    int n_nc[2][3] = {{0, 0, 0}, {0, 0, 0}};  // members [without, with sponge][nc = 0, 1, 3]
     bool any_dyn = false;
     const void* tw = nullptr;
     Sched sched;
@@ -96,6 +99,10 @@ struct GroupRun {
 inline int colour_count(const flusi_insect* ins) {
     const bool masked = ins && (ins->body != FLUSI_BODY_NONE || ins->wings);
     return masked ? (ins->wings ? 3 : 1) : 0;
+}
+inline int colour_slot(int nc) { return nc == 0 ? 0 : (nc == 1 ? 1 : 2); }
+inline bool sponge_on(const PlanData& p) {
+    return p.c_sp > 0.0 && (p.sp_thick[0] > 0.0 || p.sp_thick[1] > 0.0 || p.sp_thick[2] > 0.0);
 }
 inline int kin_dynamic(const flusi_insect* ins) {
     return colour_count(ins) > 0 &&
@@ -121,6 +128,9 @@ inline Member make_member(const PlanData& p, void* st, const flusi_insect* ins, 
     m.mean_mode = sp.mean_mode;
     m.nc = nc;
     m.dyn = kin_dynamic(ins);
+    m.sponge = sponge_on(p) ? 1 : 0;
+    m.inv_csp = m.sponge ? 1.0 / p.c_sp : 0.0;
+    for (int a = 0; a < 3; ++a) m.sp_lo[a] = (m.sponge && p.sp_thick[a] > 0.0) ? p.L - p.sp_thick[a] : 1e300;
     return m;
 }
 enum { PASS_ZINV = 0, PASS_YINV = 1, PASS_X = 2, PASS_SCALAR = 3, PASS_YFWD = 4, PASS_Z = 5 };
@@ -131,6 +141,7 @@ int ensure_scratch(void** ptr, size_t* cur, size_t need, PlanData& p);
 struct ImplBase {
     virtual ~ImplBase() {}
     virtual size_t bufA_elems() const = 0;
+    virtual size_t bufA_elems_sponge() const = 0;
     virtual size_t bufB_elems() const = 0;
     virtual int nwg_x() const = 0;
     virtual size_t state_bytes() const = 0;
@@ -164,6 +175,11 @@ struct Impl final : ImplBase {
 
     size_t bufA_elems() const override {
         const size_t a = 6ul * N * Qp, b = 3ul * N2 * KPp;
+        return a > b ? a : b;
+    }
+    // the x-pass writes 6 fields (N and chi_sp w) with the sponge
+    size_t bufA_elems_sponge() const override {
+        const size_t a = bufA_elems(), b = 6ul * N2 * KPp;
         return a > b ? a : b;
     }
     size_t bufB_elems() const override {
@@ -305,7 +321,7 @@ struct Impl final : ImplBase {
     static void y_inverse_v(const GroupRun& g) {
         const CX* w = static_cast<const CX*>(g.tw);
         constexpr int nb = nby<V>(6);
-        k_ypass<T, N, +1, 0, V><<<(unsigned)(nb * g.nmem), NT, 0, g.stream>>>(g.mt, nb, w, 0, 0);
+        k_ypass<T, N, +1, 0, V><<<(unsigned)(nb * g.nmem), NT, 0, g.stream>>>(g.mt, nb, w, 6, 0);
     }
     static void y_inverse(const GroupRun& g) {
         if (g.sched.y_inverse == 2) y_inverse_v<2>(g);
@@ -317,43 +333,65 @@ struct Impl final : ImplBase {
     template <int V>
     static void y_forward_v(const GroupRun& g, bool red) {
         const CX* w = static_cast<const CX*>(g.tw);
-        constexpr int nb = nby<V>(3);
+        const int nfwd = (g.n_nc[1][0] + g.n_nc[1][1] + g.n_nc[1][2]) ? 6 : 3;
+        const int nb = nby<V>(nfwd);
         if (red)
             k_ypass<T, N, -1, 1, V><<<(unsigned)((nb + nred_of(N)) * g.nmem), NT, 0, g.stream>>>(
-                g.mt, nb + nred_of(N), w, 0, nwg_of(g.sched.x_pass));
+                g.mt, nb + nred_of(N), w, nfwd, nwg_of(g.sched.x_pass));
         else
-            k_ypass<T, N, -1, 0, V><<<(unsigned)(nb * g.nmem), NT, 0, g.stream>>>(g.mt, nb, w, 0, 0);
+            k_ypass<T, N, -1, 0, V><<<(unsigned)(nb * g.nmem), NT, 0, g.stream>>>(g.mt, nb, w, nfwd, 0);
     }
     static void y_forward(const GroupRun& g, bool red) {
         if (g.sched.y_forward == 2) y_forward_v<2>(g, red);
         else if (g.sched.y_forward == 1) y_forward_v<1>(g, red);
         else y_forward_v<0>(g, red);
     }
+    template <int V, bool SP>
+    static const Member* xpass_range(const GroupRun& g, const Member* mt) {
+        const CX* w = static_cast<const CX*>(g.tw);
+        constexpr int nw = nwg<V>(0);
+        const int* n = g.n_nc[SP ? 1 : 0];
+        if (n[0]) k_xpass<T, N, 0, V, SP><<<(unsigned)(nw * n[0]), NT, 0, g.stream>>>(mt, w);
+        mt += n[0];
+        if (n[1]) k_xpass<T, N, 1, V, SP><<<(unsigned)(nw * n[1]), NT, 0, g.stream>>>(mt, w);
+        mt += n[1];
+        if (n[2]) k_xpass<T, N, 3, V, SP><<<(unsigned)(nw * n[2]), NT, 0, g.stream>>>(mt, w);
+        return mt + n[2];
+    }
     template <int V>
     static void xpass_v(const GroupRun& g) {
-        const CX* w = static_cast<const CX*>(g.tw);
-        const Member* mt = g.mt;
-        constexpr int nw = nwg<V>(0);
-        if (g.n_nc[0]) k_xpass<T, N, 0, V><<<(unsigned)(nw * g.n_nc[0]), NT, 0, g.stream>>>(mt, w);
-        mt += g.n_nc[0];
-        if (g.n_nc[1]) k_xpass<T, N, 1, V><<<(unsigned)(nw * g.n_nc[1]), NT, 0, g.stream>>>(mt, w);
-        mt += g.n_nc[1];
-        if (g.n_nc[2]) k_xpass<T, N, 3, V><<<(unsigned)(nw * g.n_nc[2]), NT, 0, g.stream>>>(mt, w);
+        const Member* mt = xpass_range<V, false>(g, g.mt);
+        xpass_range<V, true>(g, mt);
     }
     static void xpass(const GroupRun& g) {
         if (g.sched.x_pass == 2) xpass_v<2>(g);
         else if (g.sched.x_pass == 1) xpass_v<1>(g);
         else xpass_v<0>(g);
     }
+    template <int MODE, int V, bool SP>
+    static void zpass_launch(const GroupRun& g, const Member* mt, int nmem, int par, int s) {
+        if (nmem > 0)
+            k_zpass<T, N, MODE, V, SP><<<(unsigned)(NBZ * nmem), nt_z(N, V), 0, g.stream>>>(
+                mt, static_cast<const CX*>(g.tw), par, s);
+    }
+    // update modes: members without the sponge, then those with it (the table
+    // is ordered that way); other modes: all members in one launch
+    template <int MODE, int V>
+    static void zpass_v(const GroupRun& g, int par, int s) {
+        constexpr bool update = MODE == MODE_STEP || MODE == MODE_STEP_LAST;
+        const int nsp = g.n_nc[1][0] + g.n_nc[1][1] + g.n_nc[1][2];
+        if (update && nsp) {
+            zpass_launch<MODE, V, false>(g, g.mt, g.nmem - nsp, par, s);
+            zpass_launch<MODE, V, update>(g, g.mt + (g.nmem - nsp), nsp, par, s);
+        } else {
+            zpass_launch<MODE, V, false>(g, g.mt, g.nmem, par, s);
+        }
+    }
     template <int MODE>
     static void zpass(const GroupRun& g, int par = 0, int s = 0) {
-        const CX* w = static_cast<const CX*>(g.tw);
-        if (g.sched.z_pass == 2)
-            k_zpass<T, N, MODE, 2><<<(unsigned)(NBZ * g.nmem), nt_z(N, 2), 0, g.stream>>>(g.mt, w, par, s);
-        else if (g.sched.z_pass == 1)
-            k_zpass<T, N, MODE, 1><<<(unsigned)(NBZ * g.nmem), nt_z(N, 1), 0, g.stream>>>(g.mt, w, par, s);
-        else
-            k_zpass<T, N, MODE, 0><<<(unsigned)(NBZ * g.nmem), nt_z(N, 0), 0, g.stream>>>(g.mt, w, par, s);
+        if (g.sched.z_pass == 2) zpass_v<MODE, 2>(g, par, s);
+        else if (g.sched.z_pass == 1) zpass_v<MODE, 1>(g, par, s);
+        else zpass_v<MODE, 0>(g, par, s);
     }
 
     Sched default_sched() const override {
@@ -436,7 +474,7 @@ struct Impl final : ImplBase {
         GroupRun g;
         g.mt = p.member_dev;
         g.nmem = 1;
-        g.n_nc[m.nc == 0 ? 0 : (m.nc == 1 ? 1 : 2)] = 1;
+        g.n_nc[m.sponge][colour_slot(m.nc)] = 1;
         g.any_dyn = m.dyn != 0;
         g.tw = p.tw;
         g.sched = p.sched;

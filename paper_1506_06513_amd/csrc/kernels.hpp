@@ -148,7 +148,9 @@ struct Member {
     int mean_mode;
     int nc;                     // colours of the mask: 0 (none), 1 (body), 3 (body + wings)
     int dyn;                    // kinematics change with time
-    int pad;
+    int sponge;                 // vorticity sponge on: 3 more forward fields (chi_sp w)
+    double inv_csp;             // 1/C_sp
+    double sp_lo[3];            // chi_sp = 1 where x_a >= sp_lo[a] for some axis a
 };
 
 template <int NRED>
@@ -226,14 +228,16 @@ __global__ __launch_bounds__(NT) void k_colfft(const cx<T>* in, cx<T>* out, int 
 // Each member has nbx*nf column tiles followed by the extra workgroups:
 //   EXTRA 1: nred_of(N) workgroups reduce the x-pass sums (first level)
 // nwg: x-pass workgroups per member (records of the first-level reduction).
+// nfwd: forward fields per member (3, or 6 when a member of the launch has the
+// vorticity sponge; members without it skip fields 3..5).
 template <typename T, int N, int DIR, int EXTRA, int V>
 __global__ __launch_bounds__(NT) void k_ypass(const Member* __restrict__ mt, int per, const cx<T>* __restrict__ tw,
-                                              int p, int nwg) {
+                                              int nfwd, int nwg) {
     using G = Geo<T, N>;
     constexpr int KP = G::KP, KPp = G::KPp, Qp = G::Qp;
     constexpr int C = cols_of(N, V);
     constexpr int nbx = (N * KP + C - 1) / C;
-    constexpr int nf = DIR > 0 ? 6 : 3;
+    const int nf = DIR > 0 ? 6 : nfwd;
     __shared__ cx<T> buf[C * cm_stride(N)];
     const int lin = xcd_tile(blockIdx.x, gridDim.x);
     const Member& m = mt[lin / per];
@@ -247,6 +251,7 @@ __global__ __launch_bounds__(NT) void k_ypass(const Member* __restrict__ mt, int
         }
         return;
     }
+    if (DIR < 0 && f >= 3 && !m.sponge) return;
     __shared__ cx<T> tws[N];
     stage_twiddles<T, N>(tws, tw, NT);
     const glb<cx<T>>* A = gview(static_cast<const cx<T>*>(m.bufA));
@@ -328,7 +333,9 @@ __device__ __forceinline__ void block_reduce_store(const double (&acc)[NVAL], do
 // NC: number of colours accumulated (0 no mask, 1 single body, 3 insect).
 // ---------------------------------------------------------------------------
 // Member table: N*N/RW workgroups per member, y-partials in bufB, output in bufA.
-template <typename T, int N, int NC, int V>
+// SP: members with the vorticity sponge; chi_sp * w is transformed beside N
+// and stored as fields 3..5.
+template <typename T, int N, int NC, int V, bool SP>
 __global__ __launch_bounds__(NT) void k_xpass(const Member* __restrict__ mt, const cx<T>* __restrict__ tw) {
     using G = Geo<T, N>;
     constexpr int K = G::K, KP = G::KP, KPp = G::KPp;
@@ -344,11 +351,12 @@ __global__ __launch_bounds__(NT) void k_xpass(const Member* __restrict__ mt, con
     const int wg = blockIdx.x % NWG;
     constexpr int SC = cm_stride(N);
     constexpr int CI = 3 * RW, CF = 3 * RW / 2;
+    constexpr int CFT = SP ? 2 * CF : CF;  // forward columns (N, then chi_sp w)
     constexpr int NVAL = 3 + 12 * NC;
 
     constexpr int LP = (RW * KP + NT - 1) / NT;
     // inverse columns [0, CI), forward columns [CI, CI + CF)
-    __shared__ cx<T> buf[(CI + CF) * SC];
+    __shared__ cx<T> buf[(CI + CFT) * SC];
     cx<T>* fbuf = buf + CI * SC;
     // per-wave sums: with three colours the wave rows wred also take the three
     // lane-reduced values (slots 0..2 are free there), which saves the LDS of red
@@ -572,6 +580,14 @@ __global__ __launch_bounds__(NT) void k_xpass(const Member* __restrict__ mt, con
         if (act) {
             fbuf[lds_at<true, 1, SC>(i, r)] = cx<T>{nx, ny};
             reinterpret_cast<T*>(fbuf + lds_at<true, 1, SC>(i, RW + r / 2))[r & 1] = nz;
+            if constexpr (SP) {
+                // vorticity sponge: chi_sp * w, same column scheme after the N columns
+                const double xs = dx * i, ys = dx * (row % N), zs = dx * (row / N);
+                const bool in = xs >= m.sp_lo[0] || ys >= m.sp_lo[1] || zs >= m.sp_lo[2];
+                const T c = in ? T(1) : T(0);
+                fbuf[lds_at<true, 1, SC>(i, CF + r)] = cx<T>{c * wx, c * wy};
+                reinterpret_cast<T*>(fbuf + lds_at<true, 1, SC>(i, CF + RW + r / 2))[r & 1] = c * wz;
+            }
         }
     };
 #pragma unroll 1
@@ -608,16 +624,17 @@ __global__ __launch_bounds__(NT) void k_xpass(const Member* __restrict__ mt, con
             partial[(long)wg * NV + tid] = r;
         }
     }
-    fft_cols<T, N, -1, CF, NT, SC>(fbuf, twx);
+    fft_cols<T, N, -1, CFT, NT, SC>(fbuf, twx);
 
     // 3. split the packed spectra and store kx = 0..K
 #pragma unroll
-    for (int f = 0; f < 3; ++f) {
+    for (int f = 0; f < (SP ? 6 : 3); ++f) {
         glb<cx<T>>* O = xout + f * fs_out + (long)row0 * KPp;
+        const int fb = f % 3, c0 = f < 3 ? 0 : CF;
         for (int idx = tid; idx < RW * KP; idx += NT) {
             const int r = idx / KP, k = idx % KP;
-            const int colx = (f < 2) ? r : RW + r / 2;
-            const bool second = (f == 1) || (f == 2 && (r & 1));
+            const int colx = c0 + ((fb < 2) ? r : RW + r / 2);
+            const bool second = (fb == 1) || (fb == 2 && (r & 1));
             const cx<T> zk = fbuf[lds_at<true, 1, SC>(k, colx)];
             const cx<T> zm = fbuf[lds_at<true, 1, SC>((N - k) % N, colx)];
             cx<T> v;
@@ -873,7 +890,8 @@ enum { MODE_IMPORT = 0, MODE_STEP = 1, MODE_STEP_LAST = 2, MODE_INVERSE = 3 };
 
 // Member table: ceil(Q/C) workgroups per member.  par: slot of the current
 // time level; s: step index within the call (row of the history).
-template <typename T, int N, int MODE, int V>
+// SP: the members have the vorticity sponge (fields 3..5 of the forward input).
+template <typename T, int N, int MODE, int V, bool SP = false>
 __global__ __launch_bounds__(nt_z(N, V)) void k_zpass(const Member* __restrict__ mt, const cx<T>* __restrict__ tw,
                                                       int par, int s) {
     using G = Geo<T, N>;
@@ -944,12 +962,14 @@ __global__ __launch_bounds__(nt_z(N, V)) void k_zpass(const Member* __restrict__
     // kept kz of this thread: m = r0 + i*RS, i < PERM
     cx<T> U[3][PERM];
     if (do_fwd) {
+        // vorticity sponge: fields 3..5 hold chi_sp * w
+        constexpr bool sp = SP && (MODE == MODE_STEP || MODE == MODE_STEP_LAST);
         cx<T> Nh[3][PERM];
 #pragma unroll
         for (int f = 0; f < 3; ++f) {
 #pragma unroll
             for (int i = 0; i < RPT; ++i) buf[c * SC + cpad(r0 + i * RS)] = vn[i];
-            if (f < 2) load_field(f + 1);
+            if (f < 2 || sp) load_field(f + 1);
             fft_cols<T, N, -1, C, NTZ, SC>(buf, tws);
 #pragma unroll
             for (int i = 0; i < PERM; ++i) {
@@ -957,6 +977,43 @@ __global__ __launch_bounds__(nt_z(N, V)) void k_zpass(const Member* __restrict__
                 if (m < M) Nh[f][i] = buf[c * SC + cpad(bin_of_m(m, N, K))];
             }
             __syncthreads();
+        }
+        if constexpr (sp) {
+            // N_hat += -(1/C_sp) (i k x W_hat)/|k|^2, one W component at a time
+            // (eq. PNST_org_momentum, sponge term; zero at k = 0)
+#pragma unroll
+            for (int f = 3; f < 6; ++f) {
+#pragma unroll
+                for (int i = 0; i < RPT; ++i) buf[c * SC + cpad(r0 + i * RS)] = vn[i];
+                if (f < 5) load_field(f + 1);
+                fft_cols<T, N, -1, C, NTZ, SC>(buf, tws);
+#pragma unroll
+                for (int i = 0; i < PERM; ++i) {
+                    const int m = r0 + i * RS;
+                    if (m < M && okq) {
+                        const cx<T> w = buf[c * SC + cpad(bin_of_m(m, N, K))];
+                        const double kzv = kscale * j_of_m(m, K);
+                        const double k2 = kxv * kxv + kyv * kyv + kzv * kzv;
+                        const double a = k2 > 0.0 ? -mb.inv_csp / k2 : 0.0;
+                        // i * w = (-w.y, w.x)
+                        const double pr = -a * (double)w.y, pi = a * (double)w.x;
+                        const auto add = [&](cx<T>& t, double coef) {
+                            t = cx<T>{T((double)t.x + coef * pr), T((double)t.y + coef * pi)};
+                        };
+                        if (f == 3) {         // W_x: (k x W)_y += kz Wx, (k x W)_z -= ky Wx
+                            add(Nh[1][i], kzv);
+                            add(Nh[2][i], -kyv);
+                        } else if (f == 4) {  // W_y: (k x W)_x -= kz Wy, (k x W)_z += kx Wy
+                            add(Nh[0][i], -kzv);
+                            add(Nh[2][i], kxv);
+                        } else {              // W_z: (k x W)_x += ky Wz, (k x W)_y -= kx Wz
+                            add(Nh[0][i], kyv);
+                            add(Nh[1][i], -kxv);
+                        }
+                    }
+                }
+                __syncthreads();
+            }
         }
         double dt = 0, b1 = 0, b2 = 0, dtp = 0;
         int first = 1;
