@@ -138,8 +138,10 @@ def build_workload(name: str):
     raise SystemExit(f"unknown workload {name}")
 
 
-def gpu_run(F, torch, wl, dtype, steps, warmup, tune=True):
+def gpu_run(F, torch, wl, dtype, steps, warmup, tune=True, sponge=None):
     P = F.Plan(wl["n"], wl["L"], wl["nu"], wl["eta"], dtype)
+    if sponge:
+        P.set_sponge(*sponge)
     kw = dict(dt_fixed=wl["dt_fixed"], cfl=wl["cfl"], eta_cap=0.5, mean_mode=F.FLUSI_MEAN_FIXED)
     u0 = torch.from_numpy(wl["u0"])
     st = P.new_state(u0)
@@ -294,6 +296,7 @@ def main():
     ap.add_argument("--workload", default="sphere128",
                     choices=["sphere128", "insect256", "tg32", "ensemble48", "serve"])
     ap.add_argument("--no-serve", action="store_true", help="skip the serving-stream figure")
+    ap.add_argument("--no-sponge", action="store_true", help="skip the vorticity-sponge figure")
     ap.add_argument("--no-ensemble", action="store_true", help="skip the batched-ensemble figure")
     ap.add_argument("--no-autotune", action="store_true", help="time the default schedules")
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
@@ -401,6 +404,15 @@ def main():
         out["ensemble48"] = ensemble_run(F, torch, tune=not a.no_autotune)
     if not a.no_serve and a.workload == "sphere128":
         out["serving"] = serve_run(F, torch)
+    if not a.no_sponge and a.workload == "sphere128":
+        # the same workload with a vorticity sponge layer 3.5 <= x < 4 (C_sp = 0.1)
+        sp = {}
+        for dtype in ("f32", "f64"):
+            r = gpu_run(F, torch, wl, dtype, steps, a.warmup, tune=not a.no_autotune, sponge=(0.1, (0.5, 0.0, 0.0)))
+            sp[dtype] = round(pts * steps / (r["ev_ms"] / 1e3) / 1e6, 2)
+        out["sponge"] = {"value": sp["f32"], "fp64": sp["f64"], "unit": "Mpoint-steps/s",
+                         "description": "sphere128 with the vorticity sponge on 3.5 <= x < 4, C_sp = 0.1 "
+                                        "(3 more forward fields per step)"}
     if not a.no_cpu:
         cs = oracle_sample(wl)
         cpu_v = pts * cs["timed_steps"] / cs["seconds"] / 1e6
