@@ -22,7 +22,11 @@ What it computes (paper section / equation in brackets):
   polar-radius wing shape [Sec. 3.4],
 * force and torque from the penalization integral with the unsteady
   correction [Sec. 2.1, eqs. force_with_unst_corrections, moment_of_love],
-* the time loop of Algorithm 1 (mask -> dt -> sources -> projection -> AB2).
+* the time loop of Algorithm 1 (mask -> dt -> sources -> projection -> AB2
+  -> free flight),
+* free flight: Newton's law and the quaternion form of Euler's equations
+  [Sec. 3.5, eq. oh_my_god_look_a_vector] stepped with the same AB2, and the
+  aerodynamic power of a wing [Sec. 3.5, eq. insect_power].
 
 Where the paper is silent or garbled the readings below are used (each is
 listed in the design notes of the repository):
@@ -65,6 +69,24 @@ listed in the design notes of the repository):
       with I = sum chi u_s dV (no unsteady term at the first step); torques
       about the body centre (body) or the wing pivot (wings).
   Energy: E = 1/2 sum |u|^2 dV.
+  Quaternion matrix: the printed matrix of the quaternion maps body-frame
+      vectors to the global frame; M_body (global to body) is its transpose.
+      Only then does the printed initial quaternion reproduce eq.
+      M_body_yawpitchroll, and only then does eps' = 1/2 S^T Omega^(b)
+      describe the rotation with body angular velocity Omega^(b).
+  Free flight: F is the sum of the corrected forces of all parts; m is the
+      torque about the centre of gravity x_cntr, m = (1/C_eta) sum
+      (x - x_cntr) x chi (u - u_s) dV + (J^n - J^{n-1})/dt_{n-1} with
+      J = sum (x - x_cntr) x chi u_s dV, turned into the body frame by
+      M_body; gravity acts along -z.  The 6-vector of DoF switches multiplies
+      the three translational and the three rotational acceleration rows.
+      AB2 with the fluid's weights, Euler on the first free-flight step; the
+      quaternion is renormalized to unit length after every step.  The first
+      free-flight step starts from the prescribed kinematics at its time.
+  Aerodynamic power: P = -m . (Omega_w - Omega_b) with m the wing torque
+      about its pivot and Omega_w - Omega_b the wing's angular velocity
+      relative to the body (the Omega_w^(b) of Sec. 3.3), in the global
+      frame.
 """
 from __future__ import annotations
 
@@ -264,6 +286,11 @@ class Insect:
     phi: tuple = (0.0, 0.0, 0.0)
     alpha: tuple = (0.0, 0.0, 0.0)
     theta: tuple = (0.0, 0.0, 0.0)
+    free_flight: bool = False            # Sec. 3.5: the body moves under F, m and gravity
+    mass: float = 1.0                    # M
+    inertia: tuple = (1.0, 1.0, 1.0)     # principal moments J_x, J_y, J_z (body frame)
+    gravity: float = 0.0                 # g, acting along -z
+    dof: tuple = (1.0, 1.0, 1.0, 1.0, 1.0, 1.0)  # translation x,y,z; rotation x,y,z
 
     @staticmethod
     def from_dict(d: dict) -> "Insect":
@@ -375,12 +402,32 @@ def _apply(M, v):
     return np.einsum("ij,j...->i...", M, v)
 
 
-def body_velocity(ins: Insect, t: float, xb):
+@dataclass
+class Pose:
+    """Position, velocity, orientation and angular velocity of the body."""
+    xc: np.ndarray    # centre (global frame)
+    uc: np.ndarray    # centre velocity (global frame)
+    Mb: np.ndarray    # M_body: x_b = Mb (x_g - xc)
+    omb: np.ndarray   # body angular velocity, body frame
+
+
+def prescribed_pose(ins: Insect, t: float) -> Pose:
+    """Tethered body: the given centre and velocity, M_body and Omega_b^(b)
+    from the body angles at t  [Sec. 3.1]."""
+    return Pose(np.asarray(ins.x_cntr, dtype=np.float64), np.asarray(ins.u_cntr, dtype=np.float64),
+                M_body(ins, t), omega_body_b(ins, t))
+
+
+def _pose(ins: Insect, t: float, pose: Pose | None) -> Pose:
+    return prescribed_pose(ins, t) if pose is None else pose
+
+
+def body_velocity(ins: Insect, t: float, xb, pose: Pose | None = None):
     """u_b = u_cntr + M_body^T (Omega_b^(b) x x_b)  [eq. body_velocity_field]."""
-    Mb = M_body(ins, t)
-    om = omega_body_b(ins, t).reshape((3,) + (1,) * (np.ndim(xb) - 1))
-    ub = _apply(Mb.T, _cross(np.broadcast_to(om, np.shape(xb)), xb))
-    return ub + np.asarray(ins.u_cntr, dtype=np.float64).reshape((3,) + (1,) * (np.ndim(xb) - 1))
+    ps = _pose(ins, t, pose)
+    om = ps.omb.reshape((3,) + (1,) * (np.ndim(xb) - 1))
+    ub = _apply(ps.Mb.T, _cross(np.broadcast_to(om, np.shape(xb)), xb))
+    return ub + ps.uc.reshape((3,) + (1,) * (np.ndim(xb) - 1))
 
 
 def wing_frame(ins: Insect, t: float, side: str, xb):
@@ -390,7 +437,7 @@ def wing_frame(ins: Insect, t: float, side: str, xb):
     return _apply(M_wing(ins, t, side) @ M_stroke(ins, side), xrel)
 
 
-def wing_velocity(ins: Insect, t: float, side: str, xb):
+def wing_velocity(ins: Insect, t: float, side: str, xb, pose: Pose | None = None):
     """Solid velocity inside a wing, u_w + u_b  [eq. wing_velocity_field]:
     u_w^(w) = Omega_w^(w) x x_w with Omega_w^(w) = M_wing M_stroke Omega_w^(b),
     u_w^(g) = M_body^T M_stroke^T M_wing^T u_w^(w)."""
@@ -399,14 +446,15 @@ def wing_velocity(ins: Insect, t: float, side: str, xb):
     xw = wing_frame(ins, t, side, xb)
     om_w = (Mw @ Ms @ omega_wing_b(ins, t, side)).reshape((3,) + (1,) * (np.ndim(xb) - 1))
     uw_w = _cross(np.broadcast_to(om_w, np.shape(xw)), xw)
-    back = M_body(ins, t).T @ Ms.T @ Mw.T
-    return _apply(back, uw_w) + body_velocity(ins, t, xb)
+    ps = _pose(ins, t, pose)
+    back = ps.Mb.T @ Ms.T @ Mw.T
+    return _apply(back, uw_w) + body_velocity(ins, t, xb, ps)
 
 
-def to_body(ins: Insect, t: float, xg):
+def to_body(ins: Insect, t: float, xg, pose: Pose | None = None):
     """x_b = M_body (x_g - x_cntr)  [eq. M_body_yawpitchroll]."""
-    xc = np.asarray(ins.x_cntr, dtype=np.float64).reshape((3,) + (1,) * (np.ndim(xg) - 1))
-    return _apply(M_body(ins, t), xg - xc)
+    ps = _pose(ins, t, pose)
+    return _apply(ps.Mb, xg - ps.xc.reshape((3,) + (1,) * (np.ndim(xg) - 1)))
 
 
 # Relative tolerance under which two part values count as a tie.
@@ -428,18 +476,20 @@ def part_of_max(stack: np.ndarray) -> np.ndarray:
     return part
 
 
-def mask_at(ins: Insect, t: float, dx: float, x, y, z):
+def mask_at(ins: Insect, t: float, dx: float, x, y, z, pose: Pose | None = None):
     """chi, u_s [3] and colour at points with global coordinates x, y, z (arrays
-    of one shape), smoothing width set by the grid spacing dx  [Alg. 1 step (a)]."""
+    of one shape), smoothing width set by the grid spacing dx  [Alg. 1 step (a)].
+    pose: the body's pose (default: the prescribed kinematics at t)."""
     x, y, z = (np.asarray(v, dtype=np.float64) for v in (x, y, z))
     shp = x.shape
+    ps = _pose(ins, t, pose)
     xg = np.stack([x, y, z])
-    xb = to_body(ins, t, xg)
-    ub = body_velocity(ins, t, xb)
+    xb = to_body(ins, t, xg, ps)
+    ub = body_velocity(ins, t, xb, ps)
 
     chis, uss = [], []
     if ins.body == "sphere":
-        xc = np.asarray(ins.x_cntr, dtype=np.float64)
+        xc = ps.xc
         d = np.sqrt((x - xc[0]) ** 2 + (y - xc[1]) ** 2 + (z - xc[2]) ** 2) - ins.radius
         chis.append(chi_of_delta(d, ins, dx))
         uss.append(ub)
@@ -456,7 +506,7 @@ def mask_at(ins: Insect, t: float, dx: float, x, y, z):
             xw = wing_frame(ins, t, side, xb)
             d = delta_elliptic_wing(xw[0], xw[1], xw[2], ins.wing_A, ins.wing_B, ins.wing_t)
             chis.append(chi_of_delta(d, ins, dx))
-            uss.append(wing_velocity(ins, t, side, xb))
+            uss.append(wing_velocity(ins, t, side, xb, ps))
     else:
         chis += [np.zeros(shp)] * 2
         uss += [np.zeros((3,) + shp)] * 2
@@ -473,18 +523,121 @@ def mask_at(ins: Insect, t: float, dx: float, x, y, z):
     return chi, us, colour
 
 
-def insect_mask(g: Grid, ins: Insect, t: float):
+def insect_mask(g: Grid, ins: Insect, t: float, pose: Pose | None = None):
     """chi, u_s [3] and colour on every grid point at time t  [Alg. 1 step (a)]."""
     x, y, z = g.coords()
-    return mask_at(ins, t, g.dx, x, y, z)
+    return mask_at(ins, t, g.dx, x, y, z, pose)
 
 
-def reference_points(ins: Insect, t: float) -> np.ndarray:
+def reference_points(ins: Insect, t: float, pose: Pose | None = None) -> np.ndarray:
     """Torque reference points (global frame) per colour 1..3: body centre, pivots."""
-    Mb = M_body(ins, t)
-    xc = np.asarray(ins.x_cntr, dtype=np.float64)
-    return np.stack([xc, xc + Mb.T @ np.asarray(ins.pivot_l, dtype=np.float64),
-                     xc + Mb.T @ np.asarray(ins.pivot_r, dtype=np.float64)])
+    ps = _pose(ins, t, pose)
+    return np.stack([ps.xc, ps.xc + ps.Mb.T @ np.asarray(ins.pivot_l, dtype=np.float64),
+                     ps.xc + ps.Mb.T @ np.asarray(ins.pivot_r, dtype=np.float64)])
+
+
+# ---------------------------------------------------------------------------
+# Free flight  [Sec. 3.5, eq. oh_my_god_look_a_vector]
+#
+# Solid state y (13 values): x_cntr (3), u_cntr (3), quaternion eps (4),
+# Omega^(b) (3).
+# ---------------------------------------------------------------------------
+
+def quaternion_from_angles(psi: float, beta: float, gamma: float) -> np.ndarray:
+    """Quaternion of the orientation with roll psi, pitch beta, yaw gamma  [Sec. 3.5]."""
+    cp, sp = math.cos(psi / 2), math.sin(psi / 2)
+    cb, sb = math.cos(beta / 2), math.sin(beta / 2)
+    cg, sg = math.cos(gamma / 2), math.sin(gamma / 2)
+    return np.array([cp * cb * cg + sp * sb * sg,
+                     sp * cb * cg - cp * sb * sg,
+                     cp * sb * cg + sp * cb * sg,
+                     cp * cb * sg - sp * sb * cg])
+
+
+def quaternion_matrix(eps) -> np.ndarray:
+    """The rotation matrix of a unit quaternion as the paper prints it  [Sec. 3.5];
+    it maps body-frame vectors to the global frame."""
+    e0, e1, e2, e3 = (float(v) for v in eps)
+    return np.array([
+        [e0 * e0 + e1 * e1 - e2 * e2 - e3 * e3, 2 * (e1 * e2 - e3 * e0), 2 * (e1 * e3 + e2 * e0)],
+        [2 * (e1 * e2 + e3 * e0), e0 * e0 - e1 * e1 + e2 * e2 - e3 * e3, 2 * (e2 * e3 - e1 * e0)],
+        [2 * (e1 * e3 - e2 * e0), 2 * (e2 * e3 + e1 * e0), e0 * e0 - e1 * e1 - e2 * e2 + e3 * e3]])
+
+
+def M_body_of_quaternion(eps) -> np.ndarray:
+    """M_body (global to body) of the free-flight case: the transpose of the
+    printed quaternion matrix (so that it agrees with eq. M_body_yawpitchroll
+    for the initial quaternion of the same angles)."""
+    return quaternion_matrix(eps).T
+
+
+def solid_pose(y) -> Pose:
+    """Pose of the body from the free-flight state."""
+    y = np.asarray(y, dtype=np.float64)
+    return Pose(y[0:3].copy(), y[3:6].copy(), M_body_of_quaternion(y[6:10]), y[10:13].copy())
+
+
+def solid_init(ins: Insect, t: float) -> np.ndarray:
+    """Free-flight state equal to the prescribed kinematics at time t."""
+    psi, beta, gamma = body_angles(ins, t)
+    return np.concatenate([np.asarray(ins.x_cntr, dtype=np.float64), np.asarray(ins.u_cntr, dtype=np.float64),
+                           quaternion_from_angles(psi, beta, gamma), omega_body_b(ins, t)])
+
+
+def pose_record(ins: Insect, t: float, y=None) -> np.ndarray:
+    """The 13 state values of the body at t: the free-flight state y, or the
+    prescribed kinematics (quaternion from the body angles) when y is None."""
+    return np.asarray(y, dtype=np.float64).copy() if y is not None else solid_init(ins, t)
+
+
+def solid_rhs(ins: Insect, y, F, m_g) -> np.ndarray:
+    """Right-hand side of the 13 free-flight equations  [eq. oh_my_god_look_a_vector].
+
+    F: aerodynamic force (global frame); m_g: torque about x_cntr (global
+    frame), turned into the body frame with M_body; gravity g along -z; the
+    DoF switches multiply the translational and rotational acceleration rows."""
+    y = np.asarray(y, dtype=np.float64)
+    uc, eps, om = y[3:6], y[6:10], y[10:13]
+    e0, e1, e2, e3 = eps
+    ox, oy, oz = om
+    Jx, Jy, Jz = ins.inertia
+    mb = M_body_of_quaternion(eps) @ np.asarray(m_g, dtype=np.float64)
+    dof = np.asarray(ins.dof, dtype=np.float64)
+    f = np.empty(13)
+    f[0:3] = uc
+    f[3:6] = np.asarray(F, dtype=np.float64) / ins.mass
+    f[5] -= ins.gravity
+    f[3:6] *= dof[0:3]
+    f[6] = 0.5 * (-e1 * ox - e2 * oy - e3 * oz)
+    f[7] = 0.5 * (e0 * ox - e3 * oy + e2 * oz)
+    f[8] = 0.5 * (e3 * ox + e0 * oy - e1 * oz)
+    f[9] = 0.5 * (-e2 * ox + e1 * oy + e0 * oz)
+    f[10] = ((Jy - Jz) * oy * oz + mb[0]) / Jx
+    f[11] = ((Jz - Jx) * oz * ox + mb[1]) / Jy
+    f[12] = ((Jx - Jy) * ox * oy + mb[2]) / Jz
+    f[10:13] *= dof[3:6]
+    return f
+
+
+def solid_step(ins: Insect, y, f_prev, F, m_g, dt: float, dt_prev: float):
+    """AB2 step of the free-flight state  [Alg. 1 step (f)]: Euler when f_prev
+    is None, else the variable-step weights of the fluid; the quaternion is
+    renormalized.  Returns (y_new, f) with f the right-hand side at y."""
+    f = solid_rhs(ins, y, F, m_g)
+    if f_prev is None:
+        yn = np.asarray(y, dtype=np.float64) + dt * f
+    else:
+        r = dt / dt_prev
+        yn = np.asarray(y, dtype=np.float64) + dt * ((1.0 + 0.5 * r) * f - 0.5 * r * np.asarray(f_prev))
+    yn[6:10] /= math.sqrt(float(np.sum(yn[6:10] ** 2)))
+    return yn, f
+
+
+def aero_power(m_wing_g, Mb, om_w_b) -> float:
+    """P_aero = -m . (Omega_w - Omega_b) of one wing  [Sec. 3.5, eq. insect_power],
+    with the wing's angular velocity relative to the body given in the body
+    frame and the torque about the pivot in the global frame."""
+    return -float(np.dot(np.asarray(m_wing_g), Mb.T @ np.asarray(om_w_b)))
 
 
 # ---------------------------------------------------------------------------
@@ -608,6 +761,9 @@ class State:
     dt_prev: float = 0.0
     n: int = 0
     I_prev: np.ndarray | None = None     # [3 colours][6]: sum chi u_s dV and its moment
+    J_prev: np.ndarray | None = None     # sum (x - x_cntr) x chi u_s dV of the previous step
+    solid: np.ndarray | None = None      # free-flight state (13) at t
+    solid_f: np.ndarray | None = None    # its right-hand side of the previous step
 
 
 def init_state(p: Params, u0: np.ndarray, t0: float = 0.0) -> State:
@@ -634,8 +790,21 @@ def force_sums(g: Grid, u, chi, us, colour, xref, eta):
     return F, M, I
 
 
+def torque_about(g: Grid, u, chi, us, xc, eta):
+    """Penalization torque and J = sum (x - xc) x chi u_s dV about the point xc,
+    over the whole solid  [eq. moment_of_love]."""
+    x, y, z = g.coords()
+    r = np.stack([x - xc[0], y - xc[1], z - xc[2]])
+    pen = chi * (u - us) / eta * g.dV
+    ius = chi * us * g.dV
+    return _cross(r, pen).reshape(3, -1).sum(axis=1), _cross(r, ius).reshape(3, -1).sum(axis=1)
+
+
 def step(p: Params, st: State, ctl: StepControl, ins: Insect | None, fixed_mask=None):
-    """One pass of Algorithm 1; returns the new state and the diagnostics at t^n.
+    """One pass of Algorithm 1; returns the new state and the diagnostics at t^n
+    (with an insect also its pose record, the aerodynamic power of the wings
+    and, in free flight, the total force and the torque about x_cntr that
+    drive step (f)).
 
     fixed_mask = (chi, u_s, colour, xref) replaces the insect by a
     time-independent mask (used by tests)."""
@@ -644,8 +813,14 @@ def step(p: Params, st: State, ctl: StepControl, ins: Insect | None, fixed_mask=
     if fixed_mask is not None:
         chi, us, colour, xref = fixed_mask
     elif ins is not None:
-        chi, us, colour = insect_mask(g, ins, st.t)                    # (a)
-        xref = reference_points(ins, st.t)
+        ysol = None
+        if ins.free_flight:
+            ysol = st.solid if st.solid is not None else solid_init(ins, st.t)
+            pose = solid_pose(ysol)
+        else:
+            pose = prescribed_pose(ins, st.t)
+        chi, us, colour = insect_mask(g, ins, st.t, pose)              # (a)
+        xref = reference_points(ins, st.t, pose)
     else:
         chi = us = colour = xref = None
     u, w = physical_fields(g, st.uh)                                   # u^n, w^n
@@ -673,9 +848,26 @@ def step(p: Params, st: State, ctl: StepControl, ins: Insect | None, fixed_mask=
         I_now = I
     else:
         I_now = None
+    J_now = solid_new = f_new = None
+    if ins is not None and fixed_mask is None:
+        diag["pose"] = pose_record(ins, st.t, ysol)
+        diag["P_aero"] = np.array([aero_power(M[1 + k], pose.Mb, omega_wing_b(ins, st.t, side)) if ins.wings
+                                   else 0.0 for k, side in enumerate(("l", "r"))])
+        m_pen, J_now = torque_about(g, u, chi, us, pose.xc, p.eta)
+        if ins.free_flight:
+            Ft = F.sum(axis=0)
+            mt = m_pen
+            if st.J_prev is not None and st.dt_prev > 0.0:
+                mt = mt + (J_now - st.J_prev) / st.dt_prev
+            diag["F_total"], diag["m_cntr"] = Ft, mt
+            if dt > 0.0:                                               # (f)
+                solid_new, f_new = solid_step(ins, ysol, st.solid_f, Ft, mt, dt, st.dt_prev)
+            else:
+                solid_new, f_new = ysol, st.solid_f
     uh_new = ab2_if(p, g, st.uh, nh, st.nh_prev, dt,
                     st.dt_prev if st.nh_prev is not None else dt)      # (e)
-    new = State(uh=uh_new, nh_prev=nh, t=st.t + dt, dt_prev=dt, n=st.n + 1, I_prev=I_now)
+    new = State(uh=uh_new, nh_prev=nh, t=st.t + dt, dt_prev=dt, n=st.n + 1, I_prev=I_now,
+                J_prev=J_now, solid=solid_new, solid_f=f_new)
     return new, diag
 
 
