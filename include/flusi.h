@@ -65,24 +65,48 @@ extern "C" {
  *   [0] t^n   [1] dt_n   [2] max|u|   [3] E = 1/2 sum |u|^2 dV
  *   [4 + 6*(c-1) + 0..2]  force  F on colour c (c = 1 body, 2 left wing, 3 right wing)
  *   [4 + 6*(c-1) + 3..5]  torque m on colour c
+ *   [22..24] x_cntr  [25..27] u_cntr  [28..31] quaternion eps_0..3
+ *   [32..34] Omega_b^(b): the body's state at t^n (Sec. 3.5; for a tethered
+ *            body the prescribed kinematics, eps from the body angles)
+ *   [35] [36] aerodynamic power P_aero of the left and right wing
+ *            (Sec. 3.5, eq. insect_power)
  * Force and torque follow eqs. force_with_unst_corrections / moment_of_love
  * (Sec. 2.1): the penalization integral plus the time derivative of the solid
  * momentum, as the force acting on the solid.  Torques are taken about the
- * body centre (body) and the wing pivots (wings). */
-#define FLUSI_NDIAG 22
+ * body centre (body) and the wing pivots (wings).  P_aero = -m . (Omega_w -
+ * Omega_b) with m the wing torque about its pivot and Omega_w - Omega_b the
+ * wing's angular velocity relative to the body.  Without a mask [4..36] are
+ * zero. */
+#define FLUSI_NDIAG 37
 
 typedef struct flusi_plan_s* flusi_plan;
 
 /* Rigid insect (Sec. 3), or a single body when wings == 0.  Angles in
- * radians.  Body angles evolve as angle + rate*t.  Each wing angle is
- * mean + amplitude*cos(2*pi*freq*t + phase).  x_cntr is the body centre at
- * the current time (the body is not translated by the library) and u_cntr
- * its velocity. */
+ * radians.  Each wing angle is mean + amplitude*cos(2*pi*freq*t + phase).
+ *
+ * Tethered (free_flight == 0): body angles evolve as angle + rate*t; x_cntr is
+ * the body centre at the current time (the body is not translated by the
+ * library) and u_cntr its velocity.
+ *
+ * Free flight (free_flight == 1, Sec. 3.5, eq. oh_my_god_look_a_vector): the
+ * state keeps the 13 values x_cntr (centre of gravity), u_cntr, the unit
+ * quaternion eps and Omega_b^(b), advanced after every step with the fluid's
+ * AB2 weights (Euler on the first free-flight step) from the total force F
+ * and the torque m about x_cntr:  M u_cntr' = F - M g e_z,
+ * J Omega' + Omega x J Omega = M_body m, eps' = 1/2 S^T Omega.  M_body (global
+ * to body) is the transpose of the printed quaternion matrix; eps is
+ * renormalized after each step.  dof multiplies the acceleration rows
+ * (translation x, y, z; rotation about the body axes x, y, z; 1 on, 0 off).
+ * The first free-flight step of a state starts from the tethered kinematics
+ * at its time (x_cntr, u_cntr, eps of psi/beta/gamma at t, their Omega_b);
+ * a tethered step drops the free-flight state.  Requires a body or wings,
+ * mass > 0 and inertia > 0.  Wing kinematics stay prescribed relative to the
+ * body. */
 typedef struct {
     int body;            /* FLUSI_BODY_* */
     int wings;           /* 0: no wings; 1: left and right wing */
     int smooth;          /* FLUSI_SMOOTH_* */
-    int reserved;
+    int free_flight;     /* 0 tethered, 1 free flight */
     double c_smth;       /* smoothing half-width h = c_smth*dx */
     double x_cntr[3];
     double u_cntr[3];
@@ -100,6 +124,10 @@ typedef struct {
     double phi[3];       /* positional angle: mean, amplitude, phase */
     double alpha[3];     /* feathering angle */
     double theta[3];     /* deviation angle */
+    double mass;         /* free flight: M */
+    double inertia[3];   /* principal moments J_x, J_y, J_z about the body axes */
+    double gravity;      /* g, acting along -z of the global frame */
+    double dof[6];       /* 1/0: translation x, y, z; rotation about x_b, y_b, z_b */
 } flusi_insect;
 
 /* Controls of flusi_step (Algorithm 1 steps (a)-(e)). */
@@ -215,6 +243,19 @@ int flusi_step(flusi_plan plan, void* state, const flusi_insect* ins, const flus
  * on this state, copied to host memory (synchronous).  Returns
  * FLUSI_ENONFINITE if the state was stopped by a non-finite velocity. */
 int flusi_forces(flusi_plan plan, const void* state, double* out);
+
+/* Free-flight state of the current time level (Sec. 3.5): out[13] =
+ * x_cntr[3], u_cntr[3], eps[4], Omega_b^(b)[3] (host array; synchronous).
+ * Errors: EINVAL if the state has no free-flight body (never stepped in free
+ * flight, or last stepped tethered); ENONFINITE if it was stopped. */
+int flusi_state_solid(flusi_plan plan, const void* state, double* out);
+
+/* Set the free-flight state of the current time level from y[13] (host
+ * array, same layout); the next free-flight step starts from it with an
+ * Euler step (for restarts and prescribed initial rates).  The quaternion must
+ * have unit length (within 1e-12).  Enqueued on the plan's stream.  Errors:
+ * EINVAL. */
+int flusi_state_set_solid(flusi_plan plan, void* state, const double* y);
 
 /* Instrumentation.  While enabled, flusi_step brackets each pass it launches
  * with HIP events on the plan's stream.  Passes: 0 inverse z of the state at

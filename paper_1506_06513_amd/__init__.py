@@ -32,7 +32,7 @@ FLUSI_F32, FLUSI_F64 = 0, 1
 FLUSI_BODY_NONE, FLUSI_BODY_SPHERE, FLUSI_BODY_ELLIPSOID = 0, 1, 2
 FLUSI_SMOOTH_COS, FLUSI_SMOOTH_TANH = 0, 1
 FLUSI_MEAN_FIXED, FLUSI_MEAN_FREE = 0, 1
-FLUSI_NDIAG = 22
+FLUSI_NDIAG = 37
 FLUSI_NPASS = 6
 PASS_NAMES = ("z_inverse", "y_inverse", "x_pass", "scalar", "y_forward", "z_pass")
 SUPPORTED_N = (16, 24, 32, 48, 64, 96, 128, 192, 256, 384, 512)
@@ -46,7 +46,7 @@ class FlusiError(RuntimeError):
 
 class flusi_insect(ctypes.Structure):
     _fields_ = [
-        ("body", ctypes.c_int), ("wings", ctypes.c_int), ("smooth", ctypes.c_int), ("reserved", ctypes.c_int),
+        ("body", ctypes.c_int), ("wings", ctypes.c_int), ("smooth", ctypes.c_int), ("free_flight", ctypes.c_int),
         ("c_smth", ctypes.c_double),
         ("x_cntr", ctypes.c_double * 3), ("u_cntr", ctypes.c_double * 3),
         ("psi", ctypes.c_double), ("beta", ctypes.c_double), ("gamma", ctypes.c_double),
@@ -57,6 +57,8 @@ class flusi_insect(ctypes.Structure):
         ("wing_A", ctypes.c_double), ("wing_B", ctypes.c_double), ("wing_t", ctypes.c_double),
         ("freq", ctypes.c_double),
         ("phi", ctypes.c_double * 3), ("alpha", ctypes.c_double * 3), ("theta", ctypes.c_double * 3),
+        ("mass", ctypes.c_double), ("inertia", ctypes.c_double * 3), ("gravity", ctypes.c_double),
+        ("dof", ctypes.c_double * 6),
     ]
 
 
@@ -115,6 +117,8 @@ _SIGS = {
     "flusi_state_time": (ctypes.c_int, [_P, _P, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_longlong)]),
     "flusi_step": (ctypes.c_int, [_P, _P, ctypes.POINTER(flusi_insect), ctypes.POINTER(flusi_step_params)]),
     "flusi_forces": (ctypes.c_int, [_P, _P, ctypes.POINTER(ctypes.c_double)]),
+    "flusi_state_solid": (ctypes.c_int, [_P, _P, ctypes.POINTER(ctypes.c_double)]),
+    "flusi_state_set_solid": (ctypes.c_int, [_P, _P, ctypes.POINTER(ctypes.c_double)]),
     "flusi_profile": (ctypes.c_int, [_P, ctypes.c_int]),
     "flusi_pass_times": (ctypes.c_int, [_P, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_longlong)]),
     "flusi_plan_set_sponge": (ctypes.c_int, [_P, ctypes.c_double, ctypes.POINTER(ctypes.c_double)]),
@@ -265,6 +269,17 @@ def flusi_forces(plan, state):
     return rc, np.array(out[:])
 
 
+def flusi_state_solid(plan, state) -> np.ndarray:
+    out = (ctypes.c_double * 13)()
+    _check(lib().flusi_state_solid(plan, _ptr(state), out))
+    return np.array(out[:])
+
+
+def flusi_state_set_solid(plan, state, y):
+    v = (ctypes.c_double * 13)(*[float(x) for x in y])
+    _check(lib().flusi_state_set_solid(plan, _ptr(state), v))
+
+
 def flusi_profile(plan, enable: bool):
     _check(lib().flusi_profile(plan, 1 if enable else 0))
 
@@ -403,6 +418,11 @@ def make_insect(d: dict | None) -> flusi_insect | None:
     s.wings = 1 if d.get("wings", False) else 0
     s.smooth = _SMOOTH[d.get("smooth", "cos")]
     s.c_smth = float(d.get("c_smth", 1.0))
+    s.free_flight = 1 if d.get("free_flight", False) else 0
+    s.mass = float(d.get("mass", 1.0))
+    s.inertia[:] = [float(v) for v in d.get("inertia", (1.0, 1.0, 1.0))]
+    s.gravity = float(d.get("gravity", 0.0))
+    s.dof[:] = [float(v) for v in d.get("dof", (1.0,) * 6)]
     for k in ("x_cntr", "u_cntr", "pivot_l", "pivot_r", "phi", "alpha", "theta"):
         default = {"pivot_l": (0.0, 0.15, 0.0), "pivot_r": (0.0, -0.15, 0.0)}.get(k, (0.0, 0.0, 0.0))
         getattr(s, k)[:] = [float(v) for v in d.get(k, default)]
@@ -494,6 +514,13 @@ class Plan:
 
     def forces(self, state):
         return flusi_forces(self.handle, state)
+
+    def solid(self, state) -> np.ndarray:
+        """Free-flight state (x_cntr, u_cntr, eps, Omega_b) of the current time level."""
+        return flusi_state_solid(self.handle, state)
+
+    def set_solid(self, state, y):
+        flusi_state_set_solid(self.handle, state, y)
 
     def set_sponge(self, c_sp: float, thickness=(0.0, 0.0, 0.0)):
         """Vorticity sponge (layers at the top end of the axes with thickness > 0)."""

@@ -230,7 +230,7 @@ static int tune_group(ImplBase* impl, const GroupRun& g, PlanData& prof, int rep
 
 using namespace flusi;
 
-static_assert(sizeof(flusi_insect) == 16 + 8 * 36, "flusi_insect layout");
+static_assert(sizeof(flusi_insect) == 16 + 8 * 47, "flusi_insect layout");
 static_assert(sizeof(flusi_step_params) == 8 + 5 * 8 + 8, "flusi_step_params layout");
 
 extern "C" {
@@ -433,9 +433,40 @@ int flusi_state_time(flusi_plan plan, const void* state, double* t, long long* n
     return FLUSI_OK;
 }
 
+int flusi_state_solid(flusi_plan plan, const void* state, double* out) {
+    if (int rc = check_plan(plan)) return rc;
+    if (!state || !out) return set_error(FLUSI_EINVAL, "state_solid: null pointer");
+    StateHdr h;
+    hipError_t e = hipMemcpyAsync(&h, state, sizeof(StateHdr), hipMemcpyDeviceToHost, plan->d.stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(plan->d.stream);
+    if (e != hipSuccess) return set_error(FLUSI_EDEVICE, "state_solid: %s", hipGetErrorString(e));
+    if (h.status == FLUSI_ENONFINITE) return set_error(FLUSI_ENONFINITE, "velocity became non-finite");
+    if (h.status != 0) return set_error(h.status, "state stopped (status %d)", h.status);
+    const Slot& sl = h.slot[h.cur];
+    if (sl.ff_state != 1) return set_error(FLUSI_EINVAL, "state_solid: the state has no free-flight body");
+    std::memcpy(out, sl.ff, sizeof(sl.ff));
+    return FLUSI_OK;
+}
+
+int flusi_state_set_solid(flusi_plan plan, void* state, const double* y) {
+    if (int rc = check_plan(plan)) return rc;
+    if (!state || !y) return set_error(FLUSI_EINVAL, "state_set_solid: null pointer");
+    Solid13 v;
+    double q = 0.0;
+    for (int i = 0; i < 13; ++i) {
+        if (!std::isfinite(y[i])) return set_error(FLUSI_EINVAL, "state_set_solid: value %d not finite", i);
+        v.v[i] = y[i];
+    }
+    for (int i = 6; i < 10; ++i) q += y[i] * y[i];
+    if (std::fabs(q - 1.0) > 1e-12) return set_error(FLUSI_EINVAL, "state_set_solid: quaternion not of unit length");
+    k_solid_set<<<1, 64, 0, plan->d.stream>>>(static_cast<StateHdr*>(state), v);
+    return launch_check("state_set_solid");
+}
+
 int flusi_step(flusi_plan plan, void* state, const flusi_insect* ins, const flusi_step_params* p) {
     if (int rc = check_plan(plan)) return rc;
     if (!state || !p) return set_error(FLUSI_EINVAL, "step: null pointer");
+    if (int rc = check_insect(ins)) return rc;
     if (p->nsteps < 0) return set_error(FLUSI_EINVAL, "step: nsteps < 0");
     if (!(p->dt_fixed > 0.0) && !(p->cfl > 0.0)) return set_error(FLUSI_EINVAL, "step: need dt_fixed > 0 or cfl > 0");
     if (p->nsteps == 0) return FLUSI_OK;
@@ -475,6 +506,7 @@ int flusi_autotune(flusi_plan plan, const void* state, const flusi_insect* ins, 
     if (int rc = check_plan(plan)) return rc;
     if (!state || !p) return set_error(FLUSI_EINVAL, "autotune: null pointer");
     if (reps < 1) return set_error(FLUSI_EINVAL, "autotune: reps < 1");
+    if (int rc = check_insect(ins)) return rc;
     if (!(p->dt_fixed > 0.0) && !(p->cfl > 0.0)) return set_error(FLUSI_EINVAL, "autotune: need dt_fixed > 0 or cfl > 0");
     PlanData& d = plan->d;
     const size_t sb = d.impl->state_bytes();
@@ -497,6 +529,7 @@ int flusi_autotune(flusi_plan plan, const void* state, const flusi_insect* ins, 
         g.nmem = 1;
         g.n_nc[m.sponge][colour_slot(m.nc)] = 1;
         g.any_dyn = m.dyn != 0;
+        g.any_ff = m.ff != 0;
         g.tw = d.tw;
         g.stream = d.stream;
         rc = tune_group(d.impl, g, d, reps, &best);
@@ -547,6 +580,7 @@ int flusi_pass_times(flusi_plan plan, double* ms, long long* launches) {
 // Ensembles
 // ---------------------------------------------------------------------------
 namespace flusi {
+int insect_error(const flusi_insect* ins) { return check_insect(ins); }
 struct EnsMember {
     flusi_plan plan = nullptr;
     void* state = nullptr;
@@ -624,6 +658,7 @@ static int ens_rebuild(flusi_ensemble e) {
             host.push_back(rec);
             g.run.n_nc[rec.sponge][colour_slot(rec.nc)] += 1;
             g.run.any_dyn = g.run.any_dyn || rec.dyn;
+            g.run.any_ff = g.run.any_ff || rec.ff;
         }
         if (hipMalloc(&g.dev, host.size() * sizeof(Member)) != hipSuccess)
             return set_error(FLUSI_ENOMEM, "ensemble: member table");
@@ -717,6 +752,7 @@ int flusi_ensemble_add(flusi_ensemble e, flusi_plan plan, void* state, const flu
     if (!e) return set_error(FLUSI_EINVAL, "null ensemble");
     if (int rc = check_plan(plan)) return rc;
     if (!state || !p) return set_error(FLUSI_EINVAL, "ensemble_add: null pointer");
+    if (int rc = check_insect(ins)) return rc;
     if (plan->d.dtype != e->dtype) return set_error(FLUSI_EINVAL, "ensemble_add: plan dtype differs from the ensemble's");
     if (!(p->dt_fixed > 0.0) && !(p->cfl > 0.0)) return set_error(FLUSI_EINVAL, "ensemble_add: need dt_fixed > 0 or cfl > 0");
     for (const auto& m : e->members)

@@ -90,6 +90,7 @@ struct GroupRun {
     int nmem = 0;
     int n_nc[2][3] = {{0, 0, 0}, {0, 0, 0}};  // members [without, with sponge][nc = 0, 1, 3]
     bool any_dyn = false;
+    bool any_ff = false;      // some member is in free flight
     const void* tw = nullptr;
     Sched sched;
     hipStream_t stream = nullptr;
@@ -104,10 +105,12 @@ inline int colour_slot(int nc) { return nc == 0 ? 0 : (nc == 1 ? 1 : 2); }
 inline bool sponge_on(const PlanData& p) {
     return p.c_sp > 0.0 && (p.sp_thick[0] > 0.0 || p.sp_thick[1] > 0.0 || p.sp_thick[2] > 0.0);
 }
+inline int free_flight_on(const flusi_insect* ins) { return colour_count(ins) > 0 && ins->free_flight ? 1 : 0; }
 inline int kin_dynamic(const flusi_insect* ins) {
-    return colour_count(ins) > 0 &&
-           (ins->wings || ins->psi_dot != 0.0 || ins->beta_dot != 0.0 || ins->gamma_dot != 0.0);
+    return colour_count(ins) > 0 && (ins->wings || ins->free_flight || ins->psi_dot != 0.0 ||
+                                     ins->beta_dot != 0.0 || ins->gamma_dot != 0.0);
 }
+
 // Launch record of (plan, state) for a stepping call with parameters sp.
 inline Member make_member(const PlanData& p, void* st, const flusi_insect* ins, const flusi_step_params& sp) {
     Member m{};
@@ -129,6 +132,7 @@ inline Member make_member(const PlanData& p, void* st, const flusi_insect* ins, 
     m.nc = nc;
     m.dyn = kin_dynamic(ins);
     m.sponge = sponge_on(p) ? 1 : 0;
+    m.ff = free_flight_on(ins);
     m.inv_csp = m.sponge ? 1.0 / p.c_sp : 0.0;
     for (int a = 0; a < 3; ++a) m.sp_lo[a] = (m.sponge && p.sp_thick[a] > 0.0) ? p.L - p.sp_thick[a] : 1e300;
     return m;
@@ -137,6 +141,23 @@ enum { PASS_ZINV = 0, PASS_YINV = 1, PASS_X = 2, PASS_SCALAR = 3, PASS_YFWD = 4,
 
 int set_error(int code, const char* fmt, ...);
 int ensure_scratch(void** ptr, size_t* cur, size_t need, PlanData& p);
+
+// Checks the free-flight parameters of a body description (Sec. 3.5);
+// FLUSI_OK or FLUSI_EINVAL with a message.
+inline int check_insect(const flusi_insect* ins) {
+    if (!ins || !ins->free_flight) return FLUSI_OK;
+    if (ins->free_flight != 1) return set_error(FLUSI_EINVAL, "insect: free_flight must be 0 or 1");
+    if (colour_count(ins) == 0) return set_error(FLUSI_EINVAL, "insect: free flight needs a body or wings");
+    if (!(ins->mass > 0.0) || !std::isfinite(ins->mass)) return set_error(FLUSI_EINVAL, "insect: free flight needs mass > 0");
+    for (int i = 0; i < 3; ++i)
+        if (!(ins->inertia[i] > 0.0) || !std::isfinite(ins->inertia[i]))
+            return set_error(FLUSI_EINVAL, "insect: free flight needs inertia > 0");
+    if (!std::isfinite(ins->gravity)) return set_error(FLUSI_EINVAL, "insect: gravity not finite");
+    for (int i = 0; i < 6; ++i)
+        if (ins->dof[i] != 0.0 && ins->dof[i] != 1.0) return set_error(FLUSI_EINVAL, "insect: dof entries must be 0 or 1");
+    return FLUSI_OK;
+}
+
 
 struct ImplBase {
     virtual ~ImplBase() {}
@@ -433,6 +454,8 @@ struct Impl final : ImplBase {
                 zpass<MODE_INVERSE>(g);
             }
         }
+        // free flight: advance the body to the new current level
+        if (g.any_ff) k_kin_level<<<(unsigned)((g.nmem + 63) / 64), 64, 0, g.stream>>>(g.mt, g.nmem, nsteps & 1);
         return launch_check("step");
     }
 
@@ -476,6 +499,7 @@ struct Impl final : ImplBase {
         g.nmem = 1;
         g.n_nc[m.sponge][colour_slot(m.nc)] = 1;
         g.any_dyn = m.dyn != 0;
+        g.any_ff = m.ff != 0;
         g.tw = p.tw;
         g.sched = p.sched;
         g.stream = p.stream;

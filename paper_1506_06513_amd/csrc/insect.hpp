@@ -15,6 +15,7 @@ struct Kin {
     double xc[3];      // body centre
     double uc[3];      // body centre velocity
     double omb[3];     // body angular velocity, body frame
+    double eps[4];     // orientation quaternion (free-flight state, or of the body angles)
     double Mws[2][9];  // M_wing M_stroke for the left [0] and right [1] wing
     double piv[2][3];  // pivots, body frame
     double omw[2][3];  // wing angular velocities, body frame
@@ -71,30 +72,95 @@ __host__ __device__ inline void cross3(const double* a, const double* b, double*
     o[0] = x; o[1] = y; o[2] = z;
 }
 
-// Kinematics at time t (Sec. 3.1 and 3.3).  dx is the grid spacing.
-__host__ __device__ __forceinline__ void compute_kin(const flusi_insect& in, double t, double dx, Kin& k) {
-    const double psi = in.psi + in.psi_dot * t;
-    const double beta = in.beta + in.beta_dot * t;
-    const double gam = in.gamma + in.gamma_dot * t;
-    double Rx_[9], Ry_[9], Rz_[9], T1[9];
-    mat_rx(psi, Rx_);
-    mat_ry(beta, Ry_);
-    mat_rz(gam, Rz_);
-    mat_mul(Rx_, Ry_, T1);
-    mat_mul(T1, Rz_, k.Mb);
-    // body angular velocity: Rz^T[(0,0,gd) + Ry^T[(0,bd,0) + Rx^T (pd,0,0)]], then to body frame
-    double v[3] = {in.psi_dot, 0.0, 0.0}, w[3];
-    mat_tvec(Rx_, v, w);
-    w[1] += in.beta_dot;
-    mat_tvec(Ry_, w, v);
-    v[2] += in.gamma_dot;
-    mat_tvec(Rz_, v, w);
-    mat_vec(k.Mb, w, k.omb);
-    for (int i = 0; i < 3; ++i) {
-        k.xc[i] = in.x_cntr[i];
-        k.uc[i] = in.u_cntr[i];
-        k.xref[0][i] = in.x_cntr[i];
+// M_body (global to body) of a unit quaternion: the transpose of the matrix
+// the free-flight section prints, which maps body vectors to the global frame
+// (Sec. 3.5).
+__host__ __device__ inline void quat_mbody(const double* e, double* M) {
+    const double e0 = e[0], e1 = e[1], e2 = e[2], e3 = e[3];
+    M[0] = e0 * e0 + e1 * e1 - e2 * e2 - e3 * e3;
+    M[1] = 2.0 * (e1 * e2 + e3 * e0);
+    M[2] = 2.0 * (e1 * e3 - e2 * e0);
+    M[3] = 2.0 * (e1 * e2 - e3 * e0);
+    M[4] = e0 * e0 - e1 * e1 + e2 * e2 - e3 * e3;
+    M[5] = 2.0 * (e2 * e3 + e1 * e0);
+    M[6] = 2.0 * (e1 * e3 + e2 * e0);
+    M[7] = 2.0 * (e2 * e3 - e1 * e0);
+    M[8] = e0 * e0 - e1 * e1 - e2 * e2 + e3 * e3;
+}
+
+// Quaternion of roll psi, pitch beta, yaw gamma (Sec. 3.5).
+__host__ __device__ inline void quat_of_angles(double psi, double beta, double gam, double* e) {
+    const double cp = cos(0.5 * psi), sp = sin(0.5 * psi);
+    const double cb = cos(0.5 * beta), sb = sin(0.5 * beta);
+    const double cg = cos(0.5 * gam), sg = sin(0.5 * gam);
+    e[0] = cp * cb * cg + sp * sb * sg;
+    e[1] = sp * cb * cg - cp * sb * sg;
+    e[2] = cp * sb * cg + sp * cb * sg;
+    e[3] = cp * cb * sg - sp * sb * cg;
+}
+
+// Right-hand side of the 13 free-flight equations (Sec. 3.5, eq.
+// oh_my_god_look_a_vector).  y: x_cntr, u_cntr, eps, Omega^(b); F: total force
+// and m: torque about x_cntr, both in the global frame.
+__host__ __device__ inline void solid_rhs(const flusi_insect& in, const double* y, const double* F,
+                                          const double* m, double* f) {
+    double Mb[9], mb[3];
+    quat_mbody(y + 6, Mb);
+    mat_vec(Mb, m, mb);
+    const double e0 = y[6], e1 = y[7], e2 = y[8], e3 = y[9];
+    const double ox = y[10], oy = y[11], oz = y[12];
+    const double Jx = in.inertia[0], Jy = in.inertia[1], Jz = in.inertia[2];
+    for (int i = 0; i < 3; ++i) f[i] = y[3 + i];
+    f[3] = F[0] / in.mass * in.dof[0];
+    f[4] = F[1] / in.mass * in.dof[1];
+    f[5] = (F[2] / in.mass - in.gravity) * in.dof[2];
+    f[6] = 0.5 * (-e1 * ox - e2 * oy - e3 * oz);
+    f[7] = 0.5 * (e0 * ox - e3 * oy + e2 * oz);
+    f[8] = 0.5 * (e3 * ox + e0 * oy - e1 * oz);
+    f[9] = 0.5 * (-e2 * ox + e1 * oy + e0 * oz);
+    f[10] = ((Jy - Jz) * oy * oz + mb[0]) / Jx * in.dof[3];
+    f[11] = ((Jz - Jx) * oz * ox + mb[1]) / Jy * in.dof[4];
+    f[12] = ((Jx - Jy) * ox * oy + mb[2]) / Jz * in.dof[5];
+}
+
+// Kinematics at time t (Sec. 3.1 and 3.3).  dx is the grid spacing.  pose
+// (13 values: x_cntr, u_cntr, eps, Omega^(b)) replaces the prescribed body
+// motion in free flight (Sec. 3.5); null for a tethered body.
+__host__ __device__ __forceinline__ void compute_kin(const flusi_insect& in, double t, double dx, Kin& k,
+                                                     const double* pose = nullptr) {
+    if (pose) {
+        for (int i = 0; i < 3; ++i) {
+            k.xc[i] = pose[i];
+            k.uc[i] = pose[3 + i];
+            k.omb[i] = pose[10 + i];
+        }
+        for (int i = 0; i < 4; ++i) k.eps[i] = pose[6 + i];
+        quat_mbody(pose + 6, k.Mb);
+    } else {
+        const double psi = in.psi + in.psi_dot * t;
+        const double beta = in.beta + in.beta_dot * t;
+        const double gam = in.gamma + in.gamma_dot * t;
+        double Rx_[9], Ry_[9], Rz_[9], T1[9];
+        mat_rx(psi, Rx_);
+        mat_ry(beta, Ry_);
+        mat_rz(gam, Rz_);
+        mat_mul(Rx_, Ry_, T1);
+        mat_mul(T1, Rz_, k.Mb);
+        // body angular velocity: Rz^T[(0,0,gd) + Ry^T[(0,bd,0) + Rx^T (pd,0,0)]], then to body frame
+        double v[3] = {in.psi_dot, 0.0, 0.0}, w[3];
+        mat_tvec(Rx_, v, w);
+        w[1] += in.beta_dot;
+        mat_tvec(Ry_, w, v);
+        v[2] += in.gamma_dot;
+        mat_tvec(Rz_, v, w);
+        mat_vec(k.Mb, w, k.omb);
+        quat_of_angles(psi, beta, gam, k.eps);
+        for (int i = 0; i < 3; ++i) {
+            k.xc[i] = in.x_cntr[i];
+            k.uc[i] = in.u_cntr[i];
+        }
     }
+    for (int i = 0; i < 3; ++i) k.xref[0][i] = k.xc[i];
     k.body = in.body;
     k.wings = in.wings;
     k.smooth = in.smooth;
@@ -144,7 +210,7 @@ __host__ __device__ __forceinline__ void compute_kin(const flusi_insect& in, dou
         for (int i = 0; i < 3; ++i) k.piv[s][i] = pv[i];
         double pg[3];
         mat_tvec(k.Mb, pv, pg);
-        for (int i = 0; i < 3; ++i) k.xref[1 + s][i] = in.x_cntr[i] + pg[i];
+        for (int i = 0; i < 3; ++i) k.xref[1 + s][i] = k.xc[i] + pg[i];
         if (in.wings) {
             const double mab = fmax(in.wing_A, in.wing_B);
             const double e1 = mab + k.thr, e2 = 0.5 * in.wing_t + k.thr;

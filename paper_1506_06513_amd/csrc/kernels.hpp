@@ -98,6 +98,10 @@ __device__ __forceinline__ void stage_twiddles(cx<T>* tws, const cx<T>* __restri
     for (int e = threadIdx.x; e < N; e += nthreads) tws[e] = tw[e];
 }
 
+struct Solid13 {
+    double v[13];
+};
+
 struct StepCtl {
     double dt_fixed, cfl, dt_max, eta_cap, t_end;
     int masked, mean_mode, kin_dynamic, pad;
@@ -111,6 +115,17 @@ struct Slot {
     int have_prev;   // previous right-hand side stored
     int have_I;      // previous solid-momentum integral stored
     double I_prev[3][6];
+    double J_prev[3];  // moment of the solid momentum about the body centre (with have_I)
+    // Free flight (Sec. 3.5).  ff_state: 0 none; 1 ff is the state at t;
+    // 2 ff is the state of the previous level and still has to be advanced
+    // by ff_w[0]*f(ff; ff_F, ff_m) + ff_w[1]*ff_f (done before the level's
+    // kinematics are evaluated).
+    int ff_state;
+    int ff_have_prev;  // ff_f holds the right-hand side of the previous step
+    double ff[13];     // x_cntr, u_cntr, eps, Omega^(b)
+    double ff_f[13];
+    double ff_F[3], ff_m[3];  // total force and torque about x_cntr (global frame)
+    double ff_w[2];           // dt*b1, dt*b2
 };
 
 // Device-resident per-state scalars (first 4 KiB of a state buffer).  The time
@@ -149,6 +164,7 @@ struct Member {
     int nc;                     // colours of the mask: 0 (none), 1 (body), 3 (body + wings)
     int dyn;                    // kinematics change with time
     int sponge;                 // vorticity sponge on: 3 more forward fields (chi_sp w)
+    int ff;                     // free flight: the body pose is integrated
     double inv_csp;             // 1/C_sp
     double sp_lo[3];            // chi_sp = 1 where x_a >= sp_lo[a] for some axis a
 };
@@ -700,9 +716,15 @@ __device__ inline Coef step_coef(const double* tot, const Slot& sl, StepCtl ctl,
     return c;
 }
 
-// Diagnostics of time level p and the next time level (one thread).
+// Diagnostics of time level p and the next time level (one thread).  With a
+// mask: the body's state at t^n and the wings' aerodynamic power (Sec. 3.5),
+// the moment of the solid momentum about the body centre for the next step's
+// unsteady torque term, and in free flight the total force and torque about
+// x_cntr that advance the body (the advance itself runs with the next
+// level's kinematics).  Values go to memory as they are formed and the loops
+// over parts stay rolled: this code shares the z-pass kernel's registers.
 __device__ inline void write_step(StateHdr* h, int p, const double* tot, const Coef& c, StepCtl ctl, double dx,
-                                  double eta, double* history) {
+                                  double eta, double* history, int ff) {
     const Slot& sl = h->slot[p];
     Slot& nx = h->slot[1 - p];
     if (c.bad) {
@@ -710,28 +732,105 @@ __device__ inline void write_step(StateHdr* h, int p, const double* tot, const C
         return;
     }
     const double dV = dx * dx * dx;
-    double d[FLUSI_NDIAG];
-    d[0] = sl.t;
-    d[1] = c.dt;
-    d[2] = c.umax;
-    d[3] = c.E;
-    for (int k = 0; k < 3; ++k) {
+    double* dg = h->diag;
+    const auto put = [&](int i, double v) {
+        dg[i] = v;
+        if (history) history[i] = v;
+    };
+    put(0, sl.t);
+    put(1, c.dt);
+    put(2, c.umax);
+    put(3, c.E);
+    const bool corr = sl.have_I && sl.dt_prev > 0.0;
+    // force (i < 3) or torque (i >= 3) on part k, with the unsteady term
+    const auto part = [&](int k, int i) {
         const double* a = tot + 3 + 12 * k;
-        for (int i = 0; i < 6; ++i) {
-            double v = a[i] * dV / eta;
-            if (sl.have_I && sl.dt_prev > 0.0) v += (a[6 + i] * dV - sl.I_prev[k][i]) / sl.dt_prev;
-            d[4 + 6 * k + i] = v;
+        double v = a[i] * dV / eta;
+        if (corr) v += (a[6 + i] * dV - sl.I_prev[k][i]) / sl.dt_prev;
+        return v;
+    };
+#pragma unroll 1
+    for (int k = 0; k < 3; ++k)
+#pragma unroll 1
+        for (int i = 0; i < 6; ++i) put(4 + 6 * k + i, part(k, i));
+#pragma unroll 1
+    for (int i = 22; i < FLUSI_NDIAG; ++i) put(i, 0.0);
+    double J[3] = {0.0, 0.0, 0.0}, Ft[3] = {0.0, 0.0, 0.0}, mt[3] = {0.0, 0.0, 0.0};
+    if (ctl.masked) {
+        const Kin& K = h->kin;
+#pragma unroll 1
+        for (int i = 0; i < 3; ++i) {
+            put(22 + i, K.xc[i]);
+            put(25 + i, K.uc[i]);
+            put(32 + i, K.omb[i]);
         }
+#pragma unroll 1
+        for (int i = 0; i < 4; ++i) put(28 + i, K.eps[i]);
+        if (K.wings) {
+#pragma unroll 1
+            for (int s = 0; s < 2; ++s) {
+                double wg[3];
+                mat_tvec(K.Mb, K.omw[s], wg);
+                put(35 + s, -(part(1 + s, 3) * wg[0] + part(1 + s, 4) * wg[1] + part(1 + s, 5) * wg[2]));
+            }
+        }
+        // moments about x_cntr: part sums moved from each part's reference point
+#pragma unroll 1
+        for (int k = 0; k < 3; ++k) {
+            const double* a = tot + 3 + 12 * k;
+            double r[3], F[3], IF[3], t1[3], t2[3];
+            for (int i = 0; i < 3; ++i) {
+                r[i] = K.xref[k][i] - K.xc[i];
+                F[i] = a[i] * dV / eta;
+                IF[i] = a[6 + i] * dV;
+                Ft[i] += part(k, i);
+            }
+            cross3(r, F, t1);
+            cross3(r, IF, t2);
+            for (int i = 0; i < 3; ++i) {
+                mt[i] += a[3 + i] * dV / eta + t1[i];
+                J[i] += a[9 + i] * dV + t2[i];
+            }
+        }
+        if (corr)
+            for (int i = 0; i < 3; ++i) mt[i] += (J[i] - sl.J_prev[i]) / sl.dt_prev;
     }
-    for (int i = 0; i < FLUSI_NDIAG; ++i) h->diag[i] = d[i];
-    if (history)
-        for (int i = 0; i < FLUSI_NDIAG; ++i) history[i] = d[i];
-    nx = sl;
+    {
+        static_assert(sizeof(Slot) % 8 == 0, "slot copy by words");
+        const double* src = reinterpret_cast<const double*>(&sl);
+        double* dst = reinterpret_cast<double*>(&nx);
+#pragma unroll 1
+        for (int i = 0; i < (int)(sizeof(Slot) / 8); ++i) dst[i] = src[i];
+    }
     if (c.active) {
         if (ctl.masked) {
+#pragma unroll 1
             for (int k = 0; k < 3; ++k)
+#pragma unroll 1
                 for (int i = 0; i < 6; ++i) nx.I_prev[k][i] = tot[3 + 12 * k + 6 + i] * dV;
+            for (int i = 0; i < 3; ++i) nx.J_prev[i] = J[i];
             nx.have_I = 1;
+        } else {
+            nx.have_I = 0;
+        }
+        if (ff) {
+            // AB2 weights of the body (Euler on its first step)
+            double b1 = 1.0, b2 = 0.0;
+            if (sl.ff_have_prev) {
+                const double r = c.dt / sl.dt_prev;
+                b1 = 1.0 + 0.5 * r;
+                b2 = -0.5 * r;
+            }
+            nx.ff_w[0] = c.dt * b1;
+            nx.ff_w[1] = c.dt * b2;
+            for (int i = 0; i < 3; ++i) {
+                nx.ff_F[i] = Ft[i];
+                nx.ff_m[i] = mt[i];
+            }
+            nx.ff_state = 2;
+        } else {
+            nx.ff_state = 0;
+            nx.ff_have_prev = 0;
         }
         nx.have_prev = 1;
         nx.dt_prev = c.dt;
@@ -819,19 +918,64 @@ __device__ inline void reduce_level2(const double* __restrict__ partial2, double
     __syncthreads();
 }
 
-// Kinematics of member m at time t and its mask-evaluation blocks (one
+// Kinematics of time level p of member m and its mask-evaluation blocks (one
 // thread).  Everything is computed in registers from a register copy of the
 // body description and stored once: interleaving loads of the description and
 // stores of the block in global memory would serialize on memory round trips.
-__device__ __forceinline__ void kin_update(const Member& m, double t) {
+// In free flight the body pose is the free-flight state of the level: taken
+// from the tethered kinematics on the first free-flight step, or advanced by
+// the AB2 step that the previous step's diagnostics left pending (Alg. 1 step
+// (f); the quaternion is renormalized).
+__device__ __forceinline__ void kin_update(const Member& m, int p) {
     const flusi_insect in = *m.ins;
+    StateHdr* h = m.hdr;
+    Slot& sl = h->slot[p];
+    const double t = sl.t;
     Kin k;
-    compute_kin(in, t, m.dx, k);
+    if (!in.free_flight) {
+        compute_kin(in, t, m.dx, k);
+    } else {
+        const int st = sl.ff_state;
+        double y[13];
+        if (st == 0) {
+            compute_kin(in, t, m.dx, k);
+            for (int i = 0; i < 3; ++i) {
+                y[i] = k.xc[i];
+                y[3 + i] = k.uc[i];
+                y[10 + i] = k.omb[i];
+            }
+            for (int i = 0; i < 4; ++i) y[6 + i] = k.eps[i];
+            for (int i = 0; i < 13; ++i) sl.ff[i] = y[i];
+            sl.ff_have_prev = 0;
+        } else {
+            for (int i = 0; i < 13; ++i) y[i] = sl.ff[i];
+            if (st == 2) {
+                double F[3], mm[3], f[13], fp[13];
+                for (int i = 0; i < 3; ++i) {
+                    F[i] = sl.ff_F[i];
+                    mm[i] = sl.ff_m[i];
+                }
+                const double w0 = sl.ff_w[0], w1 = sl.ff_w[1];
+                const int hp = sl.ff_have_prev;
+                for (int i = 0; i < 13; ++i) fp[i] = sl.ff_f[i];
+                solid_rhs(in, y, F, mm, f);
+                for (int i = 0; i < 13; ++i) y[i] += hp ? w0 * f[i] + w1 * fp[i] : w0 * f[i];
+                const double q = 1.0 / sqrt(y[6] * y[6] + y[7] * y[7] + y[8] * y[8] + y[9] * y[9]);
+                for (int i = 6; i < 10; ++i) y[i] *= q;
+                for (int i = 0; i < 13; ++i) {
+                    sl.ff[i] = y[i];
+                    sl.ff_f[i] = f[i];
+                }
+                sl.ff_have_prev = 1;
+            }
+            compute_kin(in, t, m.dx, k, y);
+        }
+        sl.ff_state = 1;
+    }
     KinT<float> kf;
     KinT<double> kd;
     kin_cast<float>(k, kf);
     kin_cast<double>(k, kd);
-    StateHdr* h = m.hdr;
     h->kin = k;
     h->kf = kf;
     h->kd = kd;
@@ -848,16 +992,27 @@ static __global__ __launch_bounds__(64) void k_prologue(const Member* __restrict
         hdr->slot[0] = hdr->slot[1];
         hdr->cur = 0;
     }
-    if (m.nc > 0) kin_update(m, hdr->slot[0].t);
+    if (m.nc > 0 && !hdr->status) kin_update(m, 0);
 }
 
 // Kinematics of time level p of every member whose kinematics change with
-// time (one thread per member), before the pass that reads them.
+// time (one thread per member), before the pass that reads them; after the
+// last step of a call it completes the pending free-flight advance.
 static __global__ __launch_bounds__(64) void k_kin_level(const Member* __restrict__ mt, int nmem, int p) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= nmem) return;
     const Member& m = mt[i];
-    if (m.dyn && !m.hdr->status) kin_update(m, m.hdr->slot[p].t);
+    if (m.dyn && !m.hdr->status) kin_update(m, p);
+}
+
+// Free-flight state of the current time level of a state (one thread).
+static __global__ void k_solid_set(StateHdr* h, Solid13 y) {
+    if (threadIdx.x == 0 && blockIdx.x == 0) {
+        Slot& sl = h->slot[h->cur];
+        for (int i = 0; i < 13; ++i) sl.ff[i] = y.v[i];
+        sl.ff_state = 1;
+        sl.ff_have_prev = 0;
+    }
 }
 
 // Writes the launch record of a single plan (and the device copy of its body
@@ -950,7 +1105,8 @@ __global__ __launch_bounds__(nt_z(N, V)) void k_zpass(const Member* __restrict__
         if (tid == 0) {
             cf = step_coef(tot, hdr->slot[par], mb.ctl, dx, eta);
             if (tile == 0)
-                write_step(hdr, par, tot, cf, mb.ctl, dx, eta, mb.history ? mb.history + (long)s * FLUSI_NDIAG : nullptr);
+                write_step(hdr, par, tot, cf, mb.ctl, dx, eta, mb.history ? mb.history + (long)s * FLUSI_NDIAG : nullptr,
+                           mb.ff);
         }
         __syncthreads();
         if (cf.bad) return;

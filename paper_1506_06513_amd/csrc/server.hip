@@ -18,7 +18,9 @@
 
 namespace flusi {
 int set_error(int code, const char* fmt, ...);
+int insect_error(const flusi_insect* ins);
 }
+using flusi::insect_error;
 using flusi::set_error;
 
 namespace {
@@ -257,6 +259,8 @@ int flusi_server_submit(flusi_server s, const flusi_request* r, long long* id) {
     if (!(r->L > 0.0) || !(r->nu >= 0.0) || !(r->eta > 0.0) || r->p.nsteps < 0)
         return set_error(FLUSI_EINVAL, "server_submit: need L > 0, nu >= 0, eta > 0, nsteps >= 0");
     if (!(r->p.dt_fixed > 0.0) && !(r->p.cfl > 0.0)) return set_error(FLUSI_EINVAL, "server_submit: need dt_fixed > 0 or cfl > 0");
+    if (r->has_insect)
+        if (int rc = insect_error(&r->ins)) return rc;
     const size_t bytes = flusi_request_bytes(r->n, s->dtype);
     if (!bytes) return set_error(FLUSI_EUNSUPPORTED, "server_submit: grid size %d not supported", r->n);
     if (bytes > s->budget)

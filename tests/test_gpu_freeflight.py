@@ -1,0 +1,226 @@
+"""Free flight (Sec. 3.5, eq. oh_my_god_look_a_vector) and the aerodynamic power
+(eq. insect_power) on the GPU against the FP64 oracle; restarts, mode
+switches, chunked calls, ensembles and served requests against solo runs."""
+import math
+
+import numpy as np
+import pytest
+import torch
+
+import oracle as O
+import paper_1506_06513_amd as F
+import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+L = 4.0
+SPHERE_VOL = 4.0 / 3.0 * math.pi * 0.5 ** 3
+
+
+@pytest.fixture(autouse=True)
+def _announce(request):
+    print(f"\n[gpu case] {request.node.name}", flush=True)
+    yield
+    torch.cuda.synchronize()
+
+
+def rel_l2(a, b):
+    return float(np.linalg.norm((np.asarray(a) - np.asarray(b)).ravel()) / np.linalg.norm(np.asarray(b).ravel()))
+
+
+def falling_sphere(**kw):
+    d = W.sphere_body(L)
+    d.update(free_flight=True, mass=2.0 * SPHERE_VOL, inertia=(0.1, 0.1, 0.1), gravity=1.0,
+             u_cntr=(0.3, 0.0, 0.0), dof=(1, 1, 1, 0, 0, 0))
+    d.update(kw)
+    return d
+
+
+def free_insect(n, **kw):
+    d = W.model_insect(n, L)
+    d.update(free_flight=True, mass=0.05, inertia=(2e-3, 3e-3, 3e-3), gravity=0.5)
+    d.update(kw)
+    return d
+
+
+def _oracle_run(n, nu, eta, u0, schedule, ctl, mean_mode=O.MEAN_FIXED, solid0=None):
+    """schedule: list of (insect dict, nsteps).  Returns state and diagnostics."""
+    p = O.Params(n, L, nu, eta, mean_mode)
+    st = O.init_state(p, u0)
+    if solid0 is not None:
+        st.solid = np.asarray(solid0, dtype=np.float64)
+    hist = []
+    for body, k in schedule:
+        ins = O.Insect.from_dict(body)
+        for _ in range(k):
+            st, d = O.step(p, st, O.StepControl(**ctl), ins)
+            hist.append(d)
+    return p, st, hist
+
+
+def _gpu_run(n, nu, eta, u0, schedule, ctl, dtype, mean_mode=F.FLUSI_MEAN_FIXED, solid0=None):
+    P = F.Plan(n, L, nu, eta, dtype)
+    st = P.new_state(torch.from_numpy(u0))
+    if solid0 is not None:
+        P.set_solid(st, solid0)
+    hs = []
+    for body, k in schedule:
+        hs.append(P.step(st, k, body, history=True, mean_mode=mean_mode, **ctl).cpu().numpy())
+    return P, st, np.concatenate(hs)
+
+
+def _pose_hist(oh):
+    return np.array([d["pose"] for d in oh])
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+def test_falling_sphere_matches_oracle(dtype):
+    n, nu, eta, steps = 48, 0.02, 1e-3, 20
+    u0 = W.inflow_noise(n, L, seed=21, rms=1e-2, kmax=6.0) * 0.0
+    body = falling_sphere()
+    ctl = dict(cfl=0.1, eta_cap=0.5)
+    p, ost, oh = _oracle_run(n, nu, eta, u0, [(body, steps)], ctl)
+    P, st, h = _gpu_run(n, nu, eta, u0, [(body, steps)], ctl, dtype)
+    tol = 1e-11 if dtype == "f64" else 2e-5
+    assert rel_l2(P.velocity(st).cpu().numpy(), O.velocity(p, ost)) < tol
+    y, oy = P.solid(st), ost.solid
+    assert np.max(np.abs(y - oy)) < (1e-12 if dtype == "f64" else 2e-6) * max(1.0, np.max(np.abs(oy)))
+    ph = _pose_hist(oh)
+    assert np.max(np.abs(h[:, 22:35] - ph)) < (1e-12 if dtype == "f64" else 2e-6) * np.max(np.abs(ph))
+    oF = np.array([d["F"][0] for d in oh])
+    assert np.max(np.abs(h[:, 4:7] - oF)) <= (1e-10 if dtype == "f64" else 1e-4) * np.max(np.abs(oF))
+    # it fell and was slowed: z velocity negative, x velocity below its start
+    assert oy[5] < 0.0 and 0.0 < oy[3] < 0.3
+
+
+def test_free_insect_all_dofs_matches_oracle():
+    n, nu, eta, steps = 48, 1 / 136, 5e-4, 8
+    u0 = W.inflow_noise(n, L, seed=22, rms=1e-2, kmax=6.0)
+    body = free_insect(n)
+    ctl = dict(cfl=0.1)
+    p, ost, oh = _oracle_run(n, nu, eta, u0, [(body, steps)], ctl)
+    P, st, h = _gpu_run(n, nu, eta, u0, [(body, steps)], ctl, "f64")
+    assert rel_l2(P.velocity(st).cpu().numpy(), O.velocity(p, ost)) < 1e-11
+    y, oy = P.solid(st), ost.solid
+    assert np.max(np.abs(y - oy)) < 1e-11 * max(1.0, np.max(np.abs(oy)))
+    ph = _pose_hist(oh)
+    assert np.max(np.abs(h[:, 22:35] - ph)) < 1e-11 * np.max(np.abs(ph))
+    for c in range(3):
+        oF = np.array([d["F"][c] for d in oh])
+        oM = np.array([d["M"][c] for d in oh])
+        assert np.max(np.abs(h[:, 4 + 6 * c:7 + 6 * c] - oF)) <= 1e-9 * max(1e-12, np.max(np.abs(oF))), c
+        assert np.max(np.abs(h[:, 7 + 6 * c:10 + 6 * c] - oM)) <= 1e-9 * max(1e-12, np.max(np.abs(oM))), c
+    oP = np.array([d["P_aero"] for d in oh])
+    assert np.max(np.abs(h[:, 35:37] - oP)) <= 1e-9 * np.max(np.abs(oP))
+    # the body rotated and moved
+    assert np.max(np.abs(oy[10:13])) > 0.0 and np.max(np.abs(oy[3:6])) > 0.0
+
+
+def test_tethered_record_pose_and_power_match_oracle():
+    n, nu, eta, steps = 48, 1 / 136, 5e-4, 4
+    u0 = W.inflow_noise(n, L, seed=23, rms=1e-2, kmax=6.0)
+    body = W.model_insect(n, L)
+    body.update(psi=0.1, beta_dot=0.4, u_cntr=(0.1, 0.0, 0.0))
+    ctl = dict(cfl=0.1)
+    p, ost, oh = _oracle_run(n, nu, eta, u0, [(body, steps)], ctl)
+    P, st, h = _gpu_run(n, nu, eta, u0, [(body, steps)], ctl, "f64")
+    ph = _pose_hist(oh)
+    assert np.max(np.abs(h[:, 22:35] - ph)) < 1e-14 * np.max(np.abs(ph))
+    oP = np.array([d["P_aero"] for d in oh])
+    assert np.max(np.abs(h[:, 35:37] - oP)) <= 1e-9 * np.max(np.abs(oP))
+    with pytest.raises(F.FlusiError) as e:
+        P.solid(st)
+    assert e.value.code == F.FLUSI_EINVAL
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+def test_spinning_sphere_from_a_set_state(dtype):
+    n, nu, eta, steps = 48, 0.05, 1e-2, 10
+    body = falling_sphere(gamma=math.pi / 2, inertia=(2.0, 2.0, 2.0), gravity=0.0, u_cntr=(0.0, 0.0, 0.0),
+                          dof=(0, 0, 0, 1, 1, 1), smooth="cos")
+    y0 = O.solid_init(O.Insect.from_dict(body), 0.0)
+    y0[10:13] = (2.0, 0.0, 0.0)
+    u0 = np.zeros((3, n, n, n))
+    ctl = dict(cfl=0.1, dt_max=2e-3)
+    p, ost, oh = _oracle_run(n, nu, eta, u0, [(body, steps)], ctl, solid0=y0)
+    P, st, h = _gpu_run(n, nu, eta, u0, [(body, steps)], ctl, dtype, solid0=y0)
+    y = P.solid(st)
+    assert np.max(np.abs(y - ost.solid)) < (1e-12 if dtype == "f64" else 2e-6) * 2.0
+    assert 1.5 < y[10] < 2.0  # spun down about its own axis
+    assert rel_l2(P.velocity(st).cpu().numpy(), O.velocity(p, ost)) < (1e-11 if dtype == "f64" else 2e-5)
+
+
+def test_mode_switches_match_oracle():
+    """tethered -> free -> tethered -> free: each free phase restarts from the
+    tethered kinematics at its time; the unsteady torque term carries over."""
+    n, nu, eta = 48, 0.02, 1e-3
+    u0 = W.inflow_noise(n, L, seed=24, rms=1e-2, kmax=6.0)
+    free = falling_sphere(u_cntr=(0.2, 0.1, 0.0), dof=(1, 1, 1, 1, 1, 1))
+    teth = dict(free, free_flight=False)
+    sched = [(teth, 3), (free, 3), (teth, 2), (free, 3)]
+    ctl = dict(cfl=0.1)
+    p, ost, oh = _oracle_run(n, nu, eta, u0, sched, ctl)
+    P, st, h = _gpu_run(n, nu, eta, u0, sched, ctl, "f64")
+    assert rel_l2(P.velocity(st).cpu().numpy(), O.velocity(p, ost)) < 1e-11
+    assert np.max(np.abs(P.solid(st) - ost.solid)) < 1e-12 * max(1.0, np.max(np.abs(ost.solid)))
+    ph = _pose_hist(oh)
+    assert np.max(np.abs(h[:, 22:35] - ph)) < 1e-12 * np.max(np.abs(ph))
+
+
+def test_chunked_calls_equal_one_call():
+    n = 48
+    u0 = W.inflow_noise(n, L, seed=25, rms=1e-2, kmax=6.0)
+    body = free_insect(n)
+    Pa, Pb = F.Plan(n, L, 0.01, 1e-3, "f32"), F.Plan(n, L, 0.01, 1e-3, "f32")
+    a, b = Pa.new_state(torch.from_numpy(u0)), Pb.new_state(torch.from_numpy(u0))
+    Pa.step(a, 6, body, cfl=0.1)
+    for _ in range(3):
+        Pb.step(b, 2, body, cfl=0.1)
+    assert torch.equal(Pa.uhat(a), Pb.uhat(b))
+    assert np.array_equal(Pa.solid(a), Pb.solid(b))
+
+
+def test_free_flight_in_ensemble_and_server_equals_solo():
+    specs = [(48, free_insect(48)), (32, falling_sphere()), (48, W.sphere_body(L)), (32, free_insect(32))]
+    ens = F.Ensemble("f32")
+    pairs = []
+    for k, (n, body) in enumerate(specs):
+        u0 = W.inflow_noise(n, L, seed=30 + k, rms=1e-2, kmax=6.0)
+        Pa, Pb = F.Plan(n, L, 0.01, 1e-3, "f32"), F.Plan(n, L, 0.01, 1e-3, "f32")
+        sa, sb = Pa.new_state(torch.from_numpy(u0)), Pb.new_state(torch.from_numpy(u0))
+        ens.add(Pa, sa, body, cfl=0.1)
+        pairs.append((Pa, sa, Pb, sb, body, u0))
+    ens.step(3, graph=True)
+    ens.step(2)
+    for Pa, sa, Pb, sb, body, _ in pairs:
+        Pb.step(sb, 5, body, cfl=0.1)
+    torch.cuda.synchronize()
+    for i, (Pa, sa, Pb, sb, body, _) in enumerate(pairs):
+        assert torch.equal(Pa.uhat(sa), Pb.uhat(sb)), i
+        if body.get("free_flight"):
+            assert np.array_equal(Pa.solid(sa), Pb.solid(sb)), i
+    ens.close()
+    srv = F.Server("f32", hbm_budget=2 << 30, max_chunk=2)
+    Pa, sa, Pb, sb, body, u0 = pairs[0]
+    rid = srv.submit(48, L, 0.01, 1e-3, 5, body, u0, cfl=0.1)
+    rc, us, diag, _ = srv.wait(rid)
+    srv.close()
+    assert rc == 0 and np.array_equal(us, Pb.velocity(sb).cpu().numpy())
+    _, dsolo = Pb.forces(sb)
+    assert np.array_equal(diag, dsolo)
+
+
+def test_invalid_free_flight_parameters_are_rejected():
+    n = 32
+    P = F.Plan(n, L, 0.01, 1e-3, "f32")
+    st = P.new_state(torch.zeros((3, n, n, n)))
+    bad = [falling_sphere(mass=0.0), falling_sphere(inertia=(1.0, -1.0, 1.0)), falling_sphere(dof=(1, 0.5, 1, 0, 0, 0)),
+           dict(falling_sphere(), body="none"), falling_sphere(gravity=math.inf)]
+    for body in bad:
+        with pytest.raises(F.FlusiError) as e:
+            P.step(st, 1, body, cfl=0.1)
+        assert e.value.code == F.FLUSI_EINVAL
+    with pytest.raises(F.FlusiError):
+        P.set_solid(st, [0.0] * 13)  # zero quaternion
+    t, nstep = P.time(st)
+    assert nstep == 0

@@ -20,8 +20,8 @@ def test_library_exports_every_header_function():
 
 
 def test_struct_layouts_match_header():
-    # flusi_insect: 4 ints + 36 doubles; flusi_step_params: 2 ints, 5 doubles, 1 pointer
-    assert ctypes.sizeof(F.flusi_insect) == 16 + 8 * 36
+    # flusi_insect: 4 ints + 47 doubles; flusi_step_params: 2 ints, 5 doubles, 1 pointer
+    assert ctypes.sizeof(F.flusi_insect) == 16 + 8 * 47
     assert ctypes.sizeof(F.flusi_step_params) == 8 + 5 * 8 + 8
 
 
