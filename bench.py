@@ -105,7 +105,7 @@ def kernel_of_pass(pass_name: str, n: int, real: str, sched: dict, nc: int, dyn:
         "z_pass": f"k_zpass<{real}, {n}, {2 if split else 1}, {sched['z_pass']}>",
         "z_inverse": f"k_zpass<{real}, {n}, 3, {sched['z_pass']}>",
         "x_pass": f"k_xpass<{real}, {n}, {nc}, {sched['x_pass']}>",
-        "y_inverse": f"k_ypass<{real}, {n}, 1, {2 if dyn else 0}, {sched['y_inverse']}>",
+        "y_inverse": f"k_ypass<{real}, {n}, 1, 0, {sched['y_inverse']}>",
         "y_forward": f"k_ypass<{real}, {n}, -1, 1, {sched['y_forward']}>",
     }[pass_name]
 
@@ -297,6 +297,7 @@ def main():
                     choices=["sphere128", "insect256", "tg32", "ensemble48", "serve"])
     ap.add_argument("--no-serve", action="store_true", help="skip the serving-stream figure")
     ap.add_argument("--no-sponge", action="store_true", help="skip the vorticity-sponge figure")
+    ap.add_argument("--no-freeflight", action="store_true", help="skip the free-flight figure")
     ap.add_argument("--no-ensemble", action="store_true", help="skip the batched-ensemble figure")
     ap.add_argument("--no-autotune", action="store_true", help="time the default schedules")
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
@@ -413,6 +414,22 @@ def main():
         out["sponge"] = {"value": sp["f32"], "fp64": sp["f64"], "unit": "Mpoint-steps/s",
                          "description": "sphere128 with the vorticity sponge on 3.5 <= x < 4, C_sp = 0.1 "
                                         "(3 more forward fields per step)"}
+    if not a.no_freeflight and a.workload == "sphere128":
+        # the same workload with the sphere in free flight: density 2, gravity 1 along -z,
+        # all six degrees of freedom, J = (2/5) M R^2
+        vol = 4.0 / 3.0 * math.pi * 0.5 ** 3
+        ff_body = dict(wl["insect"], free_flight=True, mass=2.0 * vol, inertia=(0.4 * 2.0 * vol * 0.25,) * 3,
+                       gravity=1.0, dof=(1, 1, 1, 1, 1, 1))
+        ff = {}
+        for dtype in ("f32", "f64"):
+            r = gpu_run(F, torch, dict(wl, insect=ff_body), dtype, steps, a.warmup, tune=not a.no_autotune)
+            ff[dtype] = (round(pts * steps / (r["ev_ms"] / 1e3) / 1e6, 2), r["diag"])
+        d = ff["f32"][1]
+        out["freeflight"] = {"value": ff["f32"][0], "fp64": ff["f64"][0], "unit": "Mpoint-steps/s",
+                             "description": "sphere128 with the sphere in free flight (density 2, g = 1 along -z, "
+                                            "6 DoF): 13-value body state advanced each step",
+                             "body_at_last_step_f32": {"t": d[0], "x_cntr": list(d[22:25]), "u_cntr": list(d[25:28]),
+                                                       "omega_b": list(d[32:35])}}
     if not a.no_cpu:
         cs = oracle_sample(wl)
         cpu_v = pts * cs["timed_steps"] / cs["seconds"] / 1e6

@@ -391,8 +391,10 @@ struct Impl final : ImplBase {
     }
     template <int MODE, int V, bool SP>
     static void zpass_launch(const GroupRun& g, const Member* mt, int nmem, int par, int s) {
+        // update modes: one more workgroup per member (diagnostics, next level)
+        constexpr int nb = NBZ + ((MODE == MODE_STEP || MODE == MODE_STEP_LAST) ? 1 : 0);
         if (nmem > 0)
-            k_zpass<T, N, MODE, V, SP><<<(unsigned)(NBZ * nmem), nt_z(N, V), 0, g.stream>>>(
+            k_zpass<T, N, MODE, V, SP><<<(unsigned)(nb * nmem), nt_z(N, V), 0, g.stream>>>(
                 mt, static_cast<const CX*>(g.tw), par, s);
     }
     // update modes: members without the sponge, then those with it (the table

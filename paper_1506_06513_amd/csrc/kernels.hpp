@@ -799,8 +799,16 @@ __device__ inline void write_step(StateHdr* h, int p, const double* tot, const C
         static_assert(sizeof(Slot) % 8 == 0, "slot copy by words");
         const double* src = reinterpret_cast<const double*>(&sl);
         double* dst = reinterpret_cast<double*>(&nx);
+        constexpr int W = (int)(sizeof(Slot) / 8), B = 6;
+        static_assert(W % B == 0, "slot copy batches");
 #pragma unroll 1
-        for (int i = 0; i < (int)(sizeof(Slot) / 8); ++i) dst[i] = src[i];
+        for (int i = 0; i < W; i += B) {
+            double v[B];
+#pragma unroll
+            for (int j = 0; j < B; ++j) v[j] = src[i + j];
+#pragma unroll
+            for (int j = 0; j < B; ++j) dst[i + j] = v[j];
+        }
     }
     if (c.active) {
         if (ctl.masked) {
@@ -1053,12 +1061,16 @@ __global__ __launch_bounds__(nt_z(N, V)) void k_zpass(const Member* __restrict__
     constexpr int K = G::K, KP = G::KP, M = G::M, Q = G::Q, Qp = G::Qp;
     constexpr int C = cols_z(N), NTZ = nt_z(N, V);
     constexpr int NBZ = (Q + C - 1) / C;
+    // update modes: one more workgroup per member writes the diagnostics and
+    // the next time level, beside the column workgroups
+    constexpr bool STEPM = (MODE == MODE_STEP || MODE == MODE_STEP_LAST);
+    constexpr int NBZ1 = NBZ + (STEPM ? 1 : 0);
     // state fields: [uhat 3][nold 3], each padded to 256 bytes
     constexpr long fs_s = (((long)M * Qp * (long)sizeof(cx<T>) + 255) / 256 * 256) / (long)sizeof(cx<T>);
     constexpr long fs_y = (long)N * Qp, fs_z = (long)N * Qp;
     const int lin = xcd_tile(blockIdx.x, gridDim.x);
-    const Member& mb = mt[lin / NBZ];
-    const int tile = lin % NBZ;
+    const Member& mb = mt[lin / NBZ1];
+    const int tile = lin % NBZ1;
     StateHdr* hdr = mb.hdr;
     glb<cx<T>>* uhat = gview(reinterpret_cast<cx<T>*>(reinterpret_cast<char*>(hdr) + STATE_HDR_BYTES));
     glb<cx<T>>* nold = uhat + 3 * fs_s;
@@ -1102,12 +1114,13 @@ __global__ __launch_bounds__(nt_z(N, V)) void k_zpass(const Member* __restrict__
     if constexpr (FWD) load_field(0);
     if (step_mode) {
         reduce_level2<NTZ, nred_of(N)>(partial2, reinterpret_cast<double*>(smem), tot);
-        if (tid == 0) {
-            cf = step_coef(tot, hdr->slot[par], mb.ctl, dx, eta);
-            if (tile == 0)
-                write_step(hdr, par, tot, cf, mb.ctl, dx, eta, mb.history ? mb.history + (long)s * FLUSI_NDIAG : nullptr,
-                           mb.ff);
+        if (tile == NBZ) {
+            if (tid == 0)
+                write_step(hdr, par, tot, step_coef(tot, hdr->slot[par], mb.ctl, dx, eta), mb.ctl, dx, eta,
+                           mb.history ? mb.history + (long)s * FLUSI_NDIAG : nullptr, mb.ff);
+            return;
         }
+        if (tid == 0) cf = step_coef(tot, hdr->slot[par], mb.ctl, dx, eta);
         __syncthreads();
         if (cf.bad) return;
     }
