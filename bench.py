@@ -16,8 +16,10 @@ region (--no-autotune: defaults).  The default run adds two sub-objects:
 `ensemble48` (48 seeded insect simulations on mixed grids advanced by batched
 launches replayed from a hipGraph, against the same members stepped one by one)
 and `serving` (a Poisson-arrival request stream with a 512^3 insect: p50/p99
-latency and throughput).  --workload selects insect256, tg32, ensemble48 or
-serve as the main line instead.
+latency and throughput), plus `sponge` and `freeflight` (the same sphere
+workload with a vorticity sponge layer, and with the sphere in free flight).
+--workload selects freefall128, insect256, tg32, ensemble48 or serve as the
+main line instead.
 """
 from __future__ import annotations
 
@@ -110,6 +112,15 @@ def kernel_of_pass(pass_name: str, n: int, real: str, sched: dict, nc: int, dyn:
     }[pass_name]
 
 
+def free_sphere(body: dict) -> dict:
+    """The sphere of a workload in free flight: density 2 (twice the fluid's),
+    gravity 1 along -z, all six degrees of freedom, J = (2/5) M R^2."""
+    r = body.get("radius", 0.5)
+    mass = 2.0 * 4.0 / 3.0 * math.pi * r ** 3
+    return dict(body, free_flight=True, mass=mass, inertia=(0.4 * mass * r * r,) * 3, gravity=1.0,
+                dof=(1, 1, 1, 1, 1, 1))
+
+
 def build_workload(name: str):
     import workloads as W
     if name == "sphere128":
@@ -121,6 +132,11 @@ def build_workload(name: str):
                 "|k|<=8 (seed 0), nu=0.01, C_eta=1e-3, adaptive dt CFL 0.1 capped at C_eta/2")
         return dict(n=n, L=L, nu=wl["nu"], eta=wl["eta"], u0=u0, insect=body, cfl=0.1, dt_fixed=0.0,
                     desc=desc, default_steps=wl["steps"])
+    if name == "freefall128":
+        wl = build_workload("sphere128")
+        wl["insect"] = free_sphere(wl["insect"])
+        wl["desc"] = wl["desc"] + "; the sphere in free flight (density 2, g = 1 along -z, 6 DoF)"
+        return wl
     if name == "insect256":
         wl = W.WORKLOADS["insect256"]
         n, L = wl["n"], wl["L"]
@@ -294,7 +310,7 @@ def main():
     ap.add_argument("--steps", type=int, default=None)
     ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--workload", default="sphere128",
-                    choices=["sphere128", "insect256", "tg32", "ensemble48", "serve"])
+                    choices=["sphere128", "freefall128", "insect256", "tg32", "ensemble48", "serve"])
     ap.add_argument("--no-serve", action="store_true", help="skip the serving-stream figure")
     ap.add_argument("--no-sponge", action="store_true", help="skip the vorticity-sponge figure")
     ap.add_argument("--no-freeflight", action="store_true", help="skip the free-flight figure")
@@ -415,11 +431,8 @@ def main():
                          "description": "sphere128 with the vorticity sponge on 3.5 <= x < 4, C_sp = 0.1 "
                                         "(3 more forward fields per step)"}
     if not a.no_freeflight and a.workload == "sphere128":
-        # the same workload with the sphere in free flight: density 2, gravity 1 along -z,
-        # all six degrees of freedom, J = (2/5) M R^2
-        vol = 4.0 / 3.0 * math.pi * 0.5 ** 3
-        ff_body = dict(wl["insect"], free_flight=True, mass=2.0 * vol, inertia=(0.4 * 2.0 * vol * 0.25,) * 3,
-                       gravity=1.0, dof=(1, 1, 1, 1, 1, 1))
+        # the same workload with the sphere in free flight
+        ff_body = free_sphere(wl["insect"])
         ff = {}
         for dtype in ("f32", "f64"):
             r = gpu_run(F, torch, dict(wl, insect=ff_body), dtype, steps, a.warmup, tune=not a.no_autotune)

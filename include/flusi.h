@@ -260,8 +260,9 @@ int flusi_state_set_solid(flusi_plan plan, void* state, const double* y);
 /* Instrumentation.  While enabled, flusi_step brackets each pass it launches
  * with HIP events on the plan's stream.  Passes: 0 inverse z of the state at
  * the start of a call, 1 y-inverse, 2 x-pass (inverse x, source, forward x),
- * 3 scalar reduction, 4 y-forward, 5 z-pass (forward z, projection, AB2,
- * inverse z).  flusi_profile(plan, 1) clears the records and starts
+ * 3 body kinematics of a time level (and the free-flight advance), 4
+ * y-forward (with the first-level reduction), 5 z-pass (forward z,
+ * projection, AB2, inverse z).  flusi_profile(plan, 1) clears the records and starts
  * recording, flusi_profile(plan, 0) stops.  flusi_pass_times synchronizes the
  * stream and returns, per pass, the summed event time in milliseconds and the
  * number of launches recorded since the last flusi_profile(plan, 1); ms and

@@ -34,7 +34,7 @@ FLUSI_SMOOTH_COS, FLUSI_SMOOTH_TANH = 0, 1
 FLUSI_MEAN_FIXED, FLUSI_MEAN_FREE = 0, 1
 FLUSI_NDIAG = 37
 FLUSI_NPASS = 6
-PASS_NAMES = ("z_inverse", "y_inverse", "x_pass", "scalar", "y_forward", "z_pass")
+PASS_NAMES = ("z_inverse", "y_inverse", "x_pass", "kinematics", "y_forward", "z_pass")
 SUPPORTED_N = (16, 24, 32, 48, 64, 96, 128, 192, 256, 384, 512)
 
 

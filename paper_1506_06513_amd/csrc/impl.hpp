@@ -137,7 +137,7 @@ inline Member make_member(const PlanData& p, void* st, const flusi_insect* ins, 
     for (int a = 0; a < 3; ++a) m.sp_lo[a] = (m.sponge && p.sp_thick[a] > 0.0) ? p.L - p.sp_thick[a] : 1e300;
     return m;
 }
-enum { PASS_ZINV = 0, PASS_YINV = 1, PASS_X = 2, PASS_SCALAR = 3, PASS_YFWD = 4, PASS_Z = 5 };
+enum { PASS_ZINV = 0, PASS_YINV = 1, PASS_X = 2, PASS_KIN = 3, PASS_YFWD = 4, PASS_Z = 5 };
 
 int set_error(int code, const char* fmt, ...);
 int ensure_scratch(void** ptr, size_t* cur, size_t need, PlanData& p);
@@ -425,7 +425,10 @@ struct Impl final : ImplBase {
 
     int run_steps(const GroupRun& g, int nsteps) override {
         if (g.nmem <= 0 || nsteps <= 0) return FLUSI_OK;
-        k_prologue<<<(unsigned)((g.nmem + 63) / 64), 64, 0, g.stream>>>(g.mt, g.nmem);
+        {
+            PassScope ps(g.prof, PASS_KIN, g.stream);
+            k_prologue<<<(unsigned)((g.nmem + 63) / 64), 64, 0, g.stream>>>(g.mt, g.nmem);
+        }
         {
             PassScope ps(g.prof, PASS_ZINV, g.stream);
             zpass<MODE_INVERSE>(g);
@@ -433,7 +436,10 @@ struct Impl final : ImplBase {
         for (int s = 0; s < nsteps; ++s) {
             const int par = s & 1;
             // kinematics of this time level (the prologue covers the first)
-            if (g.any_dyn && s > 0) k_kin_level<<<(unsigned)((g.nmem + 63) / 64), 64, 0, g.stream>>>(g.mt, g.nmem, par);
+            if (g.any_dyn && s > 0) {
+                PassScope ps(g.prof, PASS_KIN, g.stream);
+                k_kin_level<<<(unsigned)((g.nmem + 63) / 64), 64, 0, g.stream>>>(g.mt, g.nmem, par);
+            }
             {
                 PassScope ps(g.prof, PASS_YINV, g.stream);
                 y_inverse(g);
@@ -457,7 +463,10 @@ struct Impl final : ImplBase {
             }
         }
         // free flight: advance the body to the new current level
-        if (g.any_ff) k_kin_level<<<(unsigned)((g.nmem + 63) / 64), 64, 0, g.stream>>>(g.mt, g.nmem, nsteps & 1);
+        if (g.any_ff) {
+            PassScope ps(g.prof, PASS_KIN, g.stream);
+            k_kin_level<<<(unsigned)((g.nmem + 63) / 64), 64, 0, g.stream>>>(g.mt, g.nmem, nsteps & 1);
+        }
         return launch_check("step");
     }
 

@@ -177,6 +177,19 @@ __host__ __device__ __forceinline__ void compute_kin(const flusi_insect& in, dou
     if (in.body == FLUSI_BODY_SPHERE) rall = in.radius + k.thr;
     if (in.body == FLUSI_BODY_ELLIPSOID) rall = 2.0 * (in.a + in.b) + k.thr;
 
+    if (!in.wings) {
+        // no wings: identity wing frames, zero rates, reference points at the centre
+        for (int s = 0; s < 2; ++s) {
+            for (int i = 0; i < 9; ++i) k.Mws[s][i] = (i % 4 == 0) ? 1.0 : 0.0;
+            for (int i = 0; i < 3; ++i) {
+                k.piv[s][i] = 0.0;
+                k.omw[s][i] = 0.0;
+                k.xref[1 + s][i] = k.xc[i];
+            }
+        }
+        k.r2all = rall * rall;
+        return;
+    }
     const double om = 2.0 * M_PI * in.freq;
     const double ph_phi = om * t + in.phi[2], ph_al = om * t + in.alpha[2], ph_th = om * t + in.theta[2];
     const double phi0 = in.phi[0] + in.phi[1] * cos(ph_phi), dphi0 = -in.phi[1] * om * sin(ph_phi);
