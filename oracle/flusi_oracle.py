@@ -18,8 +18,10 @@ What it computes (paper section / equation in brackets):
   smoothing_mask_as_function_of_delta],
 * the insect model: rotation matrices, body/stroke/wing frames, body and wing
   velocity fields [Sec. 3.1-3.3, eqs. M_body_yawpitchroll,
-  body_velocity_field, wing_velocity_field], body shape [Sec. 3.2] and the
-  polar-radius wing shape [Sec. 3.4],
+  body_velocity_field, wing_velocity_field], wing angles as sinusoids,
+  Fourier or Hermite series [Sec. 3.3], body shape with head and eyes
+  [Sec. 3.2] and the polar-radius wing shape, closed-form ellipse or Fourier
+  series through a 25 000-sample table [Sec. 3.4],
 * force and torque from the penalization integral with the unsteady
   correction [Sec. 2.1, eqs. force_with_unst_corrections, moment_of_love],
 * the time loop of Algorithm 1 (mask -> dt -> sources -> projection -> AB2
@@ -69,6 +71,16 @@ listed in the design notes of the repository):
       with I = sum chi u_s dV (no unsteady term at the first step); torques
       about the body centre (body) or the wing pivot (wings).
   Energy: E = 1/2 sum |u|^2 dV.
+  Wing angle series: Fourier coefficients use the convention of eq.
+      Fourier_radious_wing with the phase f t (in periods) as the variable;
+      Hermite coefficients are values and rates at K equidistant times of
+      one period, joined by periodic cubic Hermite interpolation.
+  Fourier wing: the series variable is the polar angle in turns (angle/2pi,
+      counterclockwise from +x_w about x_c^(w)); the table holds 25 000
+      samples at j/25 000 and is interpolated linearly and periodically.
+  Body parts: head and eye spheres get radii (not printed) and join the
+      thorax as a union, i.e. the minimum of the signed distances (with
+      delta < 0 inside, the printed maximum would be the intersection).
   Quaternion matrix: the printed matrix of the quaternion maps body-frame
       vectors to the global frame; M_body (global to body) is its transpose.
       Only then does the printed initial quaternion reproduce eq.
@@ -286,6 +298,18 @@ class Insect:
     phi: tuple = (0.0, 0.0, 0.0)
     alpha: tuple = (0.0, 0.0, 0.0)
     theta: tuple = (0.0, 0.0, 0.0)
+    kin: str = "sine"                    # wing angles: 'sine' | 'fourier' | 'hermite'  [Sec. 3.3]
+    kin_phi: tuple = ((), ())            # fourier: (a_0..a_n), (b_0..b_n); hermite: (values), (rates)
+    kin_alpha: tuple = ((), ())
+    kin_theta: tuple = ((), ())
+    wing_shape: str = "ellipse"          # 'ellipse' | 'fourier'  [Sec. 3.4]
+    wing_c: tuple = (0.0, 0.0)           # fourier wing: centre x_c^(w) in the wing plane
+    wing_fa: tuple = ()                  # fourier wing: a_0..a_n
+    wing_fb: tuple = ()                  # fourier wing: b_0..b_n (b_0 unused)
+    head_x: tuple = (0.0, 0.0, 0.0)      # head sphere centre (body frame); head_r <= 0: none
+    head_r: float = 0.0
+    eye_x: tuple = (0.0, 0.0, 0.0)       # eye spheres at (x, +y, z) and (x, -y, z); eye_r <= 0: none
+    eye_r: float = 0.0
     free_flight: bool = False            # Sec. 3.5: the body moves under F, m and gravity
     mass: float = 1.0                    # M
     inertia: tuple = (1.0, 1.0, 1.0)     # principal moments J_x, J_y, J_z (body frame)
@@ -297,12 +321,49 @@ class Insect:
         return Insect(**d)
 
 
+def fourier_angle(a, b, freq: float, t: float):
+    """Angle a_0/2 + sum_i a_i cos(2 pi i f t) + b_i sin(2 pi i f t) and its
+    time derivative: the series of eq. Fourier_radious_wing with the phase
+    f t (in periods) as its variable  [Sec. 3.3, 3.4]."""
+    v = 0.5 * float(a[0])
+    dv = 0.0
+    for i in range(1, len(a)):
+        w = 2.0 * math.pi * i * freq
+        ai, bi = float(a[i]), float(b[i])
+        v += ai * math.cos(w * t) + bi * math.sin(w * t)
+        dv += w * (-ai * math.sin(w * t) + bi * math.cos(w * t))
+    return v, dv
+
+
+def hermite_angle(vals, rates, freq: float, t: float):
+    """Angle and its time derivative from periodic cubic Hermite interpolation
+    of K values and rates at the equidistant times j/(K f), j = 0..K-1, of one
+    period  [Sec. 3.3]."""
+    K = len(vals)
+    T = 1.0 / freq
+    h = T / K
+    s = (t % T) / h
+    j = min(int(math.floor(s)), K - 1)
+    u = s - j
+    j1 = (j + 1) % K
+    v0, v1 = float(vals[j]), float(vals[j1])
+    m0, m1 = float(rates[j]) * h, float(rates[j1]) * h
+    h00, h10, h01, h11 = 2 * u ** 3 - 3 * u ** 2 + 1, u ** 3 - 2 * u ** 2 + u, -2 * u ** 3 + 3 * u ** 2, u ** 3 - u ** 2
+    d00, d10, d01, d11 = 6 * u ** 2 - 6 * u, 3 * u ** 2 - 4 * u + 1, -6 * u ** 2 + 6 * u, 3 * u ** 2 - 2 * u
+    return h00 * v0 + h10 * m0 + h01 * v1 + h11 * m1, (d00 * v0 + d10 * m0 + d01 * v1 + d11 * m1) / h
+
+
 def wing_angles(ins: Insect, t: float):
     """(phi, alpha, theta) and their time derivatives at time t."""
-    w = 2.0 * math.pi * ins.freq
-    out = []
-    for mean, amp, ph in (ins.phi, ins.alpha, ins.theta):
-        out.append((mean + amp * math.cos(w * t + ph), -amp * w * math.sin(w * t + ph)))
+    if ins.kin == "fourier":
+        out = [fourier_angle(c[0], c[1], ins.freq, t) for c in (ins.kin_phi, ins.kin_alpha, ins.kin_theta)]
+    elif ins.kin == "hermite":
+        out = [hermite_angle(c[0], c[1], ins.freq, t) for c in (ins.kin_phi, ins.kin_alpha, ins.kin_theta)]
+    else:
+        w = 2.0 * math.pi * ins.freq
+        out = []
+        for mean, amp, ph in (ins.phi, ins.alpha, ins.theta):
+            out.append((mean + amp * math.cos(w * t + ph), -amp * w * math.sin(w * t + ph)))
     (phi, dphi), (alpha, dalpha), (theta, dtheta) = out
     return phi, alpha, theta, dphi, dalpha, dtheta
 
@@ -389,6 +450,61 @@ def delta_elliptic_wing(xw, yw, zw, A, B, t):
     with np.errstate(invalid="ignore", divide="ignore"):
         inplane = np.where(r > 0.0, r - r / np.where(rho > 0.0, rho, 1.0), -A)
     return np.maximum(np.abs(zw) - 0.5 * t, inplane)
+
+
+# Samples of the wing radius table  [Sec. 3.4]
+R_TABLE_SIZE = 25000
+
+
+def wing_radius_series(fa, fb, v):
+    """R(v) = a_0/2 + sum_i a_i cos(2 pi i v) + b_i sin(2 pi i v)  [eq. Fourier_radious_wing];
+    v is the polar angle in turns (angle / 2 pi)."""
+    v = np.asarray(v, dtype=np.float64)
+    r = np.full(v.shape, 0.5 * float(fa[0]))
+    for i in range(1, len(fa)):
+        r = r + float(fa[i]) * np.cos(2.0 * np.pi * i * v) + float(fb[i]) * np.sin(2.0 * np.pi * i * v)
+    return r
+
+
+def wing_radius_table(fa, fb) -> np.ndarray:
+    """R at the R_TABLE_SIZE angles v_j = j / R_TABLE_SIZE (evaluated once)  [Sec. 3.4]."""
+    return wing_radius_series(fa, fb, np.arange(R_TABLE_SIZE) / R_TABLE_SIZE)
+
+
+def wing_radius_lookup(table: np.ndarray, v):
+    """Linear interpolation in the periodic radius table  [Sec. 3.4]."""
+    n = table.shape[0]
+    p = np.mod(np.asarray(v, dtype=np.float64), 1.0) * n
+    j = np.minimum(np.floor(p).astype(np.int64), n - 1)
+    f = p - j
+    return (1.0 - f) * table[j] + f * table[(j + 1) % n]
+
+
+def delta_fourier_wing(xw, yw, zw, ins: Insect, table: np.ndarray):
+    """Polar-radius wing  [Sec. 3.4]: max(|z_w| - t/2, r - R(v)) with r and the
+    angle v (in turns, counterclockwise from +x_w) about the centre x_c^(w)."""
+    ex = xw - float(ins.wing_c[0])
+    ey = yw - float(ins.wing_c[1])
+    r = np.sqrt(ex * ex + ey * ey)
+    v = np.arctan2(ey, ex) / (2.0 * np.pi)
+    return np.maximum(np.abs(zw) - 0.5 * ins.wing_t, r - wing_radius_lookup(table, v))
+
+
+def delta_body(ins: Insect, xb):
+    """Body signed distance in the body frame  [Sec. 3.2]: the thorax
+    ellipsoid joined with the head and eye spheres (union: min of the
+    distances; a sphere's distance is |x - x_0| - radius)."""
+    d = delta_ellipsoid(xb[0], xb[1], xb[2], ins.a, ins.b)
+    sph = []
+    if ins.head_r > 0.0:
+        sph.append((ins.head_x, ins.head_r))
+    if ins.eye_r > 0.0:
+        ex, ey, ez = ins.eye_x
+        sph += [((ex, ey, ez), ins.eye_r), ((ex, -ey, ez), ins.eye_r)]
+    for c, rad in sph:
+        ds = np.sqrt((xb[0] - c[0]) ** 2 + (xb[1] - c[1]) ** 2 + (xb[2] - c[2]) ** 2) - rad
+        d = np.minimum(d, ds)
+    return d
 
 
 def _cross(a, b):
@@ -494,7 +610,7 @@ def mask_at(ins: Insect, t: float, dx: float, x, y, z, pose: Pose | None = None)
         chis.append(chi_of_delta(d, ins, dx))
         uss.append(ub)
     elif ins.body == "ellipsoid":
-        d = delta_ellipsoid(xb[0], xb[1], xb[2], ins.a, ins.b)
+        d = delta_body(ins, xb)
         chis.append(chi_of_delta(d, ins, dx))
         uss.append(ub)
     else:
@@ -502,9 +618,13 @@ def mask_at(ins: Insect, t: float, dx: float, x, y, z, pose: Pose | None = None)
         uss.append(np.zeros((3,) + shp))
 
     if ins.wings:
+        table = wing_radius_table(ins.wing_fa, ins.wing_fb) if ins.wing_shape == "fourier" else None
         for side in ("l", "r"):
             xw = wing_frame(ins, t, side, xb)
-            d = delta_elliptic_wing(xw[0], xw[1], xw[2], ins.wing_A, ins.wing_B, ins.wing_t)
+            if table is not None:
+                d = delta_fourier_wing(xw[0], xw[1], xw[2], ins, table)
+            else:
+                d = delta_elliptic_wing(xw[0], xw[1], xw[2], ins.wing_A, ins.wing_B, ins.wing_t)
             chis.append(chi_of_delta(d, ins, dx))
             uss.append(wing_velocity(ins, t, side, xb, ps))
     else:
