@@ -54,6 +54,16 @@ extern "C" {
 #define FLUSI_BODY_SPHERE 1
 #define FLUSI_BODY_ELLIPSOID 2
 
+#define FLUSI_KIN_SINE 0     /* wing angle = mean + amplitude*cos(2*pi*freq*t + phase) */
+#define FLUSI_KIN_FOURIER 1  /* wing angle = a_0/2 + sum_i a_i cos(2*pi*i*freq*t) + b_i sin(...) */
+#define FLUSI_KIN_HERMITE 2  /* periodic cubic Hermite through values and rates at kin_n times */
+#define FLUSI_KIN_MAX 24     /* harmonics (Fourier) or nodes (Hermite) per angle */
+
+#define FLUSI_WING_ELLIPSE 0 /* elliptic outline: half chord wing_A, half span wing_B, centre (0, B) */
+#define FLUSI_WING_FOURIER 1 /* polar-radius outline R(v) as a Fourier series (Sec. 3.4) */
+#define FLUSI_WING_MAX 32    /* radius harmonics */
+#define FLUSI_RTABLE 25000   /* samples of the radius table (Sec. 3.4) */
+
 #define FLUSI_SMOOTH_COS 0   /* cosine layer, Sec. 2.2 eq. smoothing_mask_as_function_of_delta */
 #define FLUSI_SMOOTH_TANH 1  /* 0.5*(1 - tanh(delta/h)) */
 
@@ -128,6 +138,30 @@ typedef struct {
     double inertia[3];   /* principal moments J_x, J_y, J_z about the body axes */
     double gravity;      /* g, acting along -z of the global frame */
     double dof[6];       /* 1/0: translation x, y, z; rotation about x_b, y_b, z_b */
+    /* Wing angle parametrization (Sec. 3.3).  FLUSI_KIN_SINE uses phi/alpha/
+     * theta above.  FLUSI_KIN_FOURIER: kin_coef[angle][0][i] = a_i and
+     * [angle][1][i] = b_i, i = 0..kin_n (b_0 unused), angle 0 phi, 1 alpha,
+     * 2 theta.  FLUSI_KIN_HERMITE: kin_n nodes at t_j = j/(kin_n*freq) of one
+     * period; kin_coef[angle][0][j] = value, [angle][1][j] = rate (rad per time
+     * unit); joined by periodic cubic Hermite interpolation. */
+    int kin_type;        /* FLUSI_KIN_* */
+    int kin_n;           /* Fourier: highest harmonic (0..FLUSI_KIN_MAX); Hermite: nodes (2..FLUSI_KIN_MAX) */
+    int wing_shape;      /* FLUSI_WING_* */
+    int wing_n;          /* Fourier wing: highest harmonic (0..FLUSI_WING_MAX) */
+    double kin_coef[3][2][FLUSI_KIN_MAX + 1];
+    /* Fourier wing (Sec. 3.4, eq. Fourier_radious_wing): in the wing plane,
+     * about the centre wing_c, r - R(v) with v the polar angle in turns
+     * (counterclockwise from +x_w) and R(v) = a_0/2 + sum_i a_i cos(2 pi i v) +
+     * b_i sin(2 pi i v), wing_coef[0][i] = a_i, wing_coef[1][i] = b_i.  R is
+     * sampled at FLUSI_RTABLE angles when the coefficients change (plan-owned
+     * table) and interpolated linearly.  Thickness: wing_t. */
+    double wing_c[2];
+    double wing_coef[2][FLUSI_WING_MAX + 1];
+    /* Body parts (Sec. 3.2, ellipsoid bodies): head sphere and a mirrored pair
+     * of eye spheres at (x, +y, z) and (x, -y, z), body frame; joined with the
+     * thorax as a union (minimum of the signed distances).  Radius 0: none. */
+    double head_x[3], head_r;
+    double eye_x[3], eye_r;
 } flusi_insect;
 
 /* Controls of flusi_step (Algorithm 1 steps (a)-(e)). */

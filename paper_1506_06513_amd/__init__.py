@@ -44,6 +44,15 @@ class FlusiError(RuntimeError):
         self.code = code
 
 
+FLUSI_KIN_SINE, FLUSI_KIN_FOURIER, FLUSI_KIN_HERMITE = 0, 1, 2
+FLUSI_KIN_MAX = 24
+FLUSI_WING_ELLIPSE, FLUSI_WING_FOURIER = 0, 1
+FLUSI_WING_MAX = 32
+FLUSI_RTABLE = 25000
+_KIN = {"sine": FLUSI_KIN_SINE, "fourier": FLUSI_KIN_FOURIER, "hermite": FLUSI_KIN_HERMITE}
+_WING = {"ellipse": FLUSI_WING_ELLIPSE, "fourier": FLUSI_WING_FOURIER}
+
+
 class flusi_insect(ctypes.Structure):
     _fields_ = [
         ("body", ctypes.c_int), ("wings", ctypes.c_int), ("smooth", ctypes.c_int), ("free_flight", ctypes.c_int),
@@ -59,6 +68,12 @@ class flusi_insect(ctypes.Structure):
         ("phi", ctypes.c_double * 3), ("alpha", ctypes.c_double * 3), ("theta", ctypes.c_double * 3),
         ("mass", ctypes.c_double), ("inertia", ctypes.c_double * 3), ("gravity", ctypes.c_double),
         ("dof", ctypes.c_double * 6),
+        ("kin_type", ctypes.c_int), ("kin_n", ctypes.c_int), ("wing_shape", ctypes.c_int), ("wing_n", ctypes.c_int),
+        ("kin_coef", ((ctypes.c_double * (FLUSI_KIN_MAX + 1)) * 2) * 3),
+        ("wing_c", ctypes.c_double * 2),
+        ("wing_coef", (ctypes.c_double * (FLUSI_WING_MAX + 1)) * 2),
+        ("head_x", ctypes.c_double * 3), ("head_r", ctypes.c_double),
+        ("eye_x", ctypes.c_double * 3), ("eye_r", ctypes.c_double),
     ]
 
 
@@ -423,6 +438,35 @@ def make_insect(d: dict | None) -> flusi_insect | None:
     s.inertia[:] = [float(v) for v in d.get("inertia", (1.0, 1.0, 1.0))]
     s.gravity = float(d.get("gravity", 0.0))
     s.dof[:] = [float(v) for v in d.get("dof", (1.0,) * 6)]
+    kin = d.get("kin", "sine")
+    s.kin_type = _KIN[kin]
+    if kin != "sine":
+        series = [d.get(k, ((), ())) for k in ("kin_phi", "kin_alpha", "kin_theta")]
+        lens = {len(c[0]) for c in series} | {len(c[1]) for c in series}
+        if len(lens) != 1:
+            raise ValueError("wing angle series need equal lengths for all angles and both rows")
+        m = lens.pop()
+        if m < 1 or m > FLUSI_KIN_MAX + 1:
+            raise ValueError(f"wing angle series: 1..{FLUSI_KIN_MAX + 1} entries per row")
+        s.kin_n = m - 1 if kin == "fourier" else m
+        for a, c in enumerate(series):
+            for r in range(2):
+                for i, v in enumerate(c[r]):
+                    s.kin_coef[a][r][i] = float(v)
+    s.wing_shape = _WING[d.get("wing_shape", "ellipse")]
+    if s.wing_shape == FLUSI_WING_FOURIER:
+        fa, fb = d.get("wing_fa", ()), d.get("wing_fb", ())
+        if len(fa) != len(fb) or not 1 <= len(fa) <= FLUSI_WING_MAX + 1:
+            raise ValueError(f"Fourier wing: 1..{FLUSI_WING_MAX + 1} coefficients, as many b as a")
+        s.wing_n = len(fa) - 1
+        for i in range(len(fa)):
+            s.wing_coef[0][i] = float(fa[i])
+            s.wing_coef[1][i] = float(fb[i])
+        s.wing_c[:] = [float(v) for v in d.get("wing_c", (0.0, 0.0))]
+    s.head_x[:] = [float(v) for v in d.get("head_x", (0.0, 0.0, 0.0))]
+    s.head_r = float(d.get("head_r", 0.0))
+    s.eye_x[:] = [float(v) for v in d.get("eye_x", (0.0, 0.0, 0.0))]
+    s.eye_r = float(d.get("eye_r", 0.0))
     for k in ("x_cntr", "u_cntr", "pivot_l", "pivot_r", "phi", "alpha", "theta"):
         default = {"pivot_l": (0.0, 0.15, 0.0), "pivot_r": (0.0, -0.15, 0.0)}.get(k, (0.0, 0.0, 0.0))
         getattr(s, k)[:] = [float(v) for v in d.get(k, default)]

@@ -104,7 +104,8 @@ static int check_plan(flusi_plan p) {
     return FLUSI_OK;
 }
 static void free_plan(PlanData& d) {
-    void* ptrs[] = {d.tw, d.bufA, d.bufB, d.partial, d.partial2, d.kin, d.ins_dev, d.member_dev, d.pmax, d.spec, d.phys};
+    void* ptrs[] = {d.tw, d.bufA, d.bufB, d.partial, d.partial2, d.kin, d.ins_dev, d.member_dev, d.pmax, d.spec, d.phys,
+                    d.rtab, d.rtab32};
     for (void* q : ptrs)
         if (q) (void)hipFree(q);
     for (hipEvent_t e : d.events) (void)hipEventDestroy(e);
@@ -230,7 +231,7 @@ static int tune_group(ImplBase* impl, const GroupRun& g, PlanData& prof, int rep
 
 using namespace flusi;
 
-static_assert(sizeof(flusi_insect) == 16 + 8 * 47, "flusi_insect layout");
+static_assert(sizeof(flusi_insect) == 16 + 8 * 47 + 16 + 8 * (3 * 2 * (FLUSI_KIN_MAX + 1) + 2 + 2 * (FLUSI_WING_MAX + 1) + 8), "flusi_insect layout");
 static_assert(sizeof(flusi_step_params) == 8 + 5 * 8 + 8, "flusi_step_params layout");
 
 extern "C" {
@@ -273,13 +274,16 @@ int flusi_plan_create(int nx, int ny, int nz, double L, double nu, double eta, i
     ok = ok && hipMalloc(&d.kin, sizeof(Kin)) == hipSuccess;
     ok = ok && hipMalloc(&d.ins_dev, sizeof(flusi_insect)) == hipSuccess;
     ok = ok && hipMalloc(&d.member_dev, sizeof(Member)) == hipSuccess;
+    ok = ok && hipMalloc(&d.rtab, RTAB_BYTES64) == hipSuccess;
+    ok = ok && hipMalloc(&d.rtab32, RTAB_BYTES32) == hipSuccess;
     d.sched = impl->default_sched();
     if (!ok) {
         free_plan(d);
         delete p;
         return set_error(FLUSI_ENOMEM, "device allocation for a %d^3 plan", nx);
     }
-    d.workspace = nx * cxb + d.szA + d.szB + (size_t)d.nwg_x * NV * 8 + NRED_MAX * NV * 8 + sizeof(Kin) + sizeof(flusi_insect) + sizeof(Member);
+    d.workspace = nx * cxb + d.szA + d.szB + (size_t)d.nwg_x * NV * 8 + NRED_MAX * NV * 8 + sizeof(Kin) + sizeof(flusi_insect) +
+                  sizeof(Member) + RTAB_BYTES64 + RTAB_BYTES32;
     // FP64 twiddles exp(-2 pi i m / n); the FP32 table is rounded from them.
     std::vector<double> w(2 * nx);
     for (int m = 0; m < nx; ++m) {
@@ -322,7 +326,7 @@ int flusi_sizes(int n, int dtype, size_t* workspace_bytes, size_t* state_bytes) 
     if (workspace_bytes)
         *workspace_bytes = n * cxb + impl->bufA_elems() * cxb + impl->bufB_elems() * cxb +
                            (size_t)impl->nwg_x() * NV * 8 + NRED_MAX * NV * 8 + sizeof(Kin) + sizeof(flusi_insect) +
-                           sizeof(Member);
+                           sizeof(Member) + RTAB_BYTES64 + RTAB_BYTES32;
     if (state_bytes) *state_bytes = impl->state_bytes();
     delete impl;
     return FLUSI_OK;
@@ -521,6 +525,7 @@ int flusi_autotune(flusi_plan plan, const void* state, const flusi_insect* ins, 
         e = hipGetLastError();
     }
     int rc = FLUSI_OK;
+    if (e == hipSuccess && m.nc > 0) rc = prepare_wing_table(d, ins, d.stream);
     if (e != hipSuccess) rc = set_error(FLUSI_EDEVICE, "autotune: %s", hipGetErrorString(e));
     Sched best;
     if (!rc) {
@@ -652,6 +657,9 @@ static int ens_rebuild(flusi_ensemble e) {
             const flusi_insect* ins = m.has_ins ? &m.ins : nullptr;
             if (ins) {
                 err = hipMemcpy(pd.ins_dev, ins, sizeof(flusi_insect), hipMemcpyHostToDevice);
+                if (err != hipSuccess) return set_error(FLUSI_EDEVICE, "ensemble: %s", hipGetErrorString(err));
+                if (int rc = prepare_wing_table(pd, ins, pd.stream)) return rc;
+                err = hipStreamSynchronize(pd.stream);
                 if (err != hipSuccess) return set_error(FLUSI_EDEVICE, "ensemble: %s", hipGetErrorString(err));
             }
             const Member rec = make_member(pd, m.state, ins, m.sp);

@@ -1,7 +1,9 @@
 // Host-side launch logic of one (real type, grid size) instantiation.
 #pragma once
 #include <cstddef>
+#include <cmath>
 #include <cstdint>
+#include <cstring>
 #include <vector>
 
 #include "kernels.hpp"
@@ -16,6 +18,9 @@ struct Sched {
     int y_inverse = 0, x_pass = 0, y_forward = 0, z_pass = 0;
     int split_z = 0;
 };
+
+constexpr size_t RTAB_BYTES64 = (FLUSI_RTABLE + 1) * sizeof(double);
+constexpr size_t RTAB_BYTES32 = (FLUSI_RTABLE + 1) * sizeof(float);
 
 // Plan contents shared with the launchers.
 struct PlanData {
@@ -32,6 +37,10 @@ struct PlanData {
     double* partial2 = nullptr;
     Kin* kin = nullptr;
     flusi_insect* ins_dev = nullptr;  // device copy of the insect of the current stepping call
+    double* rtab = nullptr;           // Fourier wing radius table (FLUSI_RTABLE + 1 samples) ...
+    float* rtab32 = nullptr;          // ... and its FP32 copy
+    WingCoef rtab_key{};              // coefficients the table holds
+    bool rtab_valid = false;
     Member* member_dev = nullptr;     // launch record of the plan's own calls
     Sched sched;                      // schedule of the plan's own stepping calls
     double c_sp = 0.0;                // vorticity sponge constant (0: off)
@@ -121,6 +130,8 @@ inline Member make_member(const PlanData& p, void* st, const flusi_insect* ins, 
     m.partial = p.partial;
     m.partial2 = p.partial2;
     m.ins = p.ins_dev;
+    m.rtab = p.rtab;
+    m.rtab32 = p.rtab32;
     m.history = sp.history;
     m.dx = p.L / p.n;
     m.ks = 2.0 * M_PI / p.L;
@@ -145,7 +156,20 @@ int ensure_scratch(void** ptr, size_t* cur, size_t need, PlanData& p);
 // Checks the free-flight parameters of a body description (Sec. 3.5);
 // FLUSI_OK or FLUSI_EINVAL with a message.
 inline int check_insect(const flusi_insect* ins) {
-    if (!ins || !ins->free_flight) return FLUSI_OK;
+    if (!ins) return FLUSI_OK;
+    if (ins->kin_type < FLUSI_KIN_SINE || ins->kin_type > FLUSI_KIN_HERMITE)
+        return set_error(FLUSI_EINVAL, "insect: kin_type must be FLUSI_KIN_SINE, _FOURIER or _HERMITE");
+    if (ins->kin_type == FLUSI_KIN_FOURIER && (ins->kin_n < 0 || ins->kin_n > FLUSI_KIN_MAX))
+        return set_error(FLUSI_EINVAL, "insect: Fourier kinematics need 0 <= kin_n <= %d", FLUSI_KIN_MAX);
+    if (ins->kin_type == FLUSI_KIN_HERMITE && (ins->kin_n < 2 || ins->kin_n > FLUSI_KIN_MAX || !(ins->freq > 0.0)))
+        return set_error(FLUSI_EINVAL, "insect: Hermite kinematics need 2 <= kin_n <= %d and freq > 0", FLUSI_KIN_MAX);
+    if (ins->wing_shape != FLUSI_WING_ELLIPSE && ins->wing_shape != FLUSI_WING_FOURIER)
+        return set_error(FLUSI_EINVAL, "insect: wing_shape must be FLUSI_WING_ELLIPSE or FLUSI_WING_FOURIER");
+    if (ins->wing_shape == FLUSI_WING_FOURIER && (ins->wing_n < 0 || ins->wing_n > FLUSI_WING_MAX))
+        return set_error(FLUSI_EINVAL, "insect: Fourier wing needs 0 <= wing_n <= %d", FLUSI_WING_MAX);
+    if (!(ins->head_r >= 0.0) || !(ins->eye_r >= 0.0) || !std::isfinite(ins->head_r) || !std::isfinite(ins->eye_r))
+        return set_error(FLUSI_EINVAL, "insect: head_r and eye_r must be finite and >= 0");
+    if (!ins->free_flight) return FLUSI_OK;
     if (ins->free_flight != 1) return set_error(FLUSI_EINVAL, "insect: free_flight must be 0 or 1");
     if (colour_count(ins) == 0) return set_error(FLUSI_EINVAL, "insect: free flight needs a body or wings");
     if (!(ins->mass > 0.0) || !std::isfinite(ins->mass)) return set_error(FLUSI_EINVAL, "insect: free flight needs mass > 0");
@@ -157,6 +181,7 @@ inline int check_insect(const flusi_insect* ins) {
         if (ins->dof[i] != 0.0 && ins->dof[i] != 1.0) return set_error(FLUSI_EINVAL, "insect: dof entries must be 0 or 1");
     return FLUSI_OK;
 }
+
 
 
 struct ImplBase {
@@ -182,6 +207,23 @@ inline int launch_check(const char* what) {
     const hipError_t e = hipGetLastError();
     if (e != hipSuccess) return set_error(FLUSI_EDEVICE, "%s: %s", what, hipGetErrorString(e));
     return FLUSI_OK;
+}
+
+// Radius table of a Fourier wing: rebuilt on the stream (graph-capturable, no
+// allocation) when the coefficients differ from those it holds.
+inline int prepare_wing_table(PlanData& p, const flusi_insect* ins, hipStream_t stream) {
+    if (!ins || !ins->wings || ins->wing_shape != FLUSI_WING_FOURIER) return FLUSI_OK;
+    WingCoef c{};
+    c.n = ins->wing_n;
+    for (int i = 0; i <= ins->wing_n; ++i) {
+        c.a[i] = ins->wing_coef[0][i];
+        c.b[i] = ins->wing_coef[1][i];
+    }
+    if (p.rtab_valid && std::memcmp(&c, &p.rtab_key, sizeof(c)) == 0) return FLUSI_OK;
+    k_rtab_build<<<(unsigned)((FLUSI_RTABLE + 1 + 255) / 256), 256, 0, stream>>>(c, p.rtab, p.rtab32);
+    p.rtab_key = c;
+    p.rtab_valid = true;
+    return launch_check("wing radius table");
 }
 
 template <typename T, int N>
@@ -280,7 +322,8 @@ struct Impl final : ImplBase {
 
     int mask(PlanData& p, const flusi_insect& ins, double t, void* chi, void* us, int16_t* col) override {
         const double dx = p.L / N;
-        k_kin<<<1, 64, 0, p.stream>>>(p.kin, ins, t, dx);
+        if (int rc = prepare_wing_table(p, &ins, p.stream)) return rc;
+        k_kin<<<1, 64, 0, p.stream>>>(p.kin, ins, t, dx, p.rtab, p.rtab32);
         k_mask<T><<<(unsigned)((N3 + 255) / 256), 256, 0, p.stream>>>(p.kin, N, dx, static_cast<T*>(chi),
                                                                        static_cast<T*>(us), col);
         return launch_check("mask_insect");
@@ -505,6 +548,8 @@ struct Impl final : ImplBase {
     int step(PlanData& p, void* st, const flusi_insect* ins, const flusi_step_params& sp) override {
         const Member m = make_member(p, st, ins, sp);
         k_member_set<<<1, 64, 0, p.stream>>>(p.member_dev, m, m.nc > 0 ? *ins : flusi_insect{});
+        if (m.nc > 0)
+            if (int rc = prepare_wing_table(p, ins, p.stream)) return rc;
         GroupRun g;
         g.mt = p.member_dev;
         g.nmem = 1;

@@ -25,7 +25,18 @@ struct Kin {
     double h;          // smoothing half width
     double radius, ea, eb;       // sphere radius; ellipsoid semi-axes
     double wA, wB, wt;           // elliptic wing: half chord, half span, thickness
-    int body, wings, smooth, pad;
+    double wcen[2];    // wing outline centre in the wing plane: ellipse (0, B); Fourier wing x_c^(w)
+    double wrad;       // in-plane radius of the outline about wcen is at most this
+    double sph[3][4];  // body spheres (head, left eye, right eye): centre (body frame), radius
+    const double* rtab;  // Fourier wing radius table (FLUSI_RTABLE + 1 samples, last = first)
+    const float* rtab32; // the same rounded to FP32
+    int body, wings, smooth, wshape, nsph, pad;
+};
+
+// Radius table of a Fourier wing (Sec. 3.4): the coefficients it is built from.
+struct WingCoef {
+    int n, pad;
+    double a[FLUSI_WING_MAX + 1], b[FLUSI_WING_MAX + 1];
 };
 
 __host__ __device__ inline void mat_rx(double a, double* M) {
@@ -123,6 +134,53 @@ __host__ __device__ inline void solid_rhs(const flusi_insect& in, const double* 
     f[12] = ((Jx - Jy) * ox * oy + mb[2]) / Jz * in.dof[5];
 }
 
+// Wing angles phi, alpha, theta and their rates at time t (Sec. 3.3): the
+// sinusoid, a Fourier series a_0/2 + sum a_i cos(2 pi i f t) + b_i sin(2 pi i f t),
+// or periodic cubic Hermite interpolation of values and rates at kin_n
+// equidistant times of a period.
+__host__ __device__ inline void wing_angle_values(const flusi_insect& in, double t, double* ang, double* rate) {
+    if (in.kin_type == FLUSI_KIN_FOURIER) {
+        for (int a = 0; a < 3; ++a) {
+            double v = 0.5 * in.kin_coef[a][0][0], dv = 0.0;
+            for (int i = 1; i <= in.kin_n; ++i) {
+                const double w = 2.0 * M_PI * i * in.freq;
+                const double ai = in.kin_coef[a][0][i], bi = in.kin_coef[a][1][i];
+                const double c = cos(w * t), sn = sin(w * t);
+                v += ai * c + bi * sn;
+                dv += w * (-ai * sn + bi * c);
+            }
+            ang[a] = v;
+            rate[a] = dv;
+        }
+    } else if (in.kin_type == FLUSI_KIN_HERMITE) {
+        const int K = in.kin_n;
+        const double T = 1.0 / in.freq, h = T / K;
+        const double s = (t - floor(t / T) * T) / h;
+        int j = (int)floor(s);
+        if (j > K - 1) j = K - 1;
+        if (j < 0) j = 0;
+        const double u = s - j;
+        const int j1 = (j + 1) % K;
+        const double u2 = u * u, u3 = u2 * u;
+        const double h00 = 2 * u3 - 3 * u2 + 1, h10 = u3 - 2 * u2 + u, h01 = -2 * u3 + 3 * u2, h11 = u3 - u2;
+        const double d00 = 6 * u2 - 6 * u, d10 = 3 * u2 - 4 * u + 1, d01 = -6 * u2 + 6 * u, d11 = 3 * u2 - 2 * u;
+        for (int a = 0; a < 3; ++a) {
+            const double v0 = in.kin_coef[a][0][j], v1 = in.kin_coef[a][0][j1];
+            const double m0 = in.kin_coef[a][1][j] * h, m1 = in.kin_coef[a][1][j1] * h;
+            ang[a] = h00 * v0 + h10 * m0 + h01 * v1 + h11 * m1;
+            rate[a] = (d00 * v0 + d10 * m0 + d01 * v1 + d11 * m1) / h;
+        }
+    } else {
+        const double om = 2.0 * M_PI * in.freq;
+        const double* P[3] = {in.phi, in.alpha, in.theta};
+        for (int a = 0; a < 3; ++a) {
+            const double ph = om * t + P[a][2];
+            ang[a] = P[a][0] + P[a][1] * cos(ph);
+            rate[a] = -P[a][1] * om * sin(ph);
+        }
+    }
+}
+
 // Kinematics at time t (Sec. 3.1 and 3.3).  dx is the grid spacing.  pose
 // (13 values: x_cntr, u_cntr, eps, Omega^(b)) replaces the prescribed body
 // motion in free flight (Sec. 3.5); null for a tethered body.
@@ -176,6 +234,37 @@ __host__ __device__ __forceinline__ void compute_kin(const flusi_insect& in, dou
     double rall = 0.0;
     if (in.body == FLUSI_BODY_SPHERE) rall = in.radius + k.thr;
     if (in.body == FLUSI_BODY_ELLIPSOID) rall = 2.0 * (in.a + in.b) + k.thr;
+    // head and eye spheres of an ellipsoid body (Sec. 3.2): fixed slots head,
+    // eye at +y, eye at -y; radius 0 marks an absent sphere
+    {
+        const bool ell = in.body == FLUSI_BODY_ELLIPSOID;
+        const double hr = ell && in.head_r > 0.0 ? in.head_r : 0.0;
+        const double er = ell && in.eye_r > 0.0 ? in.eye_r : 0.0;
+        k.sph[0][0] = in.head_x[0]; k.sph[0][1] = in.head_x[1]; k.sph[0][2] = in.head_x[2]; k.sph[0][3] = hr;
+        k.sph[1][0] = in.eye_x[0]; k.sph[1][1] = in.eye_x[1]; k.sph[1][2] = in.eye_x[2]; k.sph[1][3] = er;
+        k.sph[2][0] = in.eye_x[0]; k.sph[2][1] = -in.eye_x[1]; k.sph[2][2] = in.eye_x[2]; k.sph[2][3] = er;
+        k.nsph = (hr > 0.0 || er > 0.0) ? 3 : 0;
+        for (int q = 0; q < 3; ++q)
+            if (k.sph[q][3] > 0.0)
+                rall = fmax(rall, sqrt(k.sph[q][0] * k.sph[q][0] + k.sph[q][1] * k.sph[q][1] + k.sph[q][2] * k.sph[q][2]) +
+                                      k.sph[q][3] + k.thr);
+    }
+    // wing outline: centre in the wing plane and an outer radius about it
+    k.wshape = in.wing_shape;
+    if (in.wing_shape == FLUSI_WING_FOURIER) {
+        k.wcen[0] = in.wing_c[0];
+        k.wcen[1] = in.wing_c[1];
+        double rb = fabs(0.5 * in.wing_coef[0][0]);  // |R| <= |a_0|/2 + sum |(a_i, b_i)|
+        for (int i = 1; i <= in.wing_n; ++i) rb += sqrt(in.wing_coef[0][i] * in.wing_coef[0][i] +
+                                                         in.wing_coef[1][i] * in.wing_coef[1][i]);
+        k.wrad = rb;
+    } else {
+        k.wcen[0] = 0.0;
+        k.wcen[1] = in.wing_B;
+        k.wrad = fmax(in.wing_A, in.wing_B);
+    }
+    k.rtab = nullptr;
+    k.rtab32 = nullptr;
 
     if (!in.wings) {
         // no wings: identity wing frames, zero rates, reference points at the centre
@@ -190,11 +279,9 @@ __host__ __device__ __forceinline__ void compute_kin(const flusi_insect& in, dou
         k.r2all = rall * rall;
         return;
     }
-    const double om = 2.0 * M_PI * in.freq;
-    const double ph_phi = om * t + in.phi[2], ph_al = om * t + in.alpha[2], ph_th = om * t + in.theta[2];
-    const double phi0 = in.phi[0] + in.phi[1] * cos(ph_phi), dphi0 = -in.phi[1] * om * sin(ph_phi);
-    const double al0 = in.alpha[0] + in.alpha[1] * cos(ph_al), dal0 = -in.alpha[1] * om * sin(ph_al);
-    const double th = in.theta[0] + in.theta[1] * cos(ph_th), dth = -in.theta[1] * om * sin(ph_th);
+    double ang[3], rate[3];
+    wing_angle_values(in, t, ang, rate);
+    const double phi0 = ang[0], dphi0 = rate[0], al0 = ang[1], dal0 = rate[1], th = ang[2], dth = rate[2];
     for (int s = 0; s < 2; ++s) {
         const double sg = s == 0 ? 1.0 : -1.0;  // right wing: alpha and phi mirrored
         const double phi = sg * phi0, dphi = sg * dphi0, al = sg * al0, dal = sg * dal0;
@@ -225,10 +312,10 @@ __host__ __device__ __forceinline__ void compute_kin(const flusi_insect& in, dou
         mat_tvec(k.Mb, pv, pg);
         for (int i = 0; i < 3; ++i) k.xref[1 + s][i] = k.xc[i] + pg[i];
         if (in.wings) {
-            const double mab = fmax(in.wing_A, in.wing_B);
-            const double e1 = mab + k.thr, e2 = 0.5 * in.wing_t + k.thr;
+            const double e1 = k.wrad + k.thr, e2 = 0.5 * in.wing_t + k.thr;
             const double pn = sqrt(pv[0] * pv[0] + pv[1] * pv[1] + pv[2] * pv[2]);
-            rall = fmax(rall, pn + in.wing_B + sqrt(e1 * e1 + e2 * e2));
+            const double cn = sqrt(k.wcen[0] * k.wcen[0] + k.wcen[1] * k.wcen[1]);
+            rall = fmax(rall, pn + cn + sqrt(e1 * e1 + e2 * e2));
         }
     }
     k.r2all = rall * rall;
@@ -241,9 +328,12 @@ struct KinT {
     TM Mb[9], xc[3], uc[3], omb[3], Mws[2][9], piv[2][3], omw[2][3], xref[3][3];
     TM r2all, thr, h, radius, ea, eb, wA, wB, wt;
     TM r2b;          // squared radius about xc outside which the body's chi == 0
-    TM wc[2][3];     // wing ellipse centres (global frame)
+    TM wc[2][3];     // wing outline centres (global frame)
     TM r2w;          // squared radius about wc outside which a wing's chi == 0
-    int body, wings, smooth, pad;
+    TM wcx, wcy, wrad;  // outline centre in the wing plane, outer radius about it
+    TM sph[3][4];       // body spheres: centre (body frame), radius
+    const TM* rtab;     // Fourier wing radius table in this precision
+    int body, wings, smooth, wshape, nsph, pad;
 };
 
 // FP32 tanh reaches 1 near 9.01 and FP64 tanh near 19.06: beyond these
@@ -267,6 +357,12 @@ __device__ inline void kin_cast(const Kin& a, KinT<TM>& b) {
     b.radius = TM(a.radius); b.ea = TM(a.ea); b.eb = TM(a.eb);
     b.wA = TM(a.wA); b.wB = TM(a.wB); b.wt = TM(a.wt);
     b.body = a.body; b.wings = a.wings; b.smooth = a.smooth; b.pad = 0;
+    b.wshape = a.wshape; b.nsph = a.nsph;
+    b.wcx = TM(a.wcen[0]); b.wcy = TM(a.wcen[1]); b.wrad = TM(a.wrad);
+    for (int q = 0; q < 3; ++q)
+        for (int i = 0; i < 4; ++i) b.sph[q][i] = TM(a.sph[q][i]);
+    if constexpr (sizeof(TM) == 4) b.rtab = reinterpret_cast<const TM*>(a.rtab32);
+    else b.rtab = reinterpret_cast<const TM*>(a.rtab);
     // cull radius recomputed for the precision's own tanh cut-off
     const double thr = a.smooth == FLUSI_SMOOTH_TANH ? (sizeof(TM) == 4 ? 10.0 : 20.0) * a.h : a.h;
     b.thr = TM(thr);
@@ -274,21 +370,29 @@ __device__ inline void kin_cast(const Kin& a, KinT<TM>& b) {
     // stay conservative after rounding:
     //  body: sphere delta = |r| - R; ellipsoid: if |r|^2 > (a+thr)^2 + (b+thr)^2
     //        then |x_b| > a + thr or rho > b + thr, and either way delta > thr
-    //  wing: the in-plane ellipse radius is at most max(A, B), so beyond a
-    //        distance sqrt((max(A,B)+thr)^2 + (t/2+thr)^2) from the ellipse
-    //        centre either r - R > thr or |z_w| - t/2 > thr
+    //  wing: the in-plane outline radius is at most wrad (ellipse: max(A, B)),
+    //        so beyond a distance sqrt((wrad+thr)^2 + (t/2+thr)^2) from the
+    //        outline centre either r - R > thr or |z_w| - t/2 > thr
+    //  body spheres: beyond |c| + r + thr from the body centre
     double rb2 = 0.0;
     if (a.body == FLUSI_BODY_SPHERE) rb2 = (a.radius + thr) * (a.radius + thr);
     if (a.body == FLUSI_BODY_ELLIPSOID) rb2 = (a.ea + thr) * (a.ea + thr) + (a.eb + thr) * (a.eb + thr);
+    for (int q = 0; q < 3; ++q) {
+        // a sphere's distance exceeds thr beyond |c| + r + thr from the body centre
+        if (!(a.sph[q][3] > 0.0)) continue;
+        const double e = sqrt(a.sph[q][0] * a.sph[q][0] + a.sph[q][1] * a.sph[q][1] + a.sph[q][2] * a.sph[q][2]) +
+                         a.sph[q][3] + thr;
+        rb2 = fmax(rb2, e * e);
+    }
     b.r2b = TM(rb2 * (1.0 + 1e-5));
     double rall = sqrt(rb2);
-    const double e1 = fmax(a.wA, a.wB) + thr, e2 = 0.5 * a.wt + thr;
+    const double e1 = a.wrad + thr, e2 = 0.5 * a.wt + thr;
     const double rw = sqrt(e1 * e1 + e2 * e2);
     b.r2w = TM(rw * rw * (1.0 + 1e-5));
     for (int s = 0; s < 2; ++s) {
-        // ellipse centre (0, B, 0) of the wing frame: body frame piv + (M_wing M_stroke)^T (0, B, 0)
+        // outline centre (cx, cy, 0) of the wing frame: body frame piv + (M_wing M_stroke)^T (cx, cy, 0)
         double cb[3], cg[3];
-        for (int i = 0; i < 3; ++i) cb[i] = a.piv[s][i] + a.Mws[s][3 + i] * a.wB;
+        for (int i = 0; i < 3; ++i) cb[i] = a.piv[s][i] + a.Mws[s][i] * a.wcen[0] + a.Mws[s][3 + i] * a.wcen[1];
         mat_tvec(a.Mb, cb, cg);
         for (int i = 0; i < 3; ++i) b.wc[s][i] = TM(a.xc[i] + cg[i]);
         if (a.wings) rall = fmax(rall, sqrt(cg[0] * cg[0] + cg[1] * cg[1] + cg[2] * cg[2]) + rw);
@@ -339,6 +443,21 @@ __device__ __forceinline__ void cross(const TM* a, const TM* b, TM* o) {
 // of a symmetric insect) go to the lowest colour.
 constexpr double TIE_REL = 1e-9;
 
+// Polar radius of a Fourier wing at in-plane offset (ex, ey) from its centre
+// (Sec. 3.4): angle in turns, linear interpolation in the table.  Out of line:
+// only wing points reach it, and inlined atan2 would set the register count of
+// the whole physical-space pass.
+template <typename TM>
+__device__ __attribute__((noinline)) TM table_radius(const TM* tab, TM ex, TM ey) {
+    TM v = atan2(ey, ex) / TM(2.0 * M_PI);
+    if (v < TM(0)) v += TM(1);
+    const TM pos = v * TM(FLUSI_RTABLE);
+    int j = (int)floor(pos);
+    j = j < 0 ? 0 : (j > FLUSI_RTABLE - 1 ? FLUSI_RTABLE - 1 : j);
+    const TM f = pos - TM(j);
+    return (TM(1) - f) * tab[j] + f * tab[j + 1];
+}
+
 // chi of each part (body, left wing, right wing; 0 where absent or culled) and
 // the body-frame coordinates of the point.
 template <typename TM>
@@ -354,11 +473,19 @@ __device__ __forceinline__ void part_chis(const KinT<TM>& k, TM x, TM y, TM z, T
     } else if (k.body == FLUSI_BODY_ELLIPSOID) {
         const TM q = xb[0] / k.ea;
         const TM rad = sqrt(xb[1] * xb[1] + xb[2] * xb[2]);
-        const TM d = fmax(rad - k.eb * sqrt(fmax(TM(0), TM(1) - q * q)), fabs(xb[0]) - k.ea);
+        TM d = fmax(rad - k.eb * sqrt(fmax(TM(0), TM(1) - q * q)), fabs(xb[0]) - k.ea);
+        // head and eyes: union with the thorax (Sec. 3.2)
+        if (k.nsph) {
+#pragma unroll
+            for (int p = 0; p < 3; ++p) {
+                if (!(k.sph[p][3] > TM(0))) continue;
+                const TM s0 = xb[0] - k.sph[p][0], s1 = xb[1] - k.sph[p][1], s2 = xb[2] - k.sph[p][2];
+                d = fmin(d, sqrt(s0 * s0 + s1 * s1 + s2 * s2) - k.sph[p][3]);
+            }
+        }
         c[0] = chi_of(d, k);
     }
     if (k.wings) {
-        const TM mab = fmax(k.wA, k.wB);
         for (int s = 0; s < 2; ++s) {
             const TM g0 = x - k.wc[s][0], g1 = y - k.wc[s][1], g2 = z - k.wc[s][2];
             if (g0 * g0 + g1 * g1 + g2 * g2 > k.r2w) continue;  // outside the wing's cull sphere: chi == 0
@@ -366,12 +493,17 @@ __device__ __forceinline__ void part_chis(const KinT<TM>& k, TM x, TM y, TM z, T
             TM xw[3];
             mvec(k.Mws[s], d0, xw);
             const TM dz = fabs(xw[2]) - TM(0.5) * k.wt;
-            const TM ey = xw[1] - k.wB;
-            const TM r = sqrt(xw[0] * xw[0] + ey * ey);
-            if (dz >= k.thr || r - mab >= k.thr) continue;  // chi == 0 exactly
-            const TM qa = xw[0] / k.wA, qb = ey / k.wB;
-            const TM rho = sqrt(qa * qa + qb * qb);
-            const TM inplane = r > TM(0) ? r - r / rho : -k.wA;
+            const TM ex = xw[0] - k.wcx, ey = xw[1] - k.wcy;
+            const TM r = sqrt(ex * ex + ey * ey);
+            if (dz >= k.thr || r - k.wrad >= k.thr) continue;  // chi == 0 exactly
+            TM inplane;
+            if (k.wshape == FLUSI_WING_FOURIER) {
+                inplane = r - table_radius<TM>(k.rtab, ex, ey);
+            } else {
+                const TM qa = ex / k.wA, qb = ey / k.wB;
+                const TM rho = sqrt(qa * qa + qb * qb);
+                inplane = r > TM(0) ? r - r / rho : -k.wA;
+            }
             const TM cw = chi_of(fmax(dz, inplane), k);
             if (s == 0) c[1] = cw;
             else c[2] = cw;

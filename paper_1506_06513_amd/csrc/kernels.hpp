@@ -157,6 +157,8 @@ struct Member {
     double* partial;            // NV sums per x-pass workgroup
     double* partial2;           // NV sums per first-level reduction workgroup
     const flusi_insect* ins;    // device copy of the body description
+    const double* rtab;         // Fourier wing radius table of the plan (or null)
+    const float* rtab32;
     double* history;            // FLUSI_NDIAG values per step of a call, or null
     double dx, ks, nu, eta, inv_eta;
     StepCtl ctl;
@@ -935,16 +937,19 @@ __device__ inline void reduce_level2(const double* __restrict__ partial2, double
 // the AB2 step that the previous step's diagnostics left pending (Alg. 1 step
 // (f); the quaternion is renormalized).
 __device__ __forceinline__ void kin_update(const Member& m, int p) {
-    const flusi_insect in = *m.ins;
+    // the description is read in place (it holds the series coefficients);
+    // all loads come before the stores below
+    const flusi_insect& in = *m.ins;
     StateHdr* h = m.hdr;
     Slot& sl = h->slot[p];
     const double t = sl.t;
     Kin k;
+    double y[13], f[13];
+    int st = 0;
     if (!in.free_flight) {
         compute_kin(in, t, m.dx, k);
     } else {
-        const int st = sl.ff_state;
-        double y[13];
+        st = sl.ff_state;
         if (st == 0) {
             compute_kin(in, t, m.dx, k);
             for (int i = 0; i < 3; ++i) {
@@ -953,12 +958,10 @@ __device__ __forceinline__ void kin_update(const Member& m, int p) {
                 y[10 + i] = k.omb[i];
             }
             for (int i = 0; i < 4; ++i) y[6 + i] = k.eps[i];
-            for (int i = 0; i < 13; ++i) sl.ff[i] = y[i];
-            sl.ff_have_prev = 0;
         } else {
             for (int i = 0; i < 13; ++i) y[i] = sl.ff[i];
             if (st == 2) {
-                double F[3], mm[3], f[13], fp[13];
+                double F[3], mm[3], fp[13];
                 for (int i = 0; i < 3; ++i) {
                     F[i] = sl.ff_F[i];
                     mm[i] = sl.ff_m[i];
@@ -970,23 +973,26 @@ __device__ __forceinline__ void kin_update(const Member& m, int p) {
                 for (int i = 0; i < 13; ++i) y[i] += hp ? w0 * f[i] + w1 * fp[i] : w0 * f[i];
                 const double q = 1.0 / sqrt(y[6] * y[6] + y[7] * y[7] + y[8] * y[8] + y[9] * y[9]);
                 for (int i = 6; i < 10; ++i) y[i] *= q;
-                for (int i = 0; i < 13; ++i) {
-                    sl.ff[i] = y[i];
-                    sl.ff_f[i] = f[i];
-                }
-                sl.ff_have_prev = 1;
             }
             compute_kin(in, t, m.dx, k, y);
         }
+    }
+    k.rtab = m.rtab;
+    k.rtab32 = m.rtab32;
+    // the blocks are converted straight into the header, so that the three of
+    // them are never held in registers together
+    h->kin = k;
+    kin_cast<float>(k, h->kf);
+    kin_cast<double>(k, h->kd);
+    if (in.free_flight) {
+        if (st != 1)
+            for (int i = 0; i < 13; ++i) sl.ff[i] = y[i];
+        if (st == 2)
+            for (int i = 0; i < 13; ++i) sl.ff_f[i] = f[i];
+        if (st == 0) sl.ff_have_prev = 0;
+        if (st == 2) sl.ff_have_prev = 1;
         sl.ff_state = 1;
     }
-    KinT<float> kf;
-    KinT<double> kd;
-    kin_cast<float>(k, kf);
-    kin_cast<double>(k, kd);
-    h->kin = k;
-    h->kf = kf;
-    h->kd = kd;
 }
 
 // Start of a stepping call, one thread per member: make slot 0 current and
@@ -1474,8 +1480,27 @@ __global__ void k_mask(const Kin* __restrict__ kin, int n, double dx, T* __restr
     if (colour) colour[p] = (int16_t)mp.colour;
 }
 
-static __global__ void k_kin(Kin* kin, flusi_insect ins, double t, double dx) {
-    if (threadIdx.x == 0 && blockIdx.x == 0) compute_kin(ins, t, dx, *kin);
+static __global__ void k_kin(Kin* kin, flusi_insect ins, double t, double dx, const double* rtab,
+                             const float* rtab32) {
+    if (threadIdx.x == 0 && blockIdx.x == 0) {
+        compute_kin(ins, t, dx, *kin);
+        kin->rtab = rtab;
+        kin->rtab32 = rtab32;
+    }
+}
+
+// Radius table of a Fourier wing (Sec. 3.4): R at the FLUSI_RTABLE angles
+// v_j = j / FLUSI_RTABLE in turns, plus a copy of the first sample at the end
+// for the interpolation across v = 1; FP32 copies rounded from the FP64 ones.
+static __global__ __launch_bounds__(256) void k_rtab_build(WingCoef c, double* __restrict__ tab,
+                                                           float* __restrict__ tab32) {
+    const int j = blockIdx.x * blockDim.x + threadIdx.x;
+    if (j > FLUSI_RTABLE) return;
+    const double v = (double)(j % FLUSI_RTABLE) / FLUSI_RTABLE;
+    double r = 0.5 * c.a[0];
+    for (int i = 1; i <= c.n; ++i) r += c.a[i] * cos(2.0 * M_PI * i * v) + c.b[i] * sin(2.0 * M_PI * i * v);
+    tab[j] = r;
+    tab32[j] = float(r);
 }
 
 // Pruned state spectrum [3][M][Qp] (q = my*KP + kx) -> full layout [3][n][n][n/2+1] (zeros elsewhere).
