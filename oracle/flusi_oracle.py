@@ -13,7 +13,7 @@ What it computes (paper section / equation in brackets):
   i*k, products in physical space, the 2/3 rule always on [Sec. 2.4],
 * the pressure handled by the projection of Algorithm 1 step (d) [Alg. 1],
 * Adams-Bashforth 2 with integrating factor for the viscous term [Sec. 2.4,
-  Alg. 1 step (e)],
+  Alg. 1 step (e)], or classical RK4 with explicit diffusion [Sec. 2.4],
 * the smoothed mask from a signed distance [Sec. 2.2, eq.
   smoothing_mask_as_function_of_delta],
 * the insect model: rotation matrices, body/stroke/wing frames, body and wing
@@ -53,6 +53,11 @@ listed in the design notes of the repository):
       the first step is integrating-factor Euler.
   Time step: dt = min(CFL dx / max|u|, eta_cap*C_eta (only with a mask),
       dt_max), clamped to land on t_end; or a fixed dt.
+  RK4 (the paper's second integrator, diffusion explicit): the classical
+      four stages on R = (projected, dealiased source) - nu|k|^2 u_hat with the
+      mask at t, t + dt/2, t + dt/2, t + dt; diagnostics from the first stage;
+      the adaptive dt is also kept below 2.5/(nu max|k|^2) (explicit diffusion
+      stability; the paper gives no rule).  Free flight stays with AB2.
   Mask: cosine layer with h = c_smth*dx, or 0.5*(1 - tanh(delta/(c_smth*dx)));
       delta < 0 inside the solid.
   Ellipsoid thorax: max(sqrt(y^2+z^2) - b sqrt(max(0, 1-(x/a)^2)), |x| - a).
@@ -773,6 +778,7 @@ class Params:
     mean_mode: int = MEAN_FIXED
     c_sp: float = 0.0                      # vorticity sponge constant C_sp (0: no sponge)
     sponge: tuple = (0.0, 0.0, 0.0)        # sponge layer thickness per axis (0: none on that axis)
+    integrator: str = "ab2"                # 'ab2' (integrating-factor AB2) | 'rk4' (explicit diffusion)
 
 
 def sponge_mask(g: Grid, thickness) -> np.ndarray:
@@ -859,6 +865,17 @@ def choose_dt(ctl: StepControl, umax: float, dx: float, eta: float, masked: bool
     if t + dt > ctl.t_end:
         dt = ctl.t_end - t
     return dt
+
+
+# RK4 with explicit diffusion: dt * nu * max|k|^2 is kept below this (the
+# classical RK4 is stable on the negative real axis up to about 2.785).
+RK4_VISC = 2.5
+
+
+def rk4_visc_cap(p: Params, g: Grid) -> float:
+    """Largest dt with dt * nu * max|k|^2 <= RK4_VISC over the kept modes."""
+    k2max = float(np.max(g.k2() * g.dealias()))
+    return RK4_VISC / (p.nu * k2max) if p.nu > 0.0 and k2max > 0.0 else math.inf
 
 
 def ab2_if(p: Params, g: Grid, uh, nh, nh_prev, dt, dt_prev):
@@ -948,6 +965,10 @@ def step(p: Params, st: State, ctl: StepControl, ins: Insect | None, fixed_mask=
     if not np.isfinite(umax):
         raise FloatingPointError("non-finite velocity")
     dt = choose_dt(ctl, umax, g.dx, p.eta, masked, st.t)               # (b)
+    if p.integrator == "rk4" and ctl.dt_fixed <= 0.0:
+        dt = min(dt, rk4_visc_cap(p, g))
+        if st.t + dt > ctl.t_end:
+            dt = ctl.t_end - st.t
     nphys = source_physical(u, w, 0.0 if chi is None else chi,
                             0.0 if us is None else us, p.eta)          # (c)
     nh = r2c(nphys)
@@ -969,6 +990,8 @@ def step(p: Params, st: State, ctl: StepControl, ins: Insect | None, fixed_mask=
     else:
         I_now = None
     J_now = solid_new = f_new = None
+    if p.integrator == "rk4" and ins is not None and ins.free_flight:
+        raise ValueError("free flight is stepped with AB2 only")
     if ins is not None and fixed_mask is None:
         diag["pose"] = pose_record(ins, st.t, ysol)
         diag["P_aero"] = np.array([aero_power(M[1 + k], pose.Mb, omega_wing_b(ins, st.t, side)) if ins.wings
@@ -984,11 +1007,41 @@ def step(p: Params, st: State, ctl: StepControl, ins: Insect | None, fixed_mask=
                 solid_new, f_new = solid_step(ins, ysol, st.solid_f, Ft, mt, dt, st.dt_prev)
             else:
                 solid_new, f_new = ysol, st.solid_f
+    if p.integrator == "rk4":
+        uh_new = rk4_step(p, g, st.uh, nh, st.t, dt, ins, fixed_mask)   # (e), RK4
+        new = State(uh=uh_new, nh_prev=None, t=st.t + dt, dt_prev=dt, n=st.n + 1, I_prev=I_now,
+                    J_prev=J_now, solid=solid_new, solid_f=f_new)
+        return new, diag
     uh_new = ab2_if(p, g, st.uh, nh, st.nh_prev, dt,
                     st.dt_prev if st.nh_prev is not None else dt)      # (e)
     new = State(uh=uh_new, nh_prev=nh, t=st.t + dt, dt_prev=dt, n=st.n + 1, I_prev=I_now,
                 J_prev=J_now, solid=solid_new, solid_f=f_new)
     return new, diag
+
+
+def rk4_step(p: Params, g: Grid, uh, nh1, t: float, dt: float, ins: Insect | None, fixed_mask=None):
+    """Classical fourth-order Runge-Kutta with explicit diffusion  [Sec. 2.4]:
+    R(u_hat, t) = (projected, dealiased right-hand side at t) - nu |k|^2 u_hat,
+    with the mask and solid velocity of each stage's time.  nh1 is the
+    projected right-hand side of the first stage (at u_hat, t)."""
+    k2 = g.k2()
+
+    def R(v, ts):
+        if fixed_mask is not None:
+            chi, us = fixed_mask[0], fixed_mask[1]
+        elif ins is not None:
+            chi, us, _ = insect_mask(g, ins, ts)
+        else:
+            chi = us = None
+        return rhs_hat(p, g, v, chi, us)[0] - p.nu * k2 * v
+
+    if dt <= 0.0:
+        return uh
+    k1 = nh1 - p.nu * k2 * uh
+    k2s = R(uh + 0.5 * dt * k1, t + 0.5 * dt)
+    k3 = R(uh + 0.5 * dt * k2s, t + 0.5 * dt)
+    k4 = R(uh + dt * k3, t + dt)
+    return uh + dt / 6.0 * (k1 + 2.0 * k2s + 2.0 * k3 + k4)
 
 
 def run(p: Params, u0: np.ndarray, nsteps: int, ctl: StepControl,
