@@ -67,6 +67,9 @@ extern "C" {
 #define FLUSI_SMOOTH_COS 0   /* cosine layer, Sec. 2.2 eq. smoothing_mask_as_function_of_delta */
 #define FLUSI_SMOOTH_TANH 1  /* 0.5*(1 - tanh(delta/h)) */
 
+#define FLUSI_INT_AB2 0      /* integrating-factor AB2 (Alg. 1 step (e)) */
+#define FLUSI_INT_RK4 1      /* classical RK4 with explicit diffusion (Sec. 2.4) */
+
 #define FLUSI_MEAN_FIXED 0   /* k = 0 right-hand side set to zero: the mean velocity is held */
 #define FLUSI_MEAN_FREE 1    /* k = 0 right-hand side kept */
 
@@ -194,6 +197,19 @@ int flusi_plan_destroy(flusi_plan plan);
  * (workspace) and that one state occupies, without allocating anything.
  * Errors: EINVAL, EUNSUPPORTED. */
 int flusi_sizes(int n, int dtype, size_t* workspace_bytes, size_t* state_bytes);
+
+/* Time integrator of this plan's later flusi_step calls (Sec. 2.4).
+ * FLUSI_INT_AB2 (default): integrating-factor AB2 as in Algorithm 1.
+ * FLUSI_INT_RK4: classical fourth-order Runge-Kutta with explicit diffusion,
+ * du_hat/dt = P D FFT(u x w - (chi/C_eta)(u - u_s) [+ sponge]) - nu |k|^2 u_hat,
+ * with the mask and solid velocity at t, t + dt/2, t + dt/2 and t + dt; the
+ * diagnostics record is that of the first stage; the adaptive dt is also kept
+ * below 2.5/(nu max|k|^2) over the kept modes (explicit diffusion stability).
+ * RK4 allocates three fields of stage velocity (synchronously, once) and uses
+ * the state's AB2 history storage for its stage sum, so a later AB2 step
+ * starts with Euler.  RK4 plans step alone: free flight and ensembles are
+ * AB2 only.  Errors: EINVAL, ENOMEM. */
+int flusi_plan_set_integrator(flusi_plan plan, int integrator);
 
 /* Vorticity sponge (Sec. 2.3, wake removal; the sponge term of eq.
  * PNST_org_momentum) for every later step of this plan: the right-hand side

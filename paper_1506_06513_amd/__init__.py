@@ -44,6 +44,7 @@ class FlusiError(RuntimeError):
         self.code = code
 
 
+FLUSI_INT_AB2, FLUSI_INT_RK4 = 0, 1
 FLUSI_KIN_SINE, FLUSI_KIN_FOURIER, FLUSI_KIN_HERMITE = 0, 1, 2
 FLUSI_KIN_MAX = 24
 FLUSI_WING_ELLIPSE, FLUSI_WING_FOURIER = 0, 1
@@ -133,6 +134,7 @@ _SIGS = {
     "flusi_step": (ctypes.c_int, [_P, _P, ctypes.POINTER(flusi_insect), ctypes.POINTER(flusi_step_params)]),
     "flusi_forces": (ctypes.c_int, [_P, _P, ctypes.POINTER(ctypes.c_double)]),
     "flusi_state_solid": (ctypes.c_int, [_P, _P, ctypes.POINTER(ctypes.c_double)]),
+    "flusi_plan_set_integrator": (ctypes.c_int, [_P, ctypes.c_int]),
     "flusi_state_set_solid": (ctypes.c_int, [_P, _P, ctypes.POINTER(ctypes.c_double)]),
     "flusi_profile": (ctypes.c_int, [_P, ctypes.c_int]),
     "flusi_pass_times": (ctypes.c_int, [_P, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_longlong)]),
@@ -565,6 +567,10 @@ class Plan:
 
     def set_solid(self, state, y):
         flusi_state_set_solid(self.handle, state, y)
+
+    def set_integrator(self, name: str):
+        """'ab2' (integrating-factor AB2, default) or 'rk4' (explicit diffusion)."""
+        _check(lib().flusi_plan_set_integrator(self.handle, {"ab2": FLUSI_INT_AB2, "rk4": FLUSI_INT_RK4}[name]))
 
     def set_sponge(self, c_sp: float, thickness=(0.0, 0.0, 0.0)):
         """Vorticity sponge (layers at the top end of the axes with thickness > 0)."""

@@ -105,7 +105,7 @@ static int check_plan(flusi_plan p) {
 }
 static void free_plan(PlanData& d) {
     void* ptrs[] = {d.tw, d.bufA, d.bufB, d.partial, d.partial2, d.kin, d.ins_dev, d.member_dev, d.pmax, d.spec, d.phys,
-                    d.rtab, d.rtab32};
+                    d.rtab, d.rtab32, d.ustage};
     for (void* q : ptrs)
         if (q) (void)hipFree(q);
     for (hipEvent_t e : d.events) (void)hipEventDestroy(e);
@@ -361,6 +361,24 @@ int flusi_plan_set_sponge(flusi_plan plan, double c_sp, const double* thickness)
     return FLUSI_OK;
 }
 
+int flusi_plan_set_integrator(flusi_plan plan, int integrator) {
+    if (int rc = check_plan(plan)) return rc;
+    if (integrator != FLUSI_INT_AB2 && integrator != FLUSI_INT_RK4)
+        return set_error(FLUSI_EINVAL, "set_integrator: FLUSI_INT_AB2 or FLUSI_INT_RK4");
+    PlanData& d = plan->d;
+    if (integrator == FLUSI_INT_RK4 && !d.ustage) {
+        const size_t need = d.impl->field3_bytes();
+        if (hipMalloc(&d.ustage, need) != hipSuccess) {
+            d.ustage = nullptr;
+            return set_error(FLUSI_ENOMEM, "set_integrator: stage velocity");
+        }
+        d.ustage_sz = need;
+        d.workspace += need;
+    }
+    d.integrator = integrator;
+    return FLUSI_OK;
+}
+
 int flusi_set_stream(flusi_plan plan, void* stream) {
     if (int rc = check_plan(plan)) return rc;
     plan->d.stream = static_cast<hipStream_t>(stream);
@@ -473,6 +491,8 @@ int flusi_step(flusi_plan plan, void* state, const flusi_insect* ins, const flus
     if (int rc = check_insect(ins)) return rc;
     if (p->nsteps < 0) return set_error(FLUSI_EINVAL, "step: nsteps < 0");
     if (!(p->dt_fixed > 0.0) && !(p->cfl > 0.0)) return set_error(FLUSI_EINVAL, "step: need dt_fixed > 0 or cfl > 0");
+    if (plan->d.integrator == FLUSI_INT_RK4 && free_flight_on(ins))
+        return set_error(FLUSI_EUNSUPPORTED, "step: free flight is stepped with AB2 only");
     if (p->nsteps == 0) return FLUSI_OK;
     return plan->d.impl->step(plan->d, state, ins, *p);
 }
@@ -535,6 +555,7 @@ int flusi_autotune(flusi_plan plan, const void* state, const flusi_insect* ins, 
         g.n_nc[m.sponge][colour_slot(m.nc)] = 1;
         g.any_dyn = m.dyn != 0;
         g.any_ff = m.ff != 0;
+        g.rk = m.rk != 0;
         g.tw = d.tw;
         g.stream = d.stream;
         rc = tune_group(d.impl, g, d, reps, &best);
@@ -762,6 +783,7 @@ int flusi_ensemble_add(flusi_ensemble e, flusi_plan plan, void* state, const flu
     if (!state || !p) return set_error(FLUSI_EINVAL, "ensemble_add: null pointer");
     if (int rc = check_insect(ins)) return rc;
     if (plan->d.dtype != e->dtype) return set_error(FLUSI_EINVAL, "ensemble_add: plan dtype differs from the ensemble's");
+    if (plan->d.integrator != FLUSI_INT_AB2) return set_error(FLUSI_EUNSUPPORTED, "ensemble_add: ensembles step with AB2 only");
     if (!(p->dt_fixed > 0.0) && !(p->cfl > 0.0)) return set_error(FLUSI_EINVAL, "ensemble_add: need dt_fixed > 0 or cfl > 0");
     for (const auto& m : e->members)
         if (m.used && m.plan == plan) return set_error(FLUSI_EINVAL, "ensemble_add: plan is already a member");

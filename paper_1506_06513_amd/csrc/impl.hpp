@@ -37,6 +37,9 @@ struct PlanData {
     double* partial2 = nullptr;
     Kin* kin = nullptr;
     flusi_insect* ins_dev = nullptr;  // device copy of the insect of the current stepping call
+    int integrator = FLUSI_INT_AB2;   // FLUSI_INT_*
+    void* ustage = nullptr;           // RK4 stage velocity (3 state fields), allocated when RK4 is chosen
+    size_t ustage_sz = 0;
     double* rtab = nullptr;           // Fourier wing radius table (FLUSI_RTABLE + 1 samples) ...
     float* rtab32 = nullptr;          // ... and its FP32 copy
     WingCoef rtab_key{};              // coefficients the table holds
@@ -100,6 +103,7 @@ struct GroupRun {
     int n_nc[2][3] = {{0, 0, 0}, {0, 0, 0}};  // members [without, with sponge][nc = 0, 1, 3]
     bool any_dyn = false;
     bool any_ff = false;      // some member is in free flight
+    bool rk = false;          // RK4 integrator (single-plan runs)
     const void* tw = nullptr;
     Sched sched;
     hipStream_t stream = nullptr;
@@ -144,6 +148,13 @@ inline Member make_member(const PlanData& p, void* st, const flusi_insect* ins, 
     m.dyn = kin_dynamic(ins);
     m.sponge = sponge_on(p) ? 1 : 0;
     m.ff = free_flight_on(ins);
+    m.rk = p.integrator == FLUSI_INT_RK4 ? 1 : 0;
+    m.ustage = p.ustage;
+    if (m.rk && p.nu > 0.0 && p.K > 0) {
+        // explicit diffusion: dt * nu * max|k|^2 <= 2.5 (RK4 is stable to about 2.785)
+        const double kmax = p.K * 2.0 * M_PI / p.L;
+        m.ctl.visc_cap = 2.5 / (p.nu * 3.0 * kmax * kmax);
+    }
     m.inv_csp = m.sponge ? 1.0 / p.c_sp : 0.0;
     for (int a = 0; a < 3; ++a) m.sp_lo[a] = (m.sponge && p.sp_thick[a] > 0.0) ? p.L - p.sp_thick[a] : 1e300;
     return m;
@@ -191,6 +202,7 @@ struct ImplBase {
     virtual size_t bufB_elems() const = 0;
     virtual int nwg_x() const = 0;
     virtual size_t state_bytes() const = 0;
+    virtual size_t field3_bytes() const = 0;  // three state fields (the RK4 stage velocity)
     virtual int fft_r2c(PlanData&, const void*, void*, int) = 0;
     virtual int fft_c2r(PlanData&, const void*, void*, int) = 0;
     virtual int mask(PlanData&, const flusi_insect&, double, void*, void*, int16_t*) = 0;
@@ -257,6 +269,7 @@ struct Impl final : ImplBase {
 
     static CX* st_uhat(void* st) { return reinterpret_cast<CX*>(static_cast<char*>(st) + STATE_HDR_BYTES); }
     static long st_fs() { return (long)((field_bytes() + 255) / 256 * 256 / sizeof(CX)); }
+    size_t field3_bytes() const override { return 3 * ((field_bytes() + 255) / 256 * 256); }
     static CX* st_nold(void* st) { return st_uhat(st) + 3 * st_fs(); }
 
     const CX* tw(const PlanData& p) const { return static_cast<const CX*>(p.tw); }
@@ -433,31 +446,31 @@ struct Impl final : ImplBase {
         else xpass_v<0>(g);
     }
     template <int MODE, int V, bool SP>
-    static void zpass_launch(const GroupRun& g, const Member* mt, int nmem, int par, int s) {
-        // update modes: one more workgroup per member (diagnostics, next level)
-        constexpr int nb = NBZ + ((MODE == MODE_STEP || MODE == MODE_STEP_LAST) ? 1 : 0);
+    static void zpass_launch(const GroupRun& g, const Member* mt, int nmem, int par, int s, int rk) {
+        // modes with the reduction: one more workgroup per member (diagnostics, next level)
+        constexpr int nb = NBZ + ((MODE == MODE_STEP || MODE == MODE_STEP_LAST || MODE == MODE_RK1) ? 1 : 0);
         if (nmem > 0)
             k_zpass<T, N, MODE, V, SP><<<(unsigned)(nb * nmem), nt_z(N, V), 0, g.stream>>>(
-                mt, static_cast<const CX*>(g.tw), par, s);
+                mt, static_cast<const CX*>(g.tw), par, s, rk);
     }
     // update modes: members without the sponge, then those with it (the table
     // is ordered that way); other modes: all members in one launch
     template <int MODE, int V>
-    static void zpass_v(const GroupRun& g, int par, int s) {
-        constexpr bool update = MODE == MODE_STEP || MODE == MODE_STEP_LAST;
+    static void zpass_v(const GroupRun& g, int par, int s, int rk) {
+        constexpr bool update = MODE == MODE_STEP || MODE == MODE_STEP_LAST || MODE == MODE_RK1 || MODE == MODE_RKS;
         const int nsp = g.n_nc[1][0] + g.n_nc[1][1] + g.n_nc[1][2];
         if (update && nsp) {
-            zpass_launch<MODE, V, false>(g, g.mt, g.nmem - nsp, par, s);
-            zpass_launch<MODE, V, update>(g, g.mt + (g.nmem - nsp), nsp, par, s);
+            zpass_launch<MODE, V, false>(g, g.mt, g.nmem - nsp, par, s, rk);
+            zpass_launch<MODE, V, update>(g, g.mt + (g.nmem - nsp), nsp, par, s, rk);
         } else {
-            zpass_launch<MODE, V, false>(g, g.mt, g.nmem, par, s);
+            zpass_launch<MODE, V, false>(g, g.mt, g.nmem, par, s, rk);
         }
     }
     template <int MODE>
-    static void zpass(const GroupRun& g, int par = 0, int s = 0) {
-        if (g.sched.z_pass == 2) zpass_v<MODE, 2>(g, par, s);
-        else if (g.sched.z_pass == 1) zpass_v<MODE, 1>(g, par, s);
-        else zpass_v<MODE, 0>(g, par, s);
+    static void zpass(const GroupRun& g, int par = 0, int s = 0, int rk = 0) {
+        if (g.sched.z_pass == 2) zpass_v<MODE, 2>(g, par, s, rk);
+        else if (g.sched.z_pass == 1) zpass_v<MODE, 1>(g, par, s, rk);
+        else zpass_v<MODE, 0>(g, par, s, rk);
     }
 
     Sched default_sched() const override {
@@ -466,8 +479,54 @@ struct Impl final : ImplBase {
         return d;
     }
 
+    // RK4 (Sec. 2.4): four pipeline passes per step.  The first stage reduces
+    // the x-pass sums, picks dt and writes the diagnostics and the next time
+    // level; the others use that dt, the kinematics of their own time and no
+    // reduction.  The z-pass is always the fused form here.
+    int run_steps_rk(const GroupRun& g, int nsteps) {
+        {
+            PassScope ps(g.prof, PASS_KIN, g.stream);
+            k_prologue<<<(unsigned)((g.nmem + 63) / 64), 64, 0, g.stream>>>(g.mt, g.nmem);
+        }
+        {
+            PassScope ps(g.prof, PASS_ZINV, g.stream);
+            zpass<MODE_INVERSE>(g);
+        }
+        const unsigned nbk = (unsigned)((g.nmem + 63) / 64);
+        for (int s = 0; s < nsteps; ++s) {
+            const int par = s & 1;
+            for (int stage = 1; stage <= 4; ++stage) {
+                if (g.any_dyn && (stage > 1 || s > 0)) {
+                    PassScope ps(g.prof, PASS_KIN, g.stream);
+                    if (stage == 1) k_kin_level<<<nbk, 64, 0, g.stream>>>(g.mt, g.nmem, par);
+                    else k_kin_stage<<<nbk, 64, 0, g.stream>>>(g.mt, g.nmem, par, stage == 4 ? 1.0 : 0.5);
+                }
+                {
+                    PassScope ps(g.prof, PASS_YINV, g.stream);
+                    y_inverse(g);
+                }
+                {
+                    PassScope ps(g.prof, PASS_X, g.stream);
+                    xpass(g);
+                }
+                {
+                    PassScope ps(g.prof, PASS_YFWD, g.stream);
+                    y_forward(g, stage == 1);
+                }
+                {
+                    PassScope ps(g.prof, PASS_Z, g.stream);
+                    const int inv = (stage < 4 || s + 1 < nsteps) ? 16 : 0;
+                    if (stage == 1) zpass<MODE_RK1>(g, par, s, inv);
+                    else zpass<MODE_RKS>(g, par, s, stage | inv);
+                }
+            }
+        }
+        return launch_check("step");
+    }
+
     int run_steps(const GroupRun& g, int nsteps) override {
         if (g.nmem <= 0 || nsteps <= 0) return FLUSI_OK;
+        if (g.rk) return run_steps_rk(g, nsteps);
         {
             PassScope ps(g.prof, PASS_KIN, g.stream);
             k_prologue<<<(unsigned)((g.nmem + 63) / 64), 64, 0, g.stream>>>(g.mt, g.nmem);
@@ -556,6 +615,7 @@ struct Impl final : ImplBase {
         g.n_nc[m.sponge][colour_slot(m.nc)] = 1;
         g.any_dyn = m.dyn != 0;
         g.any_ff = m.ff != 0;
+        g.rk = m.rk != 0;
         g.tw = p.tw;
         g.sched = p.sched;
         g.stream = p.stream;

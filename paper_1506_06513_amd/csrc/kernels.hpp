@@ -105,6 +105,7 @@ struct Solid13 {
 struct StepCtl {
     double dt_fixed, cfl, dt_max, eta_cap, t_end;
     int masked, mean_mode, kin_dynamic, pad;
+    double visc_cap;  // RK4: adaptive dt <= visc_cap (explicit diffusion); 0: none
 };
 
 // Per-time-level scalars of a state.
@@ -126,6 +127,8 @@ struct Slot {
     double ff_f[13];
     double ff_F[3], ff_m[3];  // total force and torque about x_cntr (global frame)
     double ff_w[2];           // dt*b1, dt*b2
+    double rk_dt;             // RK4: step size of the step that produced this level (0: no step)
+    double rk_pad[3];
 };
 
 // Device-resident per-state scalars (first 4 KiB of a state buffer).  The time
@@ -167,6 +170,8 @@ struct Member {
     int dyn;                    // kinematics change with time
     int sponge;                 // vorticity sponge on: 3 more forward fields (chi_sp w)
     int ff;                     // free flight: the body pose is integrated
+    int rk;                     // RK4 integrator (stage velocity in ustage)
+    void* ustage;               // RK4 stage velocity [3] (state field layout)
     double inv_csp;             // 1/C_sp
     double sp_lo[3];            // chi_sp = 1 where x_a >= sp_lo[a] for some axis a
 };
@@ -697,6 +702,7 @@ __device__ inline Coef step_coef(const double* tot, const Slot& sl, StepCtl ctl,
         dt = c.umax > 0.0 ? ctl.cfl * dx / c.umax : INFINITY;
         if (ctl.masked) dt = fmin(dt, ctl.eta_cap * eta);
         if (ctl.dt_max > 0.0) dt = fmin(dt, ctl.dt_max);
+        if (ctl.visc_cap > 0.0) dt = fmin(dt, ctl.visc_cap);
     }
     if (ctl.t_end > 0.0 && sl.t + dt > ctl.t_end) dt = ctl.t_end - sl.t;
     if (!isfinite(dt)) {
@@ -726,7 +732,7 @@ __device__ inline Coef step_coef(const double* tot, const Slot& sl, StepCtl ctl,
 // level's kinematics).  Values go to memory as they are formed and the loops
 // over parts stay rolled: this code shares the z-pass kernel's registers.
 __device__ inline void write_step(StateHdr* h, int p, const double* tot, const Coef& c, StepCtl ctl, double dx,
-                                  double eta, double* history, int ff) {
+                                  double eta, double* history, int ff, int rk) {
     const Slot& sl = h->slot[p];
     Slot& nx = h->slot[1 - p];
     if (c.bad) {
@@ -801,7 +807,7 @@ __device__ inline void write_step(StateHdr* h, int p, const double* tot, const C
         static_assert(sizeof(Slot) % 8 == 0, "slot copy by words");
         const double* src = reinterpret_cast<const double*>(&sl);
         double* dst = reinterpret_cast<double*>(&nx);
-        constexpr int W = (int)(sizeof(Slot) / 8), B = 6;
+        constexpr int W = (int)(sizeof(Slot) / 8), B = 8;
         static_assert(W % B == 0, "slot copy batches");
 #pragma unroll 1
         for (int i = 0; i < W; i += B) {
@@ -842,11 +848,12 @@ __device__ inline void write_step(StateHdr* h, int p, const double* tot, const C
             nx.ff_state = 0;
             nx.ff_have_prev = 0;
         }
-        nx.have_prev = 1;
+        nx.have_prev = rk ? 0 : 1;  // RK4 leaves no AB2 history (its stages use that storage)
         nx.dt_prev = c.dt;
         nx.t = sl.t + c.dt;
         nx.n = sl.n + 1;
     }
+    nx.rk_dt = c.active ? c.dt : 0.0;
     h->cur = 1 - p;
 }
 
@@ -1019,6 +1026,28 @@ static __global__ __launch_bounds__(64) void k_kin_level(const Member* __restric
     if (m.dyn && !m.hdr->status) kin_update(m, p);
 }
 
+// Kinematics at time t (no free flight), converted into the header's blocks.
+__device__ __forceinline__ void kin_update_at(const Member& m, double t) {
+    const flusi_insect& in = *m.ins;
+    StateHdr* h = m.hdr;
+    Kin k;
+    compute_kin(in, t, m.dx, k);
+    k.rtab = m.rtab;
+    k.rtab32 = m.rtab32;
+    h->kin = k;
+    kin_cast<float>(k, h->kf);
+    kin_cast<double>(k, h->kd);
+}
+
+// RK4 stage kinematics (one thread per moving member): time t^n + c*dt, with
+// t^n in slot p and dt in the slot the step's first stage wrote.
+static __global__ __launch_bounds__(64) void k_kin_stage(const Member* __restrict__ mt, int nmem, int p, double c) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= nmem) return;
+    const Member& m = mt[i];
+    if (m.dyn && !m.hdr->status) kin_update_at(m, m.hdr->slot[p].t + c * m.hdr->slot[1 - p].rk_dt);
+}
+
 // Free-flight state of the current time level of a state (one thread).
 static __global__ void k_solid_set(StateHdr* h, Solid13 y) {
     if (threadIdx.x == 0 && blockIdx.x == 0) {
@@ -1055,21 +1084,27 @@ static __global__ void k_hdr_init(StateHdr* hdr, double t0) {
 // MODE_STEP_LAST : as MODE_STEP without the inverse part
 // MODE_INVERSE   : curl and inverse z from the state uhat
 // ---------------------------------------------------------------------------
-enum { MODE_IMPORT = 0, MODE_STEP = 1, MODE_STEP_LAST = 2, MODE_INVERSE = 3 };
+enum { MODE_IMPORT = 0, MODE_STEP = 1, MODE_STEP_LAST = 2, MODE_INVERSE = 3, MODE_RK1 = 4, MODE_RKS = 5 };
+// RK4 (MODE_RK1: first stage, with the reduction, dt and the step writer;
+// MODE_RKS: stages 2-4): k_s = P N_hat - nu |k|^2 u_s; the sum k1 + 2 k2 + 2 k3
+// is kept in the state's second field set, the stage velocity in ustage;
+// stage 4 writes u^{n+1} = u^n + dt/6 (sum + k4).  rk = stage (2..4) | 16 when
+// the curl and inverse z of the new velocity follow.
 
 // Member table: ceil(Q/C) workgroups per member.  par: slot of the current
 // time level; s: step index within the call (row of the history).
 // SP: the members have the vorticity sponge (fields 3..5 of the forward input).
 template <typename T, int N, int MODE, int V, bool SP = false>
 __global__ __launch_bounds__(nt_z(N, V)) void k_zpass(const Member* __restrict__ mt, const cx<T>* __restrict__ tw,
-                                                      int par, int s) {
+                                                      int par, int s, int rk) {
     using G = Geo<T, N>;
     constexpr int K = G::K, KP = G::KP, M = G::M, Q = G::Q, Qp = G::Qp;
     constexpr int C = cols_z(N), NTZ = nt_z(N, V);
     constexpr int NBZ = (Q + C - 1) / C;
     // update modes: one more workgroup per member writes the diagnostics and
     // the next time level, beside the column workgroups
-    constexpr bool STEPM = (MODE == MODE_STEP || MODE == MODE_STEP_LAST);
+    constexpr bool STEPM = (MODE == MODE_STEP || MODE == MODE_STEP_LAST || MODE == MODE_RK1);
+    constexpr bool RKM = (MODE == MODE_RK1 || MODE == MODE_RKS);
     constexpr int NBZ1 = NBZ + (STEPM ? 1 : 0);
     // state fields: [uhat 3][nold 3], each padded to 256 bytes
     constexpr long fs_s = (((long)M * Qp * (long)sizeof(cx<T>) + 255) / 256 * 256) / (long)sizeof(cx<T>);
@@ -1107,7 +1142,7 @@ __global__ __launch_bounds__(nt_z(N, V)) void k_zpass(const Member* __restrict__
     const double kxv = kscale * kxi;
     const double kyv = kscale * j_of_m(myi, K);
 
-    const bool step_mode = (MODE == MODE_STEP || MODE == MODE_STEP_LAST);
+    const bool step_mode = (MODE == MODE_STEP || MODE == MODE_STEP_LAST || RKM);
     // forward input: field f+1 is loaded while field f is transformed; field 0
     // is in flight together with the reduction loads
     constexpr bool FWD = (MODE == MODE_IMPORT) || step_mode;
@@ -1118,27 +1153,30 @@ __global__ __launch_bounds__(nt_z(N, V)) void k_zpass(const Member* __restrict__
             vn[i] = okq ? gld(yin, f * fs_y + (long)(r0 + i * RS) * Qp + q) : cx<T>{T(0), T(0)};
     };
     if constexpr (FWD) load_field(0);
-    if (step_mode) {
+    if constexpr (STEPM) {
         reduce_level2<NTZ, nred_of(N)>(partial2, reinterpret_cast<double*>(smem), tot);
         if (tile == NBZ) {
             if (tid == 0)
                 write_step(hdr, par, tot, step_coef(tot, hdr->slot[par], mb.ctl, dx, eta), mb.ctl, dx, eta,
-                           mb.history ? mb.history + (long)s * FLUSI_NDIAG : nullptr, mb.ff);
+                           mb.history ? mb.history + (long)s * FLUSI_NDIAG : nullptr, mb.ff, mb.rk);
             return;
         }
         if (tid == 0) cf = step_coef(tot, hdr->slot[par], mb.ctl, dx, eta);
         __syncthreads();
         if (cf.bad) return;
     }
-    const bool active = step_mode ? (cf.active != 0) : true;
+    // RK stages 2-4: the step size the first stage chose (0: no step)
+    const double rdt = MODE == MODE_RKS ? *gview(&hdr->slot[1 - par].rk_dt) : 0.0;
+    if (MODE == MODE_RKS && !(rdt > 0.0)) return;
+    const bool active = STEPM ? (cf.active != 0) : true;
     const bool do_fwd = (MODE == MODE_IMPORT) || (step_mode && active);
-    const bool do_inv = (MODE == MODE_STEP) || (MODE == MODE_INVERSE);
+    const bool do_inv = (MODE == MODE_STEP) || (MODE == MODE_INVERSE) || (RKM && (rk & 16));
 
     // kept kz of this thread: m = r0 + i*RS, i < PERM
     cx<T> U[3][PERM];
     if (do_fwd) {
         // vorticity sponge: fields 3..5 hold chi_sp * w
-        constexpr bool sp = SP && (MODE == MODE_STEP || MODE == MODE_STEP_LAST);
+        constexpr bool sp = SP && (MODE == MODE_STEP || MODE == MODE_STEP_LAST || RKM);
         cx<T> Nh[3][PERM];
 #pragma unroll
         for (int f = 0; f < 3; ++f) {
@@ -1192,13 +1230,16 @@ __global__ __launch_bounds__(nt_z(N, V)) void k_zpass(const Member* __restrict__
         }
         double dt = 0, b1 = 0, b2 = 0, dtp = 0;
         int first = 1;
-        if (step_mode) {
+        if (STEPM) {
             dt = cf.dt;
             b1 = cf.b1;
             b2 = cf.b2;
             dtp = cf.dtp;
             first = cf.first;
         }
+        if (MODE == MODE_RKS) dt = rdt;
+        const int stage = MODE == MODE_RK1 ? 1 : (rk & 15);
+        glb<cx<T>>* ust = gview(static_cast<cx<T>*>(mb.ustage));
 #pragma unroll
         for (int i = 0; i < PERM; ++i) {
             const int m = r0 + i * RS;
@@ -1226,6 +1267,35 @@ __global__ __launch_bounds__(nt_z(N, V)) void k_zpass(const Member* __restrict__
                     for (int f = 0; f < 3; ++f) {
                         U[f][i] = cx<T>{T(nr[f]), T(ni[f])};
                         gst(uhat, f * fs_s + e, U[f][i]);
+                    }
+                } else if constexpr (RKM) {
+                    const double nk2 = nu * k2;
+#pragma unroll
+                    for (int f = 0; f < 3; ++f) {
+                        const cx<T> un = gld(uhat, f * fs_s + e);
+                        const cx<T> us = stage == 1 ? un : gld(ust, f * fs_s + e);
+                        const double kr = nr[f] - nk2 * (double)us.x, ki = ni[f] - nk2 * (double)us.y;
+                        double vr, vi;
+                        if (stage == 4) {
+                            const cx<T> a = gld(nold, f * fs_s + e);
+                            vr = (double)un.x + dt / 6.0 * ((double)a.x + kr);
+                            vi = (double)un.y + dt / 6.0 * ((double)a.y + ki);
+                            U[f][i] = cx<T>{T(vr), T(vi)};
+                            gst(uhat, f * fs_s + e, U[f][i]);
+                        } else {
+                            double ar = kr, ai = ki;
+                            if (stage > 1) {
+                                const cx<T> a = gld(nold, f * fs_s + e);
+                                ar = (double)a.x + 2.0 * kr;
+                                ai = (double)a.y + 2.0 * ki;
+                            }
+                            gst(nold, f * fs_s + e, cx<T>{T(ar), T(ai)});
+                            const double cs = stage == 3 ? dt : 0.5 * dt;
+                            vr = (double)un.x + cs * kr;
+                            vi = (double)un.y + cs * ki;
+                            U[f][i] = cx<T>{T(vr), T(vi)};
+                            gst(ust, f * fs_s + e, U[f][i]);
+                        }
                     }
                 } else {
                     const double e1 = exp(-nu * k2 * dt);
