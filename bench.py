@@ -16,8 +16,9 @@ region (--no-autotune: defaults).  The default run adds two sub-objects:
 `ensemble48` (48 seeded insect simulations on mixed grids advanced by batched
 launches replayed from a hipGraph, against the same members stepped one by one)
 and `serving` (a Poisson-arrival request stream with a 512^3 insect: p50/p99
-latency and throughput), plus `sponge` and `freeflight` (the same sphere
-workload with a vorticity sponge layer, and with the sphere in free flight).
+latency and throughput), plus `sponge`, `freeflight` and `rk4` (the same
+sphere workload with a vorticity sponge layer, with the sphere in free flight,
+and stepped with RK4).
 --workload selects freefall128, insect256, tg32, ensemble48 or serve as the
 main line instead.
 """
@@ -154,10 +155,11 @@ def build_workload(name: str):
     raise SystemExit(f"unknown workload {name}")
 
 
-def gpu_run(F, torch, wl, dtype, steps, warmup, tune=True, sponge=None):
+def gpu_run(F, torch, wl, dtype, steps, warmup, tune=True, sponge=None, integrator="ab2"):
     P = F.Plan(wl["n"], wl["L"], wl["nu"], wl["eta"], dtype)
     if sponge:
         P.set_sponge(*sponge)
+    P.set_integrator(integrator)
     kw = dict(dt_fixed=wl["dt_fixed"], cfl=wl["cfl"], eta_cap=0.5, mean_mode=F.FLUSI_MEAN_FIXED)
     u0 = torch.from_numpy(wl["u0"])
     st = P.new_state(u0)
@@ -314,6 +316,7 @@ def main():
     ap.add_argument("--no-serve", action="store_true", help="skip the serving-stream figure")
     ap.add_argument("--no-sponge", action="store_true", help="skip the vorticity-sponge figure")
     ap.add_argument("--no-freeflight", action="store_true", help="skip the free-flight figure")
+    ap.add_argument("--no-rk4", action="store_true", help="skip the RK4 figure")
     ap.add_argument("--no-ensemble", action="store_true", help="skip the batched-ensemble figure")
     ap.add_argument("--no-autotune", action="store_true", help="time the default schedules")
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
@@ -443,6 +446,15 @@ def main():
                                             "6 DoF): 13-value body state advanced each step",
                              "body_at_last_step_f32": {"t": d[0], "x_cntr": list(d[22:25]), "u_cntr": list(d[25:28]),
                                                        "omega_b": list(d[32:35])}}
+    if not a.no_rk4 and a.workload == "sphere128":
+        # the same workload with the RK4 integrator (explicit diffusion, 4 stages per step)
+        rk = {}
+        for dtype in ("f32", "f64"):
+            r = gpu_run(F, torch, wl, dtype, max(10, steps // 4), a.warmup, tune=not a.no_autotune, integrator="rk4")
+            rk[dtype] = round(pts * max(10, steps // 4) / (r["ev_ms"] / 1e3) / 1e6, 2)
+        out["rk4"] = {"value": rk["f32"], "fp64": rk["f64"], "unit": "Mpoint-steps/s",
+                      "description": "sphere128 stepped with classical RK4 and explicit diffusion "
+                                     "(four pipeline passes per step)"}
     if not a.no_cpu:
         cs = oracle_sample(wl)
         cpu_v = pts * cs["timed_steps"] / cs["seconds"] / 1e6
