@@ -105,12 +105,17 @@ def kernel_of_pass(pass_name: str, n: int, real: str, sched: dict, nc: int, dyn:
     """Kernel name (as rocprofv3 prints it) of a pass under a schedule."""
     split = sched["split_z"]
     return {
-        "z_pass": f"k_zpass<{real}, {n}, {2 if split else 1}, {sched['z_pass']}>",
-        "z_inverse": f"k_zpass<{real}, {n}, 3, {sched['z_pass']}>",
-        "x_pass": f"k_xpass<{real}, {n}, {nc}, {sched['x_pass']}>",
+        "z_pass": f"k_zpass<{real}, {n}, {2 if split else 1}, {sched['z_pass']}, false>",
+        "z_inverse": f"k_zpass<{real}, {n}, 3, {sched['z_pass']}, false>",
+        "x_pass": f"k_xpass<{real}, {n}, {nc}, {sched['x_pass']}, false>",
         "y_inverse": f"k_ypass<{real}, {n}, 1, 0, {sched['y_inverse']}>",
         "y_forward": f"k_ypass<{real}, {n}, -1, 1, {sched['y_forward']}>",
     }[pass_name]
+
+
+def note(msg: str):
+    """Progress line on stderr (the JSON result line goes to stdout)."""
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
 def free_sphere(body: dict) -> dict:
@@ -365,6 +370,7 @@ def main():
     res = {}
     for dtype in ("f32", "f64"):
         res[dtype] = gpu_run(F, torch, wl, dtype, steps, a.warmup, tune=not a.no_autotune)
+        note(f"{a.workload} {dtype}: {res[dtype]['ev_ms'] / steps:.4f} ms/step")
 
     def mps(r):
         return pts * steps / (r["ev_ms"] / 1e3) / 1e6
@@ -422,14 +428,17 @@ def main():
     }
     if not a.no_ensemble and a.workload == "sphere128":
         out["ensemble48"] = ensemble_run(F, torch, tune=not a.no_autotune)
+        note("ensemble48 done")
     if not a.no_serve and a.workload == "sphere128":
         out["serving"] = serve_run(F, torch)
+        note("serving done")
     if not a.no_sponge and a.workload == "sphere128":
         # the same workload with a vorticity sponge layer 3.5 <= x < 4 (C_sp = 0.1)
         sp = {}
         for dtype in ("f32", "f64"):
             r = gpu_run(F, torch, wl, dtype, steps, a.warmup, tune=not a.no_autotune, sponge=(0.1, (0.5, 0.0, 0.0)))
             sp[dtype] = round(pts * steps / (r["ev_ms"] / 1e3) / 1e6, 2)
+        note("sponge done")
         out["sponge"] = {"value": sp["f32"], "fp64": sp["f64"], "unit": "Mpoint-steps/s",
                          "description": "sphere128 with the vorticity sponge on 3.5 <= x < 4, C_sp = 0.1 "
                                         "(3 more forward fields per step)"}
@@ -441,6 +450,7 @@ def main():
             r = gpu_run(F, torch, dict(wl, insect=ff_body), dtype, steps, a.warmup, tune=not a.no_autotune)
             ff[dtype] = (round(pts * steps / (r["ev_ms"] / 1e3) / 1e6, 2), r["diag"])
         d = ff["f32"][1]
+        note("free flight done")
         out["freeflight"] = {"value": ff["f32"][0], "fp64": ff["f64"][0], "unit": "Mpoint-steps/s",
                              "description": "sphere128 with the sphere in free flight (density 2, g = 1 along -z, "
                                             "6 DoF): 13-value body state advanced each step",
@@ -452,10 +462,12 @@ def main():
         for dtype in ("f32", "f64"):
             r = gpu_run(F, torch, wl, dtype, max(10, steps // 4), a.warmup, tune=not a.no_autotune, integrator="rk4")
             rk[dtype] = round(pts * max(10, steps // 4) / (r["ev_ms"] / 1e3) / 1e6, 2)
+        note("rk4 done")
         out["rk4"] = {"value": rk["f32"], "fp64": rk["f64"], "unit": "Mpoint-steps/s",
                       "description": "sphere128 stepped with classical RK4 and explicit diffusion "
                                      "(four pipeline passes per step)"}
     if not a.no_cpu:
+        note("cpu baseline (oracle) running")
         cs = oracle_sample(wl)
         cpu_v = pts * cs["timed_steps"] / cs["seconds"] / 1e6
         out["cpu_baseline"] = {"value": round(cpu_v, 3), "unit": "Mpoint-steps/s", "cores": cs["cores"],
