@@ -110,6 +110,11 @@ static void free_plan(PlanData& d) {
         if (q) (void)hipFree(q);
     for (hipEvent_t e : d.events) (void)hipEventDestroy(e);
     d.events.clear();
+    if (d.ev_z) (void)hipEventDestroy(d.ev_z);
+    if (d.ev_k) (void)hipEventDestroy(d.ev_k);
+    if (d.side) (void)hipStreamDestroy(d.side);
+    d.ev_z = d.ev_k = nullptr;
+    d.side = nullptr;
     delete d.impl;
     d.impl = nullptr;
 }
@@ -276,6 +281,9 @@ int flusi_plan_create(int nx, int ny, int nz, double L, double nu, double eta, i
     ok = ok && hipMalloc(&d.member_dev, sizeof(Member)) == hipSuccess;
     ok = ok && hipMalloc(&d.rtab, RTAB_BYTES64) == hipSuccess;
     ok = ok && hipMalloc(&d.rtab32, RTAB_BYTES32) == hipSuccess;
+    ok = ok && hipStreamCreateWithFlags(&d.side, hipStreamNonBlocking) == hipSuccess;
+    ok = ok && hipEventCreateWithFlags(&d.ev_z, hipEventDisableTiming) == hipSuccess;
+    ok = ok && hipEventCreateWithFlags(&d.ev_k, hipEventDisableTiming) == hipSuccess;
     d.sched = impl->default_sched();
     if (!ok) {
         free_plan(d);
