@@ -20,8 +20,8 @@ What it computes (paper section / equation in brackets):
   velocity fields [Sec. 3.1-3.3, eqs. M_body_yawpitchroll,
   body_velocity_field, wing_velocity_field], wing angles as sinusoids,
   Fourier or Hermite series [Sec. 3.3], body shape with head and eyes
-  [Sec. 3.2] and the polar-radius wing shape, closed-form ellipse or Fourier
-  series through a 25 000-sample table [Sec. 3.4],
+  [Sec. 3.2] and the wing shapes: polar radius (closed-form ellipse or
+  Fourier series through a 25 000-sample table) or rectangle [Sec. 3.4],
 * force and torque from the penalization integral with the unsteady
   correction [Sec. 2.1, eqs. force_with_unst_corrections, moment_of_love],
 * the time loop of Algorithm 1 (mask -> dt -> sources -> projection -> AB2
@@ -83,6 +83,12 @@ listed in the design notes of the repository):
   Fourier wing: the series variable is the polar angle in turns (angle/2pi,
       counterclockwise from +x_w about x_c^(w)); the table holds 25 000
       samples at j/25 000 and is interpolated linearly and periodically.
+  Rectangular wing: the printed distance repeats the sign of its first chord
+      term; read as max(x - b, -x - (B - b), y - tip, a - y, |z| - t/2), a
+      chord of length B from -(B - b) to b and a span from a to tip (the
+      printed tip is 1, the normalized pivot-to-tip distance).  The printed
+      example value a = 1.6667 leaves that span empty; 0.16667 gives the
+      aspect ratio 2 of its chord 0.4167.
   Body parts: head and eye spheres get radii (not printed) and join the
       thorax as a union, i.e. the minimum of the signed distances (with
       delta < 0 inside, the printed maximum would be the intersection).
@@ -307,7 +313,11 @@ class Insect:
     kin_phi: tuple = ((), ())            # fourier: (a_0..a_n), (b_0..b_n); hermite: (values), (rates)
     kin_alpha: tuple = ((), ())
     kin_theta: tuple = ((), ())
-    wing_shape: str = "ellipse"          # 'ellipse' | 'fourier'  [Sec. 3.4]
+    wing_shape: str = "ellipse"          # 'ellipse' | 'fourier' | 'rectangle'  [Sec. 3.4]
+    rect_a: float = 0.0                  # rectangle: span from rect_a ...
+    rect_tip: float = 1.0                # ... to rect_tip along y_w
+    rect_b: float = 0.0                  # rectangle: leading edge at x_w = rect_b ...
+    rect_B: float = 0.0                  # ... chord rect_B (trailing edge at -(B - b))
     wing_c: tuple = (0.0, 0.0)           # fourier wing: centre x_c^(w) in the wing plane
     wing_fa: tuple = ()                  # fourier wing: a_0..a_n
     wing_fb: tuple = ()                  # fourier wing: b_0..b_n (b_0 unused)
@@ -495,6 +505,14 @@ def delta_fourier_wing(xw, yw, zw, ins: Insect, table: np.ndarray):
     return np.maximum(np.abs(zw) - 0.5 * ins.wing_t, r - wing_radius_lookup(table, v))
 
 
+def delta_rect_wing(xw, yw, zw, ins: Insect):
+    """Rectangular wing  [Sec. 3.4, eq. signed_distance_rectangular_wing]:
+    the intersection of the half-spaces x_w <= b, x_w >= -(B - b), y_w <= tip,
+    y_w >= a and |z_w| <= t/2, i.e. the maximum of their signed distances."""
+    return np.maximum.reduce([xw - ins.rect_b, -xw - (ins.rect_B - ins.rect_b), yw - ins.rect_tip,
+                              ins.rect_a - yw, np.abs(zw) - 0.5 * ins.wing_t])
+
+
 def delta_body(ins: Insect, xb):
     """Body signed distance in the body frame  [Sec. 3.2]: the thorax
     ellipsoid joined with the head and eye spheres (union: min of the
@@ -628,6 +646,8 @@ def mask_at(ins: Insect, t: float, dx: float, x, y, z, pose: Pose | None = None)
             xw = wing_frame(ins, t, side, xb)
             if table is not None:
                 d = delta_fourier_wing(xw[0], xw[1], xw[2], ins, table)
+            elif ins.wing_shape == "rectangle":
+                d = delta_rect_wing(xw[0], xw[1], xw[2], ins)
             else:
                 d = delta_elliptic_wing(xw[0], xw[1], xw[2], ins.wing_A, ins.wing_B, ins.wing_t)
             chis.append(chi_of_delta(d, ins, dx))

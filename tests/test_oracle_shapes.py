@@ -162,3 +162,42 @@ def test_head_and_eyes_join_the_thorax():
     # the eyes are a mirrored pair
     e = O.delta_body(ins, np.array([[0.36, 0.05, 0.02], [0.36, -0.05, 0.02]]).T)
     assert abs(e[0] - e[1]) < 1e-15
+
+
+def test_rectangular_wing_is_the_intersection_of_half_spaces():
+    ins = O.Insect(wing_shape="rectangle", rect_a=0.16667, rect_tip=1.0, rect_b=0.0667, rect_B=0.4167,
+                   wing_t=0.04171)
+    B, b, a, tip = ins.rect_B, ins.rect_b, ins.rect_a, ins.rect_tip
+    # centre: minus the smallest half-width (here the thickness)
+    xm, ym = b - B / 2, (a + tip) / 2
+    d0 = O.delta_rect_wing(np.array([xm]), np.array([ym]), np.array([0.0]), ins)[0]
+    assert abs(d0 + min(B / 2, (tip - a) / 2, ins.wing_t / 2)) < 1e-15
+    # outside along each axis through the centre: the distance to that face
+    for x, y, dist in ((b + 0.1, ym, 0.1), (b - B - 0.05, ym, 0.05), (xm, tip + 0.2, 0.2), (xm, a - 0.03, 0.03)):
+        assert abs(O.delta_rect_wing(np.array([x]), np.array([y]), np.array([0.0]), ins)[0] - dist) < 1e-14
+    # in-plane area B (tip - a)
+    m = 1200
+    gx = (np.arange(m) + 0.5) / m * 0.6 - 0.4
+    gy = (np.arange(m) + 0.5) / m * 1.2 - 0.1
+    X, Y = np.meshgrid(gx, gy, indexing="ij")
+    inside = O.delta_rect_wing(X, Y, np.zeros_like(X), ins) < 0.0
+    area = inside.sum() * (0.6 / m) * (1.2 / m)
+    assert abs(area - B * (tip - a)) < 3e-3 * B * (tip - a)
+    # the printed a = 1.6667 leaves an empty span below the unit tip
+    bad = O.Insect(wing_shape="rectangle", rect_a=1.6667, rect_tip=1.0, rect_b=b, rect_B=B, wing_t=0.04171)
+    assert np.all(O.delta_rect_wing(X, Y, np.zeros_like(X), bad) > 0.0)
+
+
+def test_rectangular_wing_insect_is_mirror_symmetric():
+    n, L = 48, 4.0
+    d = W.model_insect(n, L)
+    d.update(wing_shape="rectangle", rect_a=0.1, rect_tip=0.55, rect_b=0.06, rect_B=0.25)
+    ins = O.Insect.from_dict(d)
+    g = O.Grid(n, L)
+    chi, us, col = O.insect_mask(g, ins, 0.29)
+    assert np.sum(col == 2) > 50 and np.sum(col == 3) > 50
+    mir = lambda a: np.roll(a[:, ::-1, :], 1, axis=1)
+    assert np.max(np.abs(chi - mir(chi))) < 1e-12
+    swap = np.where(col == 2, 3, np.where(col == 3, 2, col))
+    ok = chi > 1e-9
+    assert np.array_equal(mir(swap)[ok], col[ok])
