@@ -61,6 +61,7 @@ extern "C" {
 
 #define FLUSI_WING_ELLIPSE 0 /* elliptic outline: half chord wing_A, half span wing_B, centre (0, B) */
 #define FLUSI_WING_FOURIER 1 /* polar-radius outline R(v) as a Fourier series (Sec. 3.4) */
+#define FLUSI_WING_RECT 2    /* rectangle: chord [-(B - b), b] along x_w, span [a, tip] along y_w */
 #define FLUSI_WING_MAX 32    /* radius harmonics */
 #define FLUSI_RTABLE 25000   /* samples of the radius table (Sec. 3.4) */
 
@@ -165,6 +166,10 @@ typedef struct {
      * thorax as a union (minimum of the signed distances).  Radius 0: none. */
     double head_x[3], head_r;
     double eye_x[3], eye_r;
+    /* Rectangular wing (Sec. 3.4, eq. signed_distance_rectangular_wing, read as
+     * max(x - b, -x - (B - b), y - tip, a - y, |z| - t/2)): wing_rect = {a, tip,
+     * b, B}; thickness wing_t. */
+    double wing_rect[4];
 } flusi_insect;
 
 /* Controls of flusi_step (Algorithm 1 steps (a)-(e)). */

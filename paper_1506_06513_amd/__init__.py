@@ -47,11 +47,11 @@ class FlusiError(RuntimeError):
 FLUSI_INT_AB2, FLUSI_INT_RK4 = 0, 1
 FLUSI_KIN_SINE, FLUSI_KIN_FOURIER, FLUSI_KIN_HERMITE = 0, 1, 2
 FLUSI_KIN_MAX = 24
-FLUSI_WING_ELLIPSE, FLUSI_WING_FOURIER = 0, 1
+FLUSI_WING_ELLIPSE, FLUSI_WING_FOURIER, FLUSI_WING_RECT = 0, 1, 2
 FLUSI_WING_MAX = 32
 FLUSI_RTABLE = 25000
 _KIN = {"sine": FLUSI_KIN_SINE, "fourier": FLUSI_KIN_FOURIER, "hermite": FLUSI_KIN_HERMITE}
-_WING = {"ellipse": FLUSI_WING_ELLIPSE, "fourier": FLUSI_WING_FOURIER}
+_WING = {"ellipse": FLUSI_WING_ELLIPSE, "fourier": FLUSI_WING_FOURIER, "rectangle": FLUSI_WING_RECT}
 
 
 class flusi_insect(ctypes.Structure):
@@ -75,6 +75,7 @@ class flusi_insect(ctypes.Structure):
         ("wing_coef", (ctypes.c_double * (FLUSI_WING_MAX + 1)) * 2),
         ("head_x", ctypes.c_double * 3), ("head_r", ctypes.c_double),
         ("eye_x", ctypes.c_double * 3), ("eye_r", ctypes.c_double),
+        ("wing_rect", ctypes.c_double * 4),
     ]
 
 
@@ -465,6 +466,9 @@ def make_insect(d: dict | None) -> flusi_insect | None:
             s.wing_coef[0][i] = float(fa[i])
             s.wing_coef[1][i] = float(fb[i])
         s.wing_c[:] = [float(v) for v in d.get("wing_c", (0.0, 0.0))]
+    if s.wing_shape == FLUSI_WING_RECT:
+        s.wing_rect[:] = [float(d.get(k, dv)) for k, dv in
+                          (("rect_a", 0.0), ("rect_tip", 1.0), ("rect_b", 0.0), ("rect_B", 0.0))]
     s.head_x[:] = [float(v) for v in d.get("head_x", (0.0, 0.0, 0.0))]
     s.head_r = float(d.get("head_r", 0.0))
     s.eye_x[:] = [float(v) for v in d.get("eye_x", (0.0, 0.0, 0.0))]

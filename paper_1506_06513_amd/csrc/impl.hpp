@@ -181,8 +181,11 @@ inline int check_insect(const flusi_insect* ins) {
         return set_error(FLUSI_EINVAL, "insect: Fourier kinematics need 0 <= kin_n <= %d", FLUSI_KIN_MAX);
     if (ins->kin_type == FLUSI_KIN_HERMITE && (ins->kin_n < 2 || ins->kin_n > FLUSI_KIN_MAX || !(ins->freq > 0.0)))
         return set_error(FLUSI_EINVAL, "insect: Hermite kinematics need 2 <= kin_n <= %d and freq > 0", FLUSI_KIN_MAX);
-    if (ins->wing_shape != FLUSI_WING_ELLIPSE && ins->wing_shape != FLUSI_WING_FOURIER)
-        return set_error(FLUSI_EINVAL, "insect: wing_shape must be FLUSI_WING_ELLIPSE or FLUSI_WING_FOURIER");
+    if (ins->wing_shape != FLUSI_WING_ELLIPSE && ins->wing_shape != FLUSI_WING_FOURIER &&
+        ins->wing_shape != FLUSI_WING_RECT)
+        return set_error(FLUSI_EINVAL, "insect: wing_shape must be FLUSI_WING_ELLIPSE, _FOURIER or _RECT");
+    if (ins->wing_shape == FLUSI_WING_RECT && !(ins->wing_rect[3] > 0.0 && ins->wing_rect[1] > ins->wing_rect[0]))
+        return set_error(FLUSI_EINVAL, "insect: rectangular wing needs B > 0 and tip > a");
     if (ins->wing_shape == FLUSI_WING_FOURIER && (ins->wing_n < 0 || ins->wing_n > FLUSI_WING_MAX))
         return set_error(FLUSI_EINVAL, "insect: Fourier wing needs 0 <= wing_n <= %d", FLUSI_WING_MAX);
     if (!(ins->head_r >= 0.0) || !(ins->eye_r >= 0.0) || !std::isfinite(ins->head_r) || !std::isfinite(ins->eye_r))

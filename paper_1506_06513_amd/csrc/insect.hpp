@@ -258,6 +258,17 @@ __host__ __device__ __forceinline__ void compute_kin(const flusi_insect& in, dou
         for (int i = 1; i <= in.wing_n; ++i) rb += sqrt(in.wing_coef[0][i] * in.wing_coef[0][i] +
                                                          in.wing_coef[1][i] * in.wing_coef[1][i]);
         k.wrad = rb;
+    } else if (in.wing_shape == FLUSI_WING_RECT) {
+        // rectangle about its centre: half chord and half span in wA, wB
+        const double a = in.wing_rect[0], tip = in.wing_rect[1], b = in.wing_rect[2], B = in.wing_rect[3];
+        k.wcen[0] = b - 0.5 * B;
+        k.wcen[1] = 0.5 * (a + tip);
+        k.wA = 0.5 * B;
+        k.wB = 0.5 * (tip - a);
+        // delta = max(|ex| - wA, |ey| - wB) stays below thr only inside the box
+        // widened by thr, whose circumscribed circle has radius wrad + thr
+        // (wrad grows with thr, so the FP64 cut-off also covers the FP32 one)
+        k.wrad = sqrt((k.wA + k.thr) * (k.wA + k.thr) + (k.wB + k.thr) * (k.wB + k.thr)) - k.thr;
     } else {
         k.wcen[0] = 0.0;
         k.wcen[1] = in.wing_B;
@@ -499,6 +510,8 @@ __device__ __forceinline__ void part_chis(const KinT<TM>& k, TM x, TM y, TM z, T
             TM inplane;
             if (k.wshape == FLUSI_WING_FOURIER) {
                 inplane = r - table_radius<TM>(k.rtab, ex, ey);
+            } else if (k.wshape == FLUSI_WING_RECT) {
+                inplane = fmax(fabs(ex) - k.wA, fabs(ey) - k.wB);
             } else {
                 const TM qa = ex / k.wA, qb = ey / k.wB;
                 const TM rho = sqrt(qa * qa + qb * qb);

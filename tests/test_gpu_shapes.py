@@ -68,8 +68,12 @@ def _part_stack(ins, g, t):
     tab = O.wing_radius_table(ins.wing_fa, ins.wing_fb) if ins.wing_shape == "fourier" else None
     for s in "lr":
         xw = O.wing_frame(ins, t, s, xb)
-        d = (O.delta_fourier_wing(xw[0], xw[1], xw[2], ins, tab) if tab is not None else
-             O.delta_elliptic_wing(xw[0], xw[1], xw[2], ins.wing_A, ins.wing_B, ins.wing_t))
+        if tab is not None:
+            d = O.delta_fourier_wing(xw[0], xw[1], xw[2], ins, tab)
+        elif ins.wing_shape == "rectangle":
+            d = O.delta_rect_wing(xw[0], xw[1], xw[2], ins)
+        else:
+            d = O.delta_elliptic_wing(xw[0], xw[1], xw[2], ins.wing_A, ins.wing_B, ins.wing_t)
         chis.append(O.chi_of_delta(d, ins, g.dx))
     return np.stack(chis)
 
@@ -93,6 +97,40 @@ def test_fourier_wing_and_head_mask_matches_oracle(dtype):
         assert np.max(np.abs(np_of(us)[:, ok] - us_o[:, ok])) <= (1e-12 if dtype == "f64" else 3e-5)
         # both wings and the head are present
         assert np.sum(col_o == 2) > 100 and np.sum(col_o == 3) > 100
+
+
+def rect_wing_insect(n, **kw):
+    d = W.model_insect(n, L)
+    d.update(wing_shape="rectangle", rect_a=0.1, rect_tip=0.55, rect_b=0.06, rect_B=0.25)
+    d.update(kw)
+    return d
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+def test_rectangular_wing_mask_and_steps_match_oracle(dtype):
+    n = 96
+    d = rect_wing_insect(n)
+    ins = O.Insect.from_dict(d)
+    g = O.Grid(n, L)
+    P = F.Plan(n, L, 0.01, 1e-3, dtype)
+    for t in (0.0, 0.23):
+        chi_o, us_o, col_o = O.insect_mask(g, ins, t)
+        chi, us, col = P.mask(d, t)
+        assert np.max(np.abs(np_of(chi) - chi_o)) <= (1e-13 if dtype == "f64" else 3e-5)
+        st = np.sort(_part_stack(ins, g, t), axis=0)
+        gap = 1e-9 if dtype == "f64" else 1e-5
+        ok = ~((st[-1] > 0) & (np.abs(st[-1] - st[-2]) < gap)) & (chi_o > (1e-12 if dtype == "f64" else 1e-6))
+        assert np.array_equal(np_of(col)[ok].astype(int), col_o[ok])
+        assert np.sum(col_o == 2) > 100
+    m, nu, eta, steps = 48, 1 / 136, 5e-4, 6
+    body = rect_wing_insect(m)
+    u0 = W.inflow_noise(m, L, seed=42, rms=1e-2, kmax=6.0)
+    p = O.Params(m, L, nu, eta, O.MEAN_FIXED)
+    ost, _ = O.run(p, u0, steps, O.StepControl(cfl=0.1), O.Insect.from_dict(body))
+    Q = F.Plan(m, L, nu, eta, dtype)
+    s = Q.new_state(torch.from_numpy(u0))
+    Q.step(s, steps, body, cfl=0.1)
+    assert rel_l2(Q.velocity(s).cpu().numpy(), O.velocity(p, ost)) < (1e-11 if dtype == "f64" else 2e-5)
 
 
 @pytest.mark.parametrize("kin", ["fourier", "hermite"])

@@ -21,8 +21,8 @@ def test_library_exports_every_header_function():
 
 def test_struct_layouts_match_header():
     # flusi_insect: 4 ints + 47 doubles, then 4 ints, the angle series, the Fourier wing and the
-    # head/eye spheres; flusi_step_params: 2 ints, 5 doubles, 1 pointer
-    assert ctypes.sizeof(F.flusi_insect) == 16 + 8 * 47 + 16 + 8 * (3 * 2 * 25 + 2 + 2 * 33 + 8)
+    # head/eye spheres and the rectangle; flusi_step_params: 2 ints, 5 doubles, 1 pointer
+    assert ctypes.sizeof(F.flusi_insect) == 16 + 8 * 47 + 16 + 8 * (3 * 2 * 25 + 2 + 2 * 33 + 8 + 4)
     assert ctypes.sizeof(F.flusi_step_params) == 8 + 5 * 8 + 8
 
 
