@@ -39,20 +39,32 @@ struct WingCoef {
     double a[FLUSI_WING_MAX + 1], b[FLUSI_WING_MAX + 1];
 };
 
+// sin and cos of one angle, out of line: the kinematics evaluate some twenty
+// of them in a one-thread kernel, and one shared copy of the FP64 expansion
+// keeps that kernel's code (fetched cold every launch) short.  Returned by
+// value (registers), so callers keep their matrices in registers.
+struct SinCos {
+    double s, c;
+};
+__host__ __device__ __attribute__((noinline)) inline SinCos sin_cos(double x) { return SinCos{sin(x), cos(x)}; }
+
 __host__ __device__ inline void mat_rx(double a, double* M) {
-    const double c = cos(a), s = sin(a);
+    const SinCos q = sin_cos(a);
+    const double c = q.c, s = q.s;
     M[0] = 1; M[1] = 0; M[2] = 0;
     M[3] = 0; M[4] = c; M[5] = s;
     M[6] = 0; M[7] = -s; M[8] = c;
 }
 __host__ __device__ inline void mat_ry(double a, double* M) {
-    const double c = cos(a), s = sin(a);
+    const SinCos q = sin_cos(a);
+    const double c = q.c, s = q.s;
     M[0] = c; M[1] = 0; M[2] = -s;
     M[3] = 0; M[4] = 1; M[5] = 0;
     M[6] = s; M[7] = 0; M[8] = c;
 }
 __host__ __device__ inline void mat_rz(double a, double* M) {
-    const double c = cos(a), s = sin(a);
+    const SinCos q = sin_cos(a);
+    const double c = q.c, s = q.s;
     M[0] = c; M[1] = s; M[2] = 0;
     M[3] = -s; M[4] = c; M[5] = 0;
     M[6] = 0; M[7] = 0; M[8] = 1;
@@ -101,9 +113,8 @@ __host__ __device__ inline void quat_mbody(const double* e, double* M) {
 
 // Quaternion of roll psi, pitch beta, yaw gamma (Sec. 3.5).
 __host__ __device__ inline void quat_of_angles(double psi, double beta, double gam, double* e) {
-    const double cp = cos(0.5 * psi), sp = sin(0.5 * psi);
-    const double cb = cos(0.5 * beta), sb = sin(0.5 * beta);
-    const double cg = cos(0.5 * gam), sg = sin(0.5 * gam);
+    const SinCos qp = sin_cos(0.5 * psi), qb = sin_cos(0.5 * beta), qg = sin_cos(0.5 * gam);
+    const double cp = qp.c, sp = qp.s, cb = qb.c, sb = qb.s, cg = qg.c, sg = qg.s;
     e[0] = cp * cb * cg + sp * sb * sg;
     e[1] = sp * cb * cg - cp * sb * sg;
     e[2] = cp * sb * cg + sp * cb * sg;
@@ -145,7 +156,8 @@ __host__ __device__ inline void wing_angle_values(const flusi_insect& in, double
             for (int i = 1; i <= in.kin_n; ++i) {
                 const double w = 2.0 * M_PI * i * in.freq;
                 const double ai = in.kin_coef[a][0][i], bi = in.kin_coef[a][1][i];
-                const double c = cos(w * t), sn = sin(w * t);
+                const SinCos q = sin_cos(w * t);
+                const double c = q.c, sn = q.s;
                 v += ai * c + bi * sn;
                 dv += w * (-ai * sn + bi * c);
             }
@@ -175,8 +187,9 @@ __host__ __device__ inline void wing_angle_values(const flusi_insect& in, double
         const double* P[3] = {in.phi, in.alpha, in.theta};
         for (int a = 0; a < 3; ++a) {
             const double ph = om * t + P[a][2];
-            ang[a] = P[a][0] + P[a][1] * cos(ph);
-            rate[a] = -P[a][1] * om * sin(ph);
+            const SinCos q = sin_cos(ph);
+            ang[a] = P[a][0] + P[a][1] * q.c;
+            rate[a] = -P[a][1] * om * q.s;
         }
     }
 }
