@@ -76,6 +76,9 @@ listed in the design notes of the repository):
       with I = sum chi u_s dV (no unsteady term at the first step); torques
       about the body centre (body) or the wing pivot (wings).
   Energy: E = 1/2 sum |u|^2 dV.
+  Dirichlet walls: layers at the top end of chosen axes (sharp, placed like
+      the sponge's) where chi = 1 and u_s = u_wall; they take precedence over a
+      body and carry colour 0 (outside the body's force integrals).
   Wing angle series: Fourier coefficients use the convention of eq.
       Fourier_radious_wing with the phase f t (in periods) as the variable;
       Hermite coefficients are values and rates at K equidistant times of
@@ -799,6 +802,8 @@ class Params:
     c_sp: float = 0.0                      # vorticity sponge constant C_sp (0: no sponge)
     sponge: tuple = (0.0, 0.0, 0.0)        # sponge layer thickness per axis (0: none on that axis)
     integrator: str = "ab2"                # 'ab2' (integrating-factor AB2) | 'rk4' (explicit diffusion)
+    wall: tuple = (0.0, 0.0, 0.0)          # Dirichlet layer thickness per axis (0: none on that axis)
+    u_wall: tuple = (0.0, 0.0, 0.0)        # velocity imposed in the layers
 
 
 def sponge_mask(g: Grid, thickness) -> np.ndarray:
@@ -811,6 +816,28 @@ def sponge_mask(g: Grid, thickness) -> np.ndarray:
         if d > 0.0:
             chi = np.where(c >= g.L - d, 1.0, chi)
     return chi
+
+
+def walls_on(p: Params) -> bool:
+    return any(d > 0.0 for d in p.wall)
+
+
+def apply_walls(p: Params, g: Grid, chi, us, colour):
+    """Dirichlet layers  [Sec. 2.3]: the velocity u_wall is imposed by the
+    volume penalization in layers at the top end of the axes with thickness
+    > 0 (placed like the sponge's).  There chi = 1 and u_s = u_wall; the layers
+    take precedence over a body, and their points carry colour 0, so they do
+    not enter the body's force integrals."""
+    if not walls_on(p):
+        return chi, us, colour
+    wm = sponge_mask(g, p.wall) > 0.0
+    shp = wm.shape
+    chi = np.zeros(shp) if chi is None else chi
+    us = np.zeros((3,) + shp) if us is None else us
+    colour = np.zeros(shp, dtype=np.int16) if colour is None else colour
+    uw = np.asarray(p.u_wall, dtype=np.float64).reshape(3, 1, 1, 1)
+    return (np.where(wm, 1.0, chi), np.where(wm[None], np.broadcast_to(uw, us.shape), us),
+            np.where(wm, 0, colour).astype(np.int16))
 
 
 def sponge_hat(g: Grid, w: np.ndarray, chi_sp: np.ndarray, c_sp: float) -> np.ndarray:
@@ -966,7 +993,7 @@ def step(p: Params, st: State, ctl: StepControl, ins: Insect | None, fixed_mask=
     fixed_mask = (chi, u_s, colour, xref) replaces the insect by a
     time-independent mask (used by tests)."""
     g = Grid(p.n, p.L)
-    masked = ins is not None or fixed_mask is not None
+    masked = ins is not None or fixed_mask is not None or walls_on(p)
     if fixed_mask is not None:
         chi, us, colour, xref = fixed_mask
     elif ins is not None:
@@ -980,6 +1007,10 @@ def step(p: Params, st: State, ctl: StepControl, ins: Insect | None, fixed_mask=
         xref = reference_points(ins, st.t, pose)
     else:
         chi = us = colour = xref = None
+    if walls_on(p):
+        chi, us, colour = apply_walls(p, g, chi, us, colour)
+        if xref is None:
+            xref = np.zeros((3, 3))
     u, w = physical_fields(g, st.uh)                                   # u^n, w^n
     umax = umax_of(u)
     if not np.isfinite(umax):
@@ -1053,6 +1084,7 @@ def rk4_step(p: Params, g: Grid, uh, nh1, t: float, dt: float, ins: Insect | Non
             chi, us, _ = insect_mask(g, ins, ts)
         else:
             chi = us = None
+        chi, us, _ = apply_walls(p, g, chi, us, None)
         return rhs_hat(p, g, v, chi, us)[0] - p.nu * k2 * v
 
     if dt <= 0.0:
