@@ -216,6 +216,18 @@ int flusi_sizes(int n, int dtype, size_t* workspace_bytes, size_t* state_bytes);
  * AB2 only.  Errors: EINVAL, ENOMEM. */
 int flusi_plan_set_integrator(flusi_plan plan, int integrator);
 
+/* Dirichlet layers (Sec. 2.3: velocity conditions imposed by the volume
+ * penalization, e.g. u = u_infinity at the domain borders or channel walls)
+ * for every later step of this plan: chi = 1 and u_s = u_wall where x_a >=
+ * L - thickness[a] for an axis a with thickness[a] > 0 (sharp layers at the
+ * top end of the axes, placed like the sponge's).  The layers take
+ * precedence over a body and are not part of its force integrals (their
+ * points carry colour 0); a step with layers applies the C_eta step cap.
+ * thickness and u_wall are host arrays of 3 doubles (NULL: zeros).  All
+ * thicknesses 0 switch the layers off.  Errors: EINVAL (thickness outside
+ * [0, L], non-finite velocity). */
+int flusi_plan_set_walls(flusi_plan plan, const double* thickness, const double* u_wall);
+
 /* Vorticity sponge (Sec. 2.3, wake removal; the sponge term of eq.
  * PNST_org_momentum) for every later step of this plan: the right-hand side
  * gains -(1/C_sp) (i k x W_hat)/|k|^2 with W = chi_sp * w, the Biot-Savart form

@@ -136,6 +136,7 @@ _SIGS = {
     "flusi_forces": (ctypes.c_int, [_P, _P, ctypes.POINTER(ctypes.c_double)]),
     "flusi_state_solid": (ctypes.c_int, [_P, _P, ctypes.POINTER(ctypes.c_double)]),
     "flusi_plan_set_integrator": (ctypes.c_int, [_P, ctypes.c_int]),
+    "flusi_plan_set_walls": (ctypes.c_int, [_P, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double)]),
     "flusi_state_set_solid": (ctypes.c_int, [_P, _P, ctypes.POINTER(ctypes.c_double)]),
     "flusi_profile": (ctypes.c_int, [_P, ctypes.c_int]),
     "flusi_pass_times": (ctypes.c_int, [_P, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_longlong)]),
@@ -575,6 +576,12 @@ class Plan:
     def set_integrator(self, name: str):
         """'ab2' (integrating-factor AB2, default) or 'rk4' (explicit diffusion)."""
         _check(lib().flusi_plan_set_integrator(self.handle, {"ab2": FLUSI_INT_AB2, "rk4": FLUSI_INT_RK4}[name]))
+
+    def set_walls(self, thickness=(0.0, 0.0, 0.0), u_wall=(0.0, 0.0, 0.0)):
+        """Dirichlet layers at the top end of the axes with thickness > 0, u = u_wall there."""
+        th = (ctypes.c_double * 3)(*[float(v) for v in thickness])
+        uw = (ctypes.c_double * 3)(*[float(v) for v in u_wall])
+        _check(lib().flusi_plan_set_walls(self.handle, th, uw))
 
     def set_sponge(self, c_sp: float, thickness=(0.0, 0.0, 0.0)):
         """Vorticity sponge (layers at the top end of the axes with thickness > 0)."""

@@ -340,6 +340,23 @@ int flusi_sizes(int n, int dtype, size_t* workspace_bytes, size_t* state_bytes) 
     return FLUSI_OK;
 }
 
+int flusi_plan_set_walls(flusi_plan plan, const double* thickness, const double* u_wall) {
+    if (int rc = check_plan(plan)) return rc;
+    PlanData& d = plan->d;
+    double th[3] = {0.0, 0.0, 0.0}, uw[3] = {0.0, 0.0, 0.0};
+    for (int a = 0; a < 3; ++a) {
+        if (thickness) th[a] = thickness[a];
+        if (u_wall) uw[a] = u_wall[a];
+        if (!(th[a] >= 0.0) || !(th[a] <= d.L) || !std::isfinite(uw[a]))
+            return set_error(FLUSI_EINVAL, "set_walls: thickness in [0, L] and finite velocity");
+    }
+    for (int a = 0; a < 3; ++a) {
+        d.wall_th[a] = th[a];
+        d.u_wall[a] = uw[a];
+    }
+    return FLUSI_OK;
+}
+
 int flusi_plan_set_sponge(flusi_plan plan, double c_sp, const double* thickness) {
     if (int rc = check_plan(plan)) return rc;
     PlanData& d = plan->d;

@@ -48,6 +48,8 @@ struct PlanData {
     bool rtab_valid = false;
     Member* member_dev = nullptr;     // launch record of the plan's own calls
     Sched sched;                      // schedule of the plan's own stepping calls
+    double wall_th[3] = {0.0, 0.0, 0.0};  // Dirichlet layer thickness per axis (0: none)
+    double u_wall[3] = {0.0, 0.0, 0.0};   // velocity imposed in the layers
     double c_sp = 0.0;                // vorticity sponge constant (0: off)
     double sp_thick[3] = {0.0, 0.0, 0.0};  // sponge layer thickness per axis
     double* pmax = nullptr;
@@ -149,7 +151,14 @@ inline Member make_member(const PlanData& p, void* st, const flusi_insect* ins, 
     m.nu = p.nu;
     m.eta = p.eta;
     m.inv_eta = 1.0 / p.eta;
-    m.ctl = StepCtl{sp.dt_fixed, sp.cfl, sp.dt_max, sp.eta_cap, sp.t_end, nc > 0 ? 1 : 0, sp.mean_mode, kin_dynamic(ins), 0};
+    const bool walls = p.wall_th[0] > 0.0 || p.wall_th[1] > 0.0 || p.wall_th[2] > 0.0;
+    m.ctl = StepCtl{sp.dt_fixed, sp.cfl, sp.dt_max, sp.eta_cap, sp.t_end, (nc > 0 || walls) ? 1 : 0, sp.mean_mode,
+                    kin_dynamic(ins), nc > 0 ? 1 : 0};
+    m.wall = walls ? 1 : 0;
+    for (int a = 0; a < 3; ++a) {
+        m.wall_lo[a] = p.wall_th[a] > 0.0 ? p.L - p.wall_th[a] : 1e300;
+        m.u_wall[a] = p.u_wall[a];
+    }
     m.mean_mode = sp.mean_mode;
     m.nc = nc;
     m.dyn = kin_dynamic(ins);

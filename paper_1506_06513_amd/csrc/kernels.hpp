@@ -104,7 +104,7 @@ struct Solid13 {
 
 struct StepCtl {
     double dt_fixed, cfl, dt_max, eta_cap, t_end;
-    int masked, mean_mode, kin_dynamic, pad;
+    int masked, mean_mode, kin_dynamic, body;  // body: a body or wings (kinematics exist)
     double visc_cap;  // RK4: adaptive dt <= visc_cap (explicit diffusion); 0: none
 };
 
@@ -174,6 +174,9 @@ struct Member {
     void* ustage;               // RK4 stage velocity [3] (state field layout)
     double inv_csp;             // 1/C_sp
     double sp_lo[3];            // chi_sp = 1 where x_a >= sp_lo[a] for some axis a
+    int wall, pad_w;            // Dirichlet layers on
+    double wall_lo[3];          // layer where x_a >= wall_lo[a] for some axis a ...
+    double u_wall[3];           // ... with the velocity u_wall imposed
 };
 
 template <int NRED>
@@ -384,8 +387,8 @@ __global__ __launch_bounds__(NT) void k_xpass(const Member* __restrict__ mt, con
     // per-wave sums: with three colours the wave rows wred also take the three
     // lane-reduced values (slots 0..2 are free there), which saves the LDS of red
     constexpr bool WAVE_ACC = NC > 1;
-    __shared__ double red[WAVE_ACC ? 1 : NT / 64][NV];
-    __shared__ double wred[NT / 64][NV];
+    __shared__ double red[WAVE_ACC ? 1 : NT / 64][WAVE_ACC ? 1 : NVAL];
+    __shared__ double wred[WAVE_ACC ? NT / 64 : 1][WAVE_ACC ? NV : 1];
     __shared__ KinT<T> kin;
     // FP64 kinematics for the part choice where parts overlap (FP32 runs)
     constexpr bool K64 = NC > 1 && sizeof(T) < 8;
@@ -522,13 +525,17 @@ __global__ __launch_bounds__(NT) void k_xpass(const Member* __restrict__ mt, con
             acc[0] = fmax(acc[0], u2);
             acc[1] += u2;
         }
+        // Dirichlet layer (Sec. 2.3): penalized to u_wall below, with no body
+        // terms at its points
+        const bool inwall = m.wall && (dx * i >= m.wall_lo[0] || dx * (row % N) >= m.wall_lo[1] ||
+                                       dx * (row / N) >= m.wall_lo[2]);
         if constexpr (NC > 0) {
             const double xg = dx * i, yg = dx * (row % N), zg = dx * (row / N);
             MaskPt<T> mp;
             mp.chi = T(0);
             mp.us[0] = mp.us[1] = mp.us[2] = T(0);
             mp.colour = 0;
-            if (act) {
+            if (act && !inwall) {
                 if constexpr (PH == 1) {
                     mp = eval_mask<T>(kin, xg, yg, zg, k64p);
                 } else if constexpr (K64) {
@@ -600,6 +607,12 @@ __global__ __launch_bounds__(NT) void k_xpass(const Member* __restrict__ mt, con
                 });
             }
         }
+        if (inwall) {
+            const T pen = T(inv_eta);
+            nx -= pen * (ux - T(m.u_wall[0]));
+            ny -= pen * (uy - T(m.u_wall[1]));
+            nz -= pen * (uz - T(m.u_wall[2]));
+        }
         if (act) {
             fbuf[lds_at<true, 1, SC>(i, r)] = cx<T>{nx, ny};
             reinterpret_cast<T*>(fbuf + lds_at<true, 1, SC>(i, RW + r / 2))[r & 1] = nz;
@@ -641,7 +654,10 @@ __global__ __launch_bounds__(NT) void k_xpass(const Member* __restrict__ mt, con
             double r = 0.0;
             for (int w = 0; w < NT / 64; ++w) {
                 double x = 0.0;
-                if (tid < NVAL) x = WAVE_ACC ? wred[w][tid] : red[w][tid];
+                if (tid < NVAL) {
+                    if constexpr (WAVE_ACC) x = wred[w][tid];
+                    else x = red[w][tid];
+                }
                 r = w == 0 ? x : ((tid == 0 || tid == 2) ? fmax(r, x) : r + x);
             }
             partial[(long)wg * NV + tid] = r;
@@ -764,7 +780,7 @@ __device__ inline void write_step(StateHdr* h, int p, const double* tot, const C
 #pragma unroll 1
     for (int i = 22; i < FLUSI_NDIAG; ++i) put(i, 0.0);
     double J[3] = {0.0, 0.0, 0.0}, Ft[3] = {0.0, 0.0, 0.0}, mt[3] = {0.0, 0.0, 0.0};
-    if (ctl.masked) {
+    if (ctl.body) {
         const Kin& K = h->kin;
 #pragma unroll 1
         for (int i = 0; i < 3; ++i) {
