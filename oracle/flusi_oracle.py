@@ -38,6 +38,10 @@ listed in the design notes of the repository):
       half spectrum along x.
   Wavenumbers: j = i for i < n/2, j = i - n otherwise (Nyquist = -n/2); the
       derivative of a Nyquist mode is zero.
+  Box: n points on y and z (side L), nx on x (side Lx), one spacing
+      dx = L/n = Lx/nx on every axis (the paper's non-cubic box, 6x4x4 at
+      1152x768x768, has one spacing); k_a = (2 pi/L_a) j_a and the 2/3 rule
+      on each axis with its own point count.
   2/3 rule: a mode is kept iff 3|j| < n on every axis; applied to the whole
       right-hand side after the forward transform and to the initial field.
   k = 0: the projection is the identity there; mean mode FIXED sets the k=0
@@ -159,9 +163,20 @@ def dealias_kmax(n: int) -> int:
 
 @dataclass
 class Grid:
-    """Cubic periodic box of side L with n points per axis, x_i = i*L/n."""
+    """Periodic box with n points per axis on y and z (side L) and nx points on
+    x (side Lx; nx = 0 means n, a cubic box), x_i = i*dx with one spacing
+    dx = L/n = Lx/nx on every axis (the non-cubic box of Sec. 4 and 6,
+    6x4x4 at 1152x768x768)."""
     n: int
     L: float
+    nx: int = 0
+    Lx: float = 0.0
+
+    def __post_init__(self):
+        if self.nx == 0:
+            self.nx, self.Lx = self.n, self.L
+        if abs(self.Lx / self.nx - self.L / self.n) > 1e-12 * (self.L / self.n):
+            raise ValueError("the grid spacing must be the same on every axis")
 
     @property
     def dx(self) -> float:
@@ -171,30 +186,42 @@ class Grid:
     def dV(self) -> float:
         return self.dx ** 3
 
+    @property
+    def shape(self):
+        """Physical array shape [z][y][x]."""
+        return (self.n, self.n, self.nx)
+
+    @property
+    def lengths(self):
+        """Box side per axis (x, y, z)."""
+        return (self.Lx, self.L, self.L)
+
     def coords(self):
         """Physical coordinates as three [z][y][x] arrays."""
-        x1 = np.arange(self.n, dtype=np.float64) * self.dx
-        z, y, x = np.meshgrid(x1, x1, x1, indexing="ij")
+        x1 = np.arange(self.nx, dtype=np.float64) * self.dx
+        y1 = np.arange(self.n, dtype=np.float64) * self.dx
+        z, y, x = np.meshgrid(y1, y1, x1, indexing="ij")
         return x, y, z
 
     def wavenumbers(self):
         """(jx, jy, jz) integer tables broadcastable over [kz][ky][kx]."""
         n = self.n
-        jx = half_index(n)[None, None, :]
+        jx = half_index(self.nx)[None, None, :]
         jy = signed_index(n)[None, :, None]
         jz = signed_index(n)[:, None, None]
         return jx, jy, jz
 
     def k_vectors(self, derivative: bool):
-        """Wavevector components (2 pi / L) j.  For derivatives the Nyquist
+        """Wavevector components (2 pi / L_a) j_a.  For derivatives the Nyquist
         wavenumber is zeroed (a Nyquist mode has no defined derivative)."""
         n = self.n
+        cx = 2.0 * math.pi / self.Lx
         c = 2.0 * math.pi / self.L
         jx, jy, jz = self.wavenumbers()
-        kx, ky, kz = (c * jx.astype(np.float64), c * jy.astype(np.float64),
+        kx, ky, kz = (cx * jx.astype(np.float64), c * jy.astype(np.float64),
                       c * jz.astype(np.float64))
         if derivative:
-            kx = np.where(jx == n // 2, 0.0, kx)
+            kx = np.where(jx == self.nx // 2, 0.0, kx)
             ky = np.where(np.abs(jy) == n // 2, 0.0, ky)
             kz = np.where(np.abs(jz) == n // 2, 0.0, kz)
         return kx, ky, kz
@@ -207,7 +234,7 @@ class Grid:
         """Boolean mask over the half spectrum: True where the 2/3 rule keeps the mode."""
         n = self.n
         jx, jy, jz = self.wavenumbers()
-        return dealias_keep(jx, n) & dealias_keep(jy, n) & dealias_keep(jz, n)
+        return dealias_keep(jx, self.nx) & dealias_keep(jy, n) & dealias_keep(jz, n)
 
 
 # ---------------------------------------------------------------------------
@@ -219,9 +246,11 @@ def r2c(f: np.ndarray) -> np.ndarray:
     return sfft.rfftn(f, axes=(-3, -2, -1), workers=_WORKERS)
 
 
-def c2r(fh: np.ndarray, n: int) -> np.ndarray:
-    """Inverse complex-to-real 3D transform, scaled by 1/n^3."""
-    return sfft.irfftn(fh, s=(n, n, n), axes=(-3, -2, -1), workers=_WORKERS)
+def c2r(fh: np.ndarray, n) -> np.ndarray:
+    """Inverse complex-to-real 3D transform, scaled by 1/(points); n is the
+    points per axis of a cubic grid or the physical shape (nz, ny, nx)."""
+    s = (n, n, n) if isinstance(n, (int, np.integer)) else tuple(n)
+    return sfft.irfftn(fh, s=s, axes=(-3, -2, -1), workers=_WORKERS)
 
 
 # ---------------------------------------------------------------------------
@@ -799,11 +828,17 @@ class Params:
     nu: float
     eta: float
     mean_mode: int = MEAN_FIXED
+    nx: int = 0                            # points on x (0: n, a cubic box)
+    Lx: float = 0.0                        # box side on x (with nx; same spacing as y and z)
     c_sp: float = 0.0                      # vorticity sponge constant C_sp (0: no sponge)
     sponge: tuple = (0.0, 0.0, 0.0)        # sponge layer thickness per axis (0: none on that axis)
     integrator: str = "ab2"                # 'ab2' (integrating-factor AB2) | 'rk4' (explicit diffusion)
     wall: tuple = (0.0, 0.0, 0.0)          # Dirichlet layer thickness per axis (0: none on that axis)
     u_wall: tuple = (0.0, 0.0, 0.0)        # velocity imposed in the layers
+
+
+def grid_of(p: Params) -> Grid:
+    return Grid(p.n, p.L, p.nx, p.Lx)
 
 
 def sponge_mask(g: Grid, thickness) -> np.ndarray:
@@ -812,9 +847,9 @@ def sponge_mask(g: Grid, thickness) -> np.ndarray:
     (upstream of the seam), 0 elsewhere  [Sec. 2.3, wake removal]."""
     x, y, z = g.coords()
     chi = np.zeros_like(x)
-    for c, d in zip((x, y, z), thickness):
+    for c, d, La in zip((x, y, z), thickness, g.lengths):
         if d > 0.0:
-            chi = np.where(c >= g.L - d, 1.0, chi)
+            chi = np.where(c >= La - d, 1.0, chi)
     return chi
 
 
@@ -859,7 +894,7 @@ def sponge_hat(g: Grid, w: np.ndarray, chi_sp: np.ndarray, c_sp: float) -> np.nd
 
 def physical_fields(g: Grid, uh: np.ndarray):
     """u and w = curl u on the grid."""
-    return c2r(uh, g.n), c2r(curl_hat(g, uh), g.n)
+    return c2r(uh, g.shape), c2r(curl_hat(g, uh), g.shape)
 
 
 def source_physical(u, w, chi, us, eta):
@@ -951,7 +986,7 @@ class State:
 
 
 def init_state(p: Params, u0: np.ndarray, t0: float = 0.0) -> State:
-    g = Grid(p.n, p.L)
+    g = grid_of(p)
     return State(uh=import_field(g, u0), t=t0)
 
 
@@ -992,7 +1027,7 @@ def step(p: Params, st: State, ctl: StepControl, ins: Insect | None, fixed_mask=
 
     fixed_mask = (chi, u_s, colour, xref) replaces the insect by a
     time-independent mask (used by tests)."""
-    g = Grid(p.n, p.L)
+    g = grid_of(p)
     masked = ins is not None or fixed_mask is not None or walls_on(p)
     if fixed_mask is not None:
         chi, us, colour, xref = fixed_mask
@@ -1108,17 +1143,17 @@ def run(p: Params, u0: np.ndarray, nsteps: int, ctl: StepControl,
 
 
 def velocity(p: Params, st: State) -> np.ndarray:
-    return c2r(st.uh, p.n)
+    return c2r(st.uh, grid_of(p).shape)
 
 
 def energy_spectral(g: Grid, uh: np.ndarray) -> float:
     """E = 1/2 sum |u|^2 dV through Parseval on the half spectrum."""
-    n = g.n
+    npts = float(g.nx) * g.n * g.n
     w = np.full(uh.shape[-1], 2.0)
     w[0] = 1.0
-    if n % 2 == 0:
+    if g.nx % 2 == 0:
         w[-1] = 1.0
-    return 0.5 * g.L ** 3 / float(n) ** 6 * float(np.sum(w * np.abs(uh) ** 2))
+    return 0.5 * g.Lx * g.L ** 2 / npts ** 2 * float(np.sum(w * np.abs(uh) ** 2))
 
 
 def penalization_K(nu: float, eta: float, dx: float) -> float:
