@@ -187,18 +187,24 @@ typedef struct {
 /* Message for the last failed call on this thread (never NULL). */
 const char* flusi_last_error(void);
 
-/* Create a plan for a cubic periodic box (Sec. 2.4: Fourier discretization
- * with the 2/3 rule).  nu: kinematic viscosity; eta: penalization constant
- * C_eta (Sec. 2.1); dtype: FLUSI_F32 or FLUSI_F64.  Builds the integer
- * wavenumber and dealiasing tables (kept iff 3|j| < n on each axis), FP64
- * twiddle tables (and FP32 copies rounded from them) and the scratch buffers
- * of the stepping schedule.  Errors: EINVAL, EUNSUPPORTED (nx != ny != nz or
- * n not supported), ENOMEM. */
+/* Create a plan for a periodic box of nx x ny x nz points (Sec. 2.4: Fourier
+ * discretization with the 2/3 rule) with ny = nz = n and one grid spacing
+ * L/n on every axis: L is the side along y and z, the side along x is
+ * L*nx/n (the non-cubic box of Sec. 4 and 6, 6x4x4 at 1152x768x768, has one
+ * spacing).  Grids: the cubic n^3 for n in {16, 24, 32, 48, 64, 96, 128, 192,
+ * 256, 384, 512} and the boxes 48x32x32, 64x32x32 and 192x128x128.
+ * nu: kinematic viscosity; eta: penalization constant C_eta (Sec. 2.1);
+ * dtype: FLUSI_F32 or FLUSI_F64.  Builds the integer wavenumber and
+ * dealiasing tables (kept iff 3|j| < n_a on axis a), FP64 twiddle tables (and
+ * FP32 copies rounded from them) and the scratch buffers of the stepping
+ * schedule.  Every physical field is [z][y][x] with x fastest (nx), every
+ * full-layout spectrum [z][y][nx/2+1].  Errors: EINVAL, EUNSUPPORTED (ny !=
+ * nz or a grid not listed), ENOMEM. */
 int flusi_plan_create(int nx, int ny, int nz, double L, double nu, double eta, int dtype,
                       flusi_plan* out);
 int flusi_plan_destroy(flusi_plan plan);
 
-/* Device bytes a plan of this size and dtype allocates at creation
+/* Device bytes a plan of the cubic n^3 grid and dtype allocates at creation
  * (workspace) and that one state occupies, without allocating anything.
  * Errors: EINVAL, EUNSUPPORTED. */
 int flusi_sizes(int n, int dtype, size_t* workspace_bytes, size_t* state_bytes);
@@ -219,26 +225,27 @@ int flusi_plan_set_integrator(flusi_plan plan, int integrator);
 /* Dirichlet layers (Sec. 2.3: velocity conditions imposed by the volume
  * penalization, e.g. u = u_infinity at the domain borders or channel walls)
  * for every later step of this plan: chi = 1 and u_s = u_wall where x_a >=
- * L - thickness[a] for an axis a with thickness[a] > 0 (sharp layers at the
+ * L_a - thickness[a] (L_a the box side on axis a) for an axis a with
+ * thickness[a] > 0 (sharp layers at the
  * top end of the axes, placed like the sponge's).  The layers take
  * precedence over a body and are not part of its force integrals (their
  * points carry colour 0); a step with layers applies the C_eta step cap.
  * thickness and u_wall are host arrays of 3 doubles (NULL: zeros).  All
  * thicknesses 0 switch the layers off.  Errors: EINVAL (thickness outside
- * [0, L], non-finite velocity). */
+ * [0, L_a], non-finite velocity). */
 int flusi_plan_set_walls(flusi_plan plan, const double* thickness, const double* u_wall);
 
 /* Vorticity sponge (Sec. 2.3, wake removal; the sponge term of eq.
  * PNST_org_momentum) for every later step of this plan: the right-hand side
  * gains -(1/C_sp) (i k x W_hat)/|k|^2 with W = chi_sp * w, the Biot-Savart form
  * of damping the vorticity at rate chi_sp/C_sp (divergence-free, zero at
- * k = 0).  chi_sp = 1 where x_a >= L - thickness[a] for an axis a with
+ * k = 0).  chi_sp = 1 where x_a >= L_a - thickness[a] for an axis a with
  * thickness[a] > 0 (a layer at the top end of that axis, just upstream of the
  * periodic seam), 0 elsewhere.  c_sp <= 0 or all thicknesses 0 switch it off.
  * thickness is a host array of 3 doubles (may be NULL: off).  Switching it
  * on enlarges the plan's scratch (6 instead of 3 forward fields; synchronizes
  * the plan's stream).  Not used by flusi_rhs.  Errors: EINVAL (thickness < 0
- * or > L), ENOMEM. */
+ * or > L_a), ENOMEM. */
 int flusi_plan_set_sponge(flusi_plan plan, double c_sp, const double* thickness);
 
 /* All further launches of this plan go to `stream` (a hipStream_t). */
@@ -250,12 +257,12 @@ size_t flusi_plan_workspace_bytes(flusi_plan plan);
 size_t flusi_state_bytes(flusi_plan plan);
 
 /* Copies of the integer tables the plan uses: j for the n bins of the signed
- * axis (FFT order), and the dealias flags (1 kept, 0 removed) of those bins.
- * Host pointers of n ints each; synchronous. */
+ * axes y and z (FFT order), and the dealias flags (1 kept, 0 removed) of
+ * those bins.  Host pointers of n ints each; synchronous. */
 int flusi_tables(flusi_plan plan, int* j_signed, int* keep_signed);
 
 /* Forward 3D real-to-complex transform of nf fields (Sec. 2.4).
- * in: [nf][n][n][n] real; out: [nf][n][n][n/2+1] complex (full layout). */
+ * in: [nf][n][n][nx] real; out: [nf][n][n][nx/2+1] complex (full layout). */
 int flusi_fft_r2c(flusi_plan plan, const void* in, void* out, int nf);
 
 /* Inverse 3D complex-to-real transform with 1/n^3, input preserved.  The
@@ -264,8 +271,8 @@ int flusi_fft_r2c(flusi_plan plan, const void* in, void* out, int nf);
 int flusi_fft_c2r(flusi_plan plan, const void* in, void* out, int nf);
 
 /* Algorithm 1 step (a): mask chi, solid velocity u_s and colour at time t
- * (Sec. 2.2, Sec. 3.1-3.4).  chi: [n][n][n] real; us: [3][n][n][n] real;
- * colour: [n][n][n] int16 (0 fluid, 1 body, 2 left wing, 3 right wing).  Parts
+ * (Sec. 2.2, Sec. 3.1-3.4).  chi: [n][n][nx] real; us: [3][n][n][nx] real;
+ * colour: [n][n][nx] int16 (0 fluid, 1 body, 2 left wing, 3 right wing).  Parts
  * combine by the maximum of chi; u_s and colour come from that part (ties go
  * to the lower colour); u_s = 0 where chi = 0.  Any output pointer may be
  * NULL. */
@@ -277,21 +284,22 @@ int flusi_mask_insect(flusi_plan plan, const flusi_insect* ins, double t, void* 
  * mask) computes rhs_hat = P D r2c(u x w - (chi/C_eta)(u - u_s)) with w the
  * curl, D the 2/3 rule and P the projection (identity at k = 0; the k = 0
  * value is zeroed for FLUSI_MEAN_FIXED).  umax_host (may be NULL) receives
- * max|u| (this call then synchronizes). */
+ * max|u| (this call then synchronizes).  Cubic grids only (EUNSUPPORTED
+ * otherwise). */
 int flusi_rhs(flusi_plan plan, const void* uhat, const void* chi, const void* us, void* rhs_hat,
               int mean_mode, double* umax_host);
 
 /* Initialize a state buffer of flusi_state_bytes() bytes (caller-owned device
- * memory) from the physical velocity u0 [3][n][n][n] sampled on the grid
+ * memory) from the physical velocity u0 [3][n][n][nx] sampled on the grid
  * (eq. PNST_inicond): the coefficients are dealiased and projected; time t0,
  * no step history. */
 int flusi_state_init(flusi_plan plan, void* state, const void* u0, double t0);
 
-/* Write the velocity of a state as a full-layout spectrum [3][n][n][n/2+1]
+/* Write the velocity of a state as a full-layout spectrum [3][n][n][nx/2+1]
  * (zeros outside the 2/3 band). */
 int flusi_state_export_uhat(flusi_plan plan, const void* state, void* uhat);
 
-/* Physical velocity u [3][n][n][n] of a state. */
+/* Physical velocity u [3][n][n][nx] of a state. */
 int flusi_state_velocity(flusi_plan plan, const void* state, void* u);
 
 /* Time and step count of a state (synchronous). */

@@ -487,14 +487,18 @@ def make_insect(d: dict | None) -> flusi_insect | None:
 class Plan:
     """A plan plus torch-allocated buffers on the current device and stream."""
 
-    def __init__(self, n: int, L: float, nu: float, eta: float, dtype: str = "f64"):
+    def __init__(self, n: int, L: float, nu: float, eta: float, dtype: str = "f64", nx: int | None = None):
+        """n points and side L on y and z; nx points on x (default n), whose side
+        is L*nx/n (one grid spacing on every axis)."""
         if not torch.cuda.is_available():
             raise RuntimeError("flusi needs a ROCm GPU")
+        self.nx = n if nx is None else nx
         self.n, self.L, self.nu, self.eta = n, L, nu, eta
+        self.Lx = L if self.nx == n else L * self.nx / n
         self.dtype = dtype
         self.rdt = torch.float64 if dtype == "f64" else torch.float32
         self.cdt = torch.complex128 if dtype == "f64" else torch.complex64
-        self.handle = flusi_plan_create(n, n, n, L, nu, eta, FLUSI_F64 if dtype == "f64" else FLUSI_F32)
+        self.handle = flusi_plan_create(self.nx, n, n, L, nu, eta, FLUSI_F64 if dtype == "f64" else FLUSI_F32)
         self.dev = torch.device("cuda", torch.cuda.current_device())
         self.sync_stream()
 
@@ -513,14 +517,24 @@ class Plan:
             pass
 
     # tensors
+    @property
+    def shape(self):
+        """Physical field shape [z][y][x]."""
+        return (self.n, self.n, self.nx)
+
+    def _fields(self, t, nf_shape, what):
+        if tuple(t.shape[1:]) != nf_shape or t.dim() != 4:
+            raise ValueError(f"{what}: expected [nf]{list(nf_shape)}, got {list(t.shape)}")
+
     def real(self, nf: int):
-        return torch.empty((nf, self.n, self.n, self.n), dtype=self.rdt, device=self.dev)
+        return torch.empty((nf,) + self.shape, dtype=self.rdt, device=self.dev)
 
     def spec(self, nf: int):
-        return torch.empty((nf, self.n, self.n, self.n // 2 + 1), dtype=self.cdt, device=self.dev)
+        return torch.empty((nf, self.n, self.n, self.nx // 2 + 1), dtype=self.cdt, device=self.dev)
 
     def r2c(self, f: torch.Tensor) -> torch.Tensor:
         f = f.to(self.dev, self.rdt).contiguous()
+        self._fields(f, self.shape, "r2c")
         nf = f.shape[0]
         out = self.spec(nf)
         flusi_fft_r2c(self.handle, f, out, nf)
@@ -528,15 +542,16 @@ class Plan:
 
     def c2r(self, fh: torch.Tensor) -> torch.Tensor:
         fh = fh.to(self.dev, self.cdt).contiguous()
+        self._fields(fh, (self.n, self.n, self.nx // 2 + 1), "c2r")
         nf = fh.shape[0]
         out = self.real(nf)
         flusi_fft_c2r(self.handle, fh, out, nf)
         return out
 
     def mask(self, insect: dict, t: float):
-        chi = torch.empty((self.n,) * 3, dtype=self.rdt, device=self.dev)
+        chi = torch.empty(self.shape, dtype=self.rdt, device=self.dev)
         us = self.real(3)
-        col = torch.empty((self.n,) * 3, dtype=torch.int16, device=self.dev)
+        col = torch.empty(self.shape, dtype=torch.int16, device=self.dev)
         flusi_mask_insect(self.handle, make_insect(insect), t, chi, us, col)
         return chi, us, col
 
@@ -551,6 +566,8 @@ class Plan:
     def new_state(self, u0, t0: float = 0.0) -> torch.Tensor:
         st = torch.empty(flusi_state_bytes(self.handle), dtype=torch.uint8, device=self.dev)
         u0 = torch.as_tensor(u0).to(self.dev, self.rdt).contiguous()
+        if tuple(u0.shape) != (3,) + self.shape:
+            raise ValueError(f"new_state: expected [3]{list(self.shape)}, got {list(u0.shape)}")
         flusi_state_init(self.handle, st, u0, t0)
         return st
 

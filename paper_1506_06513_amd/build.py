@@ -36,6 +36,12 @@ def sizes() -> list[int]:
     return [int(m) for m in re.findall(r"FLUSI_SIZE\((\d+)\)", txt)]
 
 
+def boxes() -> list[tuple[int, int]]:
+    """Non-cubic grids (nx, n): nx points on x, n on y and z."""
+    txt = open(os.path.join(CSRC, "sizes.def")).read()
+    return [(int(a), int(b)) for a, b in re.findall(r"FLUSI_BOX\((\d+),\s*(\d+)\)", txt)]
+
+
 def _run(cmd):
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
@@ -53,6 +59,9 @@ def build(jobs: int | None = None, out: str = LIB, verbose: bool = False) -> str
         for n in sizes():
             units.append((os.path.join(CSRC, "inst.hip"), [f"-DFLUSI_N={n}"],
                           os.path.join(tmp, f"inst_{n}.o")))
+        for nx, n in boxes():
+            units.append((os.path.join(CSRC, "inst.hip"), [f"-DFLUSI_NX={nx}", f"-DFLUSI_N={n}"],
+                          os.path.join(tmp, f"inst_{nx}x{n}.o")))
         cmds = [[hipcc(), "-c", *HIPCC_FLAGS, *defs, src, "-o", obj] for src, defs, obj in units]
         with ThreadPoolExecutor(max_workers=jobs) as ex:
             for r in ex.map(_run, cmds):

@@ -13,8 +13,10 @@
 namespace flusi {
 
 #define FLUSI_SIZE(s) ImplBase* make_impl_##s(int);
+#define FLUSI_BOX(x, s) ImplBase* make_impl_##x##_##s(int);
 #include "sizes.def"
 #undef FLUSI_SIZE
+#undef FLUSI_BOX
 
 static thread_local char g_err[512] = "no error";
 
@@ -44,16 +46,16 @@ int ensure_scratch(void** ptr, size_t* cur, size_t need, PlanData& p) {
     return FLUSI_OK;
 }
 
-static ImplBase* make_impl(int n, int dtype) {
-    switch (n) {
+// Instantiated grids: cubic n^3 (FLUSI_SIZE) and nx x n x n boxes (FLUSI_BOX).
+static ImplBase* make_impl(int nx, int n, int dtype) {
 #define FLUSI_SIZE(s) \
-    case s:           \
-        return make_impl_##s(dtype);
+    if (nx == s && n == s) return make_impl_##s(dtype);
+#define FLUSI_BOX(x, s) \
+    if (nx == x && n == s) return make_impl_##x##_##s(dtype);
 #include "sizes.def"
 #undef FLUSI_SIZE
-        default:
-            return nullptr;
-    }
+#undef FLUSI_BOX
+    return nullptr;
 }
 
 // cos and sin of 2 pi m / n (n a multiple of 8), reduced to the first octant and
@@ -104,7 +106,7 @@ static int check_plan(flusi_plan p) {
     return FLUSI_OK;
 }
 static void free_plan(PlanData& d) {
-    void* ptrs[] = {d.tw, d.bufA, d.bufB, d.partial, d.partial2, d.kin, d.ins_dev, d.member_dev, d.pmax, d.spec, d.phys,
+    void* ptrs[] = {d.tw, d.twx != d.tw ? d.twx : nullptr, d.bufA, d.bufB, d.partial, d.partial2, d.kin, d.ins_dev, d.member_dev, d.pmax, d.spec, d.phys,
                     d.rtab, d.rtab32, d.ustage};
     for (void* q : ptrs)
         if (q) (void)hipFree(q);
@@ -246,11 +248,11 @@ const char* flusi_last_error(void) { return g_err; }
 int flusi_plan_create(int nx, int ny, int nz, double L, double nu, double eta, int dtype, flusi_plan* out) {
     if (!out) return set_error(FLUSI_EINVAL, "out is NULL");
     *out = nullptr;
-    if (nx != ny || ny != nz) return set_error(FLUSI_EUNSUPPORTED, "only cubic grids are supported (%d x %d x %d)", nx, ny, nz);
+    if (ny != nz) return set_error(FLUSI_EUNSUPPORTED, "need ny = nz (%d x %d x %d)", nx, ny, nz);
     if (!(L > 0.0) || !(nu >= 0.0) || !(eta > 0.0)) return set_error(FLUSI_EINVAL, "need L > 0, nu >= 0, eta > 0");
     if (dtype != FLUSI_F32 && dtype != FLUSI_F64) return set_error(FLUSI_EINVAL, "dtype must be FLUSI_F32 or FLUSI_F64");
-    ImplBase* impl = make_impl(nx, dtype);
-    if (!impl) return set_error(FLUSI_EUNSUPPORTED, "grid size %d not supported", nx);
+    ImplBase* impl = make_impl(nx, ny, dtype);
+    if (!impl) return set_error(FLUSI_EUNSUPPORTED, "grid %d x %d x %d not supported", nx, ny, nz);
     flusi_plan p = new (std::nothrow) flusi_plan_s();
     if (!p) {
         delete impl;
@@ -258,20 +260,25 @@ int flusi_plan_create(int nx, int ny, int nz, double L, double nu, double eta, i
     }
     PlanData& d = p->d;
     d.impl = impl;
-    d.n = nx;
+    d.n = ny;
+    d.nx = nx;
     d.dtype = dtype;
     d.L = L;
+    d.Lx = nx == ny ? L : L * nx / ny;
     d.nu = nu;
     d.eta = eta;
-    d.K = kmax_of(nx);
-    d.KP = d.K + 1;
+    d.K = kmax_of(ny);
+    d.KP = kmax_of(nx) + 1;
     d.M = 2 * d.K + 1;
     d.Q = d.M * d.KP;
     const size_t cxb = dtype == FLUSI_F32 ? 8 : 16;
     d.szA = impl->bufA_elems() * cxb;
     d.szB = impl->bufB_elems() * cxb;
     d.nwg_x = impl->nwg_x();
-    bool ok = hipMalloc(&d.tw, nx * cxb) == hipSuccess;
+    const int n = ny;
+    bool ok = hipMalloc(&d.tw, n * cxb) == hipSuccess;
+    if (nx != n) ok = ok && hipMalloc(&d.twx, nx * cxb) == hipSuccess;
+    else d.twx = d.tw;
     ok = ok && hipMalloc(&d.bufA, d.szA) == hipSuccess;
     ok = ok && hipMalloc(&d.bufB, d.szB) == hipSuccess;
     ok = ok && hipMalloc(&d.partial, (size_t)d.nwg_x * NV * sizeof(double)) == hipSuccess;
@@ -288,26 +295,26 @@ int flusi_plan_create(int nx, int ny, int nz, double L, double nu, double eta, i
     if (!ok) {
         free_plan(d);
         delete p;
-        return set_error(FLUSI_ENOMEM, "device allocation for a %d^3 plan", nx);
+        return set_error(FLUSI_ENOMEM, "device allocation for a %d x %d x %d plan", nx, ny, nz);
     }
-    d.workspace = nx * cxb + d.szA + d.szB + (size_t)d.nwg_x * NV * 8 + NRED_MAX * NV * 8 + sizeof(Kin) + sizeof(flusi_insect) +
+    d.workspace = (n + (nx != n ? nx : 0)) * cxb + d.szA + d.szB + (size_t)d.nwg_x * NV * 8 + NRED_MAX * NV * 8 + sizeof(Kin) + sizeof(flusi_insect) +
                   sizeof(Member) + RTAB_BYTES64 + RTAB_BYTES32;
-    // FP64 twiddles exp(-2 pi i m / n); the FP32 table is rounded from them.
-    std::vector<double> w(2 * nx);
-    for (int m = 0; m < nx; ++m) {
-        double c, s;
-        sincos_2pi(m, nx, &c, &s);
-        w[2 * m] = c;
-        w[2 * m + 1] = -s;
-    }
-    hipError_t e;
-    if (dtype == FLUSI_F64) {
-        e = hipMemcpy(d.tw, w.data(), nx * cxb, hipMemcpyHostToDevice);
-    } else {
-        std::vector<float> wf(2 * nx);
-        for (int i = 0; i < 2 * nx; ++i) wf[i] = (float)w[i];
-        e = hipMemcpy(d.tw, wf.data(), nx * cxb, hipMemcpyHostToDevice);
-    }
+    // FP64 twiddles exp(-2 pi i m / len); the FP32 tables are rounded from them.
+    const auto upload = [&](void* dst, int len) {
+        std::vector<double> w(2 * len);
+        for (int m = 0; m < len; ++m) {
+            double c, s;
+            sincos_2pi(m, len, &c, &s);
+            w[2 * m] = c;
+            w[2 * m + 1] = -s;
+        }
+        if (dtype == FLUSI_F64) return hipMemcpy(dst, w.data(), len * cxb, hipMemcpyHostToDevice);
+        std::vector<float> wf(2 * len);
+        for (int i = 0; i < 2 * len; ++i) wf[i] = (float)w[i];
+        return hipMemcpy(dst, wf.data(), len * cxb, hipMemcpyHostToDevice);
+    };
+    hipError_t e = upload(d.tw, n);
+    if (e == hipSuccess && nx != n) e = upload(d.twx, nx);
     if (e != hipSuccess) {
         free_plan(d);
         delete p;
@@ -328,7 +335,7 @@ int flusi_plan_destroy(flusi_plan plan) {
 
 int flusi_sizes(int n, int dtype, size_t* workspace_bytes, size_t* state_bytes) {
     if (dtype != FLUSI_F32 && dtype != FLUSI_F64) return set_error(FLUSI_EINVAL, "dtype must be FLUSI_F32 or FLUSI_F64");
-    ImplBase* impl = make_impl(n, dtype);
+    ImplBase* impl = make_impl(n, n, dtype);
     if (!impl) return set_error(FLUSI_EUNSUPPORTED, "grid size %d not supported", n);
     const size_t cxb = dtype == FLUSI_F32 ? 8 : 16;
     if (workspace_bytes)
@@ -347,8 +354,8 @@ int flusi_plan_set_walls(flusi_plan plan, const double* thickness, const double*
     for (int a = 0; a < 3; ++a) {
         if (thickness) th[a] = thickness[a];
         if (u_wall) uw[a] = u_wall[a];
-        if (!(th[a] >= 0.0) || !(th[a] <= d.L) || !std::isfinite(uw[a]))
-            return set_error(FLUSI_EINVAL, "set_walls: thickness in [0, L] and finite velocity");
+        if (!(th[a] >= 0.0) || !(th[a] <= (a == 0 ? d.Lx : d.L)) || !std::isfinite(uw[a]))
+            return set_error(FLUSI_EINVAL, "set_walls: thickness in [0, side] and finite velocity");
     }
     for (int a = 0; a < 3; ++a) {
         d.wall_th[a] = th[a];
@@ -363,8 +370,8 @@ int flusi_plan_set_sponge(flusi_plan plan, double c_sp, const double* thickness)
     double th[3] = {0.0, 0.0, 0.0};
     if (thickness)
         for (int a = 0; a < 3; ++a) {
-            if (!(thickness[a] >= 0.0) || thickness[a] > d.L)
-                return set_error(FLUSI_EINVAL, "set_sponge: thickness must be in [0, L]");
+            if (!(thickness[a] >= 0.0) || thickness[a] > (a == 0 ? d.Lx : d.L))
+                return set_error(FLUSI_EINVAL, "set_sponge: thickness must be in [0, side]");
             th[a] = thickness[a];
         }
     const bool on = c_sp > 0.0 && (th[0] > 0.0 || th[1] > 0.0 || th[2] > 0.0);
@@ -582,6 +589,7 @@ int flusi_autotune(flusi_plan plan, const void* state, const flusi_insect* ins, 
         g.any_ff = m.ff != 0;
         g.rk = m.rk != 0;
         g.tw = d.tw;
+        g.twx = d.twx;
         g.stream = d.stream;
         rc = tune_group(d.impl, g, d, reps, &best);
     }
@@ -680,9 +688,9 @@ static int ens_rebuild(flusi_ensemble e) {
     hipError_t err = hipStreamSynchronize(e->own);
     if (err != hipSuccess) return set_error(FLUSI_EDEVICE, "ensemble: %s", hipGetErrorString(err));
     ens_clear_groups(e);
-    std::map<int, std::vector<int>> by_n;
+    std::map<long, std::vector<int>> by_n;  // key: grid shape (nx, n)
     for (int i = 0; i < (int)e->members.size(); ++i)
-        if (e->members[i].used) by_n[e->members[i].plan->d.n].push_back(i);
+        if (e->members[i].used) by_n[(long)e->members[i].plan->d.nx * 65536 + e->members[i].plan->d.n].push_back(i);
     for (auto& kv : by_n) {
         std::vector<int>& ids = kv.second;
         // order: without sponge, then with; within each, by colour count
@@ -692,7 +700,7 @@ static int ens_rebuild(flusi_ensemble e) {
         };
         std::stable_sort(ids.begin(), ids.end(), [&](int a, int b) { return key(a) < key(b); });
         EnsGroup g;
-        g.n = kv.first;
+        g.n = (int)(kv.first % 65536);
         g.p0 = e->members[ids[0]].plan;
         const PlanData& p0 = g.p0->d;
         g.impl = p0.impl;
@@ -725,6 +733,7 @@ static int ens_rebuild(flusi_ensemble e) {
         g.run.mt = g.dev;
         g.run.nmem = (int)host.size();
         g.run.tw = p0.tw;
+        g.run.twx = p0.twx;
         g.run.sched = p0.sched;
         e->groups.push_back(g);
     }

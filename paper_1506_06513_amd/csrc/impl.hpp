@@ -24,11 +24,12 @@ constexpr size_t RTAB_BYTES32 = (FLUSI_RTABLE + 1) * sizeof(float);
 
 // Plan contents shared with the launchers.
 struct PlanData {
-    int n = 0, dtype = 0;
-    double L = 0, nu = 0, eta = 0;
-    int K = 0, KP = 0, M = 0, Q = 0;
+    int n = 0, nx = 0, dtype = 0;  // n points on y and z, nx on x
+    double L = 0, Lx = 0, nu = 0, eta = 0;  // box side on y and z, on x (one spacing L/n)
+    int K = 0, KP = 0, M = 0, Q = 0;  // K: largest kept |j| on y, z; KP: kept kx
     hipStream_t stream = nullptr;
-    void* tw = nullptr;  // n twiddles exp(-2 pi i m/n) of the plan's real type
+    void* tw = nullptr;   // n twiddles exp(-2 pi i m/n) of the plan's real type (y and z)
+    void* twx = nullptr;  // nx twiddles of the x axis (the same table when nx = n)
     void* bufA = nullptr;
     void* bufB = nullptr;
     size_t szA = 0, szB = 0;
@@ -113,7 +114,8 @@ struct GroupRun {
     // overlap the y-inverse, which does not read them
     hipStream_t side = nullptr;
     hipEvent_t ev_z = nullptr, ev_k = nullptr;
-    const void* tw = nullptr;
+    const void* tw = nullptr;   // y and z twiddles
+    const void* twx = nullptr;  // x twiddles
     Sched sched;
     hipStream_t stream = nullptr;
     PlanData* prof = nullptr; // pass timing events, or null
@@ -148,6 +150,7 @@ inline Member make_member(const PlanData& p, void* st, const flusi_insect* ins, 
     m.history = sp.history;
     m.dx = p.L / p.n;
     m.ks = 2.0 * M_PI / p.L;
+    m.ksx = p.nx == p.n ? m.ks : 2.0 * M_PI / p.Lx;
     m.nu = p.nu;
     m.eta = p.eta;
     m.inv_eta = 1.0 / p.eta;
@@ -156,7 +159,7 @@ inline Member make_member(const PlanData& p, void* st, const flusi_insect* ins, 
                     kin_dynamic(ins), nc > 0 ? 1 : 0};
     m.wall = walls ? 1 : 0;
     for (int a = 0; a < 3; ++a) {
-        m.wall_lo[a] = p.wall_th[a] > 0.0 ? p.L - p.wall_th[a] : 1e300;
+        m.wall_lo[a] = p.wall_th[a] > 0.0 ? (a == 0 ? p.Lx : p.L) - p.wall_th[a] : 1e300;
         m.u_wall[a] = p.u_wall[a];
     }
     m.mean_mode = sp.mean_mode;
@@ -168,11 +171,12 @@ inline Member make_member(const PlanData& p, void* st, const flusi_insect* ins, 
     m.ustage = p.ustage;
     if (m.rk && p.nu > 0.0 && p.K > 0) {
         // explicit diffusion: dt * nu * max|k|^2 <= 2.5 (RK4 is stable to about 2.785)
-        const double kmax = p.K * 2.0 * M_PI / p.L;
-        m.ctl.visc_cap = 2.5 / (p.nu * 3.0 * kmax * kmax);
+        const double kx = (p.KP - 1) * m.ksx, ky = p.K * m.ks;
+        m.ctl.visc_cap = 2.5 / (p.nu * (kx * kx + ky * ky + ky * ky));
     }
     m.inv_csp = m.sponge ? 1.0 / p.c_sp : 0.0;
-    for (int a = 0; a < 3; ++a) m.sp_lo[a] = (m.sponge && p.sp_thick[a] > 0.0) ? p.L - p.sp_thick[a] : 1e300;
+    for (int a = 0; a < 3; ++a)
+        m.sp_lo[a] = (m.sponge && p.sp_thick[a] > 0.0) ? (a == 0 ? p.Lx : p.L) - p.sp_thick[a] : 1e300;
     return m;
 }
 enum { PASS_ZINV = 0, PASS_YINV = 1, PASS_X = 2, PASS_KIN = 3, PASS_YFWD = 4, PASS_Z = 5 };
@@ -257,14 +261,16 @@ inline int prepare_wing_table(PlanData& p, const flusi_insect* ins, hipStream_t 
     return launch_check("wing radius table");
 }
 
-template <typename T, int N>
+// Stepping and utilities of an NX x N x N grid (x, y, z).
+template <typename T, int NX, int N>
 struct Impl final : ImplBase {
     using CX = cx<T>;
-    static constexpr int K = kmax_of(N), KP = K + 1, M = 2 * K + 1, Q = M * KP;
-    static constexpr int KPp = Geo<T, N>::KPp, Qp = Geo<T, N>::Qp;
-    static constexpr int C = cols_of(N), RW = rows_x(N, sizeof(cx<T>)), NKX = N / 2 + 1;
+    using G = Geo<T, NX, N>;
+    static constexpr int K = G::K, KP = G::KP, M = G::M, Q = G::Q;
+    static constexpr int KPp = G::KPp, Qp = G::Qp;
+    static constexpr int C = cols_of(N), RW = rows_x(NX, sizeof(cx<T>)), NKX = NX / 2 + 1;
     static constexpr int CZ = cols_z(N);
-    static constexpr long N2 = (long)N * N, N3 = (long)N * N * N;
+    static constexpr long N2 = (long)N * N, N3 = (long)NX * N * N;  // rows along x, points
     static constexpr long FULL = N2 * NKX;  // full-layout spectrum per field
 
     size_t bufA_elems() const override {
@@ -282,7 +288,7 @@ struct Impl final : ImplBase {
     }
     // x-pass workgroups per member, largest over the tile variants (sizes the
     // partial-sum buffer)
-    int nwg_x() const override { return (int)(N2 / rows_x(N, sizeof(cx<T>), NVARIANT - 1)); }
+    int nwg_x() const override { return (int)(N2 / rows_x(NX, sizeof(cx<T>), NVARIANT - 1)); }
     static size_t field_bytes() { return (size_t)M * Qp * sizeof(CX); }
     size_t state_bytes() const override { return STATE_HDR_BYTES + 6 * ((field_bytes() + 255) / 256 * 256); }
 
@@ -292,6 +298,7 @@ struct Impl final : ImplBase {
     static CX* st_nold(void* st) { return st_uhat(st) + 3 * st_fs(); }
 
     const CX* tw(const PlanData& p) const { return static_cast<const CX*>(p.tw); }
+    const CX* twx(const PlanData& p) const { return static_cast<const CX*>(p.twx); }
     // The z-pass runs as two launches (forward + update, then curl + inverse)
     // when one fused launch would hold too many registers per thread.
     static constexpr bool split_z() { return N >= 192; }
@@ -321,12 +328,12 @@ struct Impl final : ImplBase {
     }
     void x_r2c(PlanData& p, const T* in, CX* out, long nrows, int nkx, int pitch) {
         constexpr int RR = 2 * RW;
-        k_x_r2c<T, N><<<(unsigned)((nrows + RR - 1) / RR), NT, 0, p.stream>>>(in, out, nrows, nkx, pitch, tw(p));
+        k_x_r2c<T, NX><<<(unsigned)((nrows + RR - 1) / RR), NT, 0, p.stream>>>(in, out, nrows, nkx, pitch, twx(p));
     }
     void x_c2r(PlanData& p, const CX* in, T* out, long nrows, int nkx) {
         constexpr int RR = 2 * RW;
-        k_x_c2r<T, N><<<(unsigned)((nrows + RR - 1) / RR), NT, 0, p.stream>>>(in, out, nrows, nkx,
-                                                                              T(1.0 / (double)N3), tw(p));
+        k_x_c2r<T, NX><<<(unsigned)((nrows + RR - 1) / RR), NT, 0, p.stream>>>(in, out, nrows, nkx,
+                                                                               T(1.0 / (double)N3), twx(p));
     }
 
     int fft_r2c(PlanData& p, const void* in, void* out, int nf) override {
@@ -356,13 +363,14 @@ struct Impl final : ImplBase {
         const double dx = p.L / N;
         if (int rc = prepare_wing_table(p, &ins, p.stream)) return rc;
         k_kin<<<1, 64, 0, p.stream>>>(p.kin, ins, t, dx, p.rtab, p.rtab32);
-        k_mask<T><<<(unsigned)((N3 + 255) / 256), 256, 0, p.stream>>>(p.kin, N, dx, static_cast<T*>(chi),
+        k_mask<T><<<(unsigned)((N3 + 255) / 256), 256, 0, p.stream>>>(p.kin, NX, N, dx, static_cast<T*>(chi),
                                                                        static_cast<T*>(us), col);
         return launch_check("mask_insect");
     }
 
     int rhs(PlanData& p, const void* uhat, const void* chi, const void* us, void* rhs_hat, int mean_mode,
             double* umax_host) override {
+        if (NX != N) return set_error(FLUSI_EUNSUPPORTED, "rhs: the unfused path takes cubic grids only");
         int rc = ensure_scratch(&p.spec, &p.spec_sz, 6ul * FULL * sizeof(CX), p);
         if (rc) return rc;
         rc = ensure_scratch(&p.phys, &p.phys_sz, 6ul * N3 * sizeof(T), p);
@@ -408,7 +416,7 @@ struct Impl final : ImplBase {
     template <int V>
     static constexpr int nby(int nf) { return (N * KP + cols_of(N, V) - 1) / cols_of(N, V) * nf; }
     template <int V>
-    static constexpr int nwg(int) { return (int)(N2 / rows_x(N, sizeof(cx<T>), V)); }
+    static constexpr int nwg(int) { return (int)(N2 / rows_x(NX, sizeof(cx<T>), V)); }
     static constexpr int NBZ = (Q + CZ - 1) / CZ;  // z-pass tiles per member
     static int nwg_of(int v) { return v == 2 ? nwg<2>(0) : (v == 1 ? nwg<1>(0) : nwg<0>(0)); }
 
@@ -417,14 +425,14 @@ struct Impl final : ImplBase {
     static void y_inverse_v(const GroupRun& g) {
         const CX* w = static_cast<const CX*>(g.tw);
         constexpr int nb = nby<V>(6);
-        k_ypass<T, N, +1, 0, V><<<(unsigned)(nb * g.nmem), NT, 0, g.stream>>>(g.mt, nb, w, 6, 0);
+        k_ypass<T, NX, N, +1, 0, V><<<(unsigned)(nb * g.nmem), NT, 0, g.stream>>>(g.mt, nb, w, 6, 0);
     }
     static void y_inverse(const GroupRun& g) {
         if (g.sched.y_inverse == 2) y_inverse_v<2>(g);
         else if (g.sched.y_inverse == 1) y_inverse_v<1>(g);
         else y_inverse_v<0>(g);
     }
-    // y-forward of 3 fields; with red set, nred_of(N) extra workgroups per member
+    // y-forward of 3 fields; with red set, nred_of(NX, N) extra workgroups per member
     // do the first-level reduction of the x-pass sums
     template <int V>
     static void y_forward_v(const GroupRun& g, bool red) {
@@ -432,10 +440,10 @@ struct Impl final : ImplBase {
         const int nfwd = (g.n_nc[1][0] + g.n_nc[1][1] + g.n_nc[1][2]) ? 6 : 3;
         const int nb = nby<V>(nfwd);
         if (red)
-            k_ypass<T, N, -1, 1, V><<<(unsigned)((nb + nred_of(N)) * g.nmem), NT, 0, g.stream>>>(
-                g.mt, nb + nred_of(N), w, nfwd, nwg_of(g.sched.x_pass));
+            k_ypass<T, NX, N, -1, 1, V><<<(unsigned)((nb + nred_of(NX, N)) * g.nmem), NT, 0, g.stream>>>(
+                g.mt, nb + nred_of(NX, N), w, nfwd, nwg_of(g.sched.x_pass));
         else
-            k_ypass<T, N, -1, 0, V><<<(unsigned)(nb * g.nmem), NT, 0, g.stream>>>(g.mt, nb, w, nfwd, 0);
+            k_ypass<T, NX, N, -1, 0, V><<<(unsigned)(nb * g.nmem), NT, 0, g.stream>>>(g.mt, nb, w, nfwd, 0);
     }
     static void y_forward(const GroupRun& g, bool red) {
         if (g.sched.y_forward == 2) y_forward_v<2>(g, red);
@@ -444,14 +452,14 @@ struct Impl final : ImplBase {
     }
     template <int V, bool SP>
     static const Member* xpass_range(const GroupRun& g, const Member* mt) {
-        const CX* w = static_cast<const CX*>(g.tw);
+        const CX* w = static_cast<const CX*>(g.twx);
         constexpr int nw = nwg<V>(0);
         const int* n = g.n_nc[SP ? 1 : 0];
-        if (n[0]) k_xpass<T, N, 0, V, SP><<<(unsigned)(nw * n[0]), NT, 0, g.stream>>>(mt, w);
+        if (n[0]) k_xpass<T, NX, N, 0, V, SP><<<(unsigned)(nw * n[0]), NT, 0, g.stream>>>(mt, w);
         mt += n[0];
-        if (n[1]) k_xpass<T, N, 1, V, SP><<<(unsigned)(nw * n[1]), NT, 0, g.stream>>>(mt, w);
+        if (n[1]) k_xpass<T, NX, N, 1, V, SP><<<(unsigned)(nw * n[1]), NT, 0, g.stream>>>(mt, w);
         mt += n[1];
-        if (n[2]) k_xpass<T, N, 3, V, SP><<<(unsigned)(nw * n[2]), NT, 0, g.stream>>>(mt, w);
+        if (n[2]) k_xpass<T, NX, N, 3, V, SP><<<(unsigned)(nw * n[2]), NT, 0, g.stream>>>(mt, w);
         return mt + n[2];
     }
     template <int V>
@@ -469,7 +477,7 @@ struct Impl final : ImplBase {
         // modes with the reduction: one more workgroup per member (diagnostics, next level)
         constexpr int nb = NBZ + ((MODE == MODE_STEP || MODE == MODE_STEP_LAST || MODE == MODE_RK1) ? 1 : 0);
         if (nmem > 0)
-            k_zpass<T, N, MODE, V, SP><<<(unsigned)(nb * nmem), nt_z(N, V), 0, g.stream>>>(
+            k_zpass<T, NX, N, MODE, V, SP><<<(unsigned)(nb * nmem), nt_z(N, V), 0, g.stream>>>(
                 mt, static_cast<const CX*>(g.tw), par, s, rk);
     }
     // update modes: members without the sponge, then those with it (the table
@@ -626,6 +634,7 @@ struct Impl final : ImplBase {
         g.mt = p.member_dev;
         g.nmem = 1;
         g.tw = p.tw;
+        g.twx = p.twx;
         g.stream = p.stream;
         y_forward(g, false);
         zpass<MODE_IMPORT>(g);
@@ -634,7 +643,7 @@ struct Impl final : ImplBase {
 
     int export_uhat(PlanData& p, const void* st, void* out) override {
         k_export_full<T><<<(unsigned)((FULL + 255) / 256), 256, 0, p.stream>>>(
-            st_uhat(const_cast<void*>(st)), static_cast<CX*>(out), N, st_fs(), (long)Qp);
+            st_uhat(const_cast<void*>(st)), static_cast<CX*>(out), NX, N, st_fs(), (long)Qp);
         return launch_check("export_uhat");
     }
 
@@ -660,6 +669,7 @@ struct Impl final : ImplBase {
         g.any_ff = m.ff != 0;
         g.rk = m.rk != 0;
         g.tw = p.tw;
+        g.twx = p.twx;
         g.sched = p.sched;
         g.stream = p.stream;
         // the fork/join costs a few microseconds of event latency: worth it

@@ -1,7 +1,8 @@
 // HIP kernels of the pseudo-spectral penalized Navier-Stokes step (gfx950).
 //
 // Stepping schedule, four HBM passes per time step over 2/3-pruned spectra
-// (K = (n-1)/3 is the largest kept |j|; KP = K+1 kept kx; M = 2K+1 kept ky,kz):
+// of an nx x n x n grid (K = (n-1)/3 is the largest kept |j| on y and z,
+// KX = (nx-1)/3 on x; KP = KX+1 kept kx; M = 2K+1 kept ky,kz):
 //   y-inverse   : z-partials [6][z][ky'][kx]  -> y-partials [6][z][y][kx]
 //   x-pass      : y-partials -> c2r along x -> u, w -> mask/u_s on the fly ->
 //                 N = u x w - (chi/C_eta)(u - u_s), FP64 partial sums ->
@@ -66,16 +67,17 @@ __host__ __device__ constexpr int round_up(int a, int b) { return (a + b - 1) / 
 // First-level reduction workgroups per member: every z-pass workgroup reads
 // their NV-value records, so small grids use few; large grids (many x-pass
 // records) use more so that the first level stays shorter than the y-forward.
-__host__ __device__ constexpr int nred_of(int N) {
-    const int n = N * N / rows_x(N) / 128;
+__host__ __device__ constexpr int nred_of(int NX, int N) {
+    const int n = N * N / rows_x(NX) / 128;
     return n < 16 ? 16 : (n > NRED_MAX ? NRED_MAX : n);
 }
 
-// Pruned-spectrum geometry.  Row pitches are padded to 128 bytes so that every
-// row of a pass starts on a cache line.
-template <typename T, int N>
+// Pruned-spectrum geometry of an NX x N x N grid (x, y, z): K is the largest
+// kept |j| on y and z, KX on x; KP = KX + 1 kept kx.  Row pitches are padded to
+// 128 bytes so that every row of a pass starts on a cache line.
+template <typename T, int NX, int N>
 struct Geo {
-    static constexpr int K = kmax_of(N), KP = K + 1, M = 2 * K + 1, Q = M * KP;
+    static constexpr int K = kmax_of(N), KX = kmax_of(NX), KP = KX + 1, M = 2 * K + 1, Q = M * KP;
     static constexpr int AL = 128 / (int)sizeof(cx<T>);
     static constexpr int KPp = round_up(KP, AL);  // pitch of [z][y][kx] rows
     static constexpr int Qp = round_up(Q, AL);    // pitch of [z][ky'][kx] planes
@@ -163,7 +165,7 @@ struct Member {
     const double* rtab;         // Fourier wing radius table of the plan (or null)
     const float* rtab32;
     double* history;            // FLUSI_NDIAG values per step of a call, or null
-    double dx, ks, nu, eta, inv_eta;
+    double dx, ks, ksx, nu, eta, inv_eta;  // ks = 2 pi / L on y and z, ksx on x
     StepCtl ctl;
     int mean_mode;
     int nc;                     // colours of the mask: 0 (none), 1 (body), 3 (body + wings)
@@ -252,14 +254,14 @@ __global__ __launch_bounds__(NT) void k_colfft(const cx<T>* in, cx<T>* out, int 
 //            z) -> bufB [f][z][y][kx] (pitch KPp per y)
 //   DIR = -1 (y-forward): 3 fields bufA [f][z][y][kx] -> bufB [f][z][ky'][kx]
 // Each member has nbx*nf column tiles followed by the extra workgroups:
-//   EXTRA 1: nred_of(N) workgroups reduce the x-pass sums (first level)
+//   EXTRA 1: nred_of(NX, N) workgroups reduce the x-pass sums (first level)
 // nwg: x-pass workgroups per member (records of the first-level reduction).
 // nfwd: forward fields per member (3, or 6 when a member of the launch has the
 // vorticity sponge; members without it skip fields 3..5).
-template <typename T, int N, int DIR, int EXTRA, int V>
+template <typename T, int NX, int N, int DIR, int EXTRA, int V>
 __global__ __launch_bounds__(NT) void k_ypass(const Member* __restrict__ mt, int per, const cx<T>* __restrict__ tw,
                                               int nfwd, int nwg) {
-    using G = Geo<T, N>;
+    using G = Geo<T, NX, N>;
     constexpr int KP = G::KP, KPp = G::KPp, Qp = G::Qp;
     constexpr int C = cols_of(N, V);
     constexpr int nbx = (N * KP + C - 1) / C;
@@ -273,7 +275,8 @@ __global__ __launch_bounds__(NT) void k_ypass(const Member* __restrict__ mt, int
     if (f >= nf) {
         if constexpr (EXTRA == 1) {
             __shared__ double red[NT / 64][NV];
-            if (tile - nf * nbx < nred_of(N)) reduce_level1<nred_of(N)>(m.partial, nwg, m.partial2, tile - nf * nbx, red);
+            if (tile - nf * nbx < nred_of(NX, N))
+                reduce_level1<nred_of(NX, N)>(m.partial, nwg, m.partial2, tile - nf * nbx, red);
         }
         return;
     }
@@ -361,11 +364,11 @@ __device__ __forceinline__ void block_reduce_store(const double (&acc)[NVAL], do
 // Member table: N*N/RW workgroups per member, y-partials in bufB, output in bufA.
 // SP: members with the vorticity sponge; chi_sp * w is transformed beside N
 // and stored as fields 3..5.
-template <typename T, int N, int NC, int V, bool SP>
+template <typename T, int NX, int N, int NC, int V, bool SP>
 __global__ __launch_bounds__(NT) void k_xpass(const Member* __restrict__ mt, const cx<T>* __restrict__ tw) {
-    using G = Geo<T, N>;
-    constexpr int K = G::K, KP = G::KP, KPp = G::KPp;
-    constexpr int RW = rows_x(N, sizeof(cx<T>), V);
+    using G = Geo<T, NX, N>;
+    constexpr int K = G::KX, KP = G::KP, KPp = G::KPp;  // the x axis' cut
+    constexpr int RW = rows_x(NX, sizeof(cx<T>), V);
     constexpr int NWG = N * N / RW;
     constexpr long fs_in = (long)N * N * KPp, fs_out = (long)N * N * KPp;
     const Member& m = mt[blockIdx.x / NWG];
@@ -375,7 +378,7 @@ __global__ __launch_bounds__(NT) void k_xpass(const Member* __restrict__ mt, con
     const double dx = m.dx, inv_eta = m.inv_eta;
     glb<double>* __restrict__ partial = gview(m.partial);
     const int wg = blockIdx.x % NWG;
-    constexpr int SC = cm_stride(N);
+    constexpr int SC = cm_stride(NX);
     constexpr int CI = 3 * RW, CF = 3 * RW / 2;
     constexpr int CFT = SP ? 2 * CF : CF;  // forward columns (N, then chi_sp w)
     constexpr int NVAL = 3 + 12 * NC;
@@ -393,22 +396,22 @@ __global__ __launch_bounds__(NT) void k_xpass(const Member* __restrict__ mt, con
     // FP64 kinematics for the part choice where parts overlap (FP32 runs)
     constexpr bool K64 = NC > 1 && sizeof(T) < 8;
     __shared__ typename std::conditional<K64, KinT<double>, char>::type kin64;
-    __shared__ unsigned char amb[K64 ? RW * N : 1];  // point flagged for the FP64 part decision
+    __shared__ unsigned char amb[K64 ? RW * NX : 1];  // point flagged for the FP64 part decision
     __shared__ int amb_any;
     // twiddles from LDS unless the table would cost a workgroup per CU (FP64,
     // full-size tile: the tile alone is just under half of the 160 KiB)
     constexpr bool TWL = !(sizeof(T) == 8 && V == 0);
-    __shared__ cx<T> tws[TWL ? N : 1];
+    __shared__ cx<T> tws[TWL ? NX : 1];
     if (*gview(&hdr->status)) return;
     const int tid = threadIdx.x;
     const int row0 = wg * RW;
     const cx<T>* twx = tw;
     if constexpr (TWL) {
-        stage_twiddles<T, N>(tws, tw, NT);
+        stage_twiddles<T, NX>(tws, tw, NT);
         twx = tws;
     }
     if constexpr (K64) {
-        for (int e = tid; e < RW * N; e += NT) amb[e] = 0;
+        for (int e = tid; e < RW * NX; e += NT) amb[e] = 0;
         if (tid == 0) amb_any = 0;
     }
     // kinematics blocks prepared once per time level (state header) -> LDS
@@ -439,8 +442,8 @@ __global__ __launch_bounds__(NT) void k_xpass(const Member* __restrict__ mt, con
             }
         }
     }
-    for (int idx = tid; idx < CI * (N - 2 * K - 1); idx += NT) {
-        const int c = idx / (N - 2 * K - 1), n = K + 1 + idx % (N - 2 * K - 1);
+    for (int idx = tid; idx < CI * (NX - 2 * K - 1); idx += NT) {
+        const int c = idx / (NX - 2 * K - 1), n = K + 1 + idx % (NX - 2 * K - 1);
         buf[lds_at<true, 1, SC>(n, c)] = cx<T>{T(0), T(0)};
     }
 #pragma unroll
@@ -456,12 +459,12 @@ __global__ __launch_bounds__(NT) void k_xpass(const Member* __restrict__ mt, con
                     buf[lds_at<true, 1, SC>(0, cc)] = cx<T>{a.x, b.x};
                 } else {
                     buf[lds_at<true, 1, SC>(k, cc)] = cx<T>{a.x - b.y, a.y + b.x};
-                    buf[lds_at<true, 1, SC>(N - k, cc)] = cx<T>{a.x + b.y, b.x - a.y};
+                    buf[lds_at<true, 1, SC>(NX - k, cc)] = cx<T>{a.x + b.y, b.x - a.y};
                 }
             }
         }
     }
-    fft_cols<T, N, +1, CI, NT, SC>(buf, twx);
+    fft_cols<T, NX, +1, CI, NT, SC>(buf, twx);
 
     // 2. pointwise source and partial sums, one point per iteration (the mask
     //    code is large; a rolled loop keeps the register count down).  The
@@ -479,7 +482,7 @@ __global__ __launch_bounds__(NT) void k_xpass(const Member* __restrict__ mt, con
     double acc[NLANE];
 #pragma unroll
     for (int v = 0; v < NLANE; ++v) acc[v] = 0.0;
-    const T s = T(1.0 / ((double)N * (double)N * (double)N));
+    const T s = T(1.0 / ((double)NX * (double)N * (double)N));
     const KinT<double>* k64p = nullptr;
     if constexpr (K64) k64p = &kin64;
     // One grid point.  PH = 0: main sweep (with K64, points where two parts
@@ -489,15 +492,15 @@ __global__ __launch_bounds__(NT) void k_xpass(const Member* __restrict__ mt, con
     // Sweep index g -> (row r, x index i).  Each wave takes a compact patch of
     // PR rows x PX points (PR*PX = 64) rather than 64 points of one row, so the
     // lanes that need the mask's geometry tend to share waves.
-    constexpr int PR = (RW >= 4 && N % 16 == 0) ? 4 : ((RW >= 2 && N % 32 == 0) ? 2 : 1);
+    constexpr int PR = (RW >= 4 && NX % 16 == 0) ? 4 : ((RW >= 2 && NX % 32 == 0) ? 2 : 1);
     constexpr int PX = 64 / PR;
     const auto decode = [](int g, int& r, int& i) {
         if constexpr (PR == 1) {
-            r = g / N;
-            i = g % N;
+            r = g / NX;
+            i = g % NX;
         } else {
             const int lane_ = g & 63, p = g >> 6;
-            constexpr int NPX = N / PX;
+            constexpr int NPX = NX / PX;
             r = (p / NPX) * PR + lane_ / PX;
             i = (p % NPX) * PX + lane_ % PX;
         }
@@ -627,14 +630,14 @@ __global__ __launch_bounds__(NT) void k_xpass(const Member* __restrict__ mt, con
         }
     };
 #pragma unroll 1
-    for (int idx = tid; idx < RW * N; idx += NT) point(idx, true, std::integral_constant<int, 0>{});
+    for (int idx = tid; idx < RW * NX; idx += NT) point(idx, true, std::integral_constant<int, 0>{});
     if constexpr (K64) {
         // points where two parts overlap, in a fixed order (deterministic sums);
         // every lane runs the same number of iterations for the wave sums
         __syncthreads();
         if (amb_any) {
 #pragma unroll 1
-            for (int idx = tid; idx < RW * N; idx += NT) point(idx, amb[idx] != 0, std::integral_constant<int, 1>{});
+            for (int idx = tid; idx < RW * NX; idx += NT) point(idx, amb[idx] != 0, std::integral_constant<int, 1>{});
         }
     }
     // workgroup partial sums: lane values of the first three by DPP, the wave rows
@@ -663,7 +666,7 @@ __global__ __launch_bounds__(NT) void k_xpass(const Member* __restrict__ mt, con
             partial[(long)wg * NV + tid] = r;
         }
     }
-    fft_cols<T, N, -1, CFT, NT, SC>(fbuf, twx);
+    fft_cols<T, NX, -1, CFT, NT, SC>(fbuf, twx);
 
     // 3. split the packed spectra and store kx = 0..K
 #pragma unroll
@@ -675,7 +678,7 @@ __global__ __launch_bounds__(NT) void k_xpass(const Member* __restrict__ mt, con
             const int colx = c0 + ((fb < 2) ? r : RW + r / 2);
             const bool second = (fb == 1) || (fb == 2 && (r & 1));
             const cx<T> zk = fbuf[lds_at<true, 1, SC>(k, colx)];
-            const cx<T> zm = fbuf[lds_at<true, 1, SC>((N - k) % N, colx)];
+            const cx<T> zm = fbuf[lds_at<true, 1, SC>((NX - k) % NX, colx)];
             cx<T> v;
             if (!second) {
                 v = cx<T>{T(0.5) * (zk.x + zm.x), T(0.5) * (zk.y - zm.y)};
@@ -690,9 +693,9 @@ __global__ __launch_bounds__(NT) void k_xpass(const Member* __restrict__ mt, con
 
 // ---------------------------------------------------------------------------
 // Scalar work of a step.  The x-pass leaves NV partial sums per workgroup;
-// nred_of(N) extra workgroups of the y-forward launch reduce fixed
+// nred_of(NX, N) extra workgroups of the y-forward launch reduce fixed
 // contiguous chunks of them (first level); every z-pass workgroup reduces the
-// nred_of(N) results in a fixed order (second level) and derives dt and the
+// nred_of(NX, N) results in a fixed order (second level) and derives dt and the
 // AB2 weights itself, so all workgroups agree bit for bit.  Workgroup 0 of the
 // z-pass then writes the diagnostics and the next time level.
 // ---------------------------------------------------------------------------
@@ -1110,10 +1113,10 @@ enum { MODE_IMPORT = 0, MODE_STEP = 1, MODE_STEP_LAST = 2, MODE_INVERSE = 3, MOD
 // Member table: ceil(Q/C) workgroups per member.  par: slot of the current
 // time level; s: step index within the call (row of the history).
 // SP: the members have the vorticity sponge (fields 3..5 of the forward input).
-template <typename T, int N, int MODE, int V, bool SP = false>
+template <typename T, int NX, int N, int MODE, int V, bool SP = false>
 __global__ __launch_bounds__(nt_z(N, V)) void k_zpass(const Member* __restrict__ mt, const cx<T>* __restrict__ tw,
                                                       int par, int s, int rk) {
-    using G = Geo<T, N>;
+    using G = Geo<T, NX, N>;
     constexpr int K = G::K, KP = G::KP, M = G::M, Q = G::Q, Qp = G::Qp;
     constexpr int C = cols_z(N), NTZ = nt_z(N, V);
     constexpr int NBZ = (Q + C - 1) / C;
@@ -1142,7 +1145,7 @@ __global__ __launch_bounds__(nt_z(N, V)) void k_zpass(const Member* __restrict__
     constexpr int PERM = (M + RS - 1) / RS;
     constexpr int SC = cm_stride(N);
     constexpr int BUFB = C * SC * (int)sizeof(cx<T>);
-    constexpr int REDB = nred_of(N) * NV * 8;
+    constexpr int REDB = nred_of(NX, N) * NV * 8;
     __shared__ __align__(16) unsigned char smem[BUFB > REDB ? BUFB : REDB];
     __shared__ double tot[NV];
     __shared__ Coef cf;
@@ -1155,7 +1158,7 @@ __global__ __launch_bounds__(nt_z(N, V)) void k_zpass(const Member* __restrict__
     const int q = tile * C + c;
     const bool okq = q < Q;
     const int kxi = q % KP, myi = q / KP;
-    const double kxv = kscale * kxi;
+    const double kxv = mb.ksx * kxi;
     const double kyv = kscale * j_of_m(myi, K);
 
     const bool step_mode = (MODE == MODE_STEP || MODE == MODE_STEP_LAST || RKM);
@@ -1170,7 +1173,7 @@ __global__ __launch_bounds__(nt_z(N, V)) void k_zpass(const Member* __restrict__
     };
     if constexpr (FWD) load_field(0);
     if constexpr (STEPM) {
-        reduce_level2<NTZ, nred_of(N)>(partial2, reinterpret_cast<double*>(smem), tot);
+        reduce_level2<NTZ, nred_of(NX, N)>(partial2, reinterpret_cast<double*>(smem), tot);
         if (tile == NBZ) {
             if (tid == 0)
                 write_step(hdr, par, tot, step_coef(tot, hdr->slot[par], mb.ctl, dx, eta), mb.ctl, dx, eta,
@@ -1540,7 +1543,7 @@ __global__ void k_project_full(cx<T>* __restrict__ f3, int n, double kscale, int
 
 // Materialized mask (flusi_mask_insect).
 template <typename T>
-__global__ void k_mask(const Kin* __restrict__ kin, int n, double dx, T* __restrict__ chi,
+__global__ void k_mask(const Kin* __restrict__ kin, int nx, int n, double dx, T* __restrict__ chi,
                        T* __restrict__ us, int16_t* __restrict__ colour) {
     __shared__ KinT<T> kt;
     constexpr bool K64 = sizeof(T) < 8;
@@ -1550,10 +1553,10 @@ __global__ void k_mask(const Kin* __restrict__ kin, int n, double dx, T* __restr
         if (threadIdx.x == 64) kin_cast<double>(*kin, k64s);
     }
     __syncthreads();
-    const long npts = (long)n * n * n;
+    const long npts = (long)nx * n * n;
     const long p = (long)blockIdx.x * blockDim.x + threadIdx.x;
     if (p >= npts) return;
-    const int i = p % n, j = (p / n) % n, k = p / ((long)n * n);
+    const int i = p % nx, j = (p / nx) % n, k = p / ((long)nx * n);
     const KinT<double>* k64 = nullptr;
     if constexpr (K64) k64 = &k64s;
     const MaskPt<T> mp = eval_mask<T>(kt, dx * i, dx * j, dx * k, k64);
@@ -1589,17 +1592,18 @@ static __global__ __launch_bounds__(256) void k_rtab_build(WingCoef c, double* _
     tab32[j] = float(r);
 }
 
-// Pruned state spectrum [3][M][Qp] (q = my*KP + kx) -> full layout [3][n][n][n/2+1] (zeros elsewhere).
+// Pruned state spectrum [3][M][Qp] (q = my*KP + kx) -> full layout [3][n][n][nx/2+1] (zeros elsewhere).
 template <typename T>
-__global__ void k_export_full(const cx<T>* __restrict__ st, cx<T>* __restrict__ out, int n, long fs_s, long Qp) {
-    const int nkx = n / 2 + 1;
-    const int K = kmax_of(n), KP = K + 1, M = 2 * K + 1;
+__global__ void k_export_full(const cx<T>* __restrict__ st, cx<T>* __restrict__ out, int nx, int n, long fs_s,
+                              long Qp) {
+    const int nkx = nx / 2 + 1;
+    const int K = kmax_of(n), KX = kmax_of(nx), KP = KX + 1;
     const long tot = (long)n * n * nkx;
     const long e = (long)blockIdx.x * blockDim.x + threadIdx.x;
     if (e >= tot) return;
     const int ix = e % nkx, iy = (e / nkx) % n, iz = e / ((long)nkx * n);
     const int my = m_of_bin(iy, n, K), mz = m_of_bin(iz, n, K);
-    const bool kept = ix <= K && my >= 0 && mz >= 0;
+    const bool kept = ix <= KX && my >= 0 && mz >= 0;
     for (int f = 0; f < 3; ++f)
         out[f * tot + e] = kept ? st[f * fs_s + (long)mz * Qp + (long)my * KP + ix] : cx<T>{T(0), T(0)};
 }

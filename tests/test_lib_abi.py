@@ -30,7 +30,9 @@ def test_error_paths_without_gpu():
     lib = F.lib()
     h = ctypes.c_void_p()
     assert lib.flusi_plan_create(64, 64, 32, 1.0, 0.1, 1e-3, F.FLUSI_F64, ctypes.byref(h)) == F.FLUSI_EUNSUPPORTED
-    assert b"cubic" in lib.flusi_last_error()
+    assert b"ny = nz" in lib.flusi_last_error()
+    assert lib.flusi_plan_create(40, 32, 32, 1.0, 0.1, 1e-3, F.FLUSI_F64, ctypes.byref(h)) == F.FLUSI_EUNSUPPORTED
+    assert b"40 x 32 x 32 not supported" in lib.flusi_last_error()
     assert lib.flusi_plan_create(100, 100, 100, 1.0, 0.1, 1e-3, F.FLUSI_F64, ctypes.byref(h)) == F.FLUSI_EUNSUPPORTED
     assert lib.flusi_plan_create(64, 64, 64, -1.0, 0.1, 1e-3, F.FLUSI_F64, ctypes.byref(h)) == F.FLUSI_EINVAL
     assert lib.flusi_plan_create(64, 64, 64, 1.0, 0.1, 1e-3, 7, ctypes.byref(h)) == F.FLUSI_EINVAL

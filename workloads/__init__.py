@@ -49,20 +49,24 @@ def taylor_green(n: int, L: float = 2.0 * math.pi) -> np.ndarray:
     return u
 
 
-def _random_solenoidal(n: int, seed: int, kmin: float, kmax: float, slope: float | None):
-    """Random-phase band-limited divergence-free field (unit-free amplitude).
+def _random_solenoidal(n: int, seed: int, kmin: float, kmax: float, slope: float | None, nx: int | None = None):
+    """Random-phase band-limited divergence-free field (unit-free amplitude) on
+    an nx x n x n grid with one spacing (nx = n: cubic).
 
     Each Fourier mode with kmin <= |j| <= kmax gets a random vector made
     perpendicular to j (cross product with j) and a random phase; with `slope`
-    set, mode amplitudes follow an energy spectrum E(k) ~ k^slope."""
+    set, mode amplitudes follow an energy spectrum E(k) ~ k^slope.  On a
+    longer x axis j_x is counted in units of the y and z axes' base
+    wavenumber (j_x n / nx)."""
+    nx = n if nx is None else nx
     rng = np.random.default_rng(seed)
-    jx = np.arange(n // 2 + 1)[None, None, :]
+    jx = np.arange(nx // 2 + 1)[None, None, :]
     js = np.arange(n)
     js = np.where(js < n // 2, js, js - n)
     jy = js[None, :, None]
     jz = js[:, None, None]
-    shape = (n, n, n // 2 + 1)
-    jxf = np.broadcast_to(jx, shape).astype(np.float64)
+    shape = (n, n, nx // 2 + 1)
+    jxf = np.broadcast_to(jx, shape).astype(np.float64) * (n / nx)
     jyf = np.broadcast_to(jy, shape).astype(np.float64)
     jzf = np.broadcast_to(jz, shape).astype(np.float64)
     kmag = np.sqrt(jxf ** 2 + jyf ** 2 + jzf ** 2)
@@ -78,15 +82,15 @@ def _random_solenoidal(n: int, seed: int, kmin: float, kmax: float, slope: float
         amp = np.sqrt(kk ** slope / kk ** 2)
     phase = np.exp(2j * math.pi * rng.random(shape))
     coef = a / norm * amp * phase * shell
-    return scipy.fft.irfftn(coef, s=(n, n, n), axes=(1, 2, 3), workers=os.cpu_count())
+    return scipy.fft.irfftn(coef, s=(n, n, nx), axes=(1, 2, 3), workers=os.cpu_count())
 
 
 def inflow_noise(n: int, L: float, seed: int, rms: float = 1e-3, kmax: float = 8.0,
-                 mean=(1.0, 0.0, 0.0)) -> np.ndarray:
+                 mean=(1.0, 0.0, 0.0), nx: int | None = None) -> np.ndarray:
     """Mean inflow plus random-phase solenoidal noise in 1 <= |k| <= kmax, scaled
-    so that the rms of |u'| equals `rms`."""
+    so that the rms of |u'| equals `rms`; [3][n][n][nx] with nx = n by default."""
     del L
-    up = _random_solenoidal(n, seed, 1.0, kmax, None)
+    up = _random_solenoidal(n, seed, 1.0, kmax, None, nx)
     s = math.sqrt(float(np.mean(np.sum(up * up, axis=0))))
     up *= rms / s
     up[0] += mean[0]
