@@ -101,15 +101,17 @@ def counter_traffic(workload: str, kernel_prefix: str):
     return None
 
 
-def kernel_of_pass(pass_name: str, n: int, real: str, sched: dict, nc: int, dyn: bool) -> str:
-    """Kernel name (as rocprofv3 prints it) of a pass under a schedule."""
+def kernel_of_pass(pass_name: str, n: int, real: str, sched: dict, nc: int, dyn: bool, nx: int | None = None) -> str:
+    """Kernel name (as rocprofv3 prints it) of a pass under a schedule on an
+    nx x n x n grid (nx = n: cubic)."""
     split = sched["split_z"]
+    g = f"{n if nx is None else nx}, {n}"
     return {
-        "z_pass": f"k_zpass<{real}, {n}, {2 if split else 1}, {sched['z_pass']}, false>",
-        "z_inverse": f"k_zpass<{real}, {n}, 3, {sched['z_pass']}, false>",
-        "x_pass": f"k_xpass<{real}, {n}, {nc}, {sched['x_pass']}, false>",
-        "y_inverse": f"k_ypass<{real}, {n}, 1, 0, {sched['y_inverse']}>",
-        "y_forward": f"k_ypass<{real}, {n}, -1, 1, {sched['y_forward']}>",
+        "z_pass": f"k_zpass<{real}, {g}, {2 if split else 1}, {sched['z_pass']}, false>",
+        "z_inverse": f"k_zpass<{real}, {g}, 3, {sched['z_pass']}, false>",
+        "x_pass": f"k_xpass<{real}, {g}, {nc}, {sched['x_pass']}, false>",
+        "y_inverse": f"k_ypass<{real}, {g}, 1, 0, {sched['y_inverse']}>",
+        "y_forward": f"k_ypass<{real}, {g}, -1, 1, {sched['y_forward']}>",
     }[pass_name]
 
 

@@ -218,8 +218,9 @@ int flusi_sizes(int n, int dtype, size_t* workspace_bytes, size_t* state_bytes);
  * below 2.5/(nu max|k|^2) over the kept modes (explicit diffusion stability).
  * RK4 allocates three fields of stage velocity (synchronously, once) and uses
  * the state's AB2 history storage for its stage sum, so a later AB2 step
- * starts with Euler.  RK4 plans step alone: free flight and ensembles are
- * AB2 only.  Errors: EINVAL, ENOMEM. */
+ * starts with Euler.  Free flight is AB2 only (flusi_step and
+ * flusi_ensemble_add return EUNSUPPORTED for it under RK4).  Errors: EINVAL,
+ * ENOMEM. */
 int flusi_plan_set_integrator(flusi_plan plan, int integrator);
 
 /* Dirichlet layers (Sec. 2.3: velocity conditions imposed by the volume
@@ -387,9 +388,11 @@ int flusi_autotune(flusi_plan plan, const void* state, const flusi_insect* ins, 
  * Ensembles: many independent simulations advanced together.
  *
  * A member is a (plan, state) pair with its body and step controls; plans
- * may differ in n, L, nu and eta but share the ensemble's dtype, and a plan
- * belongs to at most one member (its scratch buffers are the member's).
- * Members of equal n form a size group.  flusi_ensemble_step launches each
+ * may differ in grid, L, nu, eta and integrator but share the ensemble's
+ * dtype, and a plan belongs to at most one member (its scratch buffers are the
+ * member's).  Members of equal grid shape and integrator form a size group
+ * (the group is fixed when the ensemble is next stepped after an add or
+ * remove).  flusi_ensemble_step launches each
  * pass of Algorithm 1 once per size group over all of its members (one
  * workgroup grid spanning every member), with the size groups on parallel
  * streams forked from the ensemble's stream.  Each member follows exactly the
@@ -412,7 +415,8 @@ int flusi_ensemble_set_stream(flusi_ensemble e, void* stream);
  * flusi_step (p->nsteps is ignored; p->history, when set, receives one record
  * per step of each flusi_ensemble_step call, row s for step s of the call).
  * *id receives a member index that stays valid until the member is removed.
- * Errors: EINVAL (dtype mismatch, plan already a member, bad controls). */
+ * Errors: EINVAL (dtype mismatch, plan already a member, bad controls),
+ * EUNSUPPORTED (free flight on an RK4 plan). */
 int flusi_ensemble_add(flusi_ensemble e, flusi_plan plan, void* state, const flusi_insect* ins,
                        const flusi_step_params* p, int* id);
 /* Removes member id (its state is left as it is). */

@@ -688,9 +688,13 @@ static int ens_rebuild(flusi_ensemble e) {
     hipError_t err = hipStreamSynchronize(e->own);
     if (err != hipSuccess) return set_error(FLUSI_EDEVICE, "ensemble: %s", hipGetErrorString(err));
     ens_clear_groups(e);
-    std::map<long, std::vector<int>> by_n;  // key: grid shape (nx, n)
+    // key: grid shape (nx, n) and integrator (the RK4 and AB2 pass sequences differ)
+    std::map<long, std::vector<int>> by_n;
     for (int i = 0; i < (int)e->members.size(); ++i)
-        if (e->members[i].used) by_n[(long)e->members[i].plan->d.nx * 65536 + e->members[i].plan->d.n].push_back(i);
+        if (e->members[i].used) {
+            const PlanData& pd = e->members[i].plan->d;
+            by_n[((long)pd.nx * 65536 + pd.n) * 2 + (pd.integrator == FLUSI_INT_RK4 ? 1 : 0)].push_back(i);
+        }
     for (auto& kv : by_n) {
         std::vector<int>& ids = kv.second;
         // order: without sponge, then with; within each, by colour count
@@ -700,7 +704,8 @@ static int ens_rebuild(flusi_ensemble e) {
         };
         std::stable_sort(ids.begin(), ids.end(), [&](int a, int b) { return key(a) < key(b); });
         EnsGroup g;
-        g.n = (int)(kv.first % 65536);
+        g.n = (int)(kv.first / 2 % 65536);
+        g.run.rk = (kv.first & 1) != 0;
         g.p0 = e->members[ids[0]].plan;
         const PlanData& p0 = g.p0->d;
         g.impl = p0.impl;
@@ -817,7 +822,8 @@ int flusi_ensemble_add(flusi_ensemble e, flusi_plan plan, void* state, const flu
     if (!state || !p) return set_error(FLUSI_EINVAL, "ensemble_add: null pointer");
     if (int rc = check_insect(ins)) return rc;
     if (plan->d.dtype != e->dtype) return set_error(FLUSI_EINVAL, "ensemble_add: plan dtype differs from the ensemble's");
-    if (plan->d.integrator != FLUSI_INT_AB2) return set_error(FLUSI_EUNSUPPORTED, "ensemble_add: ensembles step with AB2 only");
+    if (plan->d.integrator == FLUSI_INT_RK4 && free_flight_on(ins))
+        return set_error(FLUSI_EUNSUPPORTED, "ensemble_add: free flight is stepped with AB2 only");
     if (!(p->dt_fixed > 0.0) && !(p->cfl > 0.0)) return set_error(FLUSI_EINVAL, "ensemble_add: need dt_fixed > 0 or cfl > 0");
     for (const auto& m : e->members)
         if (m.used && m.plan == plan) return set_error(FLUSI_EINVAL, "ensemble_add: plan is already a member");

@@ -140,7 +140,33 @@ def test_chunks_schedules_and_limits():
     assert e.value.code == F.FLUSI_EUNSUPPORTED
     ens = F.Ensemble("f32")
     with pytest.raises(F.FlusiError) as e:
-        ens.add(P, a, body, cfl=0.1)
+        ens.add(P, a, ff, cfl=0.1)
     assert e.value.code == F.FLUSI_EUNSUPPORTED
     ens.close()
     assert F.lib().flusi_plan_set_integrator(P.handle, 7) == F.FLUSI_EINVAL
+
+
+def test_rk4_members_in_ensembles_equal_solo_runs():
+    """RK4 and AB2 members of one ensemble (separate groups of the same grid,
+    graph replay) equal their solo runs bitwise."""
+    specs = [(48, "rk4", W.model_insect(48, 4.0)), (48, "ab2", W.model_insect(48, 4.0)),
+             (32, "rk4", W.sphere_body(4.0)), (48, "rk4", None)]
+    ens = F.Ensemble("f32")
+    pairs = []
+    for k, (n, integ, body) in enumerate(specs):
+        u0 = W.inflow_noise(n, 4.0, seed=70 + k, rms=1e-2, kmax=6.0)
+        Pa, Pb = F.Plan(n, 4.0, 0.01, 5e-3, "f32"), F.Plan(n, 4.0, 0.01, 5e-3, "f32")
+        Pa.set_integrator(integ)
+        Pb.set_integrator(integ)
+        sa, sb = Pa.new_state(torch.from_numpy(u0)), Pb.new_state(torch.from_numpy(u0))
+        ens.add(Pa, sa, body, cfl=0.1)
+        pairs.append((Pa, sa, Pb, sb, body))
+    assert ens.size() == (4, 3)
+    ens.step(3, graph=True)
+    ens.step(2)
+    for Pa, sa, Pb, sb, body in pairs:
+        Pb.step(sb, 5, body, cfl=0.1)
+    torch.cuda.synchronize()
+    for i, (Pa, sa, Pb, sb, _) in enumerate(pairs):
+        assert torch.equal(Pa.uhat(sa), Pb.uhat(sb)), i
+    ens.close()
