@@ -364,8 +364,18 @@ __device__ __forceinline__ void block_reduce_store(const double (&acc)[NVAL], do
 // Member table: N*N/RW workgroups per member, y-partials in bufB, output in bufA.
 // SP: members with the vorticity sponge; chi_sp * w is transformed beside N
 // and stored as fields 3..5.
+// Workgroups per CU the x-pass asks the compiler to fit (registers), where
+// its LDS allows: the FP32 full-size tile without wing parts (its twiddles
+// are then read from the table in memory, keeping the tile under 40 KiB);
+// not at nx = 512, where the 128-register budget spills.
+template <typename T, int NX, int NC, int V, bool SP>
+__host__ __device__ constexpr int xpass_min_blocks() {
+    return (sizeof(T) < 8 && V == 0 && NC <= 1 && !SP && NX < 512) ? 4 : 1;
+}
+
 template <typename T, int NX, int N, int NC, int V, bool SP>
-__global__ __launch_bounds__(NT) void k_xpass(const Member* __restrict__ mt, const cx<T>* __restrict__ tw) {
+__global__ __launch_bounds__(NT, (xpass_min_blocks<T, NX, NC, V, SP>())) void k_xpass(const Member* __restrict__ mt,
+                                                                               const cx<T>* __restrict__ tw) {
     using G = Geo<T, NX, N>;
     constexpr int K = G::KX, KP = G::KP, KPp = G::KPp;  // the x axis' cut
     constexpr int RW = rows_x(NX, sizeof(cx<T>), V);
@@ -400,7 +410,7 @@ __global__ __launch_bounds__(NT) void k_xpass(const Member* __restrict__ mt, con
     __shared__ int amb_any;
     // twiddles from LDS unless the table would cost a workgroup per CU (FP64,
     // full-size tile: the tile alone is just under half of the 160 KiB)
-    constexpr bool TWL = !(sizeof(T) == 8 && V == 0);
+    constexpr bool TWL = !(sizeof(T) == 8 && V == 0) && xpass_min_blocks<T, NX, NC, V, SP>() == 1;
     __shared__ cx<T> tws[TWL ? NX : 1];
     if (*gview(&hdr->status)) return;
     const int tid = threadIdx.x;
