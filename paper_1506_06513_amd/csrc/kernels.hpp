@@ -1123,6 +1123,14 @@ enum { MODE_IMPORT = 0, MODE_STEP = 1, MODE_STEP_LAST = 2, MODE_INVERSE = 3, MOD
 // Member table: ceil(Q/C) workgroups per member.  par: slot of the current
 // time level; s: step index within the call (row of the history).
 // SP: the members have the vorticity sponge (fields 3..5 of the forward input).
+// Fields the z-pass transforms together (one column transform over FB*C
+// columns, so that more lanes work at once): 3 where three column tiles fit
+// in 64 KiB of LDS, else 1.
+template <typename T, int N>
+__host__ __device__ constexpr int zpass_fb() {
+    return 3 * cols_z(N) * cm_stride(N) * (int)sizeof(cx<T>) <= 65536 ? 3 : 1;
+}
+
 template <typename T, int NX, int N, int MODE, int V, bool SP = false>
 __global__ __launch_bounds__(nt_z(N, V)) void k_zpass(const Member* __restrict__ mt, const cx<T>* __restrict__ tw,
                                                       int par, int s, int rk) {
@@ -1154,7 +1162,8 @@ __global__ __launch_bounds__(nt_z(N, V)) void k_zpass(const Member* __restrict__
     static_assert(NTZ % C == 0 && N % RS == 0, "column mapping");
     constexpr int PERM = (M + RS - 1) / RS;
     constexpr int SC = cm_stride(N);
-    constexpr int BUFB = C * SC * (int)sizeof(cx<T>);
+    constexpr int FB = zpass_fb<T, N>();
+    constexpr int BUFB = FB * C * SC * (int)sizeof(cx<T>);
     constexpr int REDB = nred_of(NX, N) * NV * 8;
     __shared__ __align__(16) unsigned char smem[BUFB > REDB ? BUFB : REDB];
     __shared__ double tot[NV];
@@ -1172,16 +1181,19 @@ __global__ __launch_bounds__(nt_z(N, V)) void k_zpass(const Member* __restrict__
     const double kyv = kscale * j_of_m(myi, K);
 
     const bool step_mode = (MODE == MODE_STEP || MODE == MODE_STEP_LAST || RKM);
-    // forward input: field f+1 is loaded while field f is transformed; field 0
-    // is in flight together with the reduction loads
+    // forward input: the next FB fields are loaded while the current FB are
+    // transformed; the first FB are in flight together with the reduction loads
     constexpr bool FWD = (MODE == MODE_IMPORT) || step_mode;
-    cx<T> vn[FWD ? RPT : 1];
-    const auto load_field = [&](int f) {
+    cx<T> vn[FWD ? FB : 1][RPT];
+    const auto load_field = [&](int f, int slot) {
 #pragma unroll
         for (int i = 0; i < RPT; ++i)
-            vn[i] = okq ? gld(yin, f * fs_y + (long)(r0 + i * RS) * Qp + q) : cx<T>{T(0), T(0)};
+            vn[slot][i] = okq ? gld(yin, f * fs_y + (long)(r0 + i * RS) * Qp + q) : cx<T>{T(0), T(0)};
     };
-    if constexpr (FWD) load_field(0);
+    if constexpr (FWD) {
+#pragma unroll
+        for (int f = 0; f < FB; ++f) load_field(f, f);
+    }
     if constexpr (STEPM) {
         reduce_level2<NTZ, nred_of(NX, N)>(partial2, reinterpret_cast<double*>(smem), tot);
         if (tile == NBZ) {
@@ -1207,16 +1219,29 @@ __global__ __launch_bounds__(nt_z(N, V)) void k_zpass(const Member* __restrict__
         // vorticity sponge: fields 3..5 hold chi_sp * w
         constexpr bool sp = SP && (MODE == MODE_STEP || MODE == MODE_STEP_LAST || RKM);
         cx<T> Nh[3][PERM];
+        // column c of field f0 + b of a batch sits in LDS column b*C + c
+        const auto put_batch = [&](int f0) {
 #pragma unroll
-        for (int f = 0; f < 3; ++f) {
+            for (int b = 0; b < FB; ++b) {
 #pragma unroll
-            for (int i = 0; i < RPT; ++i) buf[c * SC + cpad(r0 + i * RS)] = vn[i];
-            if (f < 2 || sp) load_field(f + 1);
-            fft_cols<T, N, -1, C, NTZ, SC>(buf, tws);
+                for (int i = 0; i < RPT; ++i) buf[(b * C + c) * SC + cpad(r0 + i * RS)] = vn[b][i];
+            }
+            if (f0 + FB < (sp ? 6 : 3)) {
 #pragma unroll
-            for (int i = 0; i < PERM; ++i) {
-                const int m = r0 + i * RS;
-                if (m < M) Nh[f][i] = buf[c * SC + cpad(bin_of_m(m, N, K))];
+                for (int b = 0; b < FB; ++b) load_field(f0 + FB + b, b);
+            }
+            fft_cols<T, N, -1, FB * C, NTZ, SC>(buf, tws);
+        };
+#pragma unroll
+        for (int f0 = 0; f0 < 3; f0 += FB) {
+            put_batch(f0);
+#pragma unroll
+            for (int b = 0; b < FB; ++b) {
+#pragma unroll
+                for (int i = 0; i < PERM; ++i) {
+                    const int m = r0 + i * RS;
+                    if (m < M) Nh[f0 + b][i] = buf[(b * C + c) * SC + cpad(bin_of_m(m, N, K))];
+                }
             }
             __syncthreads();
         }
@@ -1224,16 +1249,16 @@ __global__ __launch_bounds__(nt_z(N, V)) void k_zpass(const Member* __restrict__
             // N_hat += -(1/C_sp) (i k x W_hat)/|k|^2, one W component at a time
             // (eq. PNST_org_momentum, sponge term; zero at k = 0)
 #pragma unroll
-            for (int f = 3; f < 6; ++f) {
+            for (int f0 = 3; f0 < 6; f0 += FB) {
+                put_batch(f0);
 #pragma unroll
-                for (int i = 0; i < RPT; ++i) buf[c * SC + cpad(r0 + i * RS)] = vn[i];
-                if (f < 5) load_field(f + 1);
-                fft_cols<T, N, -1, C, NTZ, SC>(buf, tws);
+                for (int b = 0; b < FB; ++b) {
+                const int f = f0 + b;
 #pragma unroll
                 for (int i = 0; i < PERM; ++i) {
                     const int m = r0 + i * RS;
                     if (m < M && okq) {
-                        const cx<T> w = buf[c * SC + cpad(bin_of_m(m, N, K))];
+                        const cx<T> w = buf[(b * C + c) * SC + cpad(bin_of_m(m, N, K))];
                         const double kzv = kscale * j_of_m(m, K);
                         const double k2 = kxv * kxv + kyv * kyv + kzv * kzv;
                         const double a = k2 > 0.0 ? -mb.inv_csp / k2 : 0.0;
@@ -1253,6 +1278,7 @@ __global__ __launch_bounds__(nt_z(N, V)) void k_zpass(const Member* __restrict__
                             add(Nh[1][i], -kxv);
                         }
                     }
+                }
                 }
                 __syncthreads();
             }
@@ -1361,36 +1387,48 @@ __global__ __launch_bounds__(nt_z(N, V)) void k_zpass(const Member* __restrict__
     if (!do_inv) return;
 
     const T kx = T(kxv), ky = T(kyv);
+    // u and w = i k x u, FB fields per column transform (field g0 + b in LDS
+    // columns b*C ..)
 #pragma unroll
-    for (int g = 0; g < 6; ++g) {
-        for (int idx = tid; idx < C * (N - M); idx += NTZ) buf[(idx % C) * SC + cpad(K + 1 + idx / C)] = cx<T>{T(0), T(0)};
+    for (int g0 = 0; g0 < 6; g0 += FB) {
+        for (int idx = tid; idx < FB * C * (N - M); idx += NTZ) {
+            const int b = idx / (C * (N - M)), e = idx % (C * (N - M));
+            buf[(b * C + e % C) * SC + cpad(K + 1 + e / C)] = cx<T>{T(0), T(0)};
+        }
 #pragma unroll
-        for (int i = 0; i < PERM; ++i) {
-            const int m = r0 + i * RS;
-            if (m < M) {
-                cx<T> v = {T(0), T(0)};
-                if (okq) {
-                    if (g < 3) {
-                        v = U[g][i];
-                    } else {
-                        const T kz = T(kscale * j_of_m(m, K));
-                        cx<T> a;
-                        if (g == 3) a = U[2][i] * ky - U[1][i] * kz;
-                        else if (g == 4) a = U[0][i] * kz - U[2][i] * kx;
-                        else a = U[1][i] * kx - U[0][i] * ky;
-                        v = mul_pi(a);
+        for (int b = 0; b < FB; ++b) {
+            const int g = g0 + b;
+#pragma unroll
+            for (int i = 0; i < PERM; ++i) {
+                const int m = r0 + i * RS;
+                if (m < M) {
+                    cx<T> v = {T(0), T(0)};
+                    if (okq) {
+                        if (g < 3) {
+                            v = U[g][i];
+                        } else {
+                            const T kz = T(kscale * j_of_m(m, K));
+                            cx<T> a;
+                            if (g == 3) a = U[2][i] * ky - U[1][i] * kz;
+                            else if (g == 4) a = U[0][i] * kz - U[2][i] * kx;
+                            else a = U[1][i] * kx - U[0][i] * ky;
+                            v = mul_pi(a);
+                        }
                     }
+                    buf[(b * C + c) * SC + cpad(bin_of_m(m, N, K))] = v;
                 }
-                buf[c * SC + cpad(bin_of_m(m, N, K))] = v;
             }
         }
-        fft_cols<T, N, +1, C, NTZ, SC>(buf, tws);
+        fft_cols<T, N, +1, FB * C, NTZ, SC>(buf, tws);
         if (okq) {
-            cx<T> o[RPT];
 #pragma unroll
-            for (int i = 0; i < RPT; ++i) o[i] = buf[c * SC + cpad(r0 + i * RS)];
+            for (int b = 0; b < FB; ++b) {
+                cx<T> o[RPT];
 #pragma unroll
-            for (int i = 0; i < RPT; ++i) gst(zout, g * fs_z + (long)(r0 + i * RS) * Qp + q, o[i]);
+                for (int i = 0; i < RPT; ++i) o[i] = buf[(b * C + c) * SC + cpad(r0 + i * RS)];
+#pragma unroll
+                for (int i = 0; i < RPT; ++i) gst(zout, (g0 + b) * fs_z + (long)(r0 + i * RS) * Qp + q, o[i]);
+            }
         }
         __syncthreads();
     }
