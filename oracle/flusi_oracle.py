@@ -1009,9 +1009,11 @@ def force_sums(g: Grid, u, chi, us, colour, xref, eta):
     return F, M, I
 
 
-def torque_about(g: Grid, u, chi, us, xc, eta):
+def torque_about(g: Grid, u, chi, us, xc, eta, colour):
     """Penalization torque and J = sum (x - xc) x chi u_s dV about the point xc,
-    over the whole solid  [eq. moment_of_love]."""
+    over the whole body: every point of a part (colour > 0); the points of
+    wall layers (colour 0) are not the body's  [eq. moment_of_love, Sec. 2.3]."""
+    chi = np.where(colour > 0, chi, 0.0)
     x, y, z = g.coords()
     r = np.stack([x - xc[0], y - xc[1], z - xc[2]])
     pen = chi * (u - us) / eta * g.dV
@@ -1082,7 +1084,7 @@ def step(p: Params, st: State, ctl: StepControl, ins: Insect | None, fixed_mask=
         diag["pose"] = pose_record(ins, st.t, ysol)
         diag["P_aero"] = np.array([aero_power(M[1 + k], pose.Mb, omega_wing_b(ins, st.t, side)) if ins.wings
                                    else 0.0 for k, side in enumerate(("l", "r"))])
-        m_pen, J_now = torque_about(g, u, chi, us, pose.xc, p.eta)
+        m_pen, J_now = torque_about(g, u, chi, us, pose.xc, p.eta, colour)
         if ins.free_flight:
             Ft = F.sum(axis=0)
             mt = m_pen

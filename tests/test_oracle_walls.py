@@ -68,3 +68,21 @@ def test_full_layer_relaxes_to_the_wall_velocity():
         exact = uw + (np.array([0.2, 0.3, -0.1]) - uw) * math.exp(-T / eta)
         errs.append(float(np.max(np.abs(u - exact.reshape(3, 1, 1, 1)))))
     assert errs[1] < 2e-3 and 3.5 < errs[0] / errs[1] < 4.5
+
+
+def test_layers_do_not_enter_the_free_body_torque():
+    """A free-flying sphere (cosine mask) with a wall layer away from it: the
+    total force and the torque about its centre that drive the body, and the
+    body state after the first step, equal those without the layer."""
+    n, L = 24, 4.0
+    u0 = W.inflow_noise(n, L, seed=4, rms=1e-2, kmax=4.0)
+    ins = O.Insect.from_dict(dict(W.sphere_body(L), smooth="cos", free_flight=True, mass=2.0,
+                                  inertia=(0.1, 0.1, 0.1), gravity=1.0, psi_dot=0.0))
+    ctl = O.StepControl(cfl=0.1)
+    p0 = O.Params(n, L, 0.01, 1e-2, O.MEAN_FIXED)
+    p1 = O.Params(n, L, 0.01, 1e-2, O.MEAN_FIXED, wall=(0.5, 0.0, 0.0), u_wall=(1.0, 0.0, 0.0))
+    s0, d0 = O.step(p0, O.init_state(p0, u0), ctl, ins)
+    s1, d1 = O.step(p1, O.init_state(p1, u0), ctl, ins)
+    assert np.array_equal(d0["F_total"], d1["F_total"]) and np.array_equal(d0["m_cntr"], d1["m_cntr"])
+    assert np.array_equal(s0.solid, s1.solid)
+    assert np.max(np.abs(d0["m_cntr"])) > 0.0
