@@ -184,3 +184,29 @@ def test_ensemble_mixing_shapes_and_limits():
         P.set_walls((6.5, 0.0, 0.0), (0.0, 0.0, 0.0))  # thicker than the x side
     assert e.value.code == F.FLUSI_EINVAL
     P.set_walls((5.5, 0.0, 0.0), (0.0, 0.0, 0.0))  # thicker than L, within Lx
+
+
+def test_free_insect_in_a_box_with_a_wall_layer():
+    """The model insect in free flight (six DoF, gravity) in the 64x32x32 box
+    with a wall layer at the far x end: velocity, body state and forces
+    against the oracle (FP64)."""
+    nx, n = 64, 32
+    Lx = L * nx / n
+    body = W.model_insect(n, L)
+    body.update(x_cntr=(3.0, L / 2, L / 2), free_flight=True, mass=20.0, inertia=(0.5, 0.7, 0.7),
+                gravity=0.5, dof=(1, 1, 1, 1, 1, 1))
+    u0 = W.inflow_noise(n, L, seed=96, rms=1e-2, kmax=6.0, nx=nx)
+    wall = ((0.5, 0.0, 0.0), (0.0, 0.0, 0.0))
+    p = O.Params(n, L, 1 / 136, 5e-3, O.MEAN_FIXED, nx=nx, Lx=Lx, wall=wall[0], u_wall=wall[1])
+    ost, oh = O.run(p, u0, 8, O.StepControl(cfl=0.1), O.Insect.from_dict(body))
+    P = F.Plan(n, L, 1 / 136, 5e-3, "f64", nx=nx)
+    P.set_walls(*wall)
+    st = P.new_state(torch.from_numpy(u0))
+    h = P.step(st, 8, body, history=True, cfl=0.1).cpu().numpy()
+    assert rel_l2(np_of(P.velocity(st)), O.velocity(p, ost)) < 1e-11
+    y, oy = P.solid(st), ost.solid
+    assert np.max(np.abs(y - oy)) < 1e-12 * max(1.0, np.max(np.abs(oy)))
+    assert 0.0 < np.max(np.abs(oy[10:13])) < 10.0  # it turns, and the run stays bounded
+    for c in range(3):
+        oF = np.array([d["F"][c] for d in oh])
+        assert np.max(np.abs(h[:, 4 + 6 * c:7 + 6 * c] - oF)) <= 1e-9 * max(1e-12, np.max(np.abs(oF))), c

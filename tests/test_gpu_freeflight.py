@@ -37,8 +37,12 @@ def falling_sphere(**kw):
 
 
 def free_insect(n, **kw):
+    """The model insect in free flight with an insect-like density (mass about
+    1000 times the displaced fluid's): a body only a few times denser than the
+    fluid makes the explicit coupling of the penalization force with the body
+    unstable (added-mass effect), and the runs diverge."""
     d = W.model_insect(n, L)
-    d.update(free_flight=True, mass=0.05, inertia=(2e-3, 3e-3, 3e-3), gravity=0.5)
+    d.update(free_flight=True, mass=20.0, inertia=(0.5, 0.7, 0.7), gravity=0.5)
     d.update(kw)
     return d
 
