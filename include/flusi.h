@@ -12,16 +12,18 @@
  *  - Every call returns an int status: FLUSI_OK (0) or a negative FLUSI_E*
  *    code.  flusi_last_error() returns a thread-local message for the last
  *    failure.  No C++ exception crosses the ABI.
- *  - Box: cubic, side L, n points per axis (nx = ny = nz = n), grid points
- *    x_i = i*L/n.  Supported n: 16, 24, 32, 48, 64, 96, 128, 192, 256, 384,
- *    512 (even and of the form 2^a 3^b).
+ *  - Box: n points per axis on y and z (side L) and nx on x (side L*nx/n),
+ *    one spacing L/n, grid points x_i = i*L/n.  Cubic grids (nx = n) for n in
+ *    16, 24, 32, 48, 64, 96, 128, 192, 256, 384, 512 (even and of the form
+ *    2^a 3^b); boxes 48x32x32, 64x32x32 and 192x128x128 (see
+ *    flusi_plan_create).
  *  - Physical fields: [field][z][y][x] row-major, x fastest, real type of the
  *    plan (float for FLUSI_F32, double for FLUSI_F64).
- *  - Spectral fields, full layout: [field][kz][ky][kx] with kx = 0..n/2
+ *  - Spectral fields, full layout: [field][kz][ky][kx] with kx = 0..nx/2
  *    (fastest), ky and kz in FFT order (bin i holds j = i for i < n/2 and
  *    j = i - n otherwise); complex values are interleaved (re, im) pairs of
  *    the plan's real type.  The forward transform is unnormalized with
- *    exp(-i k.x); the inverse is scaled by 1/n^3.
+ *    exp(-i k.x); the inverse is scaled by 1/(nx n n).
  *  - Every field/state pointer is a DEVICE pointer owned by the caller,
  *    contiguous and 16-byte aligned.  The plan owns twiddle tables, integer
  *    tables and scratch memory.
