@@ -341,8 +341,8 @@ def main():
         print(json.dumps({"copy_bytes_read": x.numel() * 4, "copy_bytes_written": y.numel() * 4, "launches": 3}))
         return
     if a.gpus != 1:
-        print(f"bench.py: this build measures one GPU only (asked for {a.gpus}); the multi-GPU "
-              "decomposition is not part of it", file=sys.stderr)
+        print(f"bench.py: the solver runs on one GPU (asked for {a.gpus}); its fields are not "
+              "decomposed over several GPUs", file=sys.stderr)
         raise SystemExit(2)
 
     import torch
