@@ -40,19 +40,21 @@ METRIC = "Mpoint-steps/s (AB2 RHS) FP32 vs FP64 at stated err; p50/p99 solve lat
 HBM_PEAK_GBS = 8000.0
 
 
-def pass_bytes(n: int, cbytes: int, split_z: bool, x_variant: int = 0) -> dict:
-    """Algorithmic HBM bytes per launch of each pass of the pruned schedule.
+def pass_bytes(n: int, cbytes: int, split_z: bool, x_variant: int = 0, nx: int | None = None) -> dict:
+    """Algorithmic HBM bytes per launch of each pass of the pruned schedule on
+    an nx x n x n grid (nx = n by default).
 
-    K = (n-1)//3, KP = K+1 kept kx, M = 2K+1 kept ky and kz, Q = M*KP.
+    K = (n-1)//3, KP = (nx-1)//3 + 1 kept kx, M = 2K+1 kept ky and kz, Q = M*KP.
     z-partials [6][n][Q], y-partials [6][n][n][KP], x-output [3][n][n][KP],
     y-output [3][n][Q], state u_hat and previous right-hand side [3][M][Q] each.
     z_pass is forward z + projection + AB2 (+ curl and inverse z when fused);
     z_inverse is curl + inverse z from the state."""
+    nx = n if nx is None else nx
     K = (n - 1) // 3
-    KP, M = K + 1, 2 * K + 1
+    KP, M = (nx - 1) // 3 + 1, 2 * K + 1
     Q = M * KP
     s = cbytes
-    rows = max(2, 1 << int(math.log2(max(1, 1024 // n))))
+    rows = max(2, 1 << int(math.log2(max(1, 1024 // nx))))
     if x_variant and rows > 2:
         rows //= 2
     nwg = n * n // rows
@@ -66,10 +68,10 @@ def pass_bytes(n: int, cbytes: int, split_z: bool, x_variant: int = 0) -> dict:
     }
 
 
-def step_bytes(n: int, cbytes: int) -> int:
+def step_bytes(n: int, cbytes: int, nx: int | None = None) -> int:
     """Bytes the fused four-pass schedule must move per step (the algorithmic
     model; a split z-pass re-reads u_hat, which is not counted)."""
-    b = pass_bytes(n, cbytes, split_z=False)
+    b = pass_bytes(n, cbytes, split_z=False, nx=nx)
     return b["y_inverse"] + b["x_pass"] + b["y_forward"] + b["z_pass"]
 
 
@@ -139,6 +141,16 @@ def build_workload(name: str):
         desc = ("128^3 box L=4, sphere R=0.5 tanh mask 2dx, inflow (1,0,0) + solenoidal noise rms 1e-3 "
                 "|k|<=8 (seed 0), nu=0.01, C_eta=1e-3, adaptive dt CFL 0.1 capped at C_eta/2")
         return dict(n=n, L=L, nu=wl["nu"], eta=wl["eta"], u0=u0, insect=body, cfl=0.1, dt_fixed=0.0,
+                    desc=desc, default_steps=wl["steps"])
+    if name == "box192":
+        wl = W.WORKLOADS["sphere128"]
+        n, nx, L = 128, 192, wl["L"]
+        u0 = W.inflow_noise(n, L, seed=wl["seed"], rms=1e-3, kmax=8.0, nx=nx)
+        body = dict(W.sphere_body(L), x_cntr=(2.4, 2.0, 2.0))
+        desc = ("192x128x128 box 6x4x4 (one spacing 1/32, the paper's box shape), sphere R=0.5 at (2.4, 2, 2) "
+                "tanh mask 2dx, inflow (1,0,0) + solenoidal noise rms 1e-3 |k|<=8 (seed 0), nu=0.01, "
+                "C_eta=1e-3, adaptive dt CFL 0.1 capped at C_eta/2")
+        return dict(n=n, nx=nx, L=L, nu=wl["nu"], eta=wl["eta"], u0=u0, insect=body, cfl=0.1, dt_fixed=0.0,
                     desc=desc, default_steps=wl["steps"])
     if name == "freefall128":
         wl = build_workload("sphere128")
@@ -298,7 +310,8 @@ def serve_run(F, torch, count=120, seed=2, budget_gib=32.0, chunk=20, big_n=512,
 def oracle_sample(wl, budget_s=12.0, max_steps=30):
     """Oracle throughput and final velocity on a bounded sample of the workload."""
     import oracle as O
-    p = O.Params(wl["n"], wl["L"], wl["nu"], wl["eta"], O.MEAN_FIXED)
+    nx = wl.get("nx") or wl["n"]
+    p = O.Params(wl["n"], wl["L"], wl["nu"], wl["eta"], O.MEAN_FIXED, nx=nx, Lx=wl["L"] * nx / wl["n"])
     ins = O.Insect.from_dict(wl["insect"]) if wl["insect"] else None
     ctl = O.StepControl(dt_fixed=wl["dt_fixed"], cfl=wl["cfl"] or 0.1, eta_cap=0.5)
     st = O.init_state(p, wl["u0"])
@@ -319,7 +332,7 @@ def main():
     ap.add_argument("--steps", type=int, default=None)
     ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--workload", default="sphere128",
-                    choices=["sphere128", "freefall128", "insect256", "tg32", "ensemble48", "serve"])
+                    choices=["sphere128", "freefall128", "insect256", "box192", "tg32", "ensemble48", "serve"])
     ap.add_argument("--no-serve", action="store_true", help="skip the serving-stream figure")
     ap.add_argument("--no-sponge", action="store_true", help="skip the vorticity-sponge figure")
     ap.add_argument("--no-freeflight", action="store_true", help="skip the free-flight figure")
@@ -369,7 +382,8 @@ def main():
     wl = build_workload(a.workload)
     steps = a.steps or wl["default_steps"]
     n = wl["n"]
-    pts = float(n) ** 3
+    nx = wl.get("nx") or n
+    pts = float(nx) * n * n
     res = {}
     for dtype in ("f32", "f64"):
         res[dtype] = gpu_run(F, torch, wl, dtype, steps, a.warmup, tune=not a.no_autotune)
@@ -383,7 +397,7 @@ def main():
     r = res["f32"]
     names = list(F.PASS_NAMES)
     split = r["pass_cnt"][names.index("z_inverse")] > 1
-    pb = pass_bytes(n, 8, split, r["schedule"]["x_pass"])
+    pb = pass_bytes(n, 8, split, r["schedule"]["x_pass"], nx=nx)
     passes = {}
     for i, nm in enumerate(names):
         if r["pass_cnt"][i]:
@@ -396,7 +410,7 @@ def main():
     dom = max(step_names, key=lambda k: r["pass_ms"][names.index(k)])
     d_avg_s = r["pass_ms"][names.index(dom)] / r["pass_cnt"][names.index(dom)] / 1e3
     achieved = pb[dom] / d_avg_s / 1e9
-    sb = step_bytes(n, 8)
+    sb = step_bytes(n, 8, nx=nx)
     out = {
         "metric": METRIC,
         "value": round(v32, 2),
@@ -410,14 +424,15 @@ def main():
         "vs_baseline": None,
         "dtype": "f32",
         "data": "synthetic",
-        "config": {"workload": a.workload, "description": wl["desc"], "grid": n},
+        "config": {"workload": a.workload, "description": wl["desc"], "grid": n, **({"nx": nx} if nx != n else {})},
         "fp64": {"value": round(v64, 2), "unit": "Mpoint-steps/s",
                  "ms_per_step": round(res["f64"]["ev_ms"] / steps, 5),
                  "fp32_over_fp64": round(v32 / v64, 3)},
         "roofline": {"bound": "hbm", "kernel": dom, "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
                      "traffic": counter_traffic(a.workload, kernel_of_pass(dom, n, "float", r["schedule"], nc,
-                                                                           dyn=bool(ins and ins.get("wings")))),
+                                                                           dyn=bool(ins and ins.get("wings")),
+                                                                           nx=nx)),
                      "algorithmic_bytes": int(pb[dom])},
         "step_roofline": {"bytes_per_step": sb, "bytes_per_point_step": round(sb / pts, 2),
                           "achieved_gbs": round(sb / (res["f32"]["ev_ms"] / steps / 1e3) / 1e9, 1),
@@ -471,9 +486,7 @@ def main():
                                      "(four pipeline passes per step)"}
     if not a.no_box and a.workload == "sphere128":
         # the sphere workload in the 6x4x4 box shape of the paper at 192x128x128 points
-        import workloads as W
-        bx = dict(wl, nx=192, n=128, u0=W.inflow_noise(128, wl["L"], seed=0, rms=1e-3, kmax=8.0, nx=192),
-                  insect=dict(wl["insect"], x_cntr=(2.4, 2.0, 2.0)))
+        bx = build_workload("box192")
         bpts = 192.0 * 128 * 128
         bv = {}
         for dtype in ("f32", "f64"):
@@ -494,7 +507,7 @@ def main():
         # error of both precisions against the oracle after the same number of steps
         errs = {}
         for dtype in ("f32", "f64"):
-            P = F.Plan(n, wl["L"], wl["nu"], wl["eta"], dtype)
+            P = F.Plan(n, wl["L"], wl["nu"], wl["eta"], dtype, nx=wl.get("nx"))
             st = P.new_state(torch.from_numpy(wl["u0"]))
             P.step(st, cs["steps"], wl["insect"], dt_fixed=wl["dt_fixed"], cfl=wl["cfl"], eta_cap=0.5)
             u = P.velocity(st).double().cpu().numpy()
