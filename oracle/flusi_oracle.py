@@ -27,7 +27,7 @@ What it computes (paper section / equation in brackets):
 * the time loop of Algorithm 1 (mask -> dt -> sources -> projection -> AB2
   -> free flight),
 * free flight: Newton's law and the quaternion form of Euler's equations
-  [Sec. 3.5, eq. oh_my_god_look_a_vector] stepped with the same AB2, and the
+  [Sec. 3.6, eq. oh_my_god_look_a_vector] stepped with the same AB2, and the
   aerodynamic power of a wing [Sec. 3.5, eq. insect_power].
 
 Where the paper is silent or garbled the readings below are used (each is
@@ -357,7 +357,7 @@ class Insect:
     head_r: float = 0.0
     eye_x: tuple = (0.0, 0.0, 0.0)       # eye spheres at (x, +y, z) and (x, -y, z); eye_r <= 0: none
     eye_r: float = 0.0
-    free_flight: bool = False            # Sec. 3.5: the body moves under F, m and gravity
+    free_flight: bool = False            # Sec. 3.6: the body moves under F, m and gravity
     mass: float = 1.0                    # M
     inertia: tuple = (1.0, 1.0, 1.0)     # principal moments J_x, J_y, J_z (body frame)
     gravity: float = 0.0                 # g, acting along -z
@@ -714,14 +714,14 @@ def reference_points(ins: Insect, t: float, pose: Pose | None = None) -> np.ndar
 
 
 # ---------------------------------------------------------------------------
-# Free flight  [Sec. 3.5, eq. oh_my_god_look_a_vector]
+# Free flight  [Sec. 3.6, eq. oh_my_god_look_a_vector]
 #
 # Solid state y (13 values): x_cntr (3), u_cntr (3), quaternion eps (4),
 # Omega^(b) (3).
 # ---------------------------------------------------------------------------
 
 def quaternion_from_angles(psi: float, beta: float, gamma: float) -> np.ndarray:
-    """Quaternion of the orientation with roll psi, pitch beta, yaw gamma  [Sec. 3.5]."""
+    """Quaternion of the orientation with roll psi, pitch beta, yaw gamma  [Sec. 3.6]."""
     cp, sp = math.cos(psi / 2), math.sin(psi / 2)
     cb, sb = math.cos(beta / 2), math.sin(beta / 2)
     cg, sg = math.cos(gamma / 2), math.sin(gamma / 2)
@@ -732,7 +732,7 @@ def quaternion_from_angles(psi: float, beta: float, gamma: float) -> np.ndarray:
 
 
 def quaternion_matrix(eps) -> np.ndarray:
-    """The rotation matrix of a unit quaternion as the paper prints it  [Sec. 3.5];
+    """The rotation matrix of a unit quaternion as the paper prints it  [Sec. 3.6];
     it maps body-frame vectors to the global frame."""
     e0, e1, e2, e3 = (float(v) for v in eps)
     return np.array([

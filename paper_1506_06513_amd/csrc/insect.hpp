@@ -97,7 +97,7 @@ __host__ __device__ inline void cross3(const double* a, const double* b, double*
 
 // M_body (global to body) of a unit quaternion: the transpose of the matrix
 // the free-flight section prints, which maps body vectors to the global frame
-// (Sec. 3.5).
+// (Sec. 3.6).
 __host__ __device__ inline void quat_mbody(const double* e, double* M) {
     const double e0 = e[0], e1 = e[1], e2 = e[2], e3 = e[3];
     M[0] = e0 * e0 + e1 * e1 - e2 * e2 - e3 * e3;
@@ -111,7 +111,7 @@ __host__ __device__ inline void quat_mbody(const double* e, double* M) {
     M[8] = e0 * e0 - e1 * e1 - e2 * e2 + e3 * e3;
 }
 
-// Quaternion of roll psi, pitch beta, yaw gamma (Sec. 3.5).
+// Quaternion of roll psi, pitch beta, yaw gamma (Sec. 3.6).
 __host__ __device__ inline void quat_of_angles(double psi, double beta, double gam, double* e) {
     const SinCos qp = sin_cos(0.5 * psi), qb = sin_cos(0.5 * beta), qg = sin_cos(0.5 * gam);
     const double cp = qp.c, sp = qp.s, cb = qb.c, sb = qb.s, cg = qg.c, sg = qg.s;
@@ -121,7 +121,7 @@ __host__ __device__ inline void quat_of_angles(double psi, double beta, double g
     e[3] = cp * cb * sg - sp * sb * cg;
 }
 
-// Right-hand side of the 13 free-flight equations (Sec. 3.5, eq.
+// Right-hand side of the 13 free-flight equations (Sec. 3.6, eq.
 // oh_my_god_look_a_vector).  y: x_cntr, u_cntr, eps, Omega^(b); F: total force
 // and m: torque about x_cntr, both in the global frame.
 __host__ __device__ inline void solid_rhs(const flusi_insect& in, const double* y, const double* F,
@@ -196,7 +196,7 @@ __host__ __device__ inline void wing_angle_values(const flusi_insect& in, double
 
 // Kinematics at time t (Sec. 3.1 and 3.3).  dx is the grid spacing.  pose
 // (13 values: x_cntr, u_cntr, eps, Omega^(b)) replaces the prescribed body
-// motion in free flight (Sec. 3.5); null for a tethered body.
+// motion in free flight (Sec. 3.6); null for a tethered body.
 __host__ __device__ __forceinline__ void compute_kin(const flusi_insect& in, double t, double dx, Kin& k,
                                                      const double* pose = nullptr) {
     if (pose) {

@@ -1,4 +1,4 @@
-"""Free flight (Sec. 3.5, eq. oh_my_god_look_a_vector) and the aerodynamic power
+"""Free flight (Sec. 3.6, eq. oh_my_god_look_a_vector) and the aerodynamic power
 (eq. insect_power) on the GPU against the FP64 oracle; restarts, mode
 switches, chunked calls, ensembles and served requests against solo runs."""
 import math

@@ -67,13 +67,24 @@ def test_wavenumber_tables():
     assert list(O.signed_index(6)) == [0, 1, 2, -3, -2, -1]
 
 
-def test_dealias_cutoff_matches_paper(golden_dir):
+def test_dealias_cutoff_against_the_caption(golden_dir):
+    # The caption's highest resolved |j| is n/3.  The reading used here (keep iff
+    # 3|j| < n) keeps every |j| below it and drops |j| = n/3 itself, the one
+    # mode where the literal caption and the alias-free rule part.
     rows = [l.split() for l in open(os.path.join(golden_dir, "dealias_cutoff.txt"))
             if l.strip() and not l.startswith("#")]
-    for n, L, jcut in rows:
-        n, jcut = int(n), int(jcut)
-        assert O.dealias_kmax(n) == jcut - 1
-        assert not O.dealias_keep(np.array([jcut]), n)[0]
+    for n, L, jcap in rows:
+        n, jcap = int(n), int(jcap)
+        assert 3 * jcap == n
+        assert O.dealias_kmax(n) == jcap - 1
+        assert O.dealias_keep(np.array([jcap - 1]), n)[0]
+        assert not O.dealias_keep(np.array([jcap, -jcap]), n).any()
+
+
+@pytest.mark.parametrize("n", [24, 48, 96, 192, 384, 768])
+def test_readings_part_only_where_three_divides_n(n):
+    # for these n the literal caption would also keep |j| = n/3
+    assert n % 3 == 0 and O.dealias_kmax(n) == n // 3 - 1
 
 
 @pytest.mark.parametrize("n", [32, 64, 96, 128, 192, 256, 512])

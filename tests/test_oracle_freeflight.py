@@ -1,4 +1,4 @@
-"""Pins of the oracle's free-flight system (Sec. 3.5, eq. oh_my_god_look_a_vector)
+"""Pins of the oracle's free-flight system (Sec. 3.6, eq. oh_my_god_look_a_vector)
 and of the aerodynamic power (eq. insect_power) against facts that do not come
 from the oracle's own formulas: the yaw-pitch-roll matrix of Sec. 3.1, an
 independent RK4 integration, closed forms (free fall, torque-free precession of
