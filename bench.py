@@ -1,26 +1,29 @@
 """Benchmark of the pseudo-spectral penalized Navier-Stokes step on one MI355X.
 
-Workload (default): 128^3 periodic box L = 4, fixed sphere of radius 0.5 at the
-centre with a tanh mask of width 2 dx, mean inflow (1,0,0) plus seeded
-solenoidal noise of rms 1e-3 in |k| <= 8, nu = 0.01, C_eta = 1e-3, adaptive dt
-at CFL 0.1 (capped at C_eta/2).  One step = one pass of the whole hot path:
-mask on the fly, u x w and penalization, 2/3 rule, projection, IF-AB2 update,
-FP64 max|u| / force / energy reductions and the adaptive dt.
+Workload (default, the largest single-GPU configuration): 256^3 periodic box
+L = 4 with the model insect (ellipsoid body, two flat elliptic wings flapping
+at f = 1 with stroke +-70 deg and feathering +-45 deg), mask and solid
+velocity rebuilt every step, nu = 1/136, C_eta = 2.5e-4, adaptive dt at CFL
+0.1 (capped at C_eta/2), fluid at rest.  One step = one pass of the whole hot
+path: kinematics, mask on the fly, u x w and penalization, 2/3 rule,
+projection, IF-AB2 update, FP64 max|u| / force / energy reductions and the
+adaptive dt.
 
 Prints one JSON line.  `value` is FP32 Mpoint-steps/s (points x steps / s);
 the FP64 figure, each precision's error against the FP64 oracle, the roofline
 of the dominant kernel (live HIP-event timing over a timed region, algorithmic
 bytes from the pruned byte model) and the oracle's CPU throughput on a bounded
 sample are reported beside it.  Schedules are autotuned before the timed
-region (--no-autotune: defaults).  The default run adds two sub-objects:
+region (--no-autotune: defaults).  The default run adds sub-objects:
+`sphere128` (128^3 sphere in inflow, FP32 and FP64 with their roofline),
 `ensemble48` (48 seeded insect simulations on mixed grids advanced by batched
-launches replayed from a hipGraph, against the same members stepped one by one)
-and `serving` (a Poisson-arrival request stream with a 512^3 insect: p50/p99
-latency and throughput), plus `sponge`, `freeflight`, `rk4` and `box192` (the
-same sphere workload with a vorticity sponge layer, with the sphere in free
-flight, stepped with RK4, and in the 6x4x4 box at 192x128x128 points).
---workload selects freefall128, insect256, tg32, ensemble48 or serve as the
-main line instead.
+launches replayed from a hipGraph, against the same members stepped one by
+one), `serving` (a Poisson-arrival request stream with a 512^3 insect: p50/p99
+latency and throughput, and a saturated stream for capacity), plus `sponge`,
+`freeflight`, `rk4` and `box192` (the sphere workload with a vorticity sponge
+layer, with the sphere in free flight, stepped with RK4, and in the 6x4x4 box
+at 192x128x128 points).  --workload selects sphere128, freefall128, tg32,
+box192, ensemble48 or serve as the main line instead.
 """
 from __future__ import annotations
 
@@ -326,12 +329,87 @@ def oracle_sample(wl, budget_s=12.0, max_steps=30):
                 u=O.velocity(p, st))
 
 
+def error_vs_oracle(F, torch, wl, cs):
+    """Relative L2 error of both precisions against the oracle's velocity after
+    the oracle sample's step count (whole field and fluctuation about the mean)."""
+    errs = {}
+    for dtype in ("f32", "f64"):
+        P = F.Plan(wl["n"], wl["L"], wl["nu"], wl["eta"], dtype, nx=wl.get("nx"))
+        st = P.new_state(torch.from_numpy(wl["u0"]))
+        P.step(st, cs["steps"], wl["insect"], dt_fixed=wl["dt_fixed"], cfl=wl["cfl"], eta_cap=0.5)
+        u = P.velocity(st).double().cpu().numpy()
+        ou = cs["u"]
+        errs[dtype] = float(np.linalg.norm(u - ou) / np.linalg.norm(ou))
+        fl = u - u.mean(axis=(1, 2, 3), keepdims=True)
+        ofl = ou - ou.mean(axis=(1, 2, 3), keepdims=True)
+        errs[dtype + "_fluct"] = float(np.linalg.norm(fl - ofl) / np.linalg.norm(ofl))
+    return {"steps": cs["steps"], "rel_l2_f32": errs["f32"], "rel_l2_f64": errs["f64"],
+            "rel_l2_fluct_f32": errs["f32_fluct"], "rel_l2_fluct_f64": errs["f64_fluct"]}
+
+
+def measure(F, torch, name, wl, steps, warmup, tune):
+    """FP32 and FP64 runs of one workload: FP32 throughput (`value`), the FP64
+    figure, the dominant kernel's roofline (live per-pass HIP events on the
+    launch stream, algorithmic bytes of the pruned model) and the step's."""
+    n = wl["n"]
+    nx = wl.get("nx") or n
+    pts = float(nx) * n * n
+    res = {}
+    for dtype in ("f32", "f64"):
+        res[dtype] = gpu_run(F, torch, wl, dtype, steps, warmup, tune=tune)
+        note(f"{name} {dtype}: {res[dtype]['ev_ms'] / steps:.4f} ms/step")
+
+    def mps(r):
+        return pts * steps / (r["ev_ms"] / 1e3) / 1e6
+
+    v32, v64 = mps(res["f32"]), mps(res["f64"])
+    # dominant kernel of the FP32 run
+    r = res["f32"]
+    names = list(F.PASS_NAMES)
+    split = r["pass_cnt"][names.index("z_inverse")] > 1
+    pb = pass_bytes(n, 8, split, r["schedule"]["x_pass"], nx=nx)
+    passes = {}
+    for i, nm in enumerate(names):
+        if r["pass_cnt"][i]:
+            avg = r["pass_ms"][i] / r["pass_cnt"][i]
+            passes[nm] = dict(avg_us=round(avg * 1e3, 3), launches=int(r["pass_cnt"][i]),
+                              bytes=int(pb.get(nm, 0)), gbs=round(pb.get(nm, 0) / (avg * 1e-3) / 1e9, 1))
+    step_names = ["y_inverse", "x_pass", "y_forward", "z_pass"] + (["z_inverse"] if split else [])
+    ins = wl["insect"]
+    nc = 0 if ins is None else (3 if ins.get("wings") else 1)
+    dom = max(step_names, key=lambda k: r["pass_ms"][names.index(k)])
+    d_avg_s = r["pass_ms"][names.index(dom)] / r["pass_cnt"][names.index(dom)] / 1e3
+    achieved = pb[dom] / d_avg_s / 1e9
+    sb = step_bytes(n, 8, nx=nx)
+    return {
+        "value": round(v32, 2),
+        "ms_per_step": round(res["f32"]["ev_ms"] / steps, 5),
+        "fp64": {"value": round(v64, 2), "unit": "Mpoint-steps/s",
+                 "ms_per_step": round(res["f64"]["ev_ms"] / steps, 5),
+                 "fp32_over_fp64": round(v32 / v64, 3)},
+        "roofline": {"bound": "hbm", "kernel": dom, "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+                     "traffic": counter_traffic(name, kernel_of_pass(dom, n, "float", r["schedule"], nc,
+                                                                     dyn=bool(ins and ins.get("wings")), nx=nx)),
+                     "algorithmic_bytes": int(pb[dom])},
+        "step_roofline": {"bytes_per_step": sb, "bytes_per_point_step": round(sb / pts, 2),
+                          "achieved_gbs": round(sb / (res["f32"]["ev_ms"] / steps / 1e3) / 1e9, 1),
+                          "frac": round(sb / (res["f32"]["ev_ms"] / steps / 1e3) / 1e9 / HBM_PEAK_GBS, 4)},
+        "passes_f32": passes,
+        "schedule": {"f32": res["f32"]["schedule"], "f64": res["f64"]["schedule"],
+                     "chosen_by": "autotune" if tune else "default"},
+        "wall_s": {k: round(v["wall_s"], 4) for k, v in res.items()},
+        "last_diag_f32": {"t": res["f32"]["diag"][0], "dt": res["f32"]["diag"][1],
+                          "umax": res["f32"]["diag"][2], "drag": res["f32"]["diag"][4]},
+    }
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=None)
     ap.add_argument("--warmup", type=int, default=10)
-    ap.add_argument("--workload", default="sphere128",
+    ap.add_argument("--workload", default="insect256",
                     choices=["sphere128", "freefall128", "insect256", "box192", "tg32", "ensemble48", "serve"])
     ap.add_argument("--no-serve", action="store_true", help="skip the serving-stream figure")
     ap.add_argument("--no-sponge", action="store_true", help="skip the vorticity-sponge figure")
@@ -384,89 +462,61 @@ def main():
     n = wl["n"]
     nx = wl.get("nx") or n
     pts = float(nx) * n * n
-    res = {}
-    for dtype in ("f32", "f64"):
-        res[dtype] = gpu_run(F, torch, wl, dtype, steps, a.warmup, tune=not a.no_autotune)
-        note(f"{a.workload} {dtype}: {res[dtype]['ev_ms'] / steps:.4f} ms/step")
-
-    def mps(r):
-        return pts * steps / (r["ev_ms"] / 1e3) / 1e6
-
-    v32, v64 = mps(res["f32"]), mps(res["f64"])
-    # dominant kernel of the FP32 run
-    r = res["f32"]
-    names = list(F.PASS_NAMES)
-    split = r["pass_cnt"][names.index("z_inverse")] > 1
-    pb = pass_bytes(n, 8, split, r["schedule"]["x_pass"], nx=nx)
-    passes = {}
-    for i, nm in enumerate(names):
-        if r["pass_cnt"][i]:
-            avg = r["pass_ms"][i] / r["pass_cnt"][i]
-            passes[nm] = dict(avg_us=round(avg * 1e3, 3), launches=int(r["pass_cnt"][i]),
-                              bytes=int(pb.get(nm, 0)), gbs=round(pb.get(nm, 0) / (avg * 1e-3) / 1e9, 1))
-    step_names = ["y_inverse", "x_pass", "y_forward", "z_pass"] + (["z_inverse"] if split else [])
-    ins = wl["insect"]
-    nc = 0 if ins is None else (3 if ins.get("wings") else 1)
-    dom = max(step_names, key=lambda k: r["pass_ms"][names.index(k)])
-    d_avg_s = r["pass_ms"][names.index(dom)] / r["pass_cnt"][names.index(dom)] / 1e3
-    achieved = pb[dom] / d_avg_s / 1e9
-    sb = step_bytes(n, 8, nx=nx)
     out = {
         "metric": METRIC,
-        "value": round(v32, 2),
+        "value": None,
         "unit": "Mpoint-steps/s",
         "n_gpus": 1,
         "steps": steps,
         "warmup": a.warmup,
-        "ms_per_step": round(res["f32"]["ev_ms"] / steps, 5),
+        "ms_per_step": None,
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": "f32",
         "data": "synthetic",
         "config": {"workload": a.workload, "description": wl["desc"], "grid": n, **({"nx": nx} if nx != n else {})},
-        "fp64": {"value": round(v64, 2), "unit": "Mpoint-steps/s",
-                 "ms_per_step": round(res["f64"]["ev_ms"] / steps, 5),
-                 "fp32_over_fp64": round(v32 / v64, 3)},
-        "roofline": {"bound": "hbm", "kernel": dom, "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
-                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-                     "traffic": counter_traffic(a.workload, kernel_of_pass(dom, n, "float", r["schedule"], nc,
-                                                                           dyn=bool(ins and ins.get("wings")),
-                                                                           nx=nx)),
-                     "algorithmic_bytes": int(pb[dom])},
-        "step_roofline": {"bytes_per_step": sb, "bytes_per_point_step": round(sb / pts, 2),
-                          "achieved_gbs": round(sb / (res["f32"]["ev_ms"] / steps / 1e3) / 1e9, 1),
-                          "frac": round(sb / (res["f32"]["ev_ms"] / steps / 1e3) / 1e9 / HBM_PEAK_GBS, 4)},
-        "passes_f32": passes,
-        "schedule": {"f32": res["f32"]["schedule"], "f64": res["f64"]["schedule"],
-                     "chosen_by": "autotune" if not a.no_autotune else "default"},
-        "wall_s": {k: round(v["wall_s"], 4) for k, v in res.items()},
-        "last_diag_f32": {"t": res["f32"]["diag"][0], "dt": res["f32"]["diag"][1],
-                          "umax": res["f32"]["diag"][2], "drag": res["f32"]["diag"][4]},
     }
-    if not a.no_ensemble and a.workload == "sphere128":
+    m = measure(F, torch, a.workload, wl, steps, a.warmup, not a.no_autotune)
+    out["value"] = m.pop("value")
+    out["ms_per_step"] = m.pop("ms_per_step")
+    out.update(m)
+    extras = a.workload == "insect256"
+    if extras:
+        swl = build_workload("sphere128")
+        s_steps = swl["default_steps"]
+        ms = measure(F, torch, "sphere128", swl, s_steps, a.warmup, not a.no_autotune)
+        out["sphere128"] = dict(ms, steps=s_steps, description=swl["desc"])
+        if not a.no_cpu:
+            out["sphere128"]["err_vs_oracle"] = error_vs_oracle(F, torch, swl, oracle_sample(swl, budget_s=5.0))
+        note("sphere128 done")
+    else:
+        swl, s_steps = wl, steps
+    spts = float(swl["n"]) ** 3
+    if not a.no_ensemble and extras:
         out["ensemble48"] = ensemble_run(F, torch, tune=not a.no_autotune)
         note("ensemble48 done")
-    if not a.no_serve and a.workload == "sphere128":
+    if not a.no_serve and extras:
         out["serving"] = serve_run(F, torch)
         note("serving done")
-    if not a.no_sponge and a.workload == "sphere128":
+    if not a.no_sponge and extras:
         # the same workload with a vorticity sponge layer 3.5 <= x < 4 (C_sp = 0.1)
         sp = {}
         for dtype in ("f32", "f64"):
-            r = gpu_run(F, torch, wl, dtype, steps, a.warmup, tune=not a.no_autotune, sponge=(0.1, (0.5, 0.0, 0.0)))
-            sp[dtype] = round(pts * steps / (r["ev_ms"] / 1e3) / 1e6, 2)
+            r = gpu_run(F, torch, swl, dtype, s_steps, a.warmup, tune=not a.no_autotune,
+                        sponge=(0.1, (0.5, 0.0, 0.0)))
+            sp[dtype] = round(spts * s_steps / (r["ev_ms"] / 1e3) / 1e6, 2)
         note("sponge done")
         out["sponge"] = {"value": sp["f32"], "fp64": sp["f64"], "unit": "Mpoint-steps/s",
                          "description": "sphere128 with the vorticity sponge on 3.5 <= x < 4, C_sp = 0.1 "
                                         "(3 more forward fields per step)"}
-    if not a.no_freeflight and a.workload == "sphere128":
+    if not a.no_freeflight and extras:
         # the same workload with the sphere in free flight
-        ff_body = free_sphere(wl["insect"])
+        ff_body = free_sphere(swl["insect"])
         ff = {}
         for dtype in ("f32", "f64"):
-            r = gpu_run(F, torch, dict(wl, insect=ff_body), dtype, steps, a.warmup, tune=not a.no_autotune)
-            ff[dtype] = (round(pts * steps / (r["ev_ms"] / 1e3) / 1e6, 2), r["diag"])
+            r = gpu_run(F, torch, dict(swl, insect=ff_body), dtype, s_steps, a.warmup, tune=not a.no_autotune)
+            ff[dtype] = (round(spts * s_steps / (r["ev_ms"] / 1e3) / 1e6, 2), r["diag"])
         d = ff["f32"][1]
         note("free flight done")
         out["freeflight"] = {"value": ff["f32"][0], "fp64": ff["f64"][0], "unit": "Mpoint-steps/s",
@@ -474,24 +524,25 @@ def main():
                                             "6 DoF): 13-value body state advanced each step",
                              "body_at_last_step_f32": {"t": d[0], "x_cntr": list(d[22:25]), "u_cntr": list(d[25:28]),
                                                        "omega_b": list(d[32:35])}}
-    if not a.no_rk4 and a.workload == "sphere128":
+    if not a.no_rk4 and extras:
         # the same workload with the RK4 integrator (explicit diffusion, 4 stages per step)
         rk = {}
         for dtype in ("f32", "f64"):
-            r = gpu_run(F, torch, wl, dtype, max(10, steps // 4), a.warmup, tune=not a.no_autotune, integrator="rk4")
-            rk[dtype] = round(pts * max(10, steps // 4) / (r["ev_ms"] / 1e3) / 1e6, 2)
+            r = gpu_run(F, torch, swl, dtype, max(10, s_steps // 4), a.warmup, tune=not a.no_autotune,
+                        integrator="rk4")
+            rk[dtype] = round(spts * max(10, s_steps // 4) / (r["ev_ms"] / 1e3) / 1e6, 2)
         note("rk4 done")
         out["rk4"] = {"value": rk["f32"], "fp64": rk["f64"], "unit": "Mpoint-steps/s",
                       "description": "sphere128 stepped with classical RK4 and explicit diffusion "
                                      "(four pipeline passes per step)"}
-    if not a.no_box and a.workload == "sphere128":
+    if not a.no_box and extras:
         # the sphere workload in the 6x4x4 box shape of the paper at 192x128x128 points
         bx = build_workload("box192")
         bpts = 192.0 * 128 * 128
         bv = {}
         for dtype in ("f32", "f64"):
-            r = gpu_run(F, torch, bx, dtype, steps, a.warmup, tune=not a.no_autotune)
-            bv[dtype] = round(bpts * steps / (r["ev_ms"] / 1e3) / 1e6, 2)
+            r = gpu_run(F, torch, bx, dtype, s_steps, a.warmup, tune=not a.no_autotune)
+            bv[dtype] = round(bpts * s_steps / (r["ev_ms"] / 1e3) / 1e6, 2)
         note("box done")
         out["box192"] = {"value": bv["f32"], "fp64": bv["f64"], "unit": "Mpoint-steps/s",
                          "description": "192x128x128 box 6x4x4 (one spacing 1/32), sphere R=0.5 at (2.4, 2, 2), "
@@ -504,20 +555,7 @@ def main():
                                "kind": "oracle",
                                "sample": f"{cs['timed_steps']} steps of the same workload after 1 untimed step "
                                          f"({cs['seconds']:.1f} s, NumPy/SciPy FP64)"}
-        # error of both precisions against the oracle after the same number of steps
-        errs = {}
-        for dtype in ("f32", "f64"):
-            P = F.Plan(n, wl["L"], wl["nu"], wl["eta"], dtype, nx=wl.get("nx"))
-            st = P.new_state(torch.from_numpy(wl["u0"]))
-            P.step(st, cs["steps"], wl["insect"], dt_fixed=wl["dt_fixed"], cfl=wl["cfl"], eta_cap=0.5)
-            u = P.velocity(st).double().cpu().numpy()
-            ou = cs["u"]
-            errs[dtype] = float(np.linalg.norm(u - ou) / np.linalg.norm(ou))
-            fl = u - u.mean(axis=(1, 2, 3), keepdims=True)
-            ofl = ou - ou.mean(axis=(1, 2, 3), keepdims=True)
-            errs[dtype + "_fluct"] = float(np.linalg.norm(fl - ofl) / np.linalg.norm(ofl))
-        out["err_vs_oracle"] = {"steps": cs["steps"], "rel_l2_f32": errs["f32"], "rel_l2_f64": errs["f64"],
-                                "rel_l2_fluct_f32": errs["f32_fluct"], "rel_l2_fluct_f64": errs["f64_fluct"]}
+        out["err_vs_oracle"] = error_vs_oracle(F, torch, wl, cs)
     print(json.dumps(out), flush=True)
 
 

@@ -82,7 +82,7 @@ extern "C" {
  *   [4 + 6*(c-1) + 0..2]  force  F on colour c (c = 1 body, 2 left wing, 3 right wing)
  *   [4 + 6*(c-1) + 3..5]  torque m on colour c
  *   [22..24] x_cntr  [25..27] u_cntr  [28..31] quaternion eps_0..3
- *   [32..34] Omega_b^(b): the body's state at t^n (Sec. 3.5; for a tethered
+ *   [32..34] Omega_b^(b): the body's state at t^n (Sec. 3.6; for a tethered
  *            body the prescribed kinematics, eps from the body angles)
  *   [35] [36] aerodynamic power P_aero of the left and right wing
  *            (Sec. 3.5, eq. insect_power)
@@ -104,7 +104,7 @@ typedef struct flusi_plan_s* flusi_plan;
  * the body centre at the current time (the body is not translated by the
  * library) and u_cntr its velocity.
  *
- * Free flight (free_flight == 1, Sec. 3.5, eq. oh_my_god_look_a_vector): the
+ * Free flight (free_flight == 1, Sec. 3.6, eq. oh_my_god_look_a_vector): the
  * state keeps the 13 values x_cntr (centre of gravity), u_cntr, the unit
  * quaternion eps and Omega_b^(b), advanced after every step with the fluid's
  * AB2 weights (Euler on the first free-flight step) from the total force F
@@ -247,7 +247,7 @@ int flusi_plan_set_walls(flusi_plan plan, const double* thickness, const double*
  * periodic seam), 0 elsewhere.  c_sp <= 0 or all thicknesses 0 switch it off.
  * thickness is a host array of 3 doubles (may be NULL: off).  Switching it
  * on enlarges the plan's scratch (6 instead of 3 forward fields; synchronizes
- * the plan's stream).  Not used by flusi_rhs.  Errors: EINVAL (thickness < 0
+ * the device before the old buffer is freed).  Not used by flusi_rhs.  Errors: EINVAL (thickness < 0
  * or > L_a), ENOMEM. */
 int flusi_plan_set_sponge(flusi_plan plan, double c_sp, const double* thickness);
 
@@ -272,6 +272,7 @@ int flusi_fft_r2c(flusi_plan plan, const void* in, void* out, int nf);
  * imaginary parts of the kx = 0 and kx = n/2 bins are ignored (Hermitian
  * input assumed).  May allocate plan scratch on first use. */
 int flusi_fft_c2r(flusi_plan plan, const void* in, void* out, int nf);
+
 
 /* Algorithm 1 step (a): mask chi, solid velocity u_s and colour at time t
  * (Sec. 2.2, Sec. 3.1-3.4).  chi: [n][n][nx] real; us: [3][n][n][nx] real;
@@ -322,7 +323,7 @@ int flusi_step(flusi_plan plan, void* state, const flusi_insect* ins, const flus
  * FLUSI_ENONFINITE if the state was stopped by a non-finite velocity. */
 int flusi_forces(flusi_plan plan, const void* state, double* out);
 
-/* Free-flight state of the current time level (Sec. 3.5): out[13] =
+/* Free-flight state of the current time level (Sec. 3.6): out[13] =
  * x_cntr[3], u_cntr[3], eps[4], Omega_b^(b)[3] (host array; synchronous).
  * Errors: EINVAL if the state has no free-flight body (never stepped in free
  * flight, or last stepped tethered); ENONFINITE if it was stopped. */
@@ -404,6 +405,12 @@ int flusi_autotune(flusi_plan plan, const void* state, const flusi_insect* ins, 
  * Ownership: the ensemble keeps the plan and state pointers (it owns
  * neither); destroy the ensemble before them.  Adding or removing members
  * invalidates captured graphs (they are rebuilt on the next call).
+ * Changing a member plan's options (flusi_plan_set_sponge, _set_walls,
+ * _set_integrator, _set_schedule, flusi_autotune) is allowed between calls:
+ * the next flusi_ensemble_* call synchronizes the ensemble's streams, rebuilds
+ * the launch tables from the plan's current options and buffers and drops the
+ * captured graphs, so the member again equals flusi_step on its plan.  Such a
+ * change must not overlap a running ensemble call on another host thread.
  * ------------------------------------------------------------------------ */
 typedef struct flusi_ensemble_s* flusi_ensemble;
 

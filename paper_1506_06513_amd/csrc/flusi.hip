@@ -361,6 +361,7 @@ int flusi_plan_set_walls(flusi_plan plan, const double* thickness, const double*
         d.wall_th[a] = th[a];
         d.u_wall[a] = uw[a];
     }
+    d.gen += 1;
     return FLUSI_OK;
 }
 
@@ -380,7 +381,9 @@ int flusi_plan_set_sponge(flusi_plan plan, double c_sp, const double* thickness)
         const size_t need = d.impl->bufA_elems_sponge() * cxb;
         if (need > d.szA) {
             void* nb = nullptr;
-            (void)hipStreamSynchronize(d.stream);
+            // the old buffer may still be in use on any stream (the plan's own, or
+            // the streams of an ensemble that holds the plan)
+            (void)hipDeviceSynchronize();
             if (hipMalloc(&nb, need) != hipSuccess) return set_error(FLUSI_ENOMEM, "set_sponge: scratch");
             (void)hipFree(d.bufA);
             d.workspace += need - d.szA;
@@ -390,6 +393,7 @@ int flusi_plan_set_sponge(flusi_plan plan, double c_sp, const double* thickness)
     }
     d.c_sp = on ? c_sp : 0.0;
     for (int a = 0; a < 3; ++a) d.sp_thick[a] = on ? th[a] : 0.0;
+    d.gen += 1;
     return FLUSI_OK;
 }
 
@@ -408,6 +412,7 @@ int flusi_plan_set_integrator(flusi_plan plan, int integrator) {
         d.workspace += need;
     }
     d.integrator = integrator;
+    d.gen += 1;
     return FLUSI_OK;
 }
 
@@ -554,6 +559,7 @@ int flusi_plan_set_schedule(flusi_plan plan, const flusi_schedule* s) {
     if (!s) return set_error(FLUSI_EINVAL, "set_schedule: schedule is NULL");
     if (int rc = sched_check(*s)) return rc;
     plan->d.sched = sched_from(*s);
+    plan->d.gen += 1;
     return FLUSI_OK;
 }
 
@@ -597,6 +603,7 @@ int flusi_autotune(flusi_plan plan, const void* state, const flusi_insect* ins, 
     (void)hipFree(tmp);
     if (rc) return rc;
     d.sched = best;
+    d.gen += 1;
     if (out) *out = sched_to(best);
     return FLUSI_OK;
 }
@@ -647,6 +654,7 @@ struct EnsMember {
     flusi_insect ins{};
     flusi_step_params sp{};
     bool used = false;
+    unsigned long gen = 0;  // the plan's option generation the launch tables were built from
 };
 struct EnsGroup {
     int n = 0;
@@ -681,9 +689,18 @@ static void ens_clear_groups(flusi_ensemble e) {
     e->graphs.clear();
 }
 
+// A member plan whose options changed since the tables were built (sponge,
+// walls, integrator, schedule) makes the ensemble rebuild them: the records
+// carry the plan's buffers and flags, and the captured graphs their pointers.
+static void ens_check_plans(flusi_ensemble e) {
+    for (const auto& m : e->members)
+        if (m.used && m.plan->d.gen != m.gen) e->dirty = true;
+}
+
 // Groups the members by grid size, orders each group by colour count and
 // uploads the launch tables (synchronous; outside the stepping hot path).
 static int ens_rebuild(flusi_ensemble e) {
+    ens_check_plans(e);
     if (!e->dirty) return FLUSI_OK;
     hipError_t err = hipStreamSynchronize(e->own);
     if (err != hipSuccess) return set_error(FLUSI_EDEVICE, "ensemble: %s", hipGetErrorString(err));
@@ -713,6 +730,7 @@ static int ens_rebuild(flusi_ensemble e) {
         for (int i : ids) {
             EnsMember& m = e->members[i];
             PlanData& pd = m.plan->d;
+            m.gen = pd.gen;
             const flusi_insect* ins = m.has_ins ? &m.ins : nullptr;
             if (ins) {
                 err = hipMemcpy(pd.ins_dev, ins, sizeof(flusi_insect), hipMemcpyHostToDevice);

@@ -49,6 +49,7 @@ struct PlanData {
     bool rtab_valid = false;
     Member* member_dev = nullptr;     // launch record of the plan's own calls
     Sched sched;                      // schedule of the plan's own stepping calls
+    unsigned long gen = 0;            // bumped by every option change (ensembles rebuild on a change)
     double wall_th[3] = {0.0, 0.0, 0.0};  // Dirichlet layer thickness per axis (0: none)
     double u_wall[3] = {0.0, 0.0, 0.0};   // velocity imposed in the layers
     double c_sp = 0.0;                // vorticity sponge constant (0: off)
@@ -184,7 +185,7 @@ enum { PASS_ZINV = 0, PASS_YINV = 1, PASS_X = 2, PASS_KIN = 3, PASS_YFWD = 4, PA
 int set_error(int code, const char* fmt, ...);
 int ensure_scratch(void** ptr, size_t* cur, size_t need, PlanData& p);
 
-// Checks the free-flight parameters of a body description (Sec. 3.5);
+// Checks the free-flight parameters of a body description (Sec. 3.6);
 // FLUSI_OK or FLUSI_EINVAL with a message.
 inline int check_insect(const flusi_insect* ins) {
     if (!ins) return FLUSI_OK;

@@ -119,7 +119,7 @@ struct Slot {
     int have_I;      // previous solid-momentum integral stored
     double I_prev[3][6];
     double J_prev[3];  // moment of the solid momentum about the body centre (with have_I)
-    // Free flight (Sec. 3.5).  ff_state: 0 none; 1 ff is the state at t;
+    // Free flight (Sec. 3.6).  ff_state: 0 none; 1 ff is the state at t;
     // 2 ff is the state of the previous level and still has to be advanced
     // by ff_w[0]*f(ff; ff_F, ff_m) + ff_w[1]*ff_f (done before the level's
     // kinematics are evaluated).
@@ -754,7 +754,7 @@ __device__ inline Coef step_coef(const double* tot, const Slot& sl, StepCtl ctl,
 }
 
 // Diagnostics of time level p and the next time level (one thread).  With a
-// mask: the body's state at t^n and the wings' aerodynamic power (Sec. 3.5),
+// mask: the body's state at t^n (Sec. 3.6) and the wings' aerodynamic power (Sec. 3.5),
 // the moment of the solid momentum about the body centre for the next step's
 // unsteady torque term, and in free flight the total force and torque about
 // x_cntr that advance the body (the advance itself runs with the next

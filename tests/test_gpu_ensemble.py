@@ -143,3 +143,37 @@ def test_removed_member_stops_and_others_continue():
     torch.cuda.synchronize()
     assert members[1][0].time(members[1][1])[1] == t_before[1] + 1
     ens.close()
+
+
+@pytest.mark.parametrize("graph", [False, True])
+def test_member_plan_option_change_rebuilds_the_tables(graph):
+    """Switching a member plan's sponge on (which replaces its scratch buffer)
+    and changing its schedule after it joined: the next ensemble call rebuilds
+    the launch tables (and drops captured graphs), so the member still equals
+    flusi_step on its plan with the new options, bit for bit."""
+    specs = _members()[1:4]
+    ens = F.Ensemble("f64")
+    members, solos = [], []
+    for sp in specs:
+        P, st = _setup(sp, "f64")
+        ens.add(P, st, sp["body"], **sp["ctl"])
+        members.append((P, st))
+        solos.append(_setup(sp, "f64"))
+    ens.step(2, graph=graph)
+    for sp, (Ps, ss) in zip(specs, solos):
+        Ps.step(ss, 2, sp["body"], **sp["ctl"])
+    torch.cuda.synchronize()
+    # sponge on member 0 (new scratch buffer), another z-pass form on member 2
+    members[0][0].set_sponge(0.1, (0.5, 0.0, 0.0))
+    solos[0][0].set_sponge(0.1, (0.5, 0.0, 0.0))
+    members[2][0].set_schedule(dict(z_pass=1, split_z=1))
+    solos[2][0].set_schedule(dict(z_pass=1, split_z=1))
+    for call in range(2):
+        ens.step(3, graph=graph)
+        for sp, (Ps, ss) in zip(specs, solos):
+            Ps.step(ss, 3, sp["body"], **sp["ctl"])
+        torch.cuda.synchronize()
+        for sp, (P, st), (Ps, ss) in zip(specs, members, solos):
+            assert torch.equal(P.uhat(st), Ps.uhat(ss)), (sp["n"], call)
+            assert P.time(st) == Ps.time(ss)
+    ens.close()

@@ -61,15 +61,30 @@ def test_sphere128_full_size(dtype):
     assert np.allclose(h[:, 2], [d["umax"] for d in oh], rtol=1e-12 if dtype == "f64" else 1e-6)
 
 
-@pytest.mark.parametrize("dtype", ["f64", "f32"])
-def test_insect256_full_size_two_steps(dtype):
+@pytest.fixture(scope="module")
+def insect256_oracle():
     wl = W.WORKLOADS["insect256"]
     n, L = wl["n"], wl["L"]
+    p = O.Params(n, L, wl["nu"], wl["eta"], O.MEAN_FIXED)
+    ost, oh = O.run(p, np.zeros((3, n, n, n)), 10, O.StepControl(cfl=0.1, eta_cap=0.5),
+                    O.Insect.from_dict(W.model_insect(n, L)))
+    return wl, O.velocity(p, ost), oh
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+def test_insect256_full_size_ten_steps(insect256_oracle, dtype):
+    # the bench's headline workload and launch configuration, 10 steps
+    wl, ou, oh = insect256_oracle
+    n, L = wl["n"], wl["L"]
     u0 = np.zeros((3, n, n, n))
-    p, ost, oh, P, st, h = _run_both(n, L, wl["nu"], wl["eta"], W.model_insect(n, L), u0, 2, dtype)
+    P = F.Plan(n, L, wl["nu"], wl["eta"], dtype)
+    st = P.new_state(torch.from_numpy(u0))
+    h = np_of(P.step(st, 10, W.model_insect(n, L), history=True, cfl=0.1, eta_cap=0.5))
     u = np_of(P.velocity(st))
-    ou = O.velocity(p, ost)
-    assert rel_l2(u, ou) < (1e-11 if dtype == "f64" else 2e-5)
+    err = rel_l2(u, ou)
+    print(f"insect256 {dtype} 10 steps: rel L2 {err:.3e}")
+    assert err < (1e-11 if dtype == "f64" else 2e-5)
+    assert np.allclose(h[:, 1], [d["dt"] for d in oh], rtol=1e-12 if dtype == "f64" else 1e-6, atol=0)
     for c in range(3):
         oF = np.array([d["F"][c] for d in oh])
         assert np.max(np.abs(h[:, 4 + 6 * c:7 + 6 * c] - oF)) <= (1e-9 if dtype == "f64" else 2e-3) * np.max(np.abs(oF))
