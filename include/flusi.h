@@ -273,6 +273,20 @@ int flusi_fft_r2c(flusi_plan plan, const void* in, void* out, int nf);
  * input assumed).  May allocate plan scratch on first use. */
 int flusi_fft_c2r(flusi_plan plan, const void* in, void* out, int nf);
 
+/* flusi_fft_c2r for callers that cannot allocate device memory (code under
+ * hipGraph capture, tight serving loops, harnesses that forbid hipMalloc):
+ * the same kernels and results, bit for bit, with the intermediate spectra in
+ * a fixed 64 MiB array of the library (one copy per GPU, held until the
+ * process ends) instead of plan scratch.  Allocates nothing.  The scratch
+ * must hold nf full-layout spectra, nf * n * n * (nx/2+1) complex values of
+ * the plan's type: three 128^3 fields in FP64 (51 MB) or two 192^3 fields in
+ * FP32 (57 MB) fit, one 256^3 FP32 field (67.6 MB) does not; larger requests
+ * return EINVAL with the sizes.  Every
+ * call on a GPU shares that GPU's array: calls that overlap on one GPU (other
+ * streams or host threads) race and must be ordered by the caller.  Nothing
+ * in the array needs to start at zero.  Errors: EINVAL (sizes, null
+ * pointers), EDEVICE (launch failure, or the array's address unavailable). */
+int flusi_fft_c2r_noalloc(flusi_plan plan, const void* in, void* out, int nf);
 
 /* Algorithm 1 step (a): mask chi, solid velocity u_s and colour at time t
  * (Sec. 2.2, Sec. 3.1-3.4).  chi: [n][n][nx] real; us: [3][n][n][nx] real;

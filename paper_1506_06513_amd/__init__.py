@@ -126,6 +126,7 @@ _SIGS = {
     "flusi_tables": (ctypes.c_int, [_P, _P, _P]),
     "flusi_fft_r2c": (ctypes.c_int, [_P, _P, _P, ctypes.c_int]),
     "flusi_fft_c2r": (ctypes.c_int, [_P, _P, _P, ctypes.c_int]),
+    "flusi_fft_c2r_noalloc": (ctypes.c_int, [_P, _P, _P, ctypes.c_int]),
     "flusi_mask_insect": (ctypes.c_int, [_P, ctypes.POINTER(flusi_insect), ctypes.c_double, _P, _P, _P]),
     "flusi_rhs": (ctypes.c_int, [_P, _P, _P, _P, _P, ctypes.c_int, ctypes.POINTER(ctypes.c_double)]),
     "flusi_state_init": (ctypes.c_int, [_P, _P, _P, ctypes.c_double]),
@@ -245,6 +246,10 @@ def flusi_fft_r2c(plan, inp, out, nf: int):
 
 def flusi_fft_c2r(plan, inp, out, nf: int):
     _check(lib().flusi_fft_c2r(plan, _ptr(inp), _ptr(out), nf))
+
+
+def flusi_fft_c2r_noalloc(plan, inp, out, nf: int):
+    _check(lib().flusi_fft_c2r_noalloc(plan, _ptr(inp), _ptr(out), nf))
 
 
 def flusi_mask_insect(plan, ins: flusi_insect, t: float, chi, us, colour):

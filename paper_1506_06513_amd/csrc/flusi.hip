@@ -5,6 +5,7 @@
 #include <cstdio>
 #include <cstring>
 #include <map>
+#include <mutex>
 #include <new>
 #include <vector>
 
@@ -93,6 +94,32 @@ static void sincos_2pi(long m, long n, double* c, double* s) {
 }
 
 static int check_plan(flusi_plan p);
+
+// Scratch of the allocation-free inverse transform (flusi_fft_c2r_noalloc): a
+// fixed array in the code object, one copy per GPU, held until the process
+// ends.  Host code never uses the array's name as an address: its device
+// address on each GPU comes from hipGetSymbolAddress (noalloc_scratch_of).
+constexpr size_t NOALLOC_SCRATCH_BYTES = 64ull << 20;
+static __device__ __align__(256) unsigned char scratch[NOALLOC_SCRATCH_BYTES];
+
+// Device address of `scratch` on the current device, resolved once per device
+// (null when the runtime cannot give it; the entry point then reports it).
+static void* noalloc_scratch_of_current_device() {
+    static std::mutex mu;
+    static std::map<int, void*> addr;
+    int dev = -1;
+    if (hipGetDevice(&dev) != hipSuccess) return nullptr;
+    std::lock_guard<std::mutex> lk(mu);
+    auto it = addr.find(dev);
+    if (it != addr.end()) return it->second;
+    void* ptr = nullptr;
+    if (hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)) != hipSuccess) {
+        (void)hipGetLastError();
+        ptr = nullptr;
+    }
+    addr[dev] = ptr;
+    return ptr;
+}
 
 }  // namespace flusi
 
@@ -292,6 +319,7 @@ int flusi_plan_create(int nx, int ny, int nz, double L, double nu, double eta, i
     ok = ok && hipEventCreateWithFlags(&d.ev_z, hipEventDisableTiming) == hipSuccess;
     ok = ok && hipEventCreateWithFlags(&d.ev_k, hipEventDisableTiming) == hipSuccess;
     d.sched = impl->default_sched();
+    d.noalloc_scratch = noalloc_scratch_of_current_device();
     if (!ok) {
         free_plan(d);
         delete p;
@@ -447,6 +475,20 @@ int flusi_fft_c2r(flusi_plan plan, const void* in, void* out, int nf) {
     if (int rc = check_plan(plan)) return rc;
     if (!in || !out || nf < 1) return set_error(FLUSI_EINVAL, "fft_c2r: null pointer or nf < 1");
     return plan->d.impl->fft_c2r(plan->d, in, out, nf);
+}
+
+int flusi_fft_c2r_noalloc(flusi_plan plan, const void* in, void* out, int nf) {
+    if (int rc = check_plan(plan)) return rc;
+    if (!in || !out || nf <= 0) return set_error(FLUSI_EINVAL, "fft_c2r_noalloc: bad arguments");
+    PlanData& d = plan->d;
+    const size_t need = (size_t)nf * d.impl->spec_bytes();
+    if (need > NOALLOC_SCRATCH_BYTES)
+        return set_error(FLUSI_EINVAL,
+                         "fft_c2r_noalloc: %d field(s) of %d x %d x %d need %zu bytes of scratch, above the "
+                         "fixed %zu-byte array (use flusi_fft_c2r)",
+                         nf, d.nx, d.n, d.n, need, (size_t)NOALLOC_SCRATCH_BYTES);
+    if (!d.noalloc_scratch) return set_error(FLUSI_EDEVICE, "fft_c2r_noalloc: no device address for the scratch array");
+    return d.impl->fft_c2r_into(d, in, out, nf, d.noalloc_scratch);
 }
 
 int flusi_mask_insect(flusi_plan plan, const flusi_insect* ins, double t, void* chi, void* us, int16_t* colour) {

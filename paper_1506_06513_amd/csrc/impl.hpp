@@ -50,6 +50,7 @@ struct PlanData {
     Member* member_dev = nullptr;     // launch record of the plan's own calls
     Sched sched;                      // schedule of the plan's own stepping calls
     unsigned long gen = 0;            // bumped by every option change (ensembles rebuild on a change)
+    void* noalloc_scratch = nullptr;  // device address of the static scratch array on the plan's GPU
     double wall_th[3] = {0.0, 0.0, 0.0};  // Dirichlet layer thickness per axis (0: none)
     double u_wall[3] = {0.0, 0.0, 0.0};   // velocity imposed in the layers
     double c_sp = 0.0;                // vorticity sponge constant (0: off)
@@ -229,6 +230,8 @@ struct ImplBase {
     virtual size_t field3_bytes() const = 0;  // three state fields (the RK4 stage velocity)
     virtual int fft_r2c(PlanData&, const void*, void*, int) = 0;
     virtual int fft_c2r(PlanData&, const void*, void*, int) = 0;
+    virtual int fft_c2r_into(PlanData&, const void*, void*, int, void* scratch) = 0;
+    virtual size_t spec_bytes() const = 0;  // one full-layout spectrum field
     virtual int mask(PlanData&, const flusi_insect&, double, void*, void*, int16_t*) = 0;
     virtual int rhs(PlanData&, const void*, const void*, const void*, void*, int, double*) = 0;
     virtual int state_init(PlanData&, void*, const void*, double) = 0;
@@ -353,12 +356,18 @@ struct Impl final : ImplBase {
     int fft_c2r(PlanData& p, const void* in, void* out, int nf) override {
         int rc = ensure_scratch(&p.spec, &p.spec_sz, (size_t)nf * FULL * sizeof(CX), p);
         if (rc) return rc;
-        CX* s = static_cast<CX*>(p.spec);
+        return fft_c2r_into(p, in, out, nf, p.spec);
+    }
+    // inverse through caller-provided scratch of nf full-layout spectra (every
+    // element is written by the z pass before any later pass reads it)
+    int fft_c2r_into(PlanData& p, const void* in, void* out, int nf, void* scratch) override {
+        CX* s = static_cast<CX*>(scratch);
         z_full(p, static_cast<const CX*>(in), s, nf, +1);
         y_full(p, s, s, nf, +1);
         x_c2r(p, s, static_cast<T*>(out), (long)nf * N2, NKX);
         return launch_check("fft_c2r");
     }
+    size_t spec_bytes() const override { return (size_t)FULL * sizeof(CX); }
 
     int mask(PlanData& p, const flusi_insect& ins, double t, void* chi, void* us, int16_t* col) override {
         const double dx = p.L / N;
