@@ -405,8 +405,9 @@ __global__ __launch_bounds__(NT, (xpass_min_blocks<T, NX, NC, V, SP>())) void k_
     __shared__ KinT<T> kin;
     // FP64 kinematics for the part choice where parts overlap (FP32 runs)
     constexpr bool K64 = NC > 1 && sizeof(T) < 8;
-    __shared__ typename std::conditional<K64, KinT<double>, char>::type kin64;
-    __shared__ unsigned char amb[K64 ? RW * NX : 1];  // point flagged for the FP64 part decision
+    // point flagged for the FP64 part decision (one bit per point); the FP64
+    // kinematics of those few points are read from the state header
+    __shared__ unsigned amb[K64 ? (RW * NX + 31) / 32 : 1];
     __shared__ int amb_any;
     // twiddles from LDS unless the table would cost a workgroup per CU (FP64,
     // full-size tile: the tile alone is just under half of the 160 KiB)
@@ -420,10 +421,6 @@ __global__ __launch_bounds__(NT, (xpass_min_blocks<T, NX, NC, V, SP>())) void k_
         stage_twiddles<T, NX>(tws, tw, NT);
         twx = tws;
     }
-    if constexpr (K64) {
-        for (int e = tid; e < RW * NX; e += NT) amb[e] = 0;
-        if (tid == 0) amb_any = 0;
-    }
     // kinematics blocks prepared once per time level (state header) -> LDS
     const auto lds_copy = [&](const void* src, void* dst, int bytes) {
         const glb<unsigned>* a = gview(static_cast<const unsigned*>(src));
@@ -434,8 +431,16 @@ __global__ __launch_bounds__(NT, (xpass_min_blocks<T, NX, NC, V, SP>())) void k_
         if constexpr (sizeof(T) < 8) lds_copy(&hdr->kf, &kin, (int)sizeof(KinT<T>));
         else lds_copy(&hdr->kd, &kin, (int)sizeof(KinT<T>));
     }
-    if constexpr (K64) lds_copy(&hdr->kd, &kin64, (int)sizeof(KinT<double>));
 
+    if constexpr (K64) {
+        for (int e = tid; e < (RW * NX + 31) / 32; e += NT) amb[e] = 0u;
+        if (tid == 0) amb_any = 0;
+    }
+    // the wave rows of the sums start at zero; each wave clears its own row
+    // (its lane 0 adds to it later, and one wave's LDS accesses stay in order)
+    if constexpr (WAVE_ACC) {
+        if ((tid & 63) < NV) wred[tid >> 6][(tid & 63)] = 0.0;
+    }
     // 1. pack three Hermitian pairs per row: Z = X + iY over the full x axis
     cx<T> la[3][LP], lb[3][LP];
 #pragma unroll
@@ -475,6 +480,23 @@ __global__ __launch_bounds__(NT, (xpass_min_blocks<T, NX, NC, V, SP>())) void k_
         }
     }
     fft_cols<T, NX, +1, CI, NT, SC>(buf, twx);
+    // Whether any point of this workgroup's rows can lie inside the body's
+    // cull sphere (radius^2 r2all about xc, beyond which chi == 0 exactly).
+    // The rows span the whole x axis, so only their (y, z) distance counts; it
+    // is taken in FP64 with a relative margin far above the rounding of the
+    // per-point test, so a skipped workgroup has no point with chi > 0.
+    bool wg_mask = NC > 0;
+    if constexpr (NC > 0) {
+        const double cy = (double)kin.xc[1], cz = (double)kin.xc[2];
+        const double r2 = (double)kin.r2all * (1.0 + 1e-5);
+        bool any = false;
+        for (int r = 0; r < RW; ++r) {
+            const int row = row0 + r;
+            const double dy = dx * (row % N) - cy, dz = dx * (row / N) - cz;
+            any = any || (dy * dy + dz * dz <= r2);
+        }
+        wg_mask = any;
+    }
 
     // 2. pointwise source and partial sums, one point per iteration (the mask
     //    code is large; a rolled loop keeps the register count down).  The
@@ -486,15 +508,12 @@ __global__ __launch_bounds__(NT, (xpass_min_blocks<T, NX, NC, V, SP>())) void k_
     // instead, which keeps them out of the registers.
     constexpr int NLANE = WAVE_ACC ? 3 : NVAL;
     const int lane = tid & 63, wv = tid >> 6;
-    if constexpr (WAVE_ACC) {
-        for (int e = tid; e < (NT / 64) * NV; e += NT) wred[e / NV][e % NV] = 0.0;
-    }
     double acc[NLANE];
 #pragma unroll
     for (int v = 0; v < NLANE; ++v) acc[v] = 0.0;
     const T s = T(1.0 / ((double)NX * (double)N * (double)N));
     const KinT<double>* k64p = nullptr;
-    if constexpr (K64) k64p = &kin64;
+    if constexpr (K64) k64p = &hdr->kd;
     // One grid point.  PH = 0: main sweep (with K64, points where two parts
     // overlap are only flagged); PH = 1: the flagged points again, with the
     // part decided in FP64 (the grid-sum terms of u were taken in the sweep).
@@ -543,6 +562,7 @@ __global__ __launch_bounds__(NT, (xpass_min_blocks<T, NX, NC, V, SP>())) void k_
         const bool inwall = m.wall && (dx * i >= m.wall_lo[0] || dx * (row % N) >= m.wall_lo[1] ||
                                        dx * (row / N) >= m.wall_lo[2]);
         if constexpr (NC > 0) {
+          if (wg_mask) {
             const double xg = dx * i, yg = dx * (row % N), zg = dx * (row / N);
             MaskPt<T> mp;
             mp.chi = T(0);
@@ -555,7 +575,7 @@ __global__ __launch_bounds__(NT, (xpass_min_blocks<T, NX, NC, V, SP>())) void k_
                     bool defer = false;
                     mp = eval_mask<T>(kin, xg, yg, zg, nullptr, &defer);
                     if (defer) {
-                        amb[idx] = 1;
+                        atomicOr(&amb[idx >> 5], 1u << (idx & 31));
                         amb_any = 1;
                     }
                 } else {
@@ -619,6 +639,7 @@ __global__ __launch_bounds__(NT, (xpass_min_blocks<T, NX, NC, V, SP>())) void k_
                     }
                 });
             }
+          }
         }
         if (inwall) {
             const T pen = T(inv_eta);
@@ -645,9 +666,9 @@ __global__ __launch_bounds__(NT, (xpass_min_blocks<T, NX, NC, V, SP>())) void k_
         // points where two parts overlap, in a fixed order (deterministic sums);
         // every lane runs the same number of iterations for the wave sums
         __syncthreads();
-        if (amb_any) {
+        if (wg_mask && amb_any) {
 #pragma unroll 1
-            for (int idx = tid; idx < RW * NX; idx += NT) point(idx, amb[idx] != 0, std::integral_constant<int, 1>{});
+            for (int idx = tid; idx < RW * NX; idx += NT) point(idx, ((amb[idx >> 5] >> (idx & 31)) & 1u) != 0, std::integral_constant<int, 1>{});
         }
     }
     // workgroup partial sums: lane values of the first three by DPP, the wave rows
@@ -964,6 +985,31 @@ __device__ inline void reduce_level2(const double* __restrict__ partial2, double
     __syncthreads();
 }
 
+// Values 0..2 of the NRED first-level records (max |u|^2, sum |u|^2, the
+// non-finite flag) by one wave: lane b takes record b.  The maximum does not
+// depend on the order; the sum is only tested for finiteness here (the writer
+// workgroup forms every sum in the fixed order of reduce_level2).
+template <int NRED>
+__device__ inline void reduce_scalars(const double* __restrict__ partial2, double* tot) {
+    static_assert(NRED <= 64, "one record per lane");
+    const int lane = threadIdx.x & 63;
+    const glb<double>* P = gview(partial2);
+    double v0 = 0.0, v1 = 0.0, v2 = 0.0;
+    if (lane < NRED) {
+        v0 = P[(long)lane * NV + 0];
+        v1 = P[(long)lane * NV + 1];
+        v2 = P[(long)lane * NV + 2];
+    }
+    v0 = wave_max(v0);
+    v1 = wave_sum(v1);
+    v2 = wave_max(v2);
+    if (lane == 0) {
+        tot[0] = v0;
+        tot[1] = v1;
+        tot[2] = v2;
+    }
+}
+
 // Kinematics of time level p of member m and its mask-evaluation blocks (one
 // thread).  Everything is computed in registers from a register copy of the
 // body description and stored once: interleaving loads of the description and
@@ -1169,6 +1215,11 @@ __global__ __launch_bounds__(nt_z(N, V)) void k_zpass(const Member* __restrict__
     __shared__ double tot[NV];
     __shared__ Coef cf;
     __shared__ cx<T> tws[N];
+    // AB2 steps: the integrating factors exp(-nu |k|^2 dt) split into the
+    // column's exp(-nu (kx^2 + ky^2) dt) and a table of exp(-nu kz^2 dt) over
+    // the kept kz (and the same for the previous step size)
+    constexpr bool AB2M = (MODE == MODE_STEP || MODE == MODE_STEP_LAST);
+    __shared__ double exz[AB2M ? 2 : 1][AB2M ? M : 1];
     cx<T>* buf = reinterpret_cast<cx<T>*>(smem);
     if (*gview(&hdr->status)) return;
     const int tid = threadIdx.x;
@@ -1195,16 +1246,29 @@ __global__ __launch_bounds__(nt_z(N, V)) void k_zpass(const Member* __restrict__
         for (int f = 0; f < FB; ++f) load_field(f, f);
     }
     if constexpr (STEPM) {
-        reduce_level2<NTZ, nred_of(NX, N)>(partial2, reinterpret_cast<double*>(smem), tot);
         if (tile == NBZ) {
+            // the writer: every sum in the fixed order (diagnostics, forces)
+            reduce_level2<NTZ, nred_of(NX, N)>(partial2, reinterpret_cast<double*>(smem), tot);
             if (tid == 0)
                 write_step(hdr, par, tot, step_coef(tot, hdr->slot[par], mb.ctl, dx, eta), mb.ctl, dx, eta,
                            mb.history ? mb.history + (long)s * FLUSI_NDIAG : nullptr, mb.ff, mb.rk);
             return;
         }
+        // column workgroups need max|u|^2 (order-free), the finiteness of the
+        // |u|^2 sum and the non-finite flag: one wave, no LDS round trips
+        if (tid < 64) reduce_scalars<nred_of(NX, N)>(partial2, tot);
+        __syncthreads();
         if (tid == 0) cf = step_coef(tot, hdr->slot[par], mb.ctl, dx, eta);
         __syncthreads();
         if (cf.bad) return;
+        if constexpr (AB2M) {
+            // visible after the barriers of the forward transforms
+            for (int m = tid; m < M; m += NTZ) {
+                const double kz = kscale * j_of_m(m, K);
+                exz[0][m] = exp(-nu * (kz * kz) * cf.dt);
+                exz[1][m] = cf.first ? 0.0 : exp(-nu * (kz * kz) * cf.dtp);
+            }
+        }
     }
     // RK stages 2-4: the step size the first stage chose (0: no step)
     const double rdt = MODE == MODE_RKS ? *gview(&hdr->slot[1 - par].rk_dt) : 0.0;
@@ -1293,6 +1357,12 @@ __global__ __launch_bounds__(nt_z(N, V)) void k_zpass(const Member* __restrict__
             first = cf.first;
         }
         if (MODE == MODE_RKS) dt = rdt;
+        double exy[2] = {0.0, 0.0};
+        if (AB2M) {
+            const double kxy2 = kxv * kxv + kyv * kyv;
+            exy[0] = exp(-nu * kxy2 * dt);
+            exy[1] = first ? 0.0 : exp(-nu * kxy2 * dtp);
+        }
         const int stage = MODE == MODE_RK1 ? 1 : (rk & 15);
         glb<cx<T>>* ust = gview(static_cast<cx<T>*>(mb.ustage));
 #pragma unroll
@@ -1308,8 +1378,9 @@ __global__ __launch_bounds__(nt_z(N, V)) void k_zpass(const Member* __restrict__
                     ni[f] = (double)Nh[f][i].y;
                 }
                 if (k2 > 0.0) {
-                    const double sr = (kxv * nr[0] + kyv * nr[1] + kzv * nr[2]) / k2;
-                    const double si = (kxv * ni[0] + kyv * ni[1] + kzv * ni[2]) / k2;
+                    const double ik2 = 1.0 / k2;
+                    const double sr = (kxv * nr[0] + kyv * nr[1] + kzv * nr[2]) * ik2;
+                    const double si = (kxv * ni[0] + kyv * ni[1] + kzv * ni[2]) * ik2;
                     nr[0] -= kxv * sr; nr[1] -= kyv * sr; nr[2] -= kzv * sr;
                     ni[0] -= kxv * si; ni[1] -= kyv * si; ni[2] -= kzv * si;
                 } else if (step_mode && mean_mode == FLUSI_MEAN_FIXED) {
@@ -1353,8 +1424,8 @@ __global__ __launch_bounds__(nt_z(N, V)) void k_zpass(const Member* __restrict__
                         }
                     }
                 } else {
-                    const double e1 = exp(-nu * k2 * dt);
-                    const double c2 = first ? 0.0 : b2 * exp(-nu * k2 * dtp);
+                    const double e1 = exy[0] * exz[AB2M ? 0 : 0][AB2M ? m : 0];
+                    const double c2 = first ? 0.0 : b2 * (exy[1] * exz[AB2M ? 1 : 0][AB2M ? m : 0]);
 #pragma unroll
                     for (int f = 0; f < 3; ++f) {
                         const cx<T> uo = gld(uhat, f * fs_s + e);
