@@ -266,11 +266,15 @@ def ensemble_run(F, torch, count=48, steps=200, chunk=20, seed=1, tune=True):
                            f"stroke 50-80 deg; seed {seed}), fluid at rest, CFL 0.1"}
 
 
-def serve_run(F, torch, count=120, seed=2, budget_gib=32.0, chunk=20, big_n=512, big_steps=2000):
+def serve_run(F, torch, count=120, seed=2, budget_gib=32.0, chunk=20, big_n=512, big_steps=2000, saturate=False):
     """Serving stream: requests submitted at their Poisson arrival times to a
-    flusi server (FP32, HBM budget budget_gib); latency from submit to result."""
+    flusi server (FP32, HBM budget budget_gib); latency from submit to result.
+    saturate=True submits every request at once (offered load above capacity):
+    its throughput is the serving capacity."""
     import workloads as W
     reqs = W.serve_stream(count, seed=seed, big_n=big_n, big_steps=big_steps)
+    if saturate:
+        reqs = [dict(r, arrival=0.0) for r in reqs]
     big = [r for r in reqs if r["turbulent"]][0]
     t_ic = time.perf_counter()
     big_u0 = W.turbulent_inflow(big["n"], big["L"], seed=big["seed"], intensity=0.1, kmax=32.0).astype(np.float32)
@@ -304,6 +308,7 @@ def serve_run(F, torch, count=120, seed=2, budget_gib=32.0, chunk=20, big_n=512,
             "max_chunk": chunk, "arrival_span_s": round(reqs[-1]["arrival"], 2), "wall_s": round(wall, 2),
             "busy_s": round(st["busy_s"], 2), "point_steps": st["point_steps"], "dtype": "f32",
             "initial_field_s": round(t_ic, 1),
+            "arrivals": "all at t = 0 (saturated)" if saturate else "Poisson, mean 4/s",
             "description": f"{count} requests, Poisson arrivals mean 4/s (seed {seed}): one {big['n']}^3 insect "
                            f"in k^-5/3 turbulent inflow (intensity 0.1, |k| 1-32, {big['steps']} steps), the rest "
                            f"insects on {{64,96,128,192}}^3 (Re 50-500, C_eta 1e-4..1e-3, 200 steps, at rest); "
@@ -411,6 +416,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--workload", default="insect256",
                     choices=["sphere128", "freefall128", "insect256", "box192", "tg32", "ensemble48", "serve"])
+    ap.add_argument("--no-sphere", action="store_true", help="skip the 128^3 sphere figure")
     ap.add_argument("--no-serve", action="store_true", help="skip the serving-stream figure")
     ap.add_argument("--no-sponge", action="store_true", help="skip the vorticity-sponge figure")
     ap.add_argument("--no-freeflight", action="store_true", help="skip the free-flight figure")
@@ -450,6 +456,7 @@ def main():
 
     if a.workload == "serve":
         sv = serve_run(F, torch)
+        sv["saturated"] = serve_run(F, torch, saturate=True)
         print(json.dumps({"metric": METRIC, "value": sv["value"], "unit": sv["unit"], "n_gpus": 1,
                           "steps": None, "warmup": 0, "ms_per_step": None, "higher_is_better": True,
                           "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
@@ -482,16 +489,14 @@ def main():
     out["ms_per_step"] = m.pop("ms_per_step")
     out.update(m)
     extras = a.workload == "insect256"
-    if extras:
-        swl = build_workload("sphere128")
-        s_steps = swl["default_steps"]
+    swl = build_workload("sphere128") if extras else wl
+    s_steps = swl["default_steps"] if extras else steps
+    if extras and not a.no_sphere:
         ms = measure(F, torch, "sphere128", swl, s_steps, a.warmup, not a.no_autotune)
         out["sphere128"] = dict(ms, steps=s_steps, description=swl["desc"])
         if not a.no_cpu:
             out["sphere128"]["err_vs_oracle"] = error_vs_oracle(F, torch, swl, oracle_sample(swl, budget_s=5.0))
         note("sphere128 done")
-    else:
-        swl, s_steps = wl, steps
     spts = float(swl["n"]) ** 3
     if not a.no_ensemble and extras:
         out["ensemble48"] = ensemble_run(F, torch, tune=not a.no_autotune)
@@ -499,6 +504,8 @@ def main():
     if not a.no_serve and extras:
         out["serving"] = serve_run(F, torch)
         note("serving done")
+        out["serving"]["saturated"] = serve_run(F, torch, saturate=True)
+        note("saturated serving done")
     if not a.no_sponge and extras:
         # the same workload with a vorticity sponge layer 3.5 <= x < 4 (C_sp = 0.1)
         sp = {}
