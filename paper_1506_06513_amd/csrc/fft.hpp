@@ -23,6 +23,7 @@ __host__ __device__ constexpr int fft_nstages(int N) {
         case 16: return 1;
         case 24: case 32: case 64: case 96: case 128: case 256: return 2;
         case 48: case 192: case 384: case 512: case 768: case 1024: return 3;
+        case 1152: return 4;
         default: return 0;
     }
 }
@@ -41,10 +42,12 @@ __host__ __device__ constexpr int fft_radix(int N, int s) {
         case 512: return 8;
         case 768: return s == 2 ? 12 : 8;
         case 1024: return s == 2 ? 4 : 16;
+        case 1152: return s < 2 ? 12 : (s == 2 ? 4 : 2);
         default: return 1;
     }
 }
-// elements per lane (least common multiple of the radices)
+// elements per lane: a multiple of every radix (their least common multiple,
+// or a multiple of it where that leaves more than 64 lanes per column)
 __host__ __device__ constexpr int fft_E(int N) {
     switch (N) {
         case 16: return 16;
@@ -60,6 +63,7 @@ __host__ __device__ constexpr int fft_E(int N) {
         case 512: return 8;
         case 768: return 24;
         case 1024: return 16;
+        case 1152: return 36;  // a multiple of 12 whose lane count divides 64
         default: return 1;
     }
 }

@@ -54,14 +54,17 @@ __host__ __device__ constexpr int nt_z(int N, int V = 0) {
     if (V == 1) return t1;
     return fits(4 * t0) ? 4 * t0 : (fits(6 * t0) ? 6 * t0 : t1);
 }
-// Rows per workgroup of the x-pass (even): 3*RW*N ~ 3072 elements in LDS
-// (V = 0), a half (V = 1) or a quarter (V = 2) of that, at least 2 rows.
+// Rows per workgroup of the x-pass: 3*RW*N ~ 3072 elements in LDS (V = 0), a
+// half (V = 1) or a quarter (V = 2) of that, at least 2 rows (an even count
+// pairs the rows' N_z in one forward transform); a single row where two rows
+// of complex values (nine columns) would not fit the LDS (long FP64 rows).
 __host__ __device__ constexpr int rows_x(int N, int cbytes = 8, int V = 0) {
     int c = 1024 / N, p = 2;
-    (void)cbytes;
     while (p * 2 <= c) p *= 2;
     p >>= V;
-    return p < 2 ? 2 : p;
+    p = p < 2 ? 2 : p;
+    if (p == 2 && 9 * cm_stride(N) * cbytes > 150 * 1024) p = 1;
+    return p;
 }
 __host__ __device__ constexpr int round_up(int a, int b) { return (a + b - 1) / b * b; }
 // First-level reduction workgroups per member: every z-pass workgroup reads
@@ -389,7 +392,9 @@ __global__ __launch_bounds__(NT, (xpass_min_blocks<T, NX, NC, V, SP>())) void k_
     glb<double>* __restrict__ partial = gview(m.partial);
     const int wg = blockIdx.x % NWG;
     constexpr int SC = cm_stride(NX);
-    constexpr int CI = 3 * RW, CF = 3 * RW / 2;
+    // forward columns: (N_x, N_y) of each row, N_z of row pairs (one row:
+    // N_z alone, with a zero imaginary part)
+    constexpr int CI = 3 * RW, CF = RW == 1 ? 2 : 3 * RW / 2;
     constexpr int CFT = SP ? 2 * CF : CF;  // forward columns (N, then chi_sp w)
     constexpr int NVAL = 3 + 12 * NC;
 
@@ -617,25 +622,28 @@ __global__ __launch_bounds__(NT, (xpass_min_blocks<T, NX, NC, V, SP>())) void k_
                     for (int e = 0; e < 12; ++e) acc[3 + e] += val[e];
                 }
             } else {
-                // every lane takes part in the DPP sums, so the terms are formed
-                // under the branch and summed outside it
-                double val[12];
-#pragma unroll
-                for (int e = 0; e < 12; ++e) val[e] = 0.0;
-                if (has) {
-                    penalize();
-                    terms(val);
-                }
+                // every lane takes part in the DPP sums (lanes of other colours
+                // add 0); each term is formed just before its sum, so that no
+                // array of the twelve terms stays live across the branch
+                if (has) penalize();
                 const int ci = has ? mp.colour - 1 : -1;
                 static_for<NC>([&](auto cc) {
                     constexpr int col = decltype(cc)::value;
                     const bool mine = ci == col;
                     if (__any(mine)) {  // wave-uniform: only colours present in this wave
-#pragma unroll
-                        for (int e = 0; e < 12; ++e) {
-                            const double r = wave_sum(mine ? val[e] : 0.0);
+                        const double ch = mp.chi, s0 = mp.us[0], s1 = mp.us[1], s2 = mp.us[2];
+                        const double p[3] = {ch * ((double)ux - s0), ch * ((double)uy - s1), ch * ((double)uz - s2)};
+                        const double q[3] = {ch * s0, ch * s1, ch * s2};
+                        const double rx = xg - kin.xref[col][0], ry = yg - kin.xref[col][1],
+                                     rz = zg - kin.xref[col][2];
+                        const auto add = [&](int e, double v) {
+                            const double r = wave_sum(mine ? v : 0.0);
                             if (lane == 0) wred[wv][3 + 12 * col + e] += r;
-                        }
+                        };
+                        add(0, p[0]); add(1, p[1]); add(2, p[2]);
+                        add(3, ry * p[2] - rz * p[1]); add(4, rz * p[0] - rx * p[2]); add(5, rx * p[1] - ry * p[0]);
+                        add(6, q[0]); add(7, q[1]); add(8, q[2]);
+                        add(9, ry * q[2] - rz * q[1]); add(10, rz * q[0] - rx * q[2]); add(11, rx * q[1] - ry * q[0]);
                     }
                 });
             }
@@ -649,14 +657,16 @@ __global__ __launch_bounds__(NT, (xpass_min_blocks<T, NX, NC, V, SP>())) void k_
         }
         if (act) {
             fbuf[lds_at<true, 1, SC>(i, r)] = cx<T>{nx, ny};
-            reinterpret_cast<T*>(fbuf + lds_at<true, 1, SC>(i, RW + r / 2))[r & 1] = nz;
+            if constexpr (RW == 1) fbuf[lds_at<true, 1, SC>(i, 1)] = cx<T>{nz, T(0)};
+            else reinterpret_cast<T*>(fbuf + lds_at<true, 1, SC>(i, RW + r / 2))[r & 1] = nz;
             if constexpr (SP) {
                 // vorticity sponge: chi_sp * w, same column scheme after the N columns
                 const double xs = dx * i, ys = dx * (row % N), zs = dx * (row / N);
                 const bool in = xs >= m.sp_lo[0] || ys >= m.sp_lo[1] || zs >= m.sp_lo[2];
                 const T c = in ? T(1) : T(0);
                 fbuf[lds_at<true, 1, SC>(i, CF + r)] = cx<T>{c * wx, c * wy};
-                reinterpret_cast<T*>(fbuf + lds_at<true, 1, SC>(i, CF + RW + r / 2))[r & 1] = c * wz;
+                if constexpr (RW == 1) fbuf[lds_at<true, 1, SC>(i, CF + 1)] = cx<T>{c * wz, T(0)};
+                else reinterpret_cast<T*>(fbuf + lds_at<true, 1, SC>(i, CF + RW + r / 2))[r & 1] = c * wz;
             }
         }
     };
