@@ -155,6 +155,17 @@ def build_workload(name: str):
                 "C_eta=1e-3, adaptive dt CFL 0.1 capped at C_eta/2")
         return dict(n=n, nx=nx, L=L, nu=wl["nu"], eta=wl["eta"], u0=u0, insect=body, cfl=0.1, dt_fixed=0.0,
                     desc=desc, default_steps=wl["steps"])
+    if name == "box1152":
+        # the paper's box (Sec. 4 and 6): 6x4x4 at 1152x768x768 points, one
+        # spacing 1/192; the model insect at (2.4, 2, 2) in a fluid at rest
+        n, nx, L = 768, 1152, 4.0
+        wl = W.WORKLOADS["insect256"]
+        body = dict(W.model_insect(n, L), x_cntr=(2.4, 2.0, 2.0))
+        desc = ("1152x768x768 box 6x4x4 (the paper's box and resolution, one spacing 1/192), model insect at "
+                "(2.4, 2, 2) (ellipsoid body + two flapping elliptic wings), nu=1/136, C_eta=2.5e-4, CFL 0.1, "
+                "fluid at rest")
+        return dict(n=n, nx=nx, L=L, nu=wl["nu"], eta=wl["eta"], u0=None, insect=body, cfl=0.1, dt_fixed=0.0,
+                    desc=desc, default_steps=10)
     if name == "freefall128":
         wl = build_workload("sphere128")
         wl["insect"] = free_sphere(wl["insect"])
@@ -183,7 +194,10 @@ def gpu_run(F, torch, wl, dtype, steps, warmup, tune=True, sponge=None, integrat
         P.set_sponge(*sponge)
     P.set_integrator(integrator)
     kw = dict(dt_fixed=wl["dt_fixed"], cfl=wl["cfl"], eta_cap=0.5, mean_mode=F.FLUSI_MEAN_FIXED)
-    u0 = torch.from_numpy(wl["u0"])
+    if wl["u0"] is None:  # fluid at rest, built on the device
+        u0 = torch.zeros((3,) + P.shape, dtype=P.rdt, device="cuda")
+    else:
+        u0 = torch.from_numpy(wl["u0"])
     st = P.new_state(u0)
     if warmup:
         P.step(st, warmup, wl["insect"], **kw)
@@ -415,7 +429,8 @@ def main():
     ap.add_argument("--steps", type=int, default=None)
     ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--workload", default="insect256",
-                    choices=["sphere128", "freefall128", "insect256", "box192", "tg32", "ensemble48", "serve"])
+                    choices=["sphere128", "freefall128", "insect256", "box192", "box1152", "tg32", "ensemble48",
+                             "serve"])
     ap.add_argument("--no-sphere", action="store_true", help="skip the 128^3 sphere figure")
     ap.add_argument("--no-serve", action="store_true", help="skip the serving-stream figure")
     ap.add_argument("--no-sponge", action="store_true", help="skip the vorticity-sponge figure")
@@ -543,6 +558,17 @@ def main():
                       "description": "sphere128 stepped with classical RK4 and explicit diffusion "
                                      "(four pipeline passes per step)"}
     if not a.no_box and extras:
+        # the paper's own box at its own resolution: FP32 and FP64, few steps
+        bw = build_workload("box1152")
+        bpts = 1152.0 * 768 * 768
+        bv = {}
+        for dtype in ("f32", "f64"):
+            r = gpu_run(F, torch, bw, dtype, bw["default_steps"], 2, tune=False)
+            bv[dtype] = round(bpts * bw["default_steps"] / (r["ev_ms"] / 1e3) / 1e6, 2)
+            torch.cuda.empty_cache()
+        note("box1152 done")
+        out["box1152"] = {"value": bv["f32"], "fp64": bv["f64"], "unit": "Mpoint-steps/s",
+                          "steps": bw["default_steps"], "description": bw["desc"]}
         # the sphere workload in the 6x4x4 box shape of the paper at 192x128x128 points
         bx = build_workload("box192")
         bpts = 192.0 * 128 * 128

@@ -460,24 +460,18 @@ int flusi_ensemble_autotune(flusi_ensemble e, int reps);
 /* ------------------------------------------------------------------------
  * Serving: a request loop with continuous batching.
  *
- * A server owns two host threads, an ensemble and the device memory of the
- * requests it has admitted.  Submitted requests queue in arrival order.  The
- * I/O thread admits the oldest waiting requests while their device footprint
+ * A server owns a worker thread, an ensemble and the device memory of the
+ * requests it has admitted.  Submitted requests queue in arrival order; the
+ * worker admits the oldest waiting requests while their device footprint
  * (plan workspace + state + velocity-export scratch + output field) fits the
- * HBM budget, prepares them (plan, state, initial field) on a stream of its
- * own and hands them to the stepping thread, which advances every admitted
- * request together (all grid sizes in one ensemble step, size groups on
- * parallel streams, captured into graphs that are replayed while the
- * membership and chunk length stay the same) in chunks of at most max_chunk
- * steps, never past any request's last step.  A request leaves the ensemble
- * as soon as its steps are done; the I/O thread copies its final velocity and
- * diagnostics to host memory while the others keep stepping.  Its device
- * memory (plan, state, field) stays in a per-grid pool for the next request
- * of that grid, so steady serving allocates nothing; pooled memory counts
- * against the budget and is released when a request of another grid needs
- * it.  A request's result is bitwise the same as stepping it alone with
- * flusi_step (same plan parameters, body, controls and steps).  Latency =
- * completion time - submit time (host steady clock).
+ * HBM budget, advances every admitted request together (all grid sizes in
+ * one ensemble step, size groups on parallel streams) in chunks of at most
+ * max_chunk steps, never past any request's last step, and retires a request
+ * as soon as its steps are done: its final velocity and diagnostics are
+ * copied to host memory and its device memory is freed, which admits the
+ * next waiting requests.  A request's result is bitwise the same as stepping
+ * it alone with flusi_step (same plan parameters, body, controls and steps).
+ * Latency = completion time - submit time (host steady clock).
  * ------------------------------------------------------------------------ */
 typedef struct flusi_server_s* flusi_server;
 
@@ -497,7 +491,7 @@ typedef struct {
     double point_steps;             /* sum of n^3 * steps over completed requests */
     double busy_s;                  /* first submit to last completion */
     double mpoint_steps_per_s;      /* point_steps / busy_s / 1e6 */
-    size_t peak_bytes;              /* largest sum of admitted footprints and pooled memory */
+    size_t peak_bytes;              /* largest admitted footprint sum */
     int peak_active;                /* most requests on the device at once */
     int reserved;
 } flusi_server_stats;

@@ -690,21 +690,6 @@ int flusi_pass_times(flusi_plan plan, double* ms, long long* launches) {
 namespace flusi {
 int insect_error(const flusi_insect* ins) { return check_insect(ins); }
 
-// New box side, viscosity and C_eta for an existing plan of the same grid (the
-// serving loop reuses a retired request's plan): nothing the plan holds on the
-// device depends on them.  The option generation moves, so an ensemble that
-// holds the plan rebuilds its records.
-int plan_reconfigure(flusi_plan plan, double L, double nu, double eta) {
-    if (int rc = check_plan(plan)) return rc;
-    if (!(L > 0.0) || !(nu >= 0.0) || !(eta > 0.0)) return set_error(FLUSI_EINVAL, "need L > 0, nu >= 0, eta > 0");
-    PlanData& d = plan->d;
-    d.L = L;
-    d.Lx = d.nx == d.n ? L : L * d.nx / d.n;
-    d.nu = nu;
-    d.eta = eta;
-    d.gen += 1;
-    return FLUSI_OK;
-}
 struct EnsMember {
     flusi_plan plan = nullptr;
     void* state = nullptr;

@@ -19,7 +19,6 @@
 namespace flusi {
 int set_error(int code, const char* fmt, ...);
 int insect_error(const flusi_insect* ins);
-int plan_reconfigure(flusi_plan plan, double L, double nu, double eta);
 }
 using flusi::insect_error;
 using flusi::set_error;
@@ -27,29 +26,16 @@ using flusi::set_error;
 namespace {
 using clk = std::chrono::steady_clock;
 
-size_t real_bytes(int dtype) { return dtype == FLUSI_F32 ? 4 : 8; }
-size_t field_bytes(int n, int dtype) { return 3ul * n * n * n * real_bytes(dtype); }
-
-// Device resources of one admitted request of grid n: its plan, state and
-// field buffer.  A retired request's slot is kept for the next request of the
-// same grid (the plan is re-parameterized), so that steady serving allocates
-// and frees nothing; idle slots are released only when a request of another
-// grid needs their memory.
-struct Slot {
-    int n = 0;
-    size_t bytes = 0;
-    flusi_plan plan = nullptr;
-    void* state = nullptr;
-    void* ubuf = nullptr;            // device field: initial velocity, later the result
-};
-
 struct Req {
     long long id = 0;
     flusi_request r{};               // copy; r.u0 cleared
     std::vector<unsigned char> u0;   // host copy of the initial field (empty: at rest)
     size_t bytes = 0;                // footprint while admitted
     clk::time_point t_submit;
-    Slot* slot = nullptr;            // while admitted
+    // while admitted (worker thread only)
+    flusi_plan plan = nullptr;
+    void* state = nullptr;
+    void* ubuf = nullptr;            // device field: initial velocity, later the result
     int member = -1;
     int remaining = 0;
     // result (under the server mutex once done)
@@ -59,129 +45,100 @@ struct Req {
     double diag[FLUSI_NDIAG] = {0};
     double latency_ms = 0.0;
 };
+
+size_t real_bytes(int dtype) { return dtype == FLUSI_F32 ? 4 : 8; }
+size_t field_bytes(int n, int dtype) { return 3ul * n * n * n * real_bytes(dtype); }
 }  // namespace
 
-// Two host threads share the work: the worker only steps the ensemble (it
-// adds ready requests, advances every member by one chunk and removes those
-// whose steps are done); the I/O thread admits waiting requests, prepares them
-// (plan, state, initial field, on its own stream) and retires finished ones
-// (velocity export and copy to the host), so that this host work overlaps the
-// GPU's stepping of the others.
 struct flusi_server_s {
     int dtype = 0;
     size_t budget = 0;
     int max_chunk = 1;
     int device = 0;
-    hipStream_t stream = nullptr;       // ensemble stepping
-    hipStream_t io_stream = nullptr;    // preparation and export
+    hipStream_t stream = nullptr;
     flusi_ensemble ens = nullptr;
     std::mutex mu;
-    // The stepping thread captures graphs of the ensemble; HIP calls of the
-    // I/O thread (allocations, copies, launches) wait while it captures or
-    // launches, and run while the GPU executes the chunk.
-    std::mutex hip_mu;
-    std::condition_variable cv_work, cv_io, cv_done;
+    std::condition_variable cv_work, cv_done;
     std::deque<Req*> waiting;           // arrival order
-    std::vector<Req*> ready;            // prepared, to join the ensemble (I/O thread -> worker)
-    std::vector<Req*> retired;          // steps done, left the ensemble (worker -> I/O thread)
     std::vector<Req*> active;           // worker thread only
-    std::vector<Slot*> idle;            // pooled slots (under mu)
     std::map<long long, Req*> reqs;     // every request not yet collected by flusi_server_wait
     long long next_id = 1;
     bool stop = false;
-    std::thread worker, io;
+    std::thread worker;
     // statistics (under mu)
     long long submitted = 0, completed = 0, failed = 0;
     std::vector<double> lat;
     double point_steps = 0.0;
     bool have_first = false;
     clk::time_point first_submit, last_done;
-    size_t used = 0, peak_bytes = 0;    // admitted footprints plus idle pooled slots
+    size_t used = 0, peak_bytes = 0;
     int n_active = 0, peak_active = 0;
 };
 
 namespace {
 
-void free_slot(Slot* sl) {
-    if (sl->plan) flusi_plan_destroy(sl->plan);
-    if (sl->state) (void)hipFree(sl->state);
-    if (sl->ubuf) (void)hipFree(sl->ubuf);
-    delete sl;
+void free_device(Req* q) {
+    if (q->plan) flusi_plan_destroy(q->plan);
+    if (q->state) (void)hipFree(q->state);
+    if (q->ubuf) (void)hipFree(q->ubuf);
+    q->plan = nullptr;
+    q->state = nullptr;
+    q->ubuf = nullptr;
 }
 
-// The request's slot: the pooled one admission reserved for it (its plan
-// re-parameterized), or new device memory.
-int get_slot(flusi_server s, Req* q, Slot** out) {
+// Plan, state and initial field of an admitted request; joins the ensemble.
+int setup(flusi_server s, Req* q) {
     const int n = q->r.n;
-    if (q->slot) {
-        *out = q->slot;
-        return flusi::plan_reconfigure(q->slot->plan, q->r.L, q->r.nu, q->r.eta);
-    }
-    Slot* sl = new (std::nothrow) Slot();
-    if (!sl) return set_error(FLUSI_ENOMEM, "host allocation");
-    sl->n = n;
-    sl->bytes = q->bytes;
-    int rc = flusi_plan_create(n, n, n, q->r.L, q->r.nu, q->r.eta, s->dtype, &sl->plan);
+    int rc = flusi_plan_create(n, n, n, q->r.L, q->r.nu, q->r.eta, s->dtype, &q->plan);
+    if (rc) return rc;
+    flusi_set_stream(q->plan, s->stream);
     size_t ws = 0, sb = 0;
-    if (!rc) rc = flusi_sizes(n, s->dtype, &ws, &sb);
-    if (!rc && hipMalloc(&sl->state, sb) != hipSuccess) rc = set_error(FLUSI_ENOMEM, "server: state");
-    if (!rc && hipMalloc(&sl->ubuf, field_bytes(n, s->dtype)) != hipSuccess) rc = set_error(FLUSI_ENOMEM, "server: field");
-    if (rc) {
-        free_slot(sl);
-        return rc;
-    }
-    *out = sl;
+    flusi_sizes(n, s->dtype, &ws, &sb);
+    if (hipMalloc(&q->state, sb) != hipSuccess) return set_error(FLUSI_ENOMEM, "server: state");
+    const size_t fb = field_bytes(n, s->dtype);
+    if (hipMalloc(&q->ubuf, fb) != hipSuccess) return set_error(FLUSI_ENOMEM, "server: field");
+    hipError_t e;
+    if (q->u0.empty()) e = hipMemsetAsync(q->ubuf, 0, fb, s->stream);
+    else e = hipMemcpyAsync(q->ubuf, q->u0.data(), fb, hipMemcpyHostToDevice, s->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(s->stream);
+    if (e != hipSuccess) return set_error(FLUSI_EDEVICE, "server: %s", hipGetErrorString(e));
+    std::vector<unsigned char>().swap(q->u0);
+    rc = flusi_state_init(q->plan, q->state, q->ubuf, 0.0);
+    if (rc) return rc;
+    flusi_step_params p = q->r.p;
+    p.history = nullptr;
+    rc = flusi_ensemble_add(s->ens, q->plan, q->state, q->r.has_insect ? &q->r.ins : nullptr, &p, &q->member);
+    if (rc) return rc;
+    q->remaining = q->r.p.nsteps;
     return FLUSI_OK;
 }
 
-// Plan, state and initial field of an admitted request (I/O thread).
-int prepare(flusi_server s, Req* q) {
-    Slot* sl = nullptr;
-    if (int rc = get_slot(s, q, &sl)) return rc;
-    q->slot = sl;
-    flusi_set_stream(sl->plan, s->io_stream);
-    const size_t fb = field_bytes(q->r.n, s->dtype);
-    hipError_t e;
-    if (q->u0.empty()) e = hipMemsetAsync(sl->ubuf, 0, fb, s->io_stream);
-    else e = hipMemcpyAsync(sl->ubuf, q->u0.data(), fb, hipMemcpyHostToDevice, s->io_stream);
-    if (e != hipSuccess) return set_error(FLUSI_EDEVICE, "server: %s", hipGetErrorString(e));
-    int rc = flusi_state_init(sl->plan, sl->state, sl->ubuf, 0.0);
-    e = hipStreamSynchronize(s->io_stream);
-    if (!rc && e != hipSuccess) rc = set_error(FLUSI_EDEVICE, "server: %s", hipGetErrorString(e));
-    std::vector<unsigned char>().swap(q->u0);
-    q->remaining = q->r.p.nsteps;
-    return rc;
-}
-
-// Result of a request that left the ensemble (I/O thread): velocity and
-// diagnostics to the host; the slot goes back to the pool.
-void retire(flusi_server s, Req* q) {
+// Result of a request whose steps are done; frees its device memory.
+void finish(flusi_server s, Req* q) {
     int status = q->status;
-    Slot* sl = q->slot;
-    if (!status && sl) {
+    if (q->member >= 0) {
+        flusi_ensemble_remove(s->ens, q->member);
+        q->member = -1;
+    }
+    if (!status) {
         const size_t fb = field_bytes(q->r.n, s->dtype);
-        flusi_set_stream(sl->plan, s->io_stream);
-        status = flusi_state_velocity(sl->plan, sl->state, sl->ubuf);
+        status = flusi_state_velocity(q->plan, q->state, q->ubuf);
         if (!status) {
             q->u.resize(fb);
-            hipError_t e = hipMemcpyAsync(q->u.data(), sl->ubuf, fb, hipMemcpyDeviceToHost, s->io_stream);
-            if (e == hipSuccess) e = hipStreamSynchronize(s->io_stream);
+            hipError_t e = hipMemcpyAsync(q->u.data(), q->ubuf, fb, hipMemcpyDeviceToHost, s->stream);
+            if (e == hipSuccess) e = hipStreamSynchronize(s->stream);
             if (e != hipSuccess) status = set_error(FLUSI_EDEVICE, "server: %s", hipGetErrorString(e));
         }
-        const int frc = flusi_forces(sl->plan, sl->state, q->diag);
+        const int frc = flusi_forces(q->plan, q->state, q->diag);
         if (!status) status = frc;
     }
+    free_device(q);
     const clk::time_point now = clk::now();
     std::lock_guard<std::mutex> lk(s->mu);
-    if (sl) {
-        s->idle.push_back(sl);  // its bytes stay counted until it is released
-        q->slot = nullptr;
-    } else {
-        s->used -= q->bytes;    // nothing was kept
-    }
     q->status = status;
     q->latency_ms = std::chrono::duration<double, std::milli>(now - q->t_submit).count();
     q->done = true;
+    s->used -= q->bytes;
     s->n_active -= 1;
     s->last_done = now;
     if (status == FLUSI_OK) {
@@ -196,137 +153,43 @@ void retire(flusi_server s, Req* q) {
 void worker_main(flusi_server s) {
     (void)hipSetDevice(s->device);
     for (;;) {
-        std::vector<Req*> join;
+        std::vector<Req*> admit;
         {
             std::unique_lock<std::mutex> lk(s->mu);
-            s->cv_work.wait(lk, [&] { return s->stop || !s->ready.empty() || !s->active.empty(); });
+            s->cv_work.wait(lk, [&] { return s->stop || !s->waiting.empty() || !s->active.empty(); });
             if (s->stop) return;
-            join.swap(s->ready);
+            // admission in arrival order while the footprints fit
+            while (!s->waiting.empty() && s->used + s->waiting.front()->bytes <= s->budget) {
+                Req* q = s->waiting.front();
+                s->waiting.pop_front();
+                s->used += q->bytes;
+                s->n_active += 1;
+                s->peak_bytes = std::max(s->peak_bytes, s->used);
+                s->peak_active = std::max(s->peak_active, s->n_active);
+                admit.push_back(q);
+            }
         }
-        std::vector<Req*> out;
-        for (Req* q : join) {
-            flusi_step_params p = q->r.p;
-            p.history = nullptr;
-            q->status = q->remaining > 0 ? flusi_ensemble_add(s->ens, q->slot->plan, q->slot->state,
-                                                              q->r.has_insect ? &q->r.ins : nullptr, &p, &q->member)
-                                         : FLUSI_OK;
-            if (q->status || q->remaining <= 0) out.push_back(q);
+        for (Req* q : admit) {
+            q->status = setup(s, q);
+            if (q->status || q->remaining == 0) finish(s, q);
             else s->active.push_back(q);
         }
-        if (!s->active.empty()) {
-            int k = s->max_chunk;
-            for (Req* q : s->active) k = std::min(k, q->remaining);
-            // graphs are captured once per membership and chunk length and replayed
-            int rc;
-            {
-                std::lock_guard<std::mutex> hk(s->hip_mu);
-                rc = flusi_ensemble_step(s->ens, k, 1);
-            }
-            hipError_t e = hipStreamSynchronize(s->stream);
-            if (!rc && e != hipSuccess) rc = set_error(FLUSI_EDEVICE, "server: %s", hipGetErrorString(e));
-            std::vector<Req*> keep;
-            for (Req* q : s->active) {
-                q->remaining -= k;
-                if (rc) q->status = rc;
-                if (rc || q->remaining <= 0) {
-                    flusi_ensemble_remove(s->ens, q->member);
-                    q->member = -1;
-                    out.push_back(q);
-                } else {
-                    keep.push_back(q);
-                }
-            }
-            s->active.swap(keep);
+        if (!admit.empty()) s->cv_done.notify_all();
+        if (s->active.empty()) continue;
+        int k = s->max_chunk;
+        for (Req* q : s->active) k = std::min(k, q->remaining);
+        int rc = flusi_ensemble_step(s->ens, k, 0);
+        hipError_t e = hipStreamSynchronize(s->stream);
+        if (!rc && e != hipSuccess) rc = set_error(FLUSI_EDEVICE, "server: %s", hipGetErrorString(e));
+        std::vector<Req*> keep;
+        for (Req* q : s->active) {
+            q->remaining -= k;
+            if (rc) q->status = rc;
+            if (rc || q->remaining <= 0) finish(s, q);
+            else keep.push_back(q);
         }
-        if (!out.empty()) {
-            std::lock_guard<std::mutex> lk(s->mu);
-            s->retired.insert(s->retired.end(), out.begin(), out.end());
-            s->cv_io.notify_all();
-        }
-    }
-}
-
-// Oldest waiting requests whose footprints fit (under mu): an idle slot of the
-// same grid is already counted; otherwise idle slots of other grids are
-// released (largest first) when that makes room.  Arrival order, no overtaking.
-std::vector<Req*> admit_locked(flusi_server s, std::vector<Slot*>& release) {
-    std::vector<Req*> admit;
-    while (!s->waiting.empty()) {
-        Req* q = s->waiting.front();
-        auto pooled = std::find_if(s->idle.begin(), s->idle.end(), [&](const Slot* sl) { return sl->n == q->r.n; });
-        if (pooled != s->idle.end()) {
-            q->slot = *pooled;  // reserved for this request; its bytes are counted already
-            s->idle.erase(pooled);
-        } else {
-            while (s->used + q->bytes > s->budget && !s->idle.empty()) {
-                auto big = std::max_element(s->idle.begin(), s->idle.end(),
-                                            [](const Slot* a, const Slot* b) { return a->bytes < b->bytes; });
-                s->used -= (*big)->bytes;
-                release.push_back(*big);
-                s->idle.erase(big);
-            }
-            if (s->used + q->bytes > s->budget) break;
-            s->used += q->bytes;
-        }
-        s->waiting.pop_front();
-        s->n_active += 1;
-        s->peak_bytes = std::max(s->peak_bytes, s->used);
-        s->peak_active = std::max(s->peak_active, s->n_active);
-        admit.push_back(q);
-    }
-    return admit;
-}
-
-void io_main(flusi_server s) {
-    (void)hipSetDevice(s->device);
-    for (;;) {
-        std::vector<Req*> admit, done;
-        std::vector<Slot*> release;
-        {
-            std::unique_lock<std::mutex> lk(s->mu);
-            s->cv_io.wait(lk, [&] { return s->stop || !s->retired.empty() || !s->waiting.empty(); });
-            if (s->stop) return;
-            done.swap(s->retired);
-        }
-        for (Req* q : done) {
-            std::lock_guard<std::mutex> hk(s->hip_mu);
-            retire(s, q);
-        }
-        if (!done.empty()) s->cv_done.notify_all();
-        {
-            std::lock_guard<std::mutex> lk(s->mu);
-            admit = admit_locked(s, release);
-        }
-        std::vector<Req*> ok, failed;
-        {
-            std::lock_guard<std::mutex> hk(s->hip_mu);
-            for (Slot* sl : release) free_slot(sl);
-            for (Req* q : admit) {
-                q->status = prepare(s, q);
-                (q->status ? failed : ok).push_back(q);
-            }
-        }
-        if (!ok.empty()) {
-            std::lock_guard<std::mutex> lk(s->mu);
-            s->ready.insert(s->ready.end(), ok.begin(), ok.end());
-            s->cv_work.notify_all();
-        }
-        for (Req* q : failed) {
-            std::lock_guard<std::mutex> hk(s->hip_mu);
-            if (q->slot) {  // slot obtained, later preparation failed: drop it
-                Slot* sl = q->slot;
-                q->slot = nullptr;
-                free_slot(sl);
-            }
-            retire(s, q);
-        }
-        if (!failed.empty()) s->cv_done.notify_all();
-        // nothing admissible and nothing retired: wait for the next event
-        if (admit.empty() && done.empty()) {
-            std::unique_lock<std::mutex> lk(s->mu);
-            s->cv_io.wait(lk, [&] { return s->stop || !s->retired.empty(); });
-            if (s->stop) return;
-        }
+        if (keep.size() != s->active.size()) s->cv_done.notify_all();
+        s->active.swap(keep);
     }
 }
 
@@ -354,9 +217,7 @@ int flusi_server_create(int dtype, size_t hbm_budget, int max_chunk, flusi_serve
     s->max_chunk = max_chunk;
     hipError_t e = hipGetDevice(&s->device);
     if (e == hipSuccess) e = hipStreamCreateWithFlags(&s->stream, hipStreamNonBlocking);
-    if (e == hipSuccess) e = hipStreamCreateWithFlags(&s->io_stream, hipStreamNonBlocking);
     if (e != hipSuccess) {
-        if (s->stream) (void)hipStreamDestroy(s->stream);
         delete s;
         return set_error(FLUSI_EDEVICE, "server_create: %s", hipGetErrorString(e));
     }
@@ -364,13 +225,11 @@ int flusi_server_create(int dtype, size_t hbm_budget, int max_chunk, flusi_serve
     if (!rc) rc = flusi_ensemble_set_stream(s->ens, s->stream);
     if (rc) {
         if (s->ens) flusi_ensemble_destroy(s->ens);
-        (void)hipStreamDestroy(s->io_stream);
         (void)hipStreamDestroy(s->stream);
         delete s;
         return rc;
     }
     s->worker = std::thread(worker_main, s);
-    s->io = std::thread(io_main, s);
     *out = s;
     return FLUSI_OK;
 }
@@ -382,22 +241,14 @@ int flusi_server_destroy(flusi_server s) {
         s->stop = true;
     }
     s->cv_work.notify_all();
-    s->cv_io.notify_all();
     if (s->worker.joinable()) s->worker.join();
-    if (s->io.joinable()) s->io.join();
     (void)hipStreamSynchronize(s->stream);
-    (void)hipStreamSynchronize(s->io_stream);
-    // every request still on the device: leave the ensemble, give back its slot
-    std::vector<Slot*> slots = s->idle;
-    for (auto& kv : s->reqs) {
-        Req* q = kv.second;
+    for (Req* q : s->active) {
         if (q->member >= 0) flusi_ensemble_remove(s->ens, q->member);
-        if (q->slot) slots.push_back(q->slot);
-        delete q;
+        free_device(q);
     }
     flusi_ensemble_destroy(s->ens);
-    for (Slot* sl : slots) free_slot(sl);
-    (void)hipStreamDestroy(s->io_stream);
+    for (auto& kv : s->reqs) delete kv.second;
     (void)hipStreamDestroy(s->stream);
     delete s;
     return FLUSI_OK;
@@ -437,7 +288,7 @@ int flusi_server_submit(flusi_server s, const flusi_request* r, long long* id) {
         s->reqs[q->id] = q;
         s->waiting.push_back(q);
     }
-    s->cv_io.notify_all();
+    s->cv_work.notify_all();
     if (id) *id = q->id;
     return FLUSI_OK;
 }
