@@ -111,9 +111,10 @@ struct GroupRun {
     bool any_dyn = false;
     bool any_ff = false;      // some member is in free flight
     bool rk = false;          // RK4 integrator (single-plan runs)
-    // side stream for the per-level kinematics kernel (null: the kinematics run
+    // side stream for the kinematics kernel of the RK4 stages (null: they run
     // on `stream`): forked after the z-pass, joined before the x-pass, so they
-    // overlap the y-inverse, which does not read them
+    // overlap the y-inverse, which does not read them (the AB2 steps evaluate
+    // the kinematics inside the y-inverse launch instead)
     hipStream_t side = nullptr;
     hipEvent_t ev_z = nullptr, ev_k = nullptr;
     const void* tw = nullptr;   // y and z twiddles
@@ -431,16 +432,21 @@ struct Impl final : ImplBase {
     static int nwg_of(int v) { return v == 2 ? nwg<2>(0) : (v == 1 ? nwg<1>(0) : nwg<0>(0)); }
 
     // y-inverse of the 6 z-partial fields
+    // kin_par >= 0: the launch also evaluates the kinematics of time level
+    // kin_par (one extra workgroup per member, at the start of the grid)
     template <int V>
-    static void y_inverse_v(const GroupRun& g) {
+    static void y_inverse_v(const GroupRun& g, int kin_par) {
         const CX* w = static_cast<const CX*>(g.tw);
         constexpr int nb = nby<V>(6);
-        k_ypass<T, NX, N, +1, 0, V><<<(unsigned)(nb * g.nmem), NT, 0, g.stream>>>(g.mt, nb, w, 6, 0);
+        if (kin_par >= 0)
+            k_ypass<T, NX, N, +1, 2, V><<<(unsigned)((nb + 1) * g.nmem), NT, 0, g.stream>>>(g.mt, nb, w, 6, kin_par);
+        else
+            k_ypass<T, NX, N, +1, 0, V><<<(unsigned)(nb * g.nmem), NT, 0, g.stream>>>(g.mt, nb, w, 6, 0);
     }
-    static void y_inverse(const GroupRun& g) {
-        if (g.sched.y_inverse == 2) y_inverse_v<2>(g);
-        else if (g.sched.y_inverse == 1) y_inverse_v<1>(g);
-        else y_inverse_v<0>(g);
+    static void y_inverse(const GroupRun& g, int kin_par = -1) {
+        if (g.sched.y_inverse == 2) y_inverse_v<2>(g, kin_par);
+        else if (g.sched.y_inverse == 1) y_inverse_v<1>(g, kin_par);
+        else y_inverse_v<0>(g, kin_par);
     }
     // y-forward of 3 fields; with red set, nred_of(NX, N) extra workgroups per member
     // do the first-level reduction of the x-pass sums
@@ -520,7 +526,7 @@ struct Impl final : ImplBase {
     // time (c >= 0); on the side stream when the group has one.  Returns
     // whether the caller must join the side stream before the x-pass.
     static bool kin_launch(const GroupRun& g, int par, double c, hipError_t& err) {
-        const unsigned nbk = (unsigned)((g.nmem + 63) / 64);
+        const unsigned nbk = (unsigned)g.nmem;
         hipStream_t st = g.stream;
         if (g.side) {
             if (err == hipSuccess) err = hipEventRecord(g.ev_z, g.stream);
@@ -546,7 +552,7 @@ struct Impl final : ImplBase {
     int run_steps_rk(const GroupRun& g, int nsteps) {
         {
             PassScope ps(g.prof, PASS_KIN, g.stream);
-            k_prologue<<<(unsigned)((g.nmem + 63) / 64), 64, 0, g.stream>>>(g.mt, g.nmem);
+            k_prologue<<<(unsigned)g.nmem, 64, 0, g.stream>>>(g.mt, g.nmem);
         }
         {
             PassScope ps(g.prof, PASS_ZINV, g.stream);
@@ -589,7 +595,7 @@ struct Impl final : ImplBase {
         if (g.rk) return run_steps_rk(g, nsteps);
         {
             PassScope ps(g.prof, PASS_KIN, g.stream);
-            k_prologue<<<(unsigned)((g.nmem + 63) / 64), 64, 0, g.stream>>>(g.mt, g.nmem);
+            k_prologue<<<(unsigned)g.nmem, 64, 0, g.stream>>>(g.mt, g.nmem);
         }
         {
             PassScope ps(g.prof, PASS_ZINV, g.stream);
@@ -599,13 +605,11 @@ struct Impl final : ImplBase {
         for (int s = 0; s < nsteps; ++s) {
             const int par = s & 1;
             // kinematics of this time level (the prologue covers the first),
-            // overlapping the y-inverse when there is a side stream
-            const bool pend = (g.any_dyn && s > 0) ? kin_launch(g, par, -1.0, err) : false;
+            // evaluated by extra workgroups of the y-inverse
             {
                 PassScope ps(g.prof, PASS_YINV, g.stream);
-                y_inverse(g);
+                y_inverse(g, (g.any_dyn && s > 0) ? par : -1);
             }
-            kin_join(g, pend, err);
             {
                 PassScope ps(g.prof, PASS_X, g.stream);
                 xpass(g);
@@ -627,7 +631,7 @@ struct Impl final : ImplBase {
         // free flight: advance the body to the new current level
         if (g.any_ff) {
             PassScope ps(g.prof, PASS_KIN, g.stream);
-            k_kin_level<<<(unsigned)((g.nmem + 63) / 64), 64, 0, g.stream>>>(g.mt, g.nmem, nsteps & 1);
+            k_kin_level<<<(unsigned)g.nmem, 64, 0, g.stream>>>(g.mt, g.nmem, nsteps & 1);
         }
         if (err != hipSuccess) return set_error(FLUSI_EDEVICE, "step: %s", hipGetErrorString(err));
         return launch_check("step");
@@ -682,9 +686,9 @@ struct Impl final : ImplBase {
         g.twx = p.twx;
         g.sched = p.sched;
         g.stream = p.stream;
-        // the fork/join costs a few microseconds of event latency: worth it
-        // only where the y-inverse it overlaps is long (measured: +2% at 256^3,
-        // -10% at 128^3)
+        // RK4 stage kinematics on the side stream: the fork/join costs a few
+        // microseconds of event latency, worth it only where the y-inverse it
+        // overlaps is long
         if (N >= 192) {
             g.side = p.side;
             g.ev_z = p.ev_z;

@@ -1,6 +1,6 @@
 // Insect kinematics and mask evaluation (FP64), Sec. 2.2 and Sec. 3.
 //
-// The kinematics block is evaluated once per time level by one thread and
+// The kinematics block is evaluated once per time level by one workgroup and
 // read by every mask evaluation; the mask is evaluated pointwise inside the
 // physical-space pass (no chi / u_s arrays in HBM).
 #pragma once
@@ -39,31 +39,52 @@ struct WingCoef {
     double a[FLUSI_WING_MAX + 1], b[FLUSI_WING_MAX + 1];
 };
 
-// sin and cos of one angle, out of line: the kinematics evaluate some twenty
-// of them in a one-thread kernel, and one shared copy of the FP64 expansion
-// keeps that kernel's code (fetched cold every launch) short.  Returned by
-// value (registers), so callers keep their matrices in registers.
+// sin and cos of one angle, out of line: one shared copy of the FP64
+// expansion keeps the kinematics code (fetched cold every launch) short.
+// Returned by value (registers), so callers keep their matrices in registers.
 struct SinCos {
     double s, c;
 };
 __host__ __device__ __attribute__((noinline)) inline SinCos sin_cos(double x) { return SinCos{sin(x), cos(x)}; }
 
-__host__ __device__ inline void mat_rx(double a, double* M) {
-    const SinCos q = sin_cos(a);
+// Where the kinematics take their sines and cosines from: evaluated in place
+// (TrigEval), or looked up in a table that the lanes of a workgroup filled in
+// parallel beforehand, in the order the kinematics ask for them (TrigTable).
+// A table entry is used only when its argument is bitwise the one asked for,
+// so the result never depends on the table; a miss evaluates in place.
+struct TrigEval {
+    __host__ __device__ SinCos operator()(double x) { return sin_cos(x); }
+};
+struct TrigTable {
+    const double* arg;
+    const SinCos* val;
+    int n, i;  // entries; index of the next request
+    __device__ SinCos operator()(double x) {
+        const int j = i++;
+        if (j < n && __double_as_longlong(arg[j]) == __double_as_longlong(x)) return val[j];
+        return sin_cos(x);
+    }
+};
+
+template <class TR = TrigEval>
+__host__ __device__ inline void mat_rx(double a, double* M, TR&& tr = TR{}) {
+    const SinCos q = tr(a);
     const double c = q.c, s = q.s;
     M[0] = 1; M[1] = 0; M[2] = 0;
     M[3] = 0; M[4] = c; M[5] = s;
     M[6] = 0; M[7] = -s; M[8] = c;
 }
-__host__ __device__ inline void mat_ry(double a, double* M) {
-    const SinCos q = sin_cos(a);
+template <class TR = TrigEval>
+__host__ __device__ inline void mat_ry(double a, double* M, TR&& tr = TR{}) {
+    const SinCos q = tr(a);
     const double c = q.c, s = q.s;
     M[0] = c; M[1] = 0; M[2] = -s;
     M[3] = 0; M[4] = 1; M[5] = 0;
     M[6] = s; M[7] = 0; M[8] = c;
 }
-__host__ __device__ inline void mat_rz(double a, double* M) {
-    const SinCos q = sin_cos(a);
+template <class TR = TrigEval>
+__host__ __device__ inline void mat_rz(double a, double* M, TR&& tr = TR{}) {
+    const SinCos q = tr(a);
     const double c = q.c, s = q.s;
     M[0] = c; M[1] = s; M[2] = 0;
     M[3] = -s; M[4] = c; M[5] = 0;
@@ -112,8 +133,9 @@ __host__ __device__ inline void quat_mbody(const double* e, double* M) {
 }
 
 // Quaternion of roll psi, pitch beta, yaw gamma (Sec. 3.6).
-__host__ __device__ inline void quat_of_angles(double psi, double beta, double gam, double* e) {
-    const SinCos qp = sin_cos(0.5 * psi), qb = sin_cos(0.5 * beta), qg = sin_cos(0.5 * gam);
+template <class TR = TrigEval>
+__host__ __device__ inline void quat_of_angles(double psi, double beta, double gam, double* e, TR&& tr = TR{}) {
+    const SinCos qp = tr(0.5 * psi), qb = tr(0.5 * beta), qg = tr(0.5 * gam);
     const double cp = qp.c, sp = qp.s, cb = qb.c, sb = qb.s, cg = qg.c, sg = qg.s;
     e[0] = cp * cb * cg + sp * sb * sg;
     e[1] = sp * cb * cg - cp * sb * sg;
@@ -149,14 +171,16 @@ __host__ __device__ inline void solid_rhs(const flusi_insect& in, const double* 
 // sinusoid, a Fourier series a_0/2 + sum a_i cos(2 pi i f t) + b_i sin(2 pi i f t),
 // or periodic cubic Hermite interpolation of values and rates at kin_n
 // equidistant times of a period.
-__host__ __device__ inline void wing_angle_values(const flusi_insect& in, double t, double* ang, double* rate) {
+template <class TR = TrigEval>
+__host__ __device__ inline void wing_angle_values(const flusi_insect& in, double t, double* ang, double* rate,
+                                                  TR&& tr = TR{}) {
     if (in.kin_type == FLUSI_KIN_FOURIER) {
         for (int a = 0; a < 3; ++a) {
             double v = 0.5 * in.kin_coef[a][0][0], dv = 0.0;
             for (int i = 1; i <= in.kin_n; ++i) {
                 const double w = 2.0 * M_PI * i * in.freq;
                 const double ai = in.kin_coef[a][0][i], bi = in.kin_coef[a][1][i];
-                const SinCos q = sin_cos(w * t);
+                const SinCos q = tr(w * t);
                 const double c = q.c, sn = q.s;
                 v += ai * c + bi * sn;
                 dv += w * (-ai * sn + bi * c);
@@ -187,18 +211,70 @@ __host__ __device__ inline void wing_angle_values(const flusi_insect& in, double
         const double* P[3] = {in.phi, in.alpha, in.theta};
         for (int a = 0; a < 3; ++a) {
             const double ph = om * t + P[a][2];
-            const SinCos q = sin_cos(ph);
+            const SinCos q = tr(ph);
             ang[a] = P[a][0] + P[a][1] * q.c;
             rate[a] = -P[a][1] * om * q.s;
         }
     }
 }
 
+// Arguments of the sines and cosines that compute_kin evaluates, in its
+// order: the body rotations and quaternion half angles (prescribed body
+// motion), the angle series, then per wing the stroke plane, the half turn
+// (right wing) and the three wing angles.  The wing angles come from the
+// series: fill == 0 writes every other entry and flags these in dep; fill ==
+// 1 writes only these, from the series values ang.  Returns the count (at
+// most KIN_TRIG_MAX).
+constexpr int KIN_TRIG_MAX = 6 + 3 * FLUSI_KIN_MAX + 9;
+__device__ inline int kin_trig_args(const flusi_insect& in, double t, bool pose, int fill, const double* ang,
+                                    double* arg, unsigned char* dep) {
+    int n = 0;
+    auto put = [&](double x, bool wing_angle) {
+        if (n >= KIN_TRIG_MAX) return;  // only for a description the host would reject
+        if (wing_angle == (fill == 1)) arg[n] = x;
+        if (fill == 0) dep[n] = wing_angle ? 1 : 0;
+        ++n;
+    };
+    if (!pose) {
+        const double psi = in.psi + in.psi_dot * t;
+        const double beta = in.beta + in.beta_dot * t;
+        const double gam = in.gamma + in.gamma_dot * t;
+        put(psi, false);
+        put(beta, false);
+        put(gam, false);
+        put(0.5 * psi, false);
+        put(0.5 * beta, false);
+        put(0.5 * gam, false);
+    }
+    if (!in.wings) return n;
+    if (in.kin_type == FLUSI_KIN_FOURIER) {
+        for (int a = 0; a < 3; ++a)
+            for (int i = 1; i <= in.kin_n; ++i) {
+                const double w = 2.0 * M_PI * i * in.freq;
+                put(w * t, false);
+            }
+    } else if (in.kin_type != FLUSI_KIN_HERMITE) {
+        const double om = 2.0 * M_PI * in.freq;
+        const double* P[3] = {in.phi, in.alpha, in.theta};
+        for (int a = 0; a < 3; ++a) put(om * t + P[a][2], false);
+    }
+    for (int s = 0; s < 2; ++s) {
+        const double sg = s == 0 ? 1.0 : -1.0;
+        put(in.eta_stroke, false);
+        if (s == 1) put(M_PI, false);
+        put(fill ? sg * ang[1] : 0.0, true);
+        put(fill ? -ang[2] : 0.0, true);
+        put(fill ? sg * ang[0] : 0.0, true);
+    }
+    return n;
+}
+
 // Kinematics at time t (Sec. 3.1 and 3.3).  dx is the grid spacing.  pose
 // (13 values: x_cntr, u_cntr, eps, Omega^(b)) replaces the prescribed body
 // motion in free flight (Sec. 3.6); null for a tethered body.
+template <class TR = TrigEval>
 __host__ __device__ __forceinline__ void compute_kin(const flusi_insect& in, double t, double dx, Kin& k,
-                                                     const double* pose = nullptr) {
+                                                     const double* pose = nullptr, TR&& tr = TR{}) {
     if (pose) {
         for (int i = 0; i < 3; ++i) {
             k.xc[i] = pose[i];
@@ -212,9 +288,9 @@ __host__ __device__ __forceinline__ void compute_kin(const flusi_insect& in, dou
         const double beta = in.beta + in.beta_dot * t;
         const double gam = in.gamma + in.gamma_dot * t;
         double Rx_[9], Ry_[9], Rz_[9], T1[9];
-        mat_rx(psi, Rx_);
-        mat_ry(beta, Ry_);
-        mat_rz(gam, Rz_);
+        mat_rx(psi, Rx_, tr);
+        mat_ry(beta, Ry_, tr);
+        mat_rz(gam, Rz_, tr);
         mat_mul(Rx_, Ry_, T1);
         mat_mul(T1, Rz_, k.Mb);
         // body angular velocity: Rz^T[(0,0,gd) + Ry^T[(0,bd,0) + Rx^T (pd,0,0)]], then to body frame
@@ -225,7 +301,7 @@ __host__ __device__ __forceinline__ void compute_kin(const flusi_insect& in, dou
         v[2] += in.gamma_dot;
         mat_tvec(Rz_, v, w);
         mat_vec(k.Mb, w, k.omb);
-        quat_of_angles(psi, beta, gam, k.eps);
+        quat_of_angles(psi, beta, gam, k.eps, tr);
         for (int i = 0; i < 3; ++i) {
             k.xc[i] = in.x_cntr[i];
             k.uc[i] = in.u_cntr[i];
@@ -304,21 +380,21 @@ __host__ __device__ __forceinline__ void compute_kin(const flusi_insect& in, dou
         return;
     }
     double ang[3], rate[3];
-    wing_angle_values(in, t, ang, rate);
+    wing_angle_values(in, t, ang, rate, tr);
     const double phi0 = ang[0], dphi0 = rate[0], al0 = ang[1], dal0 = rate[1], th = ang[2], dth = rate[2];
     for (int s = 0; s < 2; ++s) {
         const double sg = s == 0 ? 1.0 : -1.0;  // right wing: alpha and phi mirrored
         const double phi = sg * phi0, dphi = sg * dphi0, al = sg * al0, dal = sg * dal0;
         double Ms[9], Mw[9], A[9], B[9], C[9];
-        mat_ry(in.eta_stroke, Ms);
+        mat_ry(in.eta_stroke, Ms, tr);
         if (s == 1) {
             double Rpi[9];
-            mat_rx(M_PI, Rpi);
+            mat_rx(M_PI, Rpi, tr);
             mat_mul(Rpi, Ms, Ms);
         }
-        mat_ry(al, A);
-        mat_rz(-th, B);
-        mat_rx(phi, C);
+        mat_ry(al, A, tr);
+        mat_rz(-th, B, tr);
+        mat_rx(phi, C, tr);
         mat_mul(A, B, Mw);
         mat_mul(Mw, C, Mw);
         mat_mul(Mw, Ms, k.Mws[s]);

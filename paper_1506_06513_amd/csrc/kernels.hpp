@@ -252,6 +252,124 @@ __global__ __launch_bounds__(NT) void k_colfft(const cx<T>* in, cx<T>* out, int 
                                       tile % nbx, tw, buf);
 }
 
+// Kinematics of member m and its two mask-evaluation blocks, by one wave (64
+// lanes).  The lanes stage the body description in LDS (one round trip
+// instead of a chain of dependent loads) and evaluate the sines and cosines in
+// parallel, in two rounds: the angle series and fixed angles, then the wing
+// angles that the series give.  One lane assembles the kinematics and the
+// blocks in LDS from those values; all lanes store them.
+// Time: slot p's time (at == false), or t_at (RK4 stages; no free flight).
+// In free flight the body pose is the free-flight state of the level: taken
+// from the tethered kinematics on the first free-flight step, or advanced by
+// the AB2 step that the previous step's diagnostics left pending (Alg. 1 step
+// (f); the quaternion is renormalized).
+struct KinShared {
+    flusi_insect in;
+    Kin k;
+    KinT<float> kf;
+    KinT<double> kd;
+    double arg[KIN_TRIG_MAX];
+    SinCos val[KIN_TRIG_MAX];
+    unsigned char dep[KIN_TRIG_MAX];
+    double y[13], f[13];
+    double t;
+    int n, st;
+};
+static_assert(sizeof(flusi_insect) % 8 == 0 && sizeof(Kin) % 8 == 0 && sizeof(KinT<float>) % 8 == 0 &&
+                  sizeof(KinT<double>) % 8 == 0 && offsetof(StateHdr, kin) % 8 == 0 &&
+                  offsetof(StateHdr, kf) % 8 == 0 && offsetof(StateHdr, kd) % 8 == 0,
+              "kinematics blocks are copied in 8-byte words");
+
+// nbytes (a multiple of 8; both ends 8-byte aligned) copied by the 64 lanes
+// of a wave.
+__device__ __forceinline__ void wg_copy8(void* dst, const void* src, int nbytes) {
+    auto* d = static_cast<unsigned long long*>(dst);
+    const auto* q = static_cast<const unsigned long long*>(src);
+    for (int i = threadIdx.x & 63; i < nbytes / 8; i += 64) d[i] = q[i];
+}
+
+__device__ __forceinline__ void kin_update(const Member& m, int p, bool at, double t_at, KinShared& s) {
+    const int lane = threadIdx.x & 63;
+    wg_copy8(&s.in, m.ins, (int)sizeof(flusi_insect));
+    wave_sync();
+    const flusi_insect& in = s.in;
+    StateHdr* h = m.hdr;
+    Slot& sl = h->slot[p];
+    if (lane == 0) {
+        int st = 0;
+        if (!at && in.free_flight) {
+            st = sl.ff_state;
+            if (st != 0) {
+                for (int i = 0; i < 13; ++i) s.y[i] = sl.ff[i];
+                if (st == 2) {
+                    double F[3], mm[3], fp[13];
+                    for (int i = 0; i < 3; ++i) {
+                        F[i] = sl.ff_F[i];
+                        mm[i] = sl.ff_m[i];
+                    }
+                    const double w0 = sl.ff_w[0], w1 = sl.ff_w[1];
+                    const int hp = sl.ff_have_prev;
+                    for (int i = 0; i < 13; ++i) fp[i] = sl.ff_f[i];
+                    solid_rhs(in, s.y, F, mm, s.f);
+                    for (int i = 0; i < 13; ++i) s.y[i] += hp ? w0 * s.f[i] + w1 * fp[i] : w0 * s.f[i];
+                    const double q = 1.0 / sqrt(s.y[6] * s.y[6] + s.y[7] * s.y[7] + s.y[8] * s.y[8] + s.y[9] * s.y[9]);
+                    for (int i = 6; i < 10; ++i) s.y[i] *= q;
+                }
+            }
+        }
+        s.t = at ? t_at : sl.t;
+        s.st = st;
+        s.n = kin_trig_args(in, s.t, st != 0, 0, nullptr, s.arg, s.dep);
+    }
+    wave_sync();
+    const int n = s.n;
+    for (int j = lane; j < n; j += 64)
+        if (!s.dep[j]) s.val[j] = sin_cos(s.arg[j]);
+    wave_sync();
+    if (in.wings) {
+        if (lane == 0) {
+            double ang[3], rate[3];
+            wing_angle_values(in, s.t, ang, rate, TrigTable{s.arg, s.val, n, s.st != 0 ? 0 : 6});
+            kin_trig_args(in, s.t, s.st != 0, 1, ang, s.arg, s.dep);
+        }
+        wave_sync();
+        for (int j = lane; j < n; j += 64)
+            if (s.dep[j]) s.val[j] = sin_cos(s.arg[j]);
+        wave_sync();
+    }
+    if (lane == 0) {
+        const int st = s.st;
+        // assembled in LDS: the blocks never occupy registers
+        Kin& k = s.k;
+        compute_kin(in, s.t, m.dx, k, st != 0 ? s.y : nullptr, TrigTable{s.arg, s.val, n, 0});
+        k.rtab = m.rtab;
+        k.rtab32 = m.rtab32;
+        kin_cast<float>(k, s.kf);
+        kin_cast<double>(k, s.kd);
+        if (in.free_flight && !at) {
+            if (st == 0) {
+                for (int i = 0; i < 3; ++i) {
+                    s.y[i] = k.xc[i];
+                    s.y[3 + i] = k.uc[i];
+                    s.y[10 + i] = k.omb[i];
+                }
+                for (int i = 0; i < 4; ++i) s.y[6 + i] = k.eps[i];
+            }
+            if (st != 1)
+                for (int i = 0; i < 13; ++i) sl.ff[i] = s.y[i];
+            if (st == 2)
+                for (int i = 0; i < 13; ++i) sl.ff_f[i] = s.f[i];
+            if (st == 0) sl.ff_have_prev = 0;
+            if (st == 2) sl.ff_have_prev = 1;
+            sl.ff_state = 1;
+        }
+    }
+    wave_sync();
+    wg_copy8(&h->kin, &s.k, (int)sizeof(Kin));
+    wg_copy8(&h->kf, &s.kf, (int)sizeof(KinT<float>));
+    wg_copy8(&h->kd, &s.kd, (int)sizeof(KinT<double>));
+}
+
 // y passes of the stepping schedule over a member table.
 //   DIR = +1 (y-inverse): 6 z-partial fields bufA [f][z][ky'][kx] (pitch Qp per
 //            z) -> bufB [f][z][y][kx] (pitch KPp per y)
@@ -259,18 +377,39 @@ __global__ __launch_bounds__(NT) void k_colfft(const cx<T>* in, cx<T>* out, int 
 // Each member has nbx*nf column tiles followed by the extra workgroups:
 //   EXTRA 1: nred_of(NX, N) workgroups reduce the x-pass sums (first level)
 // nwg: x-pass workgroups per member (records of the first-level reduction).
+// EXTRA 2 (y-inverse): the grid starts with one workgroup per member whose
+// first wave evaluates the member's kinematics of time level nwg (members
+// whose kinematics change with time), beside the column tiles: the y-inverse
+// does not read them, the x-pass after it does.  That path is held to the
+// register budget of four waves per SIMD, which the column tiles' LDS allows
+// at most anyway for the larger tiles.
 // nfwd: forward fields per member (3, or 6 when a member of the launch has the
 // vorticity sponge; members without it skip fields 3..5).
 template <typename T, int NX, int N, int DIR, int EXTRA, int V>
-__global__ __launch_bounds__(NT) void k_ypass(const Member* __restrict__ mt, int per, const cx<T>* __restrict__ tw,
-                                              int nfwd, int nwg) {
+__global__ __launch_bounds__(NT, EXTRA == 2 ? 4 : 1) void k_ypass(const Member* __restrict__ mt, int per,
+                                                                  const cx<T>* __restrict__ tw, int nfwd, int nwg) {
     using G = Geo<T, NX, N>;
     constexpr int KP = G::KP, KPp = G::KPp, Qp = G::Qp;
     constexpr int C = cols_of(N, V);
     constexpr int nbx = (N * KP + C - 1) / C;
+    constexpr size_t BUF = sizeof(cx<T>) * C * cm_stride(N);
+    constexpr size_t LDS = EXTRA == 2 && sizeof(KinShared) > BUF ? sizeof(KinShared) : BUF;
     const int nf = DIR > 0 ? 6 : nfwd;
-    __shared__ cx<T> buf[C * cm_stride(N)];
-    const int lin = xcd_tile(blockIdx.x, gridDim.x);
+    __shared__ __align__(16) unsigned char lds[LDS];
+    cx<T>* buf = reinterpret_cast<cx<T>*>(lds);
+    int bid = blockIdx.x, nb = gridDim.x;
+    if constexpr (EXTRA == 2) {
+        const int nmem = nb / (per + 1);
+        if (bid < nmem) {
+            const Member& m = mt[bid];
+            if (threadIdx.x < 64 && m.dyn && !*gview(&m.hdr->status))
+                kin_update(m, nwg, false, 0.0, *reinterpret_cast<KinShared*>(lds));
+            return;
+        }
+        bid -= nmem;
+        nb -= nmem;
+    }
+    const int lin = xcd_tile(bid, nb);
     const Member& m = mt[lin / per];
     const int tile = lin % per;
     if (*gview(&m.hdr->status)) return;
@@ -1020,117 +1159,38 @@ __device__ inline void reduce_scalars(const double* __restrict__ partial2, doubl
     }
 }
 
-// Kinematics of time level p of member m and its mask-evaluation blocks (one
-// thread).  Everything is computed in registers from a register copy of the
-// body description and stored once: interleaving loads of the description and
-// stores of the block in global memory would serialize on memory round trips.
-// In free flight the body pose is the free-flight state of the level: taken
-// from the tethered kinematics on the first free-flight step, or advanced by
-// the AB2 step that the previous step's diagnostics left pending (Alg. 1 step
-// (f); the quaternion is renormalized).
-__device__ __forceinline__ void kin_update(const Member& m, int p) {
-    // the description is read in place (it holds the series coefficients);
-    // all loads come before the stores below
-    const flusi_insect& in = *m.ins;
-    StateHdr* h = m.hdr;
-    Slot& sl = h->slot[p];
-    const double t = sl.t;
-    Kin k;
-    double y[13], f[13];
-    int st = 0;
-    if (!in.free_flight) {
-        compute_kin(in, t, m.dx, k);
-    } else {
-        st = sl.ff_state;
-        if (st == 0) {
-            compute_kin(in, t, m.dx, k);
-            for (int i = 0; i < 3; ++i) {
-                y[i] = k.xc[i];
-                y[3 + i] = k.uc[i];
-                y[10 + i] = k.omb[i];
-            }
-            for (int i = 0; i < 4; ++i) y[6 + i] = k.eps[i];
-        } else {
-            for (int i = 0; i < 13; ++i) y[i] = sl.ff[i];
-            if (st == 2) {
-                double F[3], mm[3], fp[13];
-                for (int i = 0; i < 3; ++i) {
-                    F[i] = sl.ff_F[i];
-                    mm[i] = sl.ff_m[i];
-                }
-                const double w0 = sl.ff_w[0], w1 = sl.ff_w[1];
-                const int hp = sl.ff_have_prev;
-                for (int i = 0; i < 13; ++i) fp[i] = sl.ff_f[i];
-                solid_rhs(in, y, F, mm, f);
-                for (int i = 0; i < 13; ++i) y[i] += hp ? w0 * f[i] + w1 * fp[i] : w0 * f[i];
-                const double q = 1.0 / sqrt(y[6] * y[6] + y[7] * y[7] + y[8] * y[8] + y[9] * y[9]);
-                for (int i = 6; i < 10; ++i) y[i] *= q;
-            }
-            compute_kin(in, t, m.dx, k, y);
-        }
-    }
-    k.rtab = m.rtab;
-    k.rtab32 = m.rtab32;
-    // the blocks are converted straight into the header, so that the three of
-    // them are never held in registers together
-    h->kin = k;
-    kin_cast<float>(k, h->kf);
-    kin_cast<double>(k, h->kd);
-    if (in.free_flight) {
-        if (st != 1)
-            for (int i = 0; i < 13; ++i) sl.ff[i] = y[i];
-        if (st == 2)
-            for (int i = 0; i < 13; ++i) sl.ff_f[i] = f[i];
-        if (st == 0) sl.ff_have_prev = 0;
-        if (st == 2) sl.ff_have_prev = 1;
-        sl.ff_state = 1;
-    }
-}
-
-// Start of a stepping call, one thread per member: make slot 0 current and
+// Start of a stepping call, one workgroup per member: make slot 0 current and
 // evaluate the kinematics of the current time level.
 static __global__ __launch_bounds__(64) void k_prologue(const Member* __restrict__ mt, int nmem) {
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= nmem) return;
-    const Member& m = mt[i];
+    if ((int)blockIdx.x >= nmem) return;
+    const Member& m = mt[blockIdx.x];
     StateHdr* hdr = m.hdr;
-    if (hdr->cur == 1) {
+    if (threadIdx.x == 0 && hdr->cur == 1) {
         hdr->slot[0] = hdr->slot[1];
         hdr->cur = 0;
     }
-    if (m.nc > 0 && !hdr->status) kin_update(m, 0);
+    __syncthreads();
+    __shared__ KinShared ks;
+    if (m.nc > 0 && !hdr->status) kin_update(m, 0, false, 0.0, ks);
 }
 
 // Kinematics of time level p of every member whose kinematics change with
-// time (one thread per member), before the pass that reads them; after the
+// time (one workgroup per member), before the pass that reads them; after the
 // last step of a call it completes the pending free-flight advance.
 static __global__ __launch_bounds__(64) void k_kin_level(const Member* __restrict__ mt, int nmem, int p) {
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= nmem) return;
-    const Member& m = mt[i];
-    if (m.dyn && !m.hdr->status) kin_update(m, p);
+    if ((int)blockIdx.x >= nmem) return;
+    const Member& m = mt[blockIdx.x];
+    __shared__ KinShared ks;
+    if (m.dyn && !m.hdr->status) kin_update(m, p, false, 0.0, ks);
 }
 
-// Kinematics at time t (no free flight), converted into the header's blocks.
-__device__ __forceinline__ void kin_update_at(const Member& m, double t) {
-    const flusi_insect& in = *m.ins;
-    StateHdr* h = m.hdr;
-    Kin k;
-    compute_kin(in, t, m.dx, k);
-    k.rtab = m.rtab;
-    k.rtab32 = m.rtab32;
-    h->kin = k;
-    kin_cast<float>(k, h->kf);
-    kin_cast<double>(k, h->kd);
-}
-
-// RK4 stage kinematics (one thread per moving member): time t^n + c*dt, with
-// t^n in slot p and dt in the slot the step's first stage wrote.
+// RK4 stage kinematics (one workgroup per moving member): time t^n + c*dt,
+// with t^n in slot p and dt in the slot the step's first stage wrote.
 static __global__ __launch_bounds__(64) void k_kin_stage(const Member* __restrict__ mt, int nmem, int p, double c) {
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= nmem) return;
-    const Member& m = mt[i];
-    if (m.dyn && !m.hdr->status) kin_update_at(m, m.hdr->slot[p].t + c * m.hdr->slot[1 - p].rk_dt);
+    if ((int)blockIdx.x >= nmem) return;
+    const Member& m = mt[blockIdx.x];
+    __shared__ KinShared ks;
+    if (m.dyn && !m.hdr->status) kin_update(m, p, true, m.hdr->slot[p].t + c * m.hdr->slot[1 - p].rk_dt, ks);
 }
 
 // Free-flight state of the current time level of a state (one thread).
