@@ -43,6 +43,22 @@ METRIC = "Mpoint-steps/s (AB2 RHS) FP32 vs FP64 at stated err; p50/p99 solve lat
 HBM_PEAK_GBS = 8000.0
 
 
+def x_rows(nx: int, cbytes: int, variant: int = 0) -> int:
+    """Rows per x-pass workgroup (the kernels' rows_x): 3*rows*nx ~ 3072 complex
+    values, halved per variant, at least 2, except one row where two rows of
+    nine columns would pass 150 KiB of LDS, or for the smaller variants of rows
+    of 1024 points or more."""
+    c, p = 1024 // nx, 2
+    while p * 2 <= c:
+        p *= 2
+    p >>= variant
+    if p < 2:
+        p = 1 if (variant > 0 and nx >= 1024) else 2
+    if p == 2 and 9 * (nx + nx // 16 + 1) * cbytes > 150 * 1024:
+        p = 1
+    return p
+
+
 def pass_bytes(n: int, cbytes: int, split_z: bool, x_variant: int = 0, nx: int | None = None) -> dict:
     """Algorithmic HBM bytes per launch of each pass of the pruned schedule on
     an nx x n x n grid (nx = n by default).
@@ -57,10 +73,7 @@ def pass_bytes(n: int, cbytes: int, split_z: bool, x_variant: int = 0, nx: int |
     KP, M = (nx - 1) // 3 + 1, 2 * K + 1
     Q = M * KP
     s = cbytes
-    rows = max(2, 1 << int(math.log2(max(1, 1024 // nx))))
-    if x_variant and rows > 2:
-        rows //= 2
-    nwg = n * n // rows
+    nwg = n * n // x_rows(nx, cbytes, x_variant)
     zup = (3 * n * Q + 4 * 3 * M * Q) * s
     return {
         "z_inverse": (3 * M * Q + 6 * n * Q) * s,
@@ -106,6 +119,12 @@ def counter_traffic(workload: str, kernel_prefix: str):
     return None
 
 
+def moving_body(ins) -> bool:
+    """Whether a body's kinematics change with time (evaluated every step)."""
+    return bool(ins) and bool(ins.get("wings") or ins.get("free_flight") or ins.get("psi_dot")
+                               or ins.get("beta_dot") or ins.get("gamma_dot"))
+
+
 def kernel_of_pass(pass_name: str, n: int, real: str, sched: dict, nc: int, dyn: bool, nx: int | None = None) -> str:
     """Kernel name (as rocprofv3 prints it) of a pass under a schedule on an
     nx x n x n grid (nx = n: cubic)."""
@@ -115,7 +134,7 @@ def kernel_of_pass(pass_name: str, n: int, real: str, sched: dict, nc: int, dyn:
         "z_pass": f"k_zpass<{real}, {g}, {2 if split else 1}, {sched['z_pass']}, false>",
         "z_inverse": f"k_zpass<{real}, {g}, 3, {sched['z_pass']}, false>",
         "x_pass": f"k_xpass<{real}, {g}, {nc}, {sched['x_pass']}, false>",
-        "y_inverse": f"k_ypass<{real}, {g}, 1, 0, {sched['y_inverse']}>",
+        "y_inverse": f"k_ypass<{real}, {g}, 1, {2 if dyn else 0}, {sched['y_inverse']}>",
         "y_forward": f"k_ypass<{real}, {g}, -1, 1, {sched['y_forward']}>",
     }[pass_name]
 
@@ -188,6 +207,25 @@ def build_workload(name: str):
     raise SystemExit(f"unknown workload {name}")
 
 
+# --schedule-file: schedules chosen by the first run are stored and reused by
+# later runs (profiler passes then see the same kernels as the timed run)
+SCHED_PIN = {"path": None, "data": {}}
+
+
+def pinned_schedule(key, apply, choose):
+    """The schedule stored under key (applied with apply), else choose() and store it."""
+    d = SCHED_PIN["data"]
+    if SCHED_PIN["path"] and key in d:
+        apply(d[key])
+        return d[key]
+    s = choose()
+    if SCHED_PIN["path"]:
+        d[key] = s
+        with open(SCHED_PIN["path"], "w") as f:
+            json.dump(d, f, indent=1, sort_keys=True)
+    return s
+
+
 def gpu_run(F, torch, wl, dtype, steps, warmup, tune=True, sponge=None, integrator="ab2"):
     P = F.Plan(wl["n"], wl["L"], wl["nu"], wl["eta"], dtype, nx=wl.get("nx"))
     if sponge:
@@ -201,7 +239,11 @@ def gpu_run(F, torch, wl, dtype, steps, warmup, tune=True, sponge=None, integrat
     st = P.new_state(u0)
     if warmup:
         P.step(st, warmup, wl["insect"], **kw)
-    sched = P.autotune(st, wl["insect"], reps=10, **kw) if tune else P.schedule()
+    ins = wl["insect"] or {}
+    key = (f"{wl.get('nx') or wl['n']}x{wl['n']}|{dtype}|{integrator}|sponge{int(bool(sponge))}|"
+           f"wings{int(bool(ins.get('wings')))}|body{int(bool(ins))}|ff{int(bool(ins.get('free_flight')))}")
+    sched = pinned_schedule(key, P.set_schedule,
+                            lambda: P.autotune(st, wl["insect"], reps=10, **kw) if tune else P.schedule())
     torch.cuda.synchronize()
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     t0 = time.perf_counter()
@@ -237,11 +279,17 @@ def ensemble_run(F, torch, count=48, steps=200, chunk=20, seed=1, tune=True):
         ens.add(P, st, sp["insect"], cfl=0.1)
         members.append((P, st, sp))
     nmem, ngroups = ens.size()
-    if tune:
+    keys = sorted({f"ensemble|{sp['n']}" for sp in specs})
+    if SCHED_PIN["path"] and all(k in SCHED_PIN["data"] for k in keys):
+        for P, st, sp in members:
+            P.set_schedule(SCHED_PIN["data"][f"ensemble|{sp['n']}"])
+    elif tune:
         ens.autotune(reps=5)
     scheds = {}
     for P, st, sp in members:
         scheds.setdefault(str(sp["n"]), P.schedule())
+    for n, sc in scheds.items():
+        pinned_schedule(f"ensemble|{n}", lambda s_: None, lambda: sc)
     ens.step(chunk, graph=True)  # capture + warm-up
     torch.cuda.synchronize()
     pts = sum(float(sp["n"]) ** 3 for sp in specs)
@@ -409,7 +457,7 @@ def measure(F, torch, name, wl, steps, warmup, tune):
         "roofline": {"bound": "hbm", "kernel": dom, "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
                      "traffic": counter_traffic(name, kernel_of_pass(dom, n, "float", r["schedule"], nc,
-                                                                     dyn=bool(ins and ins.get("wings")), nx=nx)),
+                                                                     dyn=moving_body(ins), nx=nx)),
                      "algorithmic_bytes": int(pb[dom])},
         "step_roofline": {"bytes_per_step": sb, "bytes_per_point_step": round(sb / pts, 2),
                           "achieved_gbs": round(sb / (res["f32"]["ev_ms"] / steps / 1e3) / 1e9, 1),
@@ -421,6 +469,205 @@ def measure(F, torch, name, wl, steps, warmup, tune):
         "last_diag_f32": {"t": res["f32"]["diag"][0], "dt": res["f32"]["diag"][1],
                           "umax": res["f32"]["diag"][2], "drag": res["f32"]["diag"][4]},
     }
+
+
+# ---------------------------------------------------------------------------
+# Profile summaries: rocprofv3 output of one workload -> profiles/<workload>.md
+# ---------------------------------------------------------------------------
+PROFILE_STEPS = {"box1152": (10, 4), "ensemble48": (100, 20)}  # (trace steps, counter steps); default (100, 20)
+SQ_SETS = ("SQ_WAVES SQ_INSTS_VALU SQ_INSTS_SALU SQ_INSTS_LDS SQ_WAVE_CYCLES SQ_BUSY_CYCLES SQ_LDS_BANK_CONFLICT "
+           "SQ_ACTIVE_INST_VALU",
+           "SQ_WAVES SQ_ACTIVE_INST_LDS SQ_WAIT_INST_LDS SQ_ACTIVE_INST_ANY SQ_WAIT_INST_ANY SQ_INSTS_VMEM_RD "
+           "SQ_INSTS_VMEM_WR SQ_INSTS_VALU")
+
+
+def profile_commands(w: str, d: str = "gpurun_out/prof") -> list:
+    """rocprofv3 command lines behind a workload's summary (run from the
+    repository root, in this order: the trace run writes the schedule file
+    that the counter runs reuse)."""
+    s1, s2 = PROFILE_STEPS.get(w, (100, 20))
+    skip = "--no-cpu --no-sphere --no-ensemble --no-serve --no-sponge --no-freeflight --no-rk4 --no-box"
+    a = {"ensemble48": "--workload ensemble48", "box1152": f"--workload box1152 --warmup 2 {skip}"}.get(
+        w, f"--workload {w} --warmup 5 {skip}")
+    sf = f"--schedule-file {d}/sched_{w}.json"
+    cmds = [f"rocprofv3 --kernel-trace --stats --output-format csv -d {d}/trace_{w} -o run -- "
+            f"python3 bench.py {a} --steps {s1} {sf}"]
+    for tag, ctr in (("fetch", "FETCH_SIZE"), ("write", "WRITE_SIZE")):
+        cmds.append(f"rocprofv3 --pmc {ctr} --output-format csv -d {d}/{tag}_{w} -o run -- "
+                    f"python3 bench.py {a} --steps {s2} {sf}")
+    if w in ("insect256", "sphere128"):
+        for i, ctr in enumerate(SQ_SETS):
+            cmds.append(f"rocprofv3 --pmc {ctr} --output-format csv -d {d}/sq{i + 1}_{w} -o run -- "
+                        f"python3 bench.py {a} --steps {s2} {sf}")
+    for tag, ctr in (("copy_fetch", "FETCH_SIZE"), ("copy_write", "WRITE_SIZE")):
+        cmds.append(f"rocprofv3 --pmc {ctr} --output-format csv -d {d}/{tag} -o run -- "
+                    f"python3 bench.py --copy-calibration")
+    cmds.append(f"python3 bench.py --summarize {d} --workload {w} > profiles/{w}.md")
+    return cmds
+
+
+def short_kernel(name: str) -> str:
+    """Kernel name without return type, namespace and parameter list."""
+    import re
+    name = re.sub(r"^void ", "", name.strip()).replace("flusi::", "")
+    depth = 0
+    for i, ch in enumerate(name):
+        depth += ch == "<"
+        depth -= ch == ">"
+        if ch == "(" and depth == 0:
+            return name[:i]
+    return name
+
+
+def alg_bytes(kernel: str):
+    """Algorithmic HBM bytes per member of a launch of a stepping kernel (the
+    model of pass_bytes), or None for kernels outside the step."""
+    import re
+    m = re.match(r"(k_xpass|k_ypass|k_zpass)<(float|double), (\d+), (\d+), (-?\d+), (-?\d+), (\w+)>", kernel)
+    if not m:
+        return None
+    fam, real, nx, n, a, b, c = m.groups()
+    nx, n, a, b = int(nx), int(n), int(a), int(b)
+    cb = 8 if real == "float" else 16
+    if fam == "k_xpass":
+        return None if c == "true" else pass_bytes(n, cb, False, x_variant=b, nx=nx)["x_pass"]
+    if fam == "k_ypass":
+        return pass_bytes(n, cb, False, nx=nx)["y_inverse" if a == 1 else "y_forward"]
+    if a in (1, 2):
+        return pass_bytes(n, cb, split_z=(a == 2), nx=nx)["z_pass"]
+    if a == 3:
+        return pass_bytes(n, cb, False, nx=nx)["z_inverse"]
+    return None
+
+
+def _rows(path: str):
+    import csv
+    with open(path) as f:
+        return list(csv.DictReader(f))
+
+
+def summarize(d: str, w: str) -> str:
+    """Markdown summary of the rocprofv3 runs of workload w under directory d."""
+    from collections import defaultdict
+
+    def wg(r, g="Grid_Size", b="Workgroup_Size"):
+        gs = int(r.get(g) or r.get(g + "_X"))
+        return gs // max(1, int(r.get(b) or r.get(b + "_X")))
+
+    def calib(tag, ctr):
+        v = [float(r["Counter_Value"]) for r in _rows(f"{d}/{tag}/run_counter_collection.csv")
+             if r["Kernel_Name"].startswith("__amd_rocclr_copyBuffer") and r["Counter_Name"] == ctr
+             and float(r["Counter_Value"]) > 1e5]
+        return sum(v) / len(v), (1 << 30) / 1024 / (sum(v) / len(v))
+
+    cf, sf = calib("copy_fetch", "FETCH_SIZE")
+    cw, sw = calib("copy_write", "WRITE_SIZE")
+    trace = defaultdict(list)
+    for r in _rows(f"{d}/trace_{w}/run_kernel_trace.csv"):
+        trace[(short_kernel(r["Kernel_Name"]), wg(r))].append((int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) / 1e3)
+    ctr = defaultdict(lambda: defaultdict(list))
+    for tag in ("fetch", "write", "sq1", "sq2"):
+        p = f"{d}/{tag}_{w}/run_counter_collection.csv"
+        if os.path.exists(p):
+            for r in _rows(p):
+                ctr[(short_kernel(r["Kernel_Name"]), wg(r))][r["Counter_Name"]].append(float(r["Counter_Value"]))
+    mean = lambda v: sum(v) / len(v) if v else None
+    total = sum(sum(v) for v in trace.values())
+    # one-member grid of each kernel: every launch of a solo workload; in the
+    # ensemble run, the smallest grid of a kernel also launched one by one
+    # (kernels seen at one grid only there, e.g. autotune variants: unknown)
+    per_member, grids = {}, defaultdict(set)
+    for (k, g) in trace:
+        per_member[k] = min(per_member.get(k, g), g)
+        grids[k].add(g)
+    if w == "ensemble48":
+        per_member = {k: g for k, g in per_member.items() if len(grids[k]) > 1}
+    with open(f"{d}/trace_{w}.json") as f:
+        line = json.loads(f.read())
+    desc = line.get("config", {}).get("description", "")
+    out = [f"# rocprofv3 summary: {w} ({desc})", "", f"csrc_sha256: {source_hash()}", "",
+           "Commands (repository root, MI355X; the first writes the schedule file the others reuse):", ""]
+    out += [f"    {c}" for c in profile_commands(w)]
+    out += ["", f"Copy calibration (1 GiB device copy, `__amd_rocclr_copyBuffer`): FETCH_SIZE reads {cf:.0f} KiB "
+            f"(scale x{sf:.3f}), WRITE_SIZE reads {cw:.0f} KiB (scale x{sw:.3f}).", "",
+            "Rows are split by launch grid (workgroups); members = grid / the kernel's smallest grid in the run "
+            "(one member).  alg = the algorithmic bytes of the pass model (bench.py pass_bytes) times members; "
+            "HBM = FETCH_SIZE and WRITE_SIZE scaled by the copy calibration; GB/s and frac use alg bytes and "
+            "the average duration against 8 TB/s."
+            + ("  The size groups run concurrently on their own streams, so a grouped launch's duration "
+               "includes sharing the GPU with the other groups' launches (the durations add up to more than "
+               "the wall time); the one-member rows come from the one-by-one comparison leg."
+               if w == "ensemble48" else ""), "",
+            "| kernel | grid | members | calls | avg us | % time | alg MB | HBM read MB | HBM write MB | HBM/alg | alg GB/s | frac |",
+            "|---|---:|---:|---:|---:|---:|---:|---:|---:|---:|---:|---:|"]
+    traffic = []
+    for (k, g), ts in sorted(trace.items(), key=lambda kv: -sum(kv[1])):
+        pct = 100.0 * sum(ts) / total
+        avg = sum(ts) / len(ts)
+        mem = g // per_member[k] if (k in per_member and g % per_member[k] == 0) else None
+        ab = alg_bytes(k)
+        ab = ab * mem if (ab is not None and mem) else None
+        c = ctr.get((k, g), {})
+        fb = mean(c.get("FETCH_SIZE", [])) * 1024 * sf if c.get("FETCH_SIZE") else None
+        wb = mean(c.get("WRITE_SIZE", [])) * 1024 * sw if c.get("WRITE_SIZE") else None
+        if (pct < 0.05 and ab is None) or (pct < 0.3 and fb is None):
+            continue  # autotune trials and one-off set-up launches
+        fmt = lambda x, p=2: "-" if x is None else f"{x:.{p}f}"
+        ratio = (fb + wb) / ab if (ab and fb is not None and wb is not None) else None
+        gbs = ab / (avg * 1e-6) / 1e9 if ab else None
+        out.append(f"| `{k}` | {g} | {mem or '-'} | {len(ts)} | {avg:.2f} | {pct:.2f} | {fmt(ab and ab / 1e6)} | "
+                   f"{fmt(fb and fb / 1e6)} | {fmt(wb and wb / 1e6)} | {fmt(ratio, 3)} | {fmt(gbs, 1)} | "
+                   f"{fmt(gbs and gbs / HBM_PEAK_GBS, 3)} |")
+        if mem == 1 and fb is not None and wb is not None:
+            traffic.append(f"traffic {k} {int(fb)} {int(wb)}")
+    sq = [(k, c) for k, c in ctr.items() if "SQ_WAVES" in c and alg_bytes(k[0]) is not None]
+    if sq:
+        out += ["", "## SQ counters (per launch averages; ratios per wave or per wave-cycle)", "",
+                "Instruction counts are per wave; the active and wait columns divide SQ_ACTIVE_INST_* and "
+                "SQ_WAIT_INST_* by SQ_WAVE_CYCLES (the same quad-cycle units), i.e. the fraction of a wave's "
+                "lifetime spent issuing or waiting; LDS conflict = SQ_LDS_BANK_CONFLICT cycles per LDS "
+                "instruction.", "",
+                "| kernel | grid | waves | VALU/wave | SALU/wave | LDS/wave | LDS conflict cyc/LDS inst | "
+                "VALU active/wave-cyc | LDS active/wave-cyc | LDS wait/wave-cyc | any wait/wave-cyc | "
+                "VMEM rd/wave | VMEM wr/wave |", "|---|---:|" + "---:|" * 11]
+        for (k, g), c in sorted(sq, key=lambda kc: -sum(trace.get(kc[0], [0]))):
+            m = {n: mean(v) for n, v in c.items()}
+            wv = m.get("SQ_WAVES") or 1
+            cyc = m.get("SQ_WAVE_CYCLES")
+            r = lambda n, dnm: "-" if m.get(n) is None or not dnm else f"{m[n] / dnm:.3g}"
+            out.append(f"| `{k}` | {g} | {wv:.0f} | {r('SQ_INSTS_VALU', wv)} | {r('SQ_INSTS_SALU', wv)} | "
+                       f"{r('SQ_INSTS_LDS', wv)} | {r('SQ_LDS_BANK_CONFLICT', m.get('SQ_INSTS_LDS'))} | "
+                       f"{r('SQ_ACTIVE_INST_VALU', cyc)} | {r('SQ_ACTIVE_INST_LDS', cyc)} | "
+                       f"{r('SQ_WAIT_INST_LDS', cyc)} | {r('SQ_WAIT_INST_ANY', cyc)} | "
+                       f"{r('SQ_INSTS_VMEM_RD', wv)} | {r('SQ_INSTS_VMEM_WR', wv)} |")
+    rf = line.get("roofline")
+    if rf:
+        sch = line["schedule"]["f32"]
+        ins_nc = {"insect256": 3, "box1152": 3}.get(w, 1)
+        n = line["config"].get("grid")
+        k = kernel_of_pass(rf["kernel"], n, "float", sch, ins_nc, dyn=w in ("insect256", "box1152", "freefall128"),
+                           nx=line["config"].get("nx"))
+        dyn = w in ("insect256", "box1152", "freefall128")
+        ts = trace.get((k, per_member.get(k, -1)), [])
+        if ts:
+            out += ["", f"Dominant kernel of the bench line ({rf['kernel']}, `{k}`): HIP events "
+                    f"{line['passes_f32'][rf['kernel']]['avg_us']:.2f} us per launch, rocprofv3 "
+                    f"{sum(ts) / len(ts):.2f} us ({len(ts)} launches)."]
+        # one FP32 step of the timed schedule: its pass kernels against the bench's step time
+        names = ["y_inverse", "x_pass", "y_forward", "z_pass"] + (["z_inverse"] if sch["split_z"] else [])
+        ks = [kernel_of_pass(p_, n, "float", sch, ins_nc, dyn=dyn, nx=line["config"].get("nx")) for p_ in names]
+        avgs = [trace.get((k_, per_member.get(k_, -1)), []) for k_ in ks]
+        if all(avgs):
+            tot_us = sum(sum(a_) / len(a_) for a_ in avgs)
+            sb = step_bytes(n, 8, nx=line["config"].get("nx"))
+            out += [f"FP32 step of the timed schedule: its pass kernels average {tot_us:.1f} us together "
+                    f"(rocprofv3), the bench line {line['ms_per_step'] * 1e3:.1f} us per step; {sb / 1e6:.1f} MB "
+                    f"algorithmic per step = {sb / (tot_us * 1e-6) / 1e9:.0f} GB/s over the kernel time "
+                    f"({sb / (tot_us * 1e-6) / 1e9 / HBM_PEAK_GBS:.3f} of peak)."]
+    out += ["", "## bench.py line of the trace run", "", "```json", json.dumps(line), "```", "",
+            "## Traffic per launch used by bench.py (scaled counters, bytes; one-member launches)", "", "```"]
+    out += sorted(traffic) + ["```", ""]
+    return "\n".join(out)
 
 
 def main():
@@ -439,10 +686,22 @@ def main():
     ap.add_argument("--no-box", action="store_true", help="skip the non-cubic box figure")
     ap.add_argument("--no-ensemble", action="store_true", help="skip the batched-ensemble figure")
     ap.add_argument("--no-autotune", action="store_true", help="time the default schedules")
+    ap.add_argument("--summarize", default=None, metavar="DIR",
+                    help="print the profiles/ summary of --workload from the rocprofv3 runs under DIR")
+    ap.add_argument("--schedule-file", default=None,
+                    help="JSON file of schedules: reused when present, else written from this run's choices")
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="run only a plain device copy of 1 GiB (3 launches) to scale HBM counters")
     a = ap.parse_args()
+    if a.summarize:
+        print(summarize(a.summarize, a.workload))
+        return
+    if a.schedule_file:
+        SCHED_PIN["path"] = a.schedule_file
+        if os.path.exists(a.schedule_file):
+            with open(a.schedule_file) as f:
+                SCHED_PIN["data"] = json.load(f)
     if a.copy_calibration:
         import torch
         x = torch.ones(1 << 28, dtype=torch.float32, device="cuda")
@@ -563,7 +822,7 @@ def main():
         bpts = 1152.0 * 768 * 768
         bv = {}
         for dtype in ("f32", "f64"):
-            r = gpu_run(F, torch, bw, dtype, bw["default_steps"], 2, tune=False)
+            r = gpu_run(F, torch, bw, dtype, bw["default_steps"], 2, tune=not a.no_autotune)
             bv[dtype] = round(bpts * bw["default_steps"] / (r["ev_ms"] / 1e3) / 1e6, 2)
             torch.cuda.empty_cache()
         note("box1152 done")

@@ -57,12 +57,14 @@ __host__ __device__ constexpr int nt_z(int N, int V = 0) {
 // Rows per workgroup of the x-pass: 3*RW*N ~ 3072 elements in LDS (V = 0), a
 // half (V = 1) or a quarter (V = 2) of that, at least 2 rows (an even count
 // pairs the rows' N_z in one forward transform); a single row where two rows
-// of complex values (nine columns) would not fit the LDS (long FP64 rows).
+// of complex values (nine columns) would not fit the LDS (long FP64 rows),
+// and as the smaller variants of rows of 1024 points or more, whose two-row
+// tile leaves room for one workgroup per CU only.
 __host__ __device__ constexpr int rows_x(int N, int cbytes = 8, int V = 0) {
     int c = 1024 / N, p = 2;
     while (p * 2 <= c) p *= 2;
     p >>= V;
-    p = p < 2 ? 2 : p;
+    if (p < 2) p = (V > 0 && N >= 1024) ? 1 : 2;
     if (p == 2 && 9 * cm_stride(N) * cbytes > 150 * 1024) p = 1;
     return p;
 }
@@ -554,8 +556,11 @@ __global__ __launch_bounds__(NT, (xpass_min_blocks<T, NX, NC, V, SP>())) void k_
     __shared__ unsigned amb[K64 ? (RW * NX + 31) / 32 : 1];
     __shared__ int amb_any;
     // twiddles from LDS unless the table would cost a workgroup per CU (FP64,
-    // full-size tile: the tile alone is just under half of the 160 KiB)
-    constexpr bool TWL = !(sizeof(T) == 8 && V == 0) && xpass_min_blocks<T, NX, NC, V, SP>() == 1;
+    // full-size tile: the tile alone is just under half of the 160 KiB), and
+    // not for rows of 1024 points or more, where staging the table for every
+    // workgroup costs more than the LDS reads save (1152 points, FP32: one-row
+    // tile 35.4 ms with LDS twiddles, 18.6 ms without)
+    constexpr bool TWL = !(sizeof(T) == 8 && V == 0) && xpass_min_blocks<T, NX, NC, V, SP>() == 1 && NX < 1024;
     __shared__ cx<T> tws[TWL ? NX : 1];
     if (*gview(&hdr->status)) return;
     const int tid = threadIdx.x;

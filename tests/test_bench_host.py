@@ -37,6 +37,11 @@ def test_kernel_names_and_counter_gate():
     assert bench.kernel_of_pass("x_pass", 128, "float", sched, 1, False) == "k_xpass<float, 128, 128, 1, 0, false>"
     assert bench.kernel_of_pass("z_pass", 128, "float", sched, 1, False, nx=192) == \
         "k_zpass<float, 192, 128, 1, 2, false>"
+    # the y-inverse launch that also evaluates moving kinematics is its own instantiation
+    assert bench.kernel_of_pass("y_inverse", 128, "float", sched, 3, True) == "k_ypass<float, 128, 128, 1, 2, 1>"
+    assert bench.kernel_of_pass("y_inverse", 128, "float", sched, 1, False) == "k_ypass<float, 128, 128, 1, 0, 1>"
+    assert bench.moving_body({"wings": True}) and bench.moving_body({"free_flight": True})
+    assert not bench.moving_body({"body": "sphere"}) and not bench.moving_body(None)
     assert bench.counter_traffic("no_such_workload", "k_xpass") is None
     path = os.path.join(ROOT, "profiles", "sphere128.md")
     if f"csrc_sha256: {bench.source_hash()}" in open(path).read():

@@ -165,3 +165,37 @@ def test_paper_box_insect_fp32_matches_fp64_and_sampled_mask_matches_oracle():
     err = math.sqrt(num / den)
     print(f"1152x768x768 insect FP32 vs FP64, 2 steps: rel L2 {err:.3e}")
     assert err < 2e-5
+
+
+def test_one_row_x_tiles_of_the_1152_point_axis_match_the_oracle():
+    """FP32 x-pass variants 1 and 2 take one row of 1152 points per workgroup
+    (the two-row tile holds one workgroup per CU).  A single row transforms
+    N_z alone rather than packed with the next row's, so the result equals the
+    two-row tile's only to rounding: both variants (bitwise alike, the same
+    tile) are checked against the oracle at the FP32 bar, with dt and the
+    per-part forces."""
+    nx, n = 1152, 32
+    Lx = L * nx / n
+    body = dict(W.model_insect(n, L), x_cntr=(0.4 * Lx, L / 2, L / 2))
+    u0 = W.inflow_noise(n, L, seed=98, rms=1e-2, kmax=6.0, nx=nx)
+    nu, eta, steps = 1 / 136, 5e-3, 4
+    p = O.Params(n, L, nu, eta, O.MEAN_FIXED, nx=nx, Lx=Lx)
+    ost, oh = O.run(p, u0, steps, O.StepControl(cfl=0.1, eta_cap=0.5), O.Insect.from_dict(body))
+    ou = O.velocity(p, ost)
+    P = F.Plan(n, L, nu, eta, "f32", nx=nx)
+    got = {}
+    for v in (1, 2):
+        P.set_schedule(dict(P.schedule(), x_pass=v))
+        st = P.new_state(torch.from_numpy(u0))
+        h = np_of(P.step(st, steps, body, history=True, cfl=0.1, eta_cap=0.5))
+        got[v] = P.uhat(st)
+        err = rel_l2(np_of(P.velocity(st)), ou)
+        print(f"1152x32x32 insect FP32, one-row x tile (variant {v}): rel L2 {err:.3e}")
+        assert err < 2e-5, v
+        odt = np.array([d["dt"] for d in oh])
+        assert np.max(np.abs(h[:, 1] - odt)) <= 1e-6 * odt.max(), v
+        for c in range(3):
+            oF = np.array([d["F"][c] for d in oh])
+            scale = max(1e-12, np.max(np.abs(oF)))
+            assert np.max(np.abs(h[:, 4 + 6 * c:7 + 6 * c] - oF)) <= 2e-3 * scale, (v, c)
+    assert torch.equal(got[1], got[2])
