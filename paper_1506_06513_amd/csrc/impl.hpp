@@ -471,11 +471,11 @@ struct Impl final : ImplBase {
         const CX* w = static_cast<const CX*>(g.twx);
         constexpr int nw = nwg<V>(0);
         const int* n = g.n_nc[SP ? 1 : 0];
-        if (n[0]) k_xpass<T, NX, N, 0, V, SP><<<(unsigned)(nw * n[0]), NT, 0, g.stream>>>(mt, w);
+        if (n[0]) k_xpass<T, NX, N, 0, V, SP><<<(unsigned)(nw * n[0]), xpass_threads<T, NX, V, SP>(), 0, g.stream>>>(mt, w);
         mt += n[0];
-        if (n[1]) k_xpass<T, NX, N, 1, V, SP><<<(unsigned)(nw * n[1]), NT, 0, g.stream>>>(mt, w);
+        if (n[1]) k_xpass<T, NX, N, 1, V, SP><<<(unsigned)(nw * n[1]), xpass_threads<T, NX, V, SP>(), 0, g.stream>>>(mt, w);
         mt += n[1];
-        if (n[2]) k_xpass<T, NX, N, 3, V, SP><<<(unsigned)(nw * n[2]), NT, 0, g.stream>>>(mt, w);
+        if (n[2]) k_xpass<T, NX, N, 3, V, SP><<<(unsigned)(nw * n[2]), xpass_threads<T, NX, V, SP>(), 0, g.stream>>>(mt, w);
         return mt + n[2];
     }
     template <int V>

@@ -516,10 +516,20 @@ template <typename T, int NX, int NC, int V, bool SP>
 __host__ __device__ constexpr int xpass_min_blocks() {
     return (sizeof(T) < 8 && V == 0 && NC <= 1 && !SP && NX < 512) ? 4 : 1;
 }
+// Threads per x-pass workgroup: NT, except for one-row tiles of rows of 1024
+// points or more, whose columns take 32 lanes each (36 values per lane at
+// 1152): there the row's 3 inverse and 2 forward column transforms would leave
+// most of 8 lane groups idle, so the tile gets 4 groups.  Not for FP64 with the
+// sponge, whose tile holds one workgroup per CU by its LDS alone.
+template <typename T, int NX, int V, bool SP>
+__host__ __device__ constexpr int xpass_threads() {
+    return (NX >= 1024 && rows_x(NX, sizeof(cx<T>), V) == 1 && (sizeof(T) < 8 || !SP)) ? 128 : NT;
+}
 
 template <typename T, int NX, int N, int NC, int V, bool SP>
-__global__ __launch_bounds__(NT, (xpass_min_blocks<T, NX, NC, V, SP>())) void k_xpass(const Member* __restrict__ mt,
-                                                                               const cx<T>* __restrict__ tw) {
+__global__ __launch_bounds__((xpass_threads<T, NX, V, SP>()), (xpass_min_blocks<T, NX, NC, V, SP>())) void k_xpass(
+    const Member* __restrict__ mt, const cx<T>* __restrict__ tw) {
+    constexpr int NT = xpass_threads<T, NX, V, SP>();  // this kernel's workgroup size
     using G = Geo<T, NX, N>;
     constexpr int K = G::KX, KP = G::KP, KPp = G::KPp;  // the x axis' cut
     constexpr int RW = rows_x(NX, sizeof(cx<T>), V);
@@ -540,17 +550,26 @@ __global__ __launch_bounds__(NT, (xpass_min_blocks<T, NX, NC, V, SP>())) void k_
     constexpr int NVAL = 3 + 12 * NC;
 
     constexpr int LP = (RW * KP + NT - 1) / NT;
-    // inverse columns [0, CI), forward columns [CI, CI + CF)
-    __shared__ cx<T> buf[(CI + CFT) * SC];
-    cx<T>* fbuf = buf + CI * SC;
+    // FP64 kinematics for the part choice where parts overlap (FP32 runs)
+    constexpr bool K64 = NC > 1 && sizeof(T) < 8;
+    // inverse columns [0, CI), forward columns [CI, CI + CF).  A one-row tile
+    // writes its forward columns over its first two inverse columns instead:
+    // each point's thread reads its three inverse values before it writes its
+    // N values at the same element.  Points flagged for the second sweep (K64)
+    // write nothing in the first, so their inverse values are still there when
+    // the second sweep reads them; lanes of that sweep without a flagged point
+    // read aliased values but only add zeros to the wave sums.  Not with the
+    // sponge's extra forward columns.  (1152-point rows: FP64 60 instead of
+    // 98 KB, FP32 with flagged points 29 instead of 49 KB.)
+    constexpr bool ALIAS = RW == 1 && !SP;
+    __shared__ cx<T> buf[(ALIAS ? CI : CI + CFT) * SC];
+    cx<T>* fbuf = ALIAS ? buf : buf + CI * SC;
     // per-wave sums: with three colours the wave rows wred also take the three
     // lane-reduced values (slots 0..2 are free there), which saves the LDS of red
     constexpr bool WAVE_ACC = NC > 1;
     __shared__ double red[WAVE_ACC ? 1 : NT / 64][WAVE_ACC ? 1 : NVAL];
     __shared__ double wred[WAVE_ACC ? NT / 64 : 1][WAVE_ACC ? NV : 1];
     __shared__ KinT<T> kin;
-    // FP64 kinematics for the part choice where parts overlap (FP32 runs)
-    constexpr bool K64 = NC > 1 && sizeof(T) < 8;
     // point flagged for the FP64 part decision (one bit per point); the FP64
     // kinematics of those few points are read from the state header
     __shared__ unsigned amb[K64 ? (RW * NX + 31) / 32 : 1];
@@ -708,6 +727,7 @@ __global__ __launch_bounds__(NT, (xpass_min_blocks<T, NX, NC, V, SP>())) void k_
         }
         // Dirichlet layer (Sec. 2.3): penalized to u_wall below, with no body
         // terms at its points
+        bool deferred = false;  // flagged for the second sweep (set in the first)
         const bool inwall = m.wall && (dx * i >= m.wall_lo[0] || dx * (row % N) >= m.wall_lo[1] ||
                                        dx * (row / N) >= m.wall_lo[2]);
         if constexpr (NC > 0) {
@@ -726,6 +746,7 @@ __global__ __launch_bounds__(NT, (xpass_min_blocks<T, NX, NC, V, SP>())) void k_
                     if (defer) {
                         atomicOr(&amb[idx >> 5], 1u << (idx & 31));
                         amb_any = 1;
+                        deferred = true;
                     }
                 } else {
                     mp = eval_mask<T>(kin, xg, yg, zg, nullptr);
@@ -799,7 +820,7 @@ __global__ __launch_bounds__(NT, (xpass_min_blocks<T, NX, NC, V, SP>())) void k_
             ny -= pen * (uy - T(m.u_wall[1]));
             nz -= pen * (uz - T(m.u_wall[2]));
         }
-        if (act) {
+        if (act && !(ALIAS && deferred)) {
             fbuf[lds_at<true, 1, SC>(i, r)] = cx<T>{nx, ny};
             if constexpr (RW == 1) fbuf[lds_at<true, 1, SC>(i, 1)] = cx<T>{nz, T(0)};
             else reinterpret_cast<T*>(fbuf + lds_at<true, 1, SC>(i, RW + r / 2))[r & 1] = nz;

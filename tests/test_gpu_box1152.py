@@ -122,18 +122,24 @@ def test_paper_box_eigenmode_decays_exactly(dtype):
 
 def test_paper_box_insect_fp32_matches_fp64_and_sampled_mask_matches_oracle():
     """The model insect in the 1152 x 768 x 768 box (at x = 2.4, fluid at rest):
-    FP32 against FP64 after 2 steps, and 40 000 sampled points of the
-    materialized FP64 mask against the oracle's pointwise mask."""
+    FP32 against FP64 after 2 steps, with both FP32 x tiles (two rows, and one
+    row with the forward columns over the inverse ones, where the points
+    flagged for the FP64 part decision keep their inputs for the second
+    sweep), and 40 000 sampled points of the materialized FP64 mask against
+    the oracle's pointwise mask."""
     nx, n = 1152, 768
     wl = W.WORKLOADS["insect256"]
     body = dict(W.model_insect(n, L), x_cntr=(2.4, L / 2, L / 2))
     vel = {}
-    for dtype in ("f64", "f32"):
+    for case in ("f64", "f32", "f32 one-row"):
+        dtype = case.split()[0]
         P = F.Plan(n, L, wl["nu"], wl["eta"], dtype, nx=nx)
+        if case == "f32 one-row":
+            P.set_schedule(dict(P.schedule(), x_pass=1))
         st = P.new_state(torch.zeros((3, n, n, nx), dtype=P.rdt, device="cuda"))
         P.step(st, 2, body, cfl=0.1)
         assert P.forces(st)[0] == 0
-        vel[dtype] = P.velocity(st)
+        vel[case] = P.velocity(st)
         if dtype == "f64":
             t = 0.3
             chi, us, col = P.mask(body, t)
@@ -158,13 +164,14 @@ def test_paper_box_insect_fp32_matches_fp64_and_sampled_mask_matches_oracle():
             del chi, us, col
         del P, st
         torch.cuda.empty_cache()
-    num = den = 0.0
-    for c in range(3):
-        num += float(torch.sum((vel["f32"][c].double() - vel["f64"][c]) ** 2))
-        den += float(torch.sum(vel["f64"][c] ** 2))
-    err = math.sqrt(num / den)
-    print(f"1152x768x768 insect FP32 vs FP64, 2 steps: rel L2 {err:.3e}")
-    assert err < 2e-5
+    for case in ("f32", "f32 one-row"):
+        num = den = 0.0
+        for c in range(3):
+            num += float(torch.sum((vel[case][c].double() - vel["f64"][c]) ** 2))
+            den += float(torch.sum(vel["f64"][c] ** 2))
+        err = math.sqrt(num / den)
+        print(f"1152x768x768 insect {case} vs FP64, 2 steps: rel L2 {err:.3e}")
+        assert err < 2e-5, case
 
 
 def test_one_row_x_tiles_of_the_1152_point_axis_match_the_oracle():
