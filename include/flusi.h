@@ -86,14 +86,18 @@ extern "C" {
  *            body the prescribed kinematics, eps from the body angles)
  *   [35] [36] aerodynamic power P_aero of the left and right wing
  *            (Sec. 3.5, eq. insect_power)
+ *   [37] [38] inertial power P_inert of the left and right wing (Sec. 3.5)
+ *   [39] [40] P_total = max(P_inert + P_aero, 0) of the left and right wing
  * Force and torque follow eqs. force_with_unst_corrections / moment_of_love
  * (Sec. 2.1): the penalization integral plus the time derivative of the solid
  * momentum, as the force acting on the solid.  Torques are taken about the
  * body centre (body) and the wing pivots (wings).  P_aero = -m . (Omega_w -
  * Omega_b) with m the wing torque about its pivot and Omega_w - Omega_b the
- * wing's angular velocity relative to the body.  Without a mask [4..36] are
- * zero. */
-#define FLUSI_NDIAG 37
+ * wing's angular velocity relative to the body.  P_inert = W . (J W' + W x J W)
+ * with W the wing's angular velocity in its own frame, W' its time derivative
+ * (exact, from the angle series' second derivatives) and J = wing_J; zero when
+ * wing_J is zero.  Without a mask [4..40] are zero. */
+#define FLUSI_NDIAG 41
 
 typedef struct flusi_plan_s* flusi_plan;
 
@@ -172,6 +176,11 @@ typedef struct {
      * max(x - b, -x - (B - b), y - tip, a - y, |z| - t/2)): wing_rect = {a, tip,
      * b, B}; thickness wing_t. */
     double wing_rect[4];
+    /* Wing tensor of inertia J^(w) about the pivot in the wing's own frame, for
+     * the inertial power (Sec. 3.5; the paper gives no values): {J_xx, J_yy,
+     * J_zz, J_xy, J_xz, J_yz}, symmetric, the same for both wings in their own
+     * frames.  All zero: no inertial power. */
+    double wing_J[6];
 } flusi_insect;
 
 /* Controls of flusi_step (Algorithm 1 steps (a)-(e)). */

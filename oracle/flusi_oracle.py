@@ -362,6 +362,7 @@ class Insect:
     inertia: tuple = (1.0, 1.0, 1.0)     # principal moments J_x, J_y, J_z (body frame)
     gravity: float = 0.0                 # g, acting along -z
     dof: tuple = (1.0, 1.0, 1.0, 1.0, 1.0, 1.0)  # translation x,y,z; rotation x,y,z
+    wing_J: tuple = (0.0,) * 6           # wing inertia (wing frame, about the pivot): Jxx, Jyy, Jzz, Jxy, Jxz, Jyz
 
     @staticmethod
     def from_dict(d: dict) -> "Insect":
@@ -451,8 +452,8 @@ def M_wing(ins: Insect, t: float, side: str) -> np.ndarray:
     return Ry(-alpha) @ Rz(-theta) @ Rx(-phi)
 
 
-def omega_wing_b(ins: Insect, t: float, side: str) -> np.ndarray:
-    """Wing angular velocity in the body frame  [Sec. 3.3].
+def omega_wing_s(ins: Insect, t: float, side: str) -> np.ndarray:
+    """Wing angular velocity in the stroke-plane frame  [Sec. 3.3].
 
     Right wing: the same expression with (alpha, phi) and their rates negated,
     matching its wing matrix."""
@@ -460,10 +461,42 @@ def omega_wing_b(ins: Insect, t: float, side: str) -> np.ndarray:
     if side == "r":
         phi, alpha, dphi, dalpha = -phi, -alpha, -dphi, -dalpha
     # Omega^(s) = Rx^T(phi)[ (dphi,0,0) + Rz^T(-theta)[ (0,0,-dtheta) + Ry^T(alpha)(0,dalpha,0) ] ]
-    om_s = Rx(phi).T @ (np.array([dphi, 0.0, 0.0])
+    return Rx(phi).T @ (np.array([dphi, 0.0, 0.0])
                         + Rz(-theta).T @ (np.array([0.0, 0.0, -dtheta])
                                           + Ry(alpha).T @ np.array([0.0, dalpha, 0.0])))
-    return M_stroke(ins, side).T @ om_s
+
+
+def omega_wing_b(ins: Insect, t: float, side: str) -> np.ndarray:
+    """Wing angular velocity in the body frame  [Sec. 3.3]."""
+    return M_stroke(ins, side).T @ omega_wing_s(ins, t, side)
+
+
+def omega_wing_w(ins: Insect, t: float, side: str) -> np.ndarray:
+    """Wing angular velocity Omega_w^(w) in the wing's own frame: the stroke-frame
+    vector mapped by the wing matrix  [Sec. 3.3, 3.5]."""
+    return M_wing(ins, t, side) @ omega_wing_s(ins, t, side)
+
+
+def wing_inertia(ins: Insect) -> np.ndarray:
+    """Symmetric wing tensor of inertia J^(w) from (Jxx, Jyy, Jzz, Jxy, Jxz, Jyz)."""
+    jxx, jyy, jzz, jxy, jxz, jyz = (float(v) for v in ins.wing_J)
+    return np.array([[jxx, jxy, jxz], [jxy, jyy, jyz], [jxz, jyz, jzz]])
+
+
+def inertial_power(ins: Insect, t: float, side: str) -> float:
+    """P_inert = Omega^(w) . (J^(w) dOmega^(w)/dt + Omega^(w) x J^(w) Omega^(w)) of one
+    wing  [Sec. 3.5].  The paper does not say how the angular acceleration is
+    obtained; here it is the fourth-order central difference of Omega^(w)(t)
+    with a step of 1e-4 of a period (truncation below 1e-8 relative for the
+    harmonics the angle series allow)."""
+    J = wing_inertia(ins)
+    if not J.any():
+        return 0.0
+    h = 1e-4 / ins.freq if ins.freq > 0.0 else 1e-4
+    om = omega_wing_w(ins, t, side)
+    dom = (omega_wing_w(ins, t - 2 * h, side) - 8.0 * omega_wing_w(ins, t - h, side)
+           + 8.0 * omega_wing_w(ins, t + h, side) - omega_wing_w(ins, t + 2 * h, side)) / (12.0 * h)
+    return float(np.dot(om, J @ dom + np.cross(om, J @ om)))
 
 
 # ---------------------------------------------------------------------------
@@ -1084,6 +1117,9 @@ def step(p: Params, st: State, ctl: StepControl, ins: Insect | None, fixed_mask=
         diag["pose"] = pose_record(ins, st.t, ysol)
         diag["P_aero"] = np.array([aero_power(M[1 + k], pose.Mb, omega_wing_b(ins, st.t, side)) if ins.wings
                                    else 0.0 for k, side in enumerate(("l", "r"))])
+        diag["P_inert"] = np.array([inertial_power(ins, st.t, side) if ins.wings else 0.0 for side in ("l", "r")])
+        # total power without energy storage in the muscles  [Sec. 3.5]
+        diag["P_total"] = np.maximum(diag["P_inert"] + diag["P_aero"], 0.0)
         m_pen, J_now = torque_about(g, u, chi, us, pose.xc, p.eta, colour)
         if ins.free_flight:
             Ft = F.sum(axis=0)

@@ -32,7 +32,7 @@ FLUSI_F32, FLUSI_F64 = 0, 1
 FLUSI_BODY_NONE, FLUSI_BODY_SPHERE, FLUSI_BODY_ELLIPSOID = 0, 1, 2
 FLUSI_SMOOTH_COS, FLUSI_SMOOTH_TANH = 0, 1
 FLUSI_MEAN_FIXED, FLUSI_MEAN_FREE = 0, 1
-FLUSI_NDIAG = 37
+FLUSI_NDIAG = 41
 FLUSI_NPASS = 6
 PASS_NAMES = ("z_inverse", "y_inverse", "x_pass", "kinematics", "y_forward", "z_pass")
 SUPPORTED_N = (16, 24, 32, 48, 64, 96, 128, 192, 256, 384, 512)
@@ -76,6 +76,7 @@ class flusi_insect(ctypes.Structure):
         ("head_x", ctypes.c_double * 3), ("head_r", ctypes.c_double),
         ("eye_x", ctypes.c_double * 3), ("eye_r", ctypes.c_double),
         ("wing_rect", ctypes.c_double * 4),
+        ("wing_J", ctypes.c_double * 6),
     ]
 
 
@@ -479,6 +480,7 @@ def make_insect(d: dict | None) -> flusi_insect | None:
     s.head_r = float(d.get("head_r", 0.0))
     s.eye_x[:] = [float(v) for v in d.get("eye_x", (0.0, 0.0, 0.0))]
     s.eye_r = float(d.get("eye_r", 0.0))
+    s.wing_J[:] = [float(v) for v in d.get("wing_J", (0.0,) * 6)]
     for k in ("x_cntr", "u_cntr", "pivot_l", "pivot_r", "phi", "alpha", "theta"):
         default = {"pivot_l": (0.0, 0.15, 0.0), "pivot_r": (0.0, -0.15, 0.0)}.get(k, (0.0, 0.0, 0.0))
         getattr(s, k)[:] = [float(v) for v in d.get(k, default)]

@@ -265,7 +265,7 @@ static int tune_group(ImplBase* impl, const GroupRun& g, PlanData& prof, int rep
 
 using namespace flusi;
 
-static_assert(sizeof(flusi_insect) == 16 + 8 * 47 + 16 + 8 * (3 * 2 * (FLUSI_KIN_MAX + 1) + 2 + 2 * (FLUSI_WING_MAX + 1) + 8 + 4), "flusi_insect layout");
+static_assert(sizeof(flusi_insect) == 16 + 8 * 47 + 16 + 8 * (3 * 2 * (FLUSI_KIN_MAX + 1) + 2 + 2 * (FLUSI_WING_MAX + 1) + 8 + 4 + 6), "flusi_insect layout");
 static_assert(sizeof(flusi_step_params) == 8 + 5 * 8 + 8, "flusi_step_params layout");
 
 extern "C" {

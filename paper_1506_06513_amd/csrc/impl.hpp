@@ -206,6 +206,8 @@ inline int check_insect(const flusi_insect* ins) {
         return set_error(FLUSI_EINVAL, "insect: Fourier wing needs 0 <= wing_n <= %d", FLUSI_WING_MAX);
     if (!(ins->head_r >= 0.0) || !(ins->eye_r >= 0.0) || !std::isfinite(ins->head_r) || !std::isfinite(ins->eye_r))
         return set_error(FLUSI_EINVAL, "insect: head_r and eye_r must be finite and >= 0");
+    for (int i = 0; i < 6; ++i)
+        if (!std::isfinite(ins->wing_J[i])) return set_error(FLUSI_EINVAL, "insect: wing_J not finite");
     if (!ins->free_flight) return FLUSI_OK;
     if (ins->free_flight != 1) return set_error(FLUSI_EINVAL, "insect: free_flight must be 0 or 1");
     if (colour_count(ins) == 0) return set_error(FLUSI_EINVAL, "insect: free flight needs a body or wings");

@@ -19,6 +19,7 @@ struct Kin {
     double Mws[2][9];  // M_wing M_stroke for the left [0] and right [1] wing
     double piv[2][3];  // pivots, body frame
     double omw[2][3];  // wing angular velocities, body frame
+    double pinert[2];  // inertial power of the left and right wing (Sec. 3.5)
     double xref[3][3]; // torque reference points (global): body centre, left pivot, right pivot
     double r2all;      // squared radius (about xc) outside which chi == 0 exactly
     double thr;        // delta above which chi == 0 exactly
@@ -170,13 +171,14 @@ __host__ __device__ inline void solid_rhs(const flusi_insect& in, const double* 
 // Wing angles phi, alpha, theta and their rates at time t (Sec. 3.3): the
 // sinusoid, a Fourier series a_0/2 + sum a_i cos(2 pi i f t) + b_i sin(2 pi i f t),
 // or periodic cubic Hermite interpolation of values and rates at kin_n
-// equidistant times of a period.
+// equidistant times of a period; with acc, also the second derivatives (the
+// Hermite cubic's within its interval).
 template <class TR = TrigEval>
 __host__ __device__ inline void wing_angle_values(const flusi_insect& in, double t, double* ang, double* rate,
-                                                  TR&& tr = TR{}) {
+                                                  TR&& tr = TR{}, double* acc = nullptr) {
     if (in.kin_type == FLUSI_KIN_FOURIER) {
         for (int a = 0; a < 3; ++a) {
-            double v = 0.5 * in.kin_coef[a][0][0], dv = 0.0;
+            double v = 0.5 * in.kin_coef[a][0][0], dv = 0.0, d2v = 0.0;
             for (int i = 1; i <= in.kin_n; ++i) {
                 const double w = 2.0 * M_PI * i * in.freq;
                 const double ai = in.kin_coef[a][0][i], bi = in.kin_coef[a][1][i];
@@ -184,9 +186,11 @@ __host__ __device__ inline void wing_angle_values(const flusi_insect& in, double
                 const double c = q.c, sn = q.s;
                 v += ai * c + bi * sn;
                 dv += w * (-ai * sn + bi * c);
+                d2v -= w * w * (ai * c + bi * sn);
             }
             ang[a] = v;
             rate[a] = dv;
+            if (acc) acc[a] = d2v;
         }
     } else if (in.kin_type == FLUSI_KIN_HERMITE) {
         const int K = in.kin_n;
@@ -200,11 +204,13 @@ __host__ __device__ inline void wing_angle_values(const flusi_insect& in, double
         const double u2 = u * u, u3 = u2 * u;
         const double h00 = 2 * u3 - 3 * u2 + 1, h10 = u3 - 2 * u2 + u, h01 = -2 * u3 + 3 * u2, h11 = u3 - u2;
         const double d00 = 6 * u2 - 6 * u, d10 = 3 * u2 - 4 * u + 1, d01 = -6 * u2 + 6 * u, d11 = 3 * u2 - 2 * u;
+        const double e00 = 12 * u - 6, e10 = 6 * u - 4, e01 = -12 * u + 6, e11 = 6 * u - 2;
         for (int a = 0; a < 3; ++a) {
             const double v0 = in.kin_coef[a][0][j], v1 = in.kin_coef[a][0][j1];
             const double m0 = in.kin_coef[a][1][j] * h, m1 = in.kin_coef[a][1][j1] * h;
             ang[a] = h00 * v0 + h10 * m0 + h01 * v1 + h11 * m1;
             rate[a] = (d00 * v0 + d10 * m0 + d01 * v1 + d11 * m1) / h;
+            if (acc) acc[a] = (e00 * v0 + e10 * m0 + e01 * v1 + e11 * m1) / (h * h);
         }
     } else {
         const double om = 2.0 * M_PI * in.freq;
@@ -214,8 +220,41 @@ __host__ __device__ inline void wing_angle_values(const flusi_insect& in, double
             const SinCos q = tr(ph);
             ang[a] = P[a][0] + P[a][1] * q.c;
             rate[a] = -P[a][1] * om * q.s;
+            if (acc) acc[a] = -P[a][1] * om * om * q.c;
         }
     }
+}
+
+// Inertial power of a wing (Sec. 3.5): W . (J W' + W x J W), with W the
+// wing's angular velocity in its own frame and J = {J_xx, J_yy, J_zz, J_xy,
+// J_xz, J_yz} its inertia tensor there.  With A = Ry(alpha) and B = Rz(-theta)
+// (the wing matrix is A B Rx(phi)), W = phi' A B e_x - theta' A e_z + alpha' e_y,
+// so W' = phi'' A B e_x + phi' (alpha' A_a B e_x + theta' A (sin(-theta),
+// cos(-theta), 0)) - theta'' A e_z - theta' alpha' A_a e_z + alpha'' e_y, with
+// A_a = dRy/dalpha.
+__host__ __device__ inline double wing_inertial_power(const double* Jw, const double* A, const double* B,
+                                                      double dphi, double dal, double dth, double ddphi,
+                                                      double ddal, double ddth) {
+    const double bx[3] = {B[0], B[3], B[6]};  // B e_x
+    double abx[3], abd[3];
+    mat_vec(A, bx, abx);
+    const double bd[3] = {B[1], B[0], 0.0};  // d(B e_x)/d(theta)
+    mat_vec(A, bd, abd);
+    const double az[3] = {A[2], A[5], A[8]};                                              // A e_z
+    const double aabx[3] = {-A[6] * bx[0] - A[0] * bx[2], 0.0, A[0] * bx[0] - A[6] * bx[2]};  // A_a B e_x
+    const double aaz[3] = {-A[0], 0.0, -A[6]};                                             // A_a e_z
+    double W[3], Wd[3];
+    for (int i = 0; i < 3; ++i) {
+        W[i] = dphi * abx[i] - dth * az[i] + (i == 1 ? dal : 0.0);
+        Wd[i] = ddphi * abx[i] + dphi * (dal * aabx[i] + dth * abd[i]) - ddth * az[i] - dth * dal * aaz[i] +
+                (i == 1 ? ddal : 0.0);
+    }
+    const double J[9] = {Jw[0], Jw[3], Jw[4], Jw[3], Jw[1], Jw[5], Jw[4], Jw[5], Jw[2]};
+    double JW[3], JWd[3];
+    mat_vec(J, W, JW);
+    mat_vec(J, Wd, JWd);
+    const double g0 = W[1] * JW[2] - W[2] * JW[1], g1 = W[2] * JW[0] - W[0] * JW[2], g2 = W[0] * JW[1] - W[1] * JW[0];
+    return W[0] * (JWd[0] + g0) + W[1] * (JWd[1] + g1) + W[2] * (JWd[2] + g2);
 }
 
 // Arguments of the sines and cosines that compute_kin evaluates, in its
@@ -375,13 +414,16 @@ __host__ __device__ __forceinline__ void compute_kin(const flusi_insect& in, dou
                 k.omw[s][i] = 0.0;
                 k.xref[1 + s][i] = k.xc[i];
             }
+            k.pinert[s] = 0.0;
         }
         k.r2all = rall * rall;
         return;
     }
-    double ang[3], rate[3];
-    wing_angle_values(in, t, ang, rate, tr);
+    double ang[3], rate[3], acc[3];
+    wing_angle_values(in, t, ang, rate, tr, acc);
     const double phi0 = ang[0], dphi0 = rate[0], al0 = ang[1], dal0 = rate[1], th = ang[2], dth = rate[2];
+    bool inert = false;
+    for (int i = 0; i < 6; ++i) inert = inert || in.wing_J[i] != 0.0;
     for (int s = 0; s < 2; ++s) {
         const double sg = s == 0 ? 1.0 : -1.0;  // right wing: alpha and phi mirrored
         const double phi = sg * phi0, dphi = sg * dphi0, al = sg * al0, dal = sg * dal0;
@@ -406,6 +448,8 @@ __host__ __device__ __forceinline__ void compute_kin(const flusi_insect& in, dou
         a1[0] += dphi;
         mat_tvec(C, a1, a2);
         mat_tvec(Ms, a2, k.omw[s]);
+        k.pinert[s] = inert ? wing_inertial_power(in.wing_J, A, B, dphi, dal, dth, sg * acc[0], sg * acc[1], acc[2])
+                            : 0.0;
         const double* pv = s == 0 ? in.pivot_l : in.pivot_r;
         for (int i = 0; i < 3; ++i) k.piv[s][i] = pv[i];
         double pg[3];

@@ -1004,7 +1004,10 @@ __device__ inline void write_step(StateHdr* h, int p, const double* tot, const C
             for (int s = 0; s < 2; ++s) {
                 double wg[3];
                 mat_tvec(K.Mb, K.omw[s], wg);
-                put(35 + s, -(part(1 + s, 3) * wg[0] + part(1 + s, 4) * wg[1] + part(1 + s, 5) * wg[2]));
+                const double pa = -(part(1 + s, 3) * wg[0] + part(1 + s, 4) * wg[1] + part(1 + s, 5) * wg[2]);
+                put(35 + s, pa);
+                put(37 + s, K.pinert[s]);               // inertial power (Sec. 3.5)
+                put(39 + s, fmax(K.pinert[s] + pa, 0.0));  // total power, no energy storage
             }
         }
         // moments about x_cntr: part sums moved from each part's reference point

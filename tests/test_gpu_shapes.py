@@ -154,6 +154,37 @@ def test_general_insect_steps_match_oracle(kin, dtype):
         assert np.max(np.abs(h[:, 35:37] - oP)) <= 1e-9 * np.max(np.abs(oP))
 
 
+@pytest.mark.parametrize("kin", ["sine", "fourier", "hermite"])
+def test_inertial_and_total_power_match_oracle(kin):
+    """P_inert (Sec. 3.5) with a general wing tensor of inertia: the device
+    differentiates the wing's angular velocity exactly from the angle series,
+    the oracle by a central difference; P_total = max(P_inert + P_aero, 0)."""
+    n, nu, eta, steps = 32, 1 / 136, 5e-4, 6
+    extra = {"sine": {}, "fourier": fourier_kinematics(), "hermite": hermite_kinematics()}[kin]
+    body = dict(W.model_insect(n, L), wing_J=(2.0e-3, 5.0e-4, 2.4e-3, 3.0e-4, -2.0e-4, 1.5e-4), **extra)
+    u0 = W.inflow_noise(n, L, seed=41, rms=1e-2, kmax=4.0)
+    p = O.Params(n, L, nu, eta, O.MEAN_FIXED)
+    ost, oh = O.run(p, u0, steps, O.StepControl(cfl=0.1), O.Insect.from_dict(body))
+    P = F.Plan(n, L, nu, eta, "f64")
+    st = P.new_state(torch.from_numpy(u0))
+    h = P.step(st, steps, body, history=True, cfl=0.1).cpu().numpy()
+    # the Hermite cubic's second derivative jumps at its nodes; t = 0 is one,
+    # where the oracle's central difference averages the two sides
+    r = slice(1, None) if kin == "hermite" else slice(None)
+    oI = np.array([d["P_inert"] for d in oh])[r]
+    oT = np.array([d["P_total"] for d in oh])[r]
+    assert np.max(np.abs(oI)) > 1e-4
+    assert np.max(np.abs(h[r, 37:39] - oI)) <= 1e-7 * np.max(np.abs(oI))
+    assert np.max(np.abs(h[r, 39:41] - oT)) <= 1e-7 * max(np.max(np.abs(oT)), np.max(np.abs(oI)))
+    assert np.all(h[:, 39:41] >= 0.0)
+    # without a tensor of inertia the inertial power is zero and P_total = max(P_aero, 0)
+    body0 = dict(body, wing_J=(0.0,) * 6)
+    st0 = P.new_state(torch.from_numpy(u0))
+    h0 = P.step(st0, 2, body0, history=True, cfl=0.1).cpu().numpy()
+    assert np.all(h0[:, 37:39] == 0.0)
+    assert np.array_equal(h0[:, 39:41], np.maximum(h0[:, 35:37], 0.0))
+
+
 def test_wing_table_follows_coefficient_changes_and_ensembles():
     """A plan stepped with wing A, then wing B, equals fresh plans (the table is
     rebuilt on the stream); ensemble members with different wings equal their

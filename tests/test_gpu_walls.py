@@ -60,7 +60,7 @@ def test_layers_without_a_body():
     ou, oh, u, h = _both(n, 0.02, 1e-2, u0, None, 15, "f64", (0.5, 0.75, 0.0), (0.5, -0.25, 0.1),
                          mean_mode=F.FLUSI_MEAN_FREE, cfl=0.1)
     assert rel_l2(u, ou) < 1e-11
-    assert np.all(h[:, 4:37] == 0.0)  # no body: no force, pose or power records
+    assert np.all(h[:, 4:41] == 0.0)  # no body: no force, pose or power records
 
 
 def test_layers_with_sponge_and_rk4():

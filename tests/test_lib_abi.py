@@ -21,8 +21,8 @@ def test_library_exports_every_header_function():
 
 def test_struct_layouts_match_header():
     # flusi_insect: 4 ints + 47 doubles, then 4 ints, the angle series, the Fourier wing and the
-    # head/eye spheres and the rectangle; flusi_step_params: 2 ints, 5 doubles, 1 pointer
-    assert ctypes.sizeof(F.flusi_insect) == 16 + 8 * 47 + 16 + 8 * (3 * 2 * 25 + 2 + 2 * 33 + 8 + 4)
+    # head/eye spheres, the rectangle and the wing inertia; flusi_step_params: 2 ints, 5 doubles, 1 pointer
+    assert ctypes.sizeof(F.flusi_insect) == 16 + 8 * 47 + 16 + 8 * (3 * 2 * 25 + 2 + 2 * 33 + 8 + 4 + 6)
     assert ctypes.sizeof(F.flusi_step_params) == 8 + 5 * 8 + 8
 
 
@@ -47,6 +47,9 @@ def test_insect_struct_from_dict():
     assert s.body == F.FLUSI_BODY_ELLIPSOID and s.wings == 1 and s.smooth == F.FLUSI_SMOOTH_COS
     assert abs(s.wing_t - 4 * 4.0 / 256) < 1e-15
     assert list(s.pivot_r) == [0.0, -0.15, 0.0]
+    assert list(s.wing_J) == [0.0] * 6
+    s = F.make_insect(dict(W.model_insect(64, 4.0), wing_J=(1, 2, 3, 4, 5, 6)))
+    assert list(s.wing_J) == [1.0, 2.0, 3.0, 4.0, 5.0, 6.0]
 
 
 def test_size_queries_need_no_device():
