@@ -537,8 +537,8 @@ struct Impl final : ImplBase {
         }
         {
             PassScope ps(g.prof, PASS_KIN, st);
-            if (c < 0.0) k_kin_level<<<nbk, 64, 0, st>>>(g.mt, g.nmem, par);
-            else k_kin_stage<<<nbk, 64, 0, st>>>(g.mt, g.nmem, par, c);
+            if (c < 0.0) k_kin_level<T><<<nbk, NT_KIN, 0, st>>>(g.mt, g.nmem, par);
+            else k_kin_stage<T><<<nbk, NT_KIN, 0, st>>>(g.mt, g.nmem, par, c);
         }
         if (g.side && err == hipSuccess) err = hipEventRecord(g.ev_k, g.side);
         return g.side != nullptr;
@@ -554,7 +554,7 @@ struct Impl final : ImplBase {
     int run_steps_rk(const GroupRun& g, int nsteps) {
         {
             PassScope ps(g.prof, PASS_KIN, g.stream);
-            k_prologue<<<(unsigned)g.nmem, 64, 0, g.stream>>>(g.mt, g.nmem);
+            k_prologue<T><<<(unsigned)g.nmem, NT_KIN, 0, g.stream>>>(g.mt, g.nmem);
         }
         {
             PassScope ps(g.prof, PASS_ZINV, g.stream);
@@ -597,7 +597,7 @@ struct Impl final : ImplBase {
         if (g.rk) return run_steps_rk(g, nsteps);
         {
             PassScope ps(g.prof, PASS_KIN, g.stream);
-            k_prologue<<<(unsigned)g.nmem, 64, 0, g.stream>>>(g.mt, g.nmem);
+            k_prologue<T><<<(unsigned)g.nmem, NT_KIN, 0, g.stream>>>(g.mt, g.nmem);
         }
         {
             PassScope ps(g.prof, PASS_ZINV, g.stream);
@@ -633,7 +633,7 @@ struct Impl final : ImplBase {
         // free flight: advance the body to the new current level
         if (g.any_ff) {
             PassScope ps(g.prof, PASS_KIN, g.stream);
-            k_kin_level<<<(unsigned)g.nmem, 64, 0, g.stream>>>(g.mt, g.nmem, nsteps & 1);
+            k_kin_level<T><<<(unsigned)g.nmem, NT_KIN, 0, g.stream>>>(g.mt, g.nmem, nsteps & 1);
         }
         if (err != hipSuccess) return set_error(FLUSI_EDEVICE, "step: %s", hipGetErrorString(err));
         return launch_check("step");

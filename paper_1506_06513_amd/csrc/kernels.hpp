@@ -254,12 +254,15 @@ __global__ __launch_bounds__(NT) void k_colfft(const cx<T>* in, cx<T>* out, int 
                                       tile % nbx, tw, buf);
 }
 
-// Kinematics of member m and its two mask-evaluation blocks, by one wave (64
-// lanes).  The lanes stage the body description in LDS (one round trip
-// instead of a chain of dependent loads) and evaluate the sines and cosines in
-// parallel, in two rounds: the angle series and fixed angles, then the wing
-// angles that the series give.  One lane assembles the kinematics and the
-// blocks in LDS from those values; all lanes store them.
+// Kinematics of member m and the mask-evaluation blocks its passes read, by one
+// workgroup (one wave or more).  The threads stage the body description in
+// LDS (one round trip instead of a chain of dependent loads) and evaluate the
+// sines and cosines in parallel, in two rounds: the angle series and fixed
+// angles, then the wing angles that the series give.  One thread assembles
+// the kinematics in LDS from those values; the FP64 and FP32 blocks are then
+// converted by two waves at once where the workgroup has them, and only the
+// ones the plan's passes read (FP32: the FP32 block, and the FP64 one for the
+// part decision where parts overlap; FP64: the FP64 block); all threads store.
 // Time: slot p's time (at == false), or t_at (RK4 stages; no free flight).
 // In free flight the body pose is the free-flight state of the level: taken
 // from the tethered kinematics on the first free-flight step, or advanced by
@@ -282,22 +285,24 @@ static_assert(sizeof(flusi_insect) % 8 == 0 && sizeof(Kin) % 8 == 0 && sizeof(Ki
                   offsetof(StateHdr, kf) % 8 == 0 && offsetof(StateHdr, kd) % 8 == 0,
               "kinematics blocks are copied in 8-byte words");
 
-// nbytes (a multiple of 8; both ends 8-byte aligned) copied by the 64 lanes
-// of a wave.
+// nbytes (a multiple of 8; both ends 8-byte aligned) copied by the workgroup.
 __device__ __forceinline__ void wg_copy8(void* dst, const void* src, int nbytes) {
     auto* d = static_cast<unsigned long long*>(dst);
     const auto* q = static_cast<const unsigned long long*>(src);
-    for (int i = threadIdx.x & 63; i < nbytes / 8; i += 64) d[i] = q[i];
+    for (int i = threadIdx.x; i < nbytes / 8; i += blockDim.x) d[i] = q[i];
 }
 
+template <typename T>
 __device__ __forceinline__ void kin_update(const Member& m, int p, bool at, double t_at, KinShared& s) {
-    const int lane = threadIdx.x & 63;
-    wg_copy8(&s.in, m.ins, (int)sizeof(flusi_insect));
-    wave_sync();
-    const flusi_insect& in = s.in;
+    const int tid = threadIdx.x, nth = blockDim.x;
     StateHdr* h = m.hdr;
     Slot& sl = h->slot[p];
-    if (lane == 0) {
+    // the level's time is loaded alongside the description
+    const double t_lvl = at ? t_at : sl.t;
+    wg_copy8(&s.in, m.ins, (int)sizeof(flusi_insect));
+    __syncthreads();
+    const flusi_insect& in = s.in;
+    if (tid == 0) {
         int st = 0;
         if (!at && in.free_flight) {
             st = sl.ff_state;
@@ -319,35 +324,33 @@ __device__ __forceinline__ void kin_update(const Member& m, int p, bool at, doub
                 }
             }
         }
-        s.t = at ? t_at : sl.t;
+        s.t = t_lvl;
         s.st = st;
         s.n = kin_trig_args(in, s.t, st != 0, 0, nullptr, s.arg, s.dep);
     }
-    wave_sync();
+    __syncthreads();
     const int n = s.n;
-    for (int j = lane; j < n; j += 64)
+    for (int j = tid; j < n; j += nth)
         if (!s.dep[j]) s.val[j] = sin_cos(s.arg[j]);
-    wave_sync();
+    __syncthreads();
     if (in.wings) {
-        if (lane == 0) {
+        if (tid == 0) {
             double ang[3], rate[3];
             wing_angle_values(in, s.t, ang, rate, TrigTable{s.arg, s.val, n, s.st != 0 ? 0 : 6});
             kin_trig_args(in, s.t, s.st != 0, 1, ang, s.arg, s.dep);
         }
-        wave_sync();
-        for (int j = lane; j < n; j += 64)
+        __syncthreads();
+        for (int j = tid; j < n; j += nth)
             if (s.dep[j]) s.val[j] = sin_cos(s.arg[j]);
-        wave_sync();
+        __syncthreads();
     }
-    if (lane == 0) {
+    if (tid == 0) {
         const int st = s.st;
-        // assembled in LDS: the blocks never occupy registers
+        // assembled in LDS: the block never occupies registers
         Kin& k = s.k;
         compute_kin(in, s.t, m.dx, k, st != 0 ? s.y : nullptr, TrigTable{s.arg, s.val, n, 0});
         k.rtab = m.rtab;
         k.rtab32 = m.rtab32;
-        kin_cast<float>(k, s.kf);
-        kin_cast<double>(k, s.kd);
         if (in.free_flight && !at) {
             if (st == 0) {
                 for (int i = 0; i < 3; ++i) {
@@ -366,10 +369,16 @@ __device__ __forceinline__ void kin_update(const Member& m, int p, bool at, doub
             sl.ff_state = 1;
         }
     }
-    wave_sync();
+    __syncthreads();
+    constexpr bool F64 = sizeof(T) == 8;
+    const bool need_kd = F64 || m.nc > 1, need_kf = !F64;
+    const int tkf = nth > 64 ? 64 : 0;  // second wave where there is one
+    if (tid == 0 && need_kd) kin_cast<double>(s.k, s.kd);
+    if (tid == tkf && need_kf) kin_cast<float>(s.k, s.kf);
+    __syncthreads();
     wg_copy8(&h->kin, &s.k, (int)sizeof(Kin));
-    wg_copy8(&h->kf, &s.kf, (int)sizeof(KinT<float>));
-    wg_copy8(&h->kd, &s.kd, (int)sizeof(KinT<double>));
+    if (need_kf) wg_copy8(&h->kf, &s.kf, (int)sizeof(KinT<float>));
+    if (need_kd) wg_copy8(&h->kd, &s.kd, (int)sizeof(KinT<double>));
 }
 
 // y passes of the stepping schedule over a member table.
@@ -379,10 +388,10 @@ __device__ __forceinline__ void kin_update(const Member& m, int p, bool at, doub
 // Each member has nbx*nf column tiles followed by the extra workgroups:
 //   EXTRA 1: nred_of(NX, N) workgroups reduce the x-pass sums (first level)
 // nwg: x-pass workgroups per member (records of the first-level reduction).
-// EXTRA 2 (y-inverse): the grid starts with one workgroup per member whose
-// first wave evaluates the member's kinematics of time level nwg (members
-// whose kinematics change with time), beside the column tiles: the y-inverse
-// does not read them, the x-pass after it does.  That path is held to the
+// EXTRA 2 (y-inverse): the grid starts with one workgroup per member that
+// evaluates the member's kinematics of time level nwg (members whose
+// kinematics change with time), beside the column tiles: the y-inverse does
+// not read them, the x-pass after it does.  That path is held to the
 // register budget of four waves per SIMD, which the column tiles' LDS allows
 // at most anyway for the larger tiles.
 // nfwd: forward fields per member (3, or 6 when a member of the launch has the
@@ -404,8 +413,8 @@ __global__ __launch_bounds__(NT, EXTRA == 2 ? 4 : 1) void k_ypass(const Member* 
         const int nmem = nb / (per + 1);
         if (bid < nmem) {
             const Member& m = mt[bid];
-            if (threadIdx.x < 64 && m.dyn && !*gview(&m.hdr->status))
-                kin_update(m, nwg, false, 0.0, *reinterpret_cast<KinShared*>(lds));
+            if (m.dyn && !*gview(&m.hdr->status))
+                kin_update<T>(m, nwg, false, 0.0, *reinterpret_cast<KinShared*>(lds));
             return;
         }
         bid -= nmem;
@@ -1188,9 +1197,14 @@ __device__ inline void reduce_scalars(const double* __restrict__ partial2, doubl
     }
 }
 
+// Threads of the stand-alone kinematics kernels (two waves: the two
+// mask-block conversions run at once).
+constexpr int NT_KIN = 128;
+
 // Start of a stepping call, one workgroup per member: make slot 0 current and
 // evaluate the kinematics of the current time level.
-static __global__ __launch_bounds__(64) void k_prologue(const Member* __restrict__ mt, int nmem) {
+template <typename T>
+static __global__ __launch_bounds__(NT_KIN) void k_prologue(const Member* __restrict__ mt, int nmem) {
     if ((int)blockIdx.x >= nmem) return;
     const Member& m = mt[blockIdx.x];
     StateHdr* hdr = m.hdr;
@@ -1200,26 +1214,28 @@ static __global__ __launch_bounds__(64) void k_prologue(const Member* __restrict
     }
     __syncthreads();
     __shared__ KinShared ks;
-    if (m.nc > 0 && !hdr->status) kin_update(m, 0, false, 0.0, ks);
+    if (m.nc > 0 && !hdr->status) kin_update<T>(m, 0, false, 0.0, ks);
 }
 
 // Kinematics of time level p of every member whose kinematics change with
-// time (one workgroup per member), before the pass that reads them; after the
-// last step of a call it completes the pending free-flight advance.
-static __global__ __launch_bounds__(64) void k_kin_level(const Member* __restrict__ mt, int nmem, int p) {
+// time (one workgroup per member); after the last step of a call it
+// completes the pending free-flight advance.
+template <typename T>
+static __global__ __launch_bounds__(NT_KIN) void k_kin_level(const Member* __restrict__ mt, int nmem, int p) {
     if ((int)blockIdx.x >= nmem) return;
     const Member& m = mt[blockIdx.x];
     __shared__ KinShared ks;
-    if (m.dyn && !m.hdr->status) kin_update(m, p, false, 0.0, ks);
+    if (m.dyn && !m.hdr->status) kin_update<T>(m, p, false, 0.0, ks);
 }
 
 // RK4 stage kinematics (one workgroup per moving member): time t^n + c*dt,
 // with t^n in slot p and dt in the slot the step's first stage wrote.
-static __global__ __launch_bounds__(64) void k_kin_stage(const Member* __restrict__ mt, int nmem, int p, double c) {
+template <typename T>
+static __global__ __launch_bounds__(NT_KIN) void k_kin_stage(const Member* __restrict__ mt, int nmem, int p, double c) {
     if ((int)blockIdx.x >= nmem) return;
     const Member& m = mt[blockIdx.x];
     __shared__ KinShared ks;
-    if (m.dyn && !m.hdr->status) kin_update(m, p, true, m.hdr->slot[p].t + c * m.hdr->slot[1 - p].rk_dt, ks);
+    if (m.dyn && !m.hdr->status) kin_update<T>(m, p, true, m.hdr->slot[p].t + c * m.hdr->slot[1 - p].rk_dt, ks);
 }
 
 // Free-flight state of the current time level of a state (one thread).
