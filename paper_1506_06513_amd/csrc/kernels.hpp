@@ -1541,17 +1541,25 @@ __global__ __launch_bounds__(nt_z(N, V)) void k_zpass(const Member* __restrict__
                 } else {
                     const double e1 = exy[0] * exz[AB2M ? 0 : 0][AB2M ? m : 0];
                     const double c2 = first ? 0.0 : b2 * (exy[1] * exz[AB2M ? 1 : 0][AB2M ? m : 0]);
+                    // the six loads of this mode are issued before its first
+                    // store, so that they are in flight together (interleaved
+                    // with the stores, which may alias them as far as the
+                    // compiler knows, each would wait one memory round trip)
+                    cx<T> uo[3], no[3];
 #pragma unroll
                     for (int f = 0; f < 3; ++f) {
-                        const cx<T> uo = gld(uhat, f * fs_s + e);
+                        uo[f] = gld(uhat, f * fs_s + e);
+                        if (!first) no[f] = gld(nold, f * fs_s + e);
+                    }
+#pragma unroll
+                    for (int f = 0; f < 3; ++f) {
                         double ar = nr[f], ai = ni[f];
                         if (!first) {
-                            const cx<T> no = gld(nold, f * fs_s + e);
-                            ar = b1 * nr[f] + c2 * (double)no.x;
-                            ai = b1 * ni[f] + c2 * (double)no.y;
+                            ar = b1 * nr[f] + c2 * (double)no[f].x;
+                            ai = b1 * ni[f] + c2 * (double)no[f].y;
                         }
-                        const double vr = e1 * ((double)uo.x + dt * ar);
-                        const double vi = e1 * ((double)uo.y + dt * ai);
+                        const double vr = e1 * ((double)uo[f].x + dt * ar);
+                        const double vi = e1 * ((double)uo[f].y + dt * ai);
                         U[f][i] = cx<T>{T(vr), T(vi)};
                         gst(uhat, f * fs_s + e, U[f][i]);
                         gst(nold, f * fs_s + e, cx<T>{T(nr[f]), T(ni[f])});
