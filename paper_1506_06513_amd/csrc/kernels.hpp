@@ -475,6 +475,42 @@ __device__ __forceinline__ double wave_sum(double v) {
     return __hiloint2double(__builtin_amdgcn_readlane(__double2hiint(v), 63),
                             __builtin_amdgcn_readlane(__double2loint(v), 63));
 }
+
+// Wave sums of twelve FP64 values per lane at once, in a fixed order.  The
+// values are halved over lanes twice with the gfx950 half-wave and row swaps
+// (lanes 0-31 go on with values 0-5 summed over lanes l and l + 32, lanes 32-63
+// with values 6-11; then row r of 16 lanes with values 3r .. 3r + 2), and the
+// three left in each row are summed within the row by DPP.  Lane 16r + 15
+// returns the totals of values 3r, 3r + 1, 3r + 2 in s[0..2].  About a quarter
+// of the instructions of twelve separate wave sums.
+__device__ __forceinline__ double swap_add32(double x, double y) {
+    const auto lo = __builtin_amdgcn_permlane32_swap((unsigned)__double2loint(x), (unsigned)__double2loint(y), false, false);
+    const auto hi = __builtin_amdgcn_permlane32_swap((unsigned)__double2hiint(x), (unsigned)__double2hiint(y), false, false);
+    // first: x on lanes 0-31, y's lanes 0-31 on 32-63; second: x's lanes 32-63
+    // on 0-31, y on 32-63
+    return __hiloint2double((int)hi[0], (int)lo[0]) + __hiloint2double((int)hi[1], (int)lo[1]);
+}
+__device__ __forceinline__ double swap_add16(double x, double y) {
+    const auto lo = __builtin_amdgcn_permlane16_swap((unsigned)__double2loint(x), (unsigned)__double2loint(y), false, false);
+    const auto hi = __builtin_amdgcn_permlane16_swap((unsigned)__double2hiint(x), (unsigned)__double2hiint(y), false, false);
+    // first: rows 0 and 2 of x, rows 0 and 2 of y in rows 1 and 3; second:
+    // rows 1 and 3 of x in rows 0 and 2, rows 1 and 3 of y
+    return __hiloint2double((int)hi[0], (int)lo[0]) + __hiloint2double((int)hi[1], (int)lo[1]);
+}
+__device__ __forceinline__ void wave_sum12(const double (&v)[12], double (&s)[3]) {
+    double a[6];
+#pragma unroll
+    for (int j = 0; j < 6; ++j) a[j] = swap_add32(v[j], v[j + 6]);
+#pragma unroll
+    for (int j = 0; j < 3; ++j) {
+        double b = swap_add16(a[j], a[j + 3]);
+        b += dpp_move<0xb1, 0xf, 0xf>(b);   // quad_perm [1,0,3,2]
+        b += dpp_move<0x4e, 0xf, 0xf>(b);   // quad_perm [2,3,0,1]
+        b += dpp_move<0x114, 0xf, 0xe>(b);  // row_shr:4
+        b += dpp_move<0x118, 0xf, 0xc>(b);  // row_shr:8
+        s[j] = b;
+    }
+}
 __device__ __forceinline__ double wave_max(double v) {
     v = wave_reduce63<true>(v);
     return __hiloint2double(__builtin_amdgcn_readlane(__double2hiint(v), 63),
@@ -518,12 +554,21 @@ __device__ __forceinline__ void block_reduce_store(const double (&acc)[NVAL], do
 // SP: members with the vorticity sponge; chi_sp * w is transformed beside N
 // and stored as fields 3..5.
 // Workgroups per CU the x-pass asks the compiler to fit (registers), where
-// its LDS allows: the FP32 full-size tile without wing parts (its twiddles
-// are then read from the table in memory, keeping the tile under 40 KiB);
-// not at nx = 512, where the 128-register budget spills.
+// its LDS allows: the FP32 full-size tile without the sponge (its twiddles are
+// then read from the table in memory, and the three-colour tile also drops the
+// column pad, keeping the tile under 40 KiB); not at nx = 512, where the
+// 128-register budget spills.
 template <typename T, int NX, int NC, int V, bool SP>
 __host__ __device__ constexpr int xpass_min_blocks() {
-    return (sizeof(T) < 8 && V == 0 && NC <= 1 && !SP && NX < 512) ? 4 : 1;
+    return (sizeof(T) < 8 && V == 0 && !SP && NX < 512) ? 4 : 1;
+}
+// Column stride of the x-pass tile: the FFT layout's (cm_stride), without its
+// one-element pad for the three-colour tile at 4 workgroups per CU (the pad
+// spreads the column starts over the LDS banks; without it 256^3 and 128^3
+// measured no slower, and the tile fits in 40 KiB).
+template <typename T, int NX, int NC, int V, bool SP>
+__host__ __device__ constexpr int xpass_stride() {
+    return (NC > 1 && xpass_min_blocks<T, NX, NC, V, SP>() == 4) ? NX + NX / 16 : cm_stride(NX);
 }
 // Threads per x-pass workgroup: NT, except for one-row tiles of rows of 1024
 // points or more, whose columns take 32 lanes each (36 values per lane at
@@ -551,7 +596,7 @@ __global__ __launch_bounds__((xpass_threads<T, NX, V, SP>()), (xpass_min_blocks<
     const double dx = m.dx, inv_eta = m.inv_eta;
     glb<double>* __restrict__ partial = gview(m.partial);
     const int wg = blockIdx.x % NWG;
-    constexpr int SC = cm_stride(NX);
+    constexpr int SC = xpass_stride<T, NX, NC, V, SP>();
     // forward columns: (N_x, N_y) of each row, N_z of row pairs (one row:
     // N_z alone, with a zero imaginary part)
     constexpr int CI = 3 * RW, CF = RW == 1 ? 2 : 3 * RW / 2;
@@ -796,9 +841,9 @@ __global__ __launch_bounds__((xpass_threads<T, NX, V, SP>()), (xpass_min_blocks<
                     for (int e = 0; e < 12; ++e) acc[3 + e] += val[e];
                 }
             } else {
-                // every lane takes part in the DPP sums (lanes of other colours
-                // add 0); each term is formed just before its sum, so that no
-                // array of the twelve terms stays live across the branch
+                // every lane takes part in the wave sums (lanes of other colours
+                // add 0); the twelve terms of a colour are formed only in waves
+                // where it is present and summed together (wave_sum12)
                 if (has) penalize();
                 const int ci = has ? mp.colour - 1 : -1;
                 static_for<NC>([&](auto cc) {
@@ -810,14 +855,18 @@ __global__ __launch_bounds__((xpass_threads<T, NX, V, SP>()), (xpass_min_blocks<
                         const double q[3] = {ch * s0, ch * s1, ch * s2};
                         const double rx = xg - kin.xref[col][0], ry = yg - kin.xref[col][1],
                                      rz = zg - kin.xref[col][2];
-                        const auto add = [&](int e, double v) {
-                            const double r = wave_sum(mine ? v : 0.0);
-                            if (lane == 0) wred[wv][3 + 12 * col + e] += r;
-                        };
-                        add(0, p[0]); add(1, p[1]); add(2, p[2]);
-                        add(3, ry * p[2] - rz * p[1]); add(4, rz * p[0] - rx * p[2]); add(5, rx * p[1] - ry * p[0]);
-                        add(6, q[0]); add(7, q[1]); add(8, q[2]);
-                        add(9, ry * q[2] - rz * q[1]); add(10, rz * q[0] - rx * q[2]); add(11, rx * q[1] - ry * q[0]);
+                        const double t[12] = {p[0], p[1], p[2],
+                                              ry * p[2] - rz * p[1], rz * p[0] - rx * p[2], rx * p[1] - ry * p[0],
+                                              q[0], q[1], q[2],
+                                              ry * q[2] - rz * q[1], rz * q[0] - rx * q[2], rx * q[1] - ry * q[0]};
+                        double v[12], sr[3];
+#pragma unroll
+                        for (int e = 0; e < 12; ++e) v[e] = mine ? t[e] : 0.0;
+                        wave_sum12(v, sr);
+                        if ((lane & 15) == 15) {
+#pragma unroll
+                            for (int j = 0; j < 3; ++j) wred[wv][3 + 12 * col + 3 * (lane >> 4) + j] += sr[j];
+                        }
                     }
                 });
             }
