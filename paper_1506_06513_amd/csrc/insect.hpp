@@ -311,9 +311,16 @@ __device__ inline int kin_trig_args(const flusi_insect& in, double t, bool pose,
 // Kinematics at time t (Sec. 3.1 and 3.3).  dx is the grid spacing.  pose
 // (13 values: x_cntr, u_cntr, eps, Omega^(b)) replaces the prescribed body
 // motion in free flight (Sec. 3.6); null for a tethered body.
+// In three parts, which the device runs on different lanes: kin_body (the
+// body, the outline and every field but the wing frames; returns the cull
+// radius of the body parts about x_cntr), kin_wing (the frames, rates and
+// reference point of wing s, from the wing angles; returns the cull radius
+// that wing adds), kin_nowings.  The sines and cosines are requested in the
+// order kin_trig_args lists them: kin_body's six, the angle series
+// (wing_angle_values), then four for the left wing and five for the right.
 template <class TR = TrigEval>
-__host__ __device__ __forceinline__ void compute_kin(const flusi_insect& in, double t, double dx, Kin& k,
-                                                     const double* pose = nullptr, TR&& tr = TR{}) {
+__host__ __device__ __forceinline__ double kin_body(const flusi_insect& in, double t, double dx, Kin& k,
+                                                    const double* pose = nullptr, TR&& tr = TR{}) {
     if (pose) {
         for (int i = 0; i < 3; ++i) {
             k.xc[i] = pose[i];
@@ -404,64 +411,84 @@ __host__ __device__ __forceinline__ void compute_kin(const flusi_insect& in, dou
     }
     k.rtab = nullptr;
     k.rtab32 = nullptr;
+    return rall;
+}
 
-    if (!in.wings) {
-        // no wings: identity wing frames, zero rates, reference points at the centre
-        for (int s = 0; s < 2; ++s) {
-            for (int i = 0; i < 9; ++i) k.Mws[s][i] = (i % 4 == 0) ? 1.0 : 0.0;
-            for (int i = 0; i < 3; ++i) {
-                k.piv[s][i] = 0.0;
-                k.omw[s][i] = 0.0;
-                k.xref[1 + s][i] = k.xc[i];
-            }
-            k.pinert[s] = 0.0;
+__host__ __device__ inline void kin_nowings(Kin& k) {
+    // no wings: identity wing frames, zero rates, reference points at the centre
+    for (int s = 0; s < 2; ++s) {
+        for (int i = 0; i < 9; ++i) k.Mws[s][i] = (i % 4 == 0) ? 1.0 : 0.0;
+        for (int i = 0; i < 3; ++i) {
+            k.piv[s][i] = 0.0;
+            k.omw[s][i] = 0.0;
+            k.xref[1 + s][i] = k.xc[i];
         }
+        k.pinert[s] = 0.0;
+    }
+}
+
+// wing s (0 left, 1 right) from the wing angles ang, their rates and second
+// derivatives; inert: the wings have a tensor of inertia
+template <class TR = TrigEval>
+__host__ __device__ __forceinline__ double kin_wing(const flusi_insect& in, Kin& k, int s, const double* ang,
+                                                    const double* rate, const double* acc, bool inert,
+                                                    TR&& tr = TR{}) {
+    const double phi0 = ang[0], dphi0 = rate[0], al0 = ang[1], dal0 = rate[1], th = ang[2], dth = rate[2];
+    const double sg = s == 0 ? 1.0 : -1.0;  // right wing: alpha and phi mirrored
+    const double phi = sg * phi0, dphi = sg * dphi0, al = sg * al0, dal = sg * dal0;
+    double Ms[9], Mw[9], A[9], B[9], C[9];
+    mat_ry(in.eta_stroke, Ms, tr);
+    if (s == 1) {
+        double Rpi[9];
+        mat_rx(M_PI, Rpi, tr);
+        mat_mul(Rpi, Ms, Ms);
+    }
+    mat_ry(al, A, tr);
+    mat_rz(-th, B, tr);
+    mat_rx(phi, C, tr);
+    mat_mul(A, B, Mw);
+    mat_mul(Mw, C, Mw);
+    mat_mul(Mw, Ms, k.Mws[s]);
+    // stroke-frame angular velocity: Rx^T(phi)[(dphi,0,0) + Rz^T(-th)[(0,0,-dth) + Ry^T(al)(0,dal,0)]]
+    double a1[3] = {0.0, dal, 0.0}, a2[3];
+    mat_tvec(A, a1, a2);
+    a2[2] -= dth;
+    mat_tvec(B, a2, a1);
+    a1[0] += dphi;
+    mat_tvec(C, a1, a2);
+    mat_tvec(Ms, a2, k.omw[s]);
+    k.pinert[s] = inert ? wing_inertial_power(in.wing_J, A, B, dphi, dal, dth, sg * acc[0], sg * acc[1], acc[2])
+                        : 0.0;
+    const double* pv = s == 0 ? in.pivot_l : in.pivot_r;
+    for (int i = 0; i < 3; ++i) k.piv[s][i] = pv[i];
+    double pg[3];
+    mat_tvec(k.Mb, pv, pg);
+    for (int i = 0; i < 3; ++i) k.xref[1 + s][i] = k.xc[i] + pg[i];
+    const double e1 = k.wrad + k.thr, e2 = 0.5 * in.wing_t + k.thr;
+    const double pn = sqrt(pv[0] * pv[0] + pv[1] * pv[1] + pv[2] * pv[2]);
+    const double cn = sqrt(k.wcen[0] * k.wcen[0] + k.wcen[1] * k.wcen[1]);
+    return pn + cn + sqrt(e1 * e1 + e2 * e2);
+}
+
+__host__ __device__ inline bool wings_inert(const flusi_insect& in) {
+    bool inert = false;
+    for (int i = 0; i < 6; ++i) inert = inert || in.wing_J[i] != 0.0;
+    return inert;
+}
+
+template <class TR = TrigEval>
+__host__ __device__ __forceinline__ void compute_kin(const flusi_insect& in, double t, double dx, Kin& k,
+                                                     const double* pose = nullptr, TR&& tr = TR{}) {
+    double rall = kin_body(in, t, dx, k, pose, tr);
+    if (!in.wings) {
+        kin_nowings(k);
         k.r2all = rall * rall;
         return;
     }
     double ang[3], rate[3], acc[3];
     wing_angle_values(in, t, ang, rate, tr, acc);
-    const double phi0 = ang[0], dphi0 = rate[0], al0 = ang[1], dal0 = rate[1], th = ang[2], dth = rate[2];
-    bool inert = false;
-    for (int i = 0; i < 6; ++i) inert = inert || in.wing_J[i] != 0.0;
-    for (int s = 0; s < 2; ++s) {
-        const double sg = s == 0 ? 1.0 : -1.0;  // right wing: alpha and phi mirrored
-        const double phi = sg * phi0, dphi = sg * dphi0, al = sg * al0, dal = sg * dal0;
-        double Ms[9], Mw[9], A[9], B[9], C[9];
-        mat_ry(in.eta_stroke, Ms, tr);
-        if (s == 1) {
-            double Rpi[9];
-            mat_rx(M_PI, Rpi, tr);
-            mat_mul(Rpi, Ms, Ms);
-        }
-        mat_ry(al, A, tr);
-        mat_rz(-th, B, tr);
-        mat_rx(phi, C, tr);
-        mat_mul(A, B, Mw);
-        mat_mul(Mw, C, Mw);
-        mat_mul(Mw, Ms, k.Mws[s]);
-        // stroke-frame angular velocity: Rx^T(phi)[(dphi,0,0) + Rz^T(-th)[(0,0,-dth) + Ry^T(al)(0,dal,0)]]
-        double a1[3] = {0.0, dal, 0.0}, a2[3];
-        mat_tvec(A, a1, a2);
-        a2[2] -= dth;
-        mat_tvec(B, a2, a1);
-        a1[0] += dphi;
-        mat_tvec(C, a1, a2);
-        mat_tvec(Ms, a2, k.omw[s]);
-        k.pinert[s] = inert ? wing_inertial_power(in.wing_J, A, B, dphi, dal, dth, sg * acc[0], sg * acc[1], acc[2])
-                            : 0.0;
-        const double* pv = s == 0 ? in.pivot_l : in.pivot_r;
-        for (int i = 0; i < 3; ++i) k.piv[s][i] = pv[i];
-        double pg[3];
-        mat_tvec(k.Mb, pv, pg);
-        for (int i = 0; i < 3; ++i) k.xref[1 + s][i] = k.xc[i] + pg[i];
-        if (in.wings) {
-            const double e1 = k.wrad + k.thr, e2 = 0.5 * in.wing_t + k.thr;
-            const double pn = sqrt(pv[0] * pv[0] + pv[1] * pv[1] + pv[2] * pv[2]);
-            const double cn = sqrt(k.wcen[0] * k.wcen[0] + k.wcen[1] * k.wcen[1]);
-            rall = fmax(rall, pn + cn + sqrt(e1 * e1 + e2 * e2));
-        }
-    }
+    const bool inert = wings_inert(in);
+    for (int s = 0; s < 2; ++s) rall = fmax(rall, kin_wing(in, k, s, ang, rate, acc, inert, tr));
     k.r2all = rall * rall;
 }
 
@@ -485,26 +512,41 @@ struct KinT {
 template <typename TM>
 __device__ __forceinline__ TM tanh_cut() { return sizeof(TM) == 4 ? TM(10) : TM(20); }
 
+// The conversion in two parts: the 69 array elements (Mb, xc, uc, omb; Mws,
+// piv, omw; xref; sph), which the lanes of a wave share (element e on lane
+// e mod nl), and the rest with the cull radii (one lane).
 template <typename TM>
-__device__ inline void kin_cast(const Kin& a, KinT<TM>& b) {
-    for (int i = 0; i < 9; ++i) {
-        b.Mb[i] = TM(a.Mb[i]);
-        b.Mws[0][i] = TM(a.Mws[0][i]);
-        b.Mws[1][i] = TM(a.Mws[1][i]);
+__device__ inline void kin_cast_arrays(const Kin& a, KinT<TM>& b, int lane, int nl) {
+    // runs of arrays that are contiguous in both layouts
+    static_assert(offsetof(Kin, xc) == offsetof(Kin, Mb) + 9 * sizeof(double) &&
+                      offsetof(Kin, omb) == offsetof(Kin, Mb) + 15 * sizeof(double) &&
+                      offsetof(Kin, omw) == offsetof(Kin, Mws) + 24 * sizeof(double) &&
+                      offsetof(KinT<TM>, xc) == offsetof(KinT<TM>, Mb) + 9 * sizeof(TM) &&
+                      offsetof(KinT<TM>, omb) == offsetof(KinT<TM>, Mb) + 15 * sizeof(TM) &&
+                      offsetof(KinT<TM>, Mws) == offsetof(KinT<TM>, Mb) + 18 * sizeof(TM) &&
+                      offsetof(KinT<TM>, omw) == offsetof(KinT<TM>, Mws) + 24 * sizeof(TM),
+                  "contiguous kinematics arrays");
+    const char* pa = reinterpret_cast<const char*>(&a);
+    char* pb = reinterpret_cast<char*>(&b);
+    for (int e = lane; e < 69; e += nl) {
+        size_t oa, ob;
+        int o;
+        if (e < 18) { oa = offsetof(Kin, Mb); ob = offsetof(KinT<TM>, Mb); o = e; }
+        else if (e < 48) { oa = offsetof(Kin, Mws); ob = offsetof(KinT<TM>, Mws); o = e - 18; }
+        else if (e < 57) { oa = offsetof(Kin, xref); ob = offsetof(KinT<TM>, xref); o = e - 48; }
+        else { oa = offsetof(Kin, sph); ob = offsetof(KinT<TM>, sph); o = e - 57; }
+        reinterpret_cast<TM*>(pb + ob)[o] = TM(reinterpret_cast<const double*>(pa + oa)[o]);
     }
-    for (int i = 0; i < 3; ++i) {
-        b.xc[i] = TM(a.xc[i]); b.uc[i] = TM(a.uc[i]); b.omb[i] = TM(a.omb[i]);
-        for (int s = 0; s < 2; ++s) { b.piv[s][i] = TM(a.piv[s][i]); b.omw[s][i] = TM(a.omw[s][i]); }
-        for (int c = 0; c < 3; ++c) b.xref[c][i] = TM(a.xref[c][i]);
-    }
+}
+
+template <typename TM>
+__device__ inline void kin_cast_rest(const Kin& a, KinT<TM>& b) {
     b.h = TM(a.h);
     b.radius = TM(a.radius); b.ea = TM(a.ea); b.eb = TM(a.eb);
     b.wA = TM(a.wA); b.wB = TM(a.wB); b.wt = TM(a.wt);
     b.body = a.body; b.wings = a.wings; b.smooth = a.smooth; b.pad = 0;
     b.wshape = a.wshape; b.nsph = a.nsph;
     b.wcx = TM(a.wcen[0]); b.wcy = TM(a.wcen[1]); b.wrad = TM(a.wrad);
-    for (int q = 0; q < 3; ++q)
-        for (int i = 0; i < 4; ++i) b.sph[q][i] = TM(a.sph[q][i]);
     if constexpr (sizeof(TM) == 4) b.rtab = reinterpret_cast<const TM*>(a.rtab32);
     else b.rtab = reinterpret_cast<const TM*>(a.rtab);
     // cull radius recomputed for the precision's own tanh cut-off
@@ -542,6 +584,12 @@ __device__ inline void kin_cast(const Kin& a, KinT<TM>& b) {
         if (a.wings) rall = fmax(rall, sqrt(cg[0] * cg[0] + cg[1] * cg[1] + cg[2] * cg[2]) + rw);
     }
     b.r2all = TM(rall * rall * (1.0 + 1e-5));
+}
+
+template <typename TM>
+__device__ inline void kin_cast(const Kin& a, KinT<TM>& b) {
+    kin_cast_arrays(a, b, 0, 1);
+    kin_cast_rest(a, b);
 }
 
 template <typename TM>

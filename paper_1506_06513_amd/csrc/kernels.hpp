@@ -258,11 +258,13 @@ __global__ __launch_bounds__(NT) void k_colfft(const cx<T>* in, cx<T>* out, int 
 // workgroup (one wave or more).  The threads stage the body description in
 // LDS (one round trip instead of a chain of dependent loads) and evaluate the
 // sines and cosines in parallel, in two rounds: the angle series and fixed
-// angles, then the wing angles that the series give.  One thread assembles
-// the kinematics in LDS from those values; the FP64 and FP32 blocks are then
-// converted by two waves at once where the workgroup has them, and only the
-// ones the plan's passes read (FP32: the FP32 block, and the FP64 one for the
-// part decision where parts overlap; FP64: the FP64 block); all threads store.
+// angles, then the wing angles that the series give.  From those values one
+// thread assembles the body part of the kinematics in LDS and two lanes the
+// two wings (kin_body, kin_wing); the FP64 and FP32 blocks are then converted,
+// their arrays on all lanes of a wave, by two waves at once where the
+// workgroup has them, and only the ones the plan's passes read (FP32: the
+// FP32 block, and the FP64 one for the part decision where parts overlap;
+// FP64: the FP64 block); all threads store.
 // Time: slot p's time (at == false), or t_at (RK4 stages; no free flight).
 // In free flight the body pose is the free-flight state of the level: taken
 // from the tethered kinematics on the first free-flight step, or advanced by
@@ -277,6 +279,7 @@ struct KinShared {
     SinCos val[KIN_TRIG_MAX];
     unsigned char dep[KIN_TRIG_MAX];
     double y[13], f[13];
+    double rall[3];  // cull radii of the body parts and of each wing (kin_body, kin_wing)
     double t;
     int n, st;
 };
@@ -344,37 +347,67 @@ __device__ __forceinline__ void kin_update(const Member& m, int p, bool at, doub
             if (s.dep[j]) s.val[j] = sin_cos(s.arg[j]);
         __syncthreads();
     }
+    // assembled in LDS: the block never occupies registers
+    Kin& k = s.k;
+    const int st = s.st;
     if (tid == 0) {
-        const int st = s.st;
-        // assembled in LDS: the block never occupies registers
-        Kin& k = s.k;
-        compute_kin(in, s.t, m.dx, k, st != 0 ? s.y : nullptr, TrigTable{s.arg, s.val, n, 0});
+        const double rb = kin_body(in, s.t, m.dx, k, st != 0 ? s.y : nullptr, TrigTable{s.arg, s.val, n, 0});
+        s.rall[0] = rb;
+        if (!in.wings) {
+            kin_nowings(k);
+            k.r2all = rb * rb;
+        }
         k.rtab = m.rtab;
         k.rtab32 = m.rtab32;
-        if (in.free_flight && !at) {
-            if (st == 0) {
-                for (int i = 0; i < 3; ++i) {
-                    s.y[i] = k.xc[i];
-                    s.y[3 + i] = k.uc[i];
-                    s.y[10 + i] = k.omb[i];
-                }
-                for (int i = 0; i < 4; ++i) s.y[6 + i] = k.eps[i];
-            }
-            if (st != 1)
-                for (int i = 0; i < 13; ++i) sl.ff[i] = s.y[i];
-            if (st == 2)
-                for (int i = 0; i < 13; ++i) sl.ff_f[i] = s.f[i];
-            if (st == 0) sl.ff_have_prev = 0;
-            if (st == 2) sl.ff_have_prev = 1;
-            sl.ff_state = 1;
-        }
     }
     __syncthreads();
+    if (in.wings) {
+        // the two wings on lanes 0 and 1 (one instruction stream for both);
+        // each reads its sines and cosines at its own place in the table
+        if (tid < 2) {
+            TrigTable tt{s.arg, s.val, n, st != 0 ? 0 : 6};
+            double ang[3], rate[3], acc[3];
+            wing_angle_values(in, s.t, ang, rate, tt, acc);
+            if (tid == 1) tt.i += 4;  // past the left wing's four
+            s.rall[1 + tid] = kin_wing(in, k, tid, ang, rate, acc, wings_inert(in), tt);
+        }
+        __syncthreads();
+        if (tid == 0) {
+            const double r = fmax(fmax(s.rall[0], s.rall[1]), s.rall[2]);
+            k.r2all = r * r;
+        }
+    }
+    if (tid == 0 && in.free_flight && !at) {
+        if (st == 0) {
+            for (int i = 0; i < 3; ++i) {
+                s.y[i] = k.xc[i];
+                s.y[3 + i] = k.uc[i];
+                s.y[10 + i] = k.omb[i];
+            }
+            for (int i = 0; i < 4; ++i) s.y[6 + i] = k.eps[i];
+        }
+        if (st != 1)
+            for (int i = 0; i < 13; ++i) sl.ff[i] = s.y[i];
+        if (st == 2)
+            for (int i = 0; i < 13; ++i) sl.ff_f[i] = s.f[i];
+        if (st == 0) sl.ff_have_prev = 0;
+        if (st == 2) sl.ff_have_prev = 1;
+        sl.ff_state = 1;
+    }
+    __syncthreads();
+    // the blocks' arrays on all lanes of a wave, the rest on its first lane;
+    // FP64 on the first wave and FP32 on the second where there is one
     constexpr bool F64 = sizeof(T) == 8;
     const bool need_kd = F64 || m.nc > 1, need_kf = !F64;
-    const int tkf = nth > 64 ? 64 : 0;  // second wave where there is one
-    if (tid == 0 && need_kd) kin_cast<double>(s.k, s.kd);
-    if (tid == tkf && need_kf) kin_cast<float>(s.k, s.kf);
+    const int wv = tid >> 6, ln = tid & 63, wkf = nth > 64 ? 1 : 0;
+    if (need_kd && wv == 0) {
+        kin_cast_arrays<double>(k, s.kd, ln, 64);
+        if (ln == 0) kin_cast_rest<double>(k, s.kd);
+    }
+    if (need_kf && wv == wkf) {
+        kin_cast_arrays<float>(k, s.kf, ln, 64);
+        if (ln == 0) kin_cast_rest<float>(k, s.kf);
+    }
     __syncthreads();
     wg_copy8(&h->kin, &s.k, (int)sizeof(Kin));
     if (need_kf) wg_copy8(&h->kf, &s.kf, (int)sizeof(KinT<float>));
