@@ -144,15 +144,6 @@ def note(msg: str):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
-def free_sphere(body: dict) -> dict:
-    """The sphere of a workload in free flight: density 2 (twice the fluid's),
-    gravity 1 along -z, all six degrees of freedom, J = (2/5) M R^2."""
-    r = body.get("radius", 0.5)
-    mass = 2.0 * 4.0 / 3.0 * math.pi * r ** 3
-    return dict(body, free_flight=True, mass=mass, inertia=(0.4 * mass * r * r,) * 3, gravity=1.0,
-                dof=(1, 1, 1, 1, 1, 1))
-
-
 def build_workload(name: str):
     import workloads as W
     if name == "sphere128":
@@ -187,7 +178,7 @@ def build_workload(name: str):
                     desc=desc, default_steps=10)
     if name == "freefall128":
         wl = build_workload("sphere128")
-        wl["insect"] = free_sphere(wl["insect"])
+        wl["insect"] = W.free_sphere(wl["insect"])
         wl["desc"] = wl["desc"] + "; the sphere in free flight (density 2, g = 1 along -z, 6 DoF)"
         return wl
     if name == "insect256":
@@ -793,7 +784,8 @@ def main():
                                         "(3 more forward fields per step)"}
     if not a.no_freeflight and extras:
         # the same workload with the sphere in free flight
-        ff_body = free_sphere(swl["insect"])
+        import workloads as W
+        ff_body = W.free_sphere(swl["insect"])
         ff = {}
         for dtype in ("f32", "f64"):
             r = gpu_run(F, torch, dict(swl, insect=ff_body), dtype, s_steps, a.warmup, tune=not a.no_autotune)

@@ -130,6 +130,15 @@ def sphere_body(L: float = 4.0, radius: float = 0.5) -> dict:
                 smooth="tanh", c_smth=1.0)
 
 
+def free_sphere(body: dict) -> dict:
+    """The sphere of a workload in free flight: density 2 (twice the fluid's),
+    gravity 1 along -z, all six degrees of freedom, J = (2/5) M R^2."""
+    r = body.get("radius", 0.5)
+    mass = 2.0 * 4.0 / 3.0 * math.pi * r ** 3
+    return dict(body, free_flight=True, mass=mass, inertia=(0.4 * mass * r * r,) * 3, gravity=1.0,
+                dof=(1, 1, 1, 1, 1, 1))
+
+
 def model_insect(n: int, L: float = 4.0, phi_m: float = 70.0 * DEG,
                  alpha_m: float = 45.0 * DEG) -> dict:
     """Tethered model insect at the box centre: horizontal stroke plane
