@@ -1,20 +1,22 @@
-"""Writes box192_100.txt and freefall128_100.txt: the oracle's results for two
-of the benchmark's sphere workloads after 100 steps of Algorithm 1 (CFL 0.1,
-dt <= C_eta / 2; nu = 0.01, C_eta = 1e-3; inflow (1, 0, 0) plus solenoidal noise
-of rms 1e-3 on |k| <= 8, seed 0):
+"""Writes the oracle's results for the benchmark's sphere workloads after 100
+steps (CFL 0.1, dt <= C_eta / 2; nu = 0.01, C_eta = 1e-3; inflow (1, 0, 0) plus
+solenoidal noise of rms 1e-3 on |k| <= 8, seed 0; a sphere of radius 0.5):
 
-- box192_100.txt: the 192x128x128 box (6 x 4 x 4) with the sphere of radius 0.5
-  at (2.4, 2, 2);
-- freefall128_100.txt: the 128^3 box with the sphere at the centre in free
-  flight (density 2, gravity 1 along -z, six degrees of freedom).
+- box192_100.txt: the 192x128x128 box (6 x 4 x 4), the sphere at (2.4, 2, 2);
+- freefall128_100.txt: the 128^3 box, the sphere at the centre in free flight
+  (density 2, gravity 1 along -z, six degrees of freedom);
+- sponge128_100.txt: the 128^3 box with the vorticity sponge on 3.5 <= x < 4
+  (C_sp = 0.1, Sec. 2.3);
+- rk4_128_100.txt: the 128^3 box stepped with RK4 (Sec. 2.4) instead of AB2.
 
 Each file holds the time, step size and max |u| of every step, the body's
 force and torque at every step, and the velocity at 2048 seeded grid points
 (half of them drawn from the box around the sphere); the free-flight file also
 holds the 13-value body state after the steps.  The script calls only the oracle
-and the seeded input generators; about 20 minutes on 8 host cores:
+and the seeded input generators; about an hour on 8 host cores for all cases
+(names as arguments select some):
 
-    python tests/golden/make_sphere_workloads.py
+    python tests/golden/make_sphere_workloads.py [name ...]
 """
 import os
 import sys
@@ -33,7 +35,19 @@ CASES = {
     # name: (nx, n, body centre, free flight)
     "box192_100": (192, 128, (2.4, 2.0, 2.0), False),
     "freefall128_100": (128, 128, (2.0, 2.0, 2.0), True),
+    "sponge128_100": (128, 128, (2.0, 2.0, 2.0), False),
+    "rk4_128_100": (128, 128, (2.0, 2.0, 2.0), False),
 }
+# the vorticity sponge of the sponge case: C_sp and the layer thickness per axis
+SPONGE = (0.1, (0.5, 0.0, 0.0))
+
+
+def case_integrator(name: str) -> str:
+    return "rk4" if name.startswith("rk4") else "ab2"
+
+
+def case_sponge(name: str):
+    return SPONGE if name.startswith("sponge") else None
 
 
 def case_body(name: str) -> dict:
@@ -61,7 +75,12 @@ def sample_points(nx: int, n: int, xc) -> np.ndarray:
 
 def main():
     for name, (nx, n, xc, free) in CASES.items():
+        if len(sys.argv) > 1 and name not in sys.argv[1:]:
+            continue
         kw = dict(nx=nx, Lx=L * nx / n) if nx != n else {}
+        kw["integrator"] = case_integrator(name)
+        if case_sponge(name):
+            kw.update(c_sp=case_sponge(name)[0], sponge=tuple(case_sponge(name)[1]))
         p = O.Params(n, L, NU, ETA, O.MEAN_FIXED, **kw)
         ins = O.Insect.from_dict(case_body(name))
         st, hist = O.run(p, case_input(name), STEPS, O.StepControl(cfl=0.1, eta_cap=0.5), ins)

@@ -15,9 +15,10 @@ the 100-step parity tests (FP64 and FP32):
   seed 2), two steps at CFL 0.1 with dt <= C_eta/2;
 - insect256_100.txt (make_insect256.py): the headline workload, the flapping
   model insect in the 256^3 box from rest, 100 steps with the same controls;
-- box192_100.txt and freefall128_100.txt (make_sphere_workloads.py): the
-  benchmark's 192x128x128 box sphere and its 128^3 sphere in free flight, in
-  inflow with noise, 100 steps (the free flight also compares the body state)."""
+- box192_100.txt, freefall128_100.txt, sponge128_100.txt and rk4_128_100.txt
+  (make_sphere_workloads.py): the benchmark's sphere in inflow with noise in
+  the 192x128x128 box, and at 128^3 in free flight (the body state is compared
+  too), with the vorticity sponge, and stepped with RK4; 100 steps each."""
 import os
 import sys
 
@@ -51,11 +52,15 @@ def _golden(golden_dir, name, with_solid=False):
     return steps, forces, pts, vel
 
 
-def _run(n, L, u0, dtype, nsteps, pts, body=None, nu=1.0 / 136.0, eta=2.5e-4, nx=None):
+def _run(n, L, u0, dtype, nsteps, pts, body=None, nu=1.0 / 136.0, eta=2.5e-4, nx=None, sponge=None,
+         integrator="ab2"):
     """GPU steps (CFL 0.1, dt <= C_eta/2) of the body (default: the model
     insect, nu = 1/136, C_eta = 2.5e-4) from u0; the step history, the velocity
     at the grid points pts (i, j, k) and the body state."""
     P = F.Plan(n, L, nu, eta, dtype, nx=nx) if nx else F.Plan(n, L, nu, eta, dtype)
+    if sponge is not None:
+        P.set_sponge(*sponge)
+    P.set_integrator(integrator)
     st = P.new_state(u0)
     body = W.model_insect(n, L) if body is None else body
     h = P.step(st, nsteps, body, history=True, cfl=0.1, eta_cap=0.5).detach().cpu().numpy()
@@ -123,7 +128,7 @@ TOLSPH = {"f64": (1e-11, 1e-12, 1e-11, 1e-9, 1e-11), "f32": (2e-5, 1e-6, 2e-5, 1
 
 
 @pytest.mark.parametrize("dtype", ["f64", "f32"])
-@pytest.mark.parametrize("name", ["box192_100", "freefall128_100"])
+@pytest.mark.parametrize("name", ["box192_100", "freefall128_100", "sponge128_100", "rk4_128_100"])
 def test_sphere_workloads_hundred_steps_match_the_oracle(golden_dir, name, dtype):
     sys.path.insert(0, golden_dir)
     import make_sphere_workloads as M
@@ -132,7 +137,8 @@ def test_sphere_workloads_hundred_steps_match_the_oracle(golden_dir, name, dtype
     nx, n, _, free = M.CASES[name]
     u0 = torch.from_numpy(M.case_input(name))
     h, gvel, solid = _run(n, M.L, u0, dtype, len(steps), pts, body=M.case_body(name), nu=M.NU, eta=M.ETA,
-                          nx=nx if nx != n else None)
+                          nx=nx if nx != n else None, sponge=M.case_sponge(name),
+                          integrator=M.case_integrator(name))
     err = float(np.linalg.norm(gvel - ovel) / np.linalg.norm(ovel))
     print(f"{name} {dtype}, {len(steps)} steps: relative L2 over the sampled points = {err:.3e}")
     assert err <= tol_u
